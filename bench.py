@@ -1,0 +1,172 @@
+"""Throughput benchmark: exact 36-motif counting of the power-law workload.
+
+One step = the whole counting path on one synthetic graph already resident
+in HBM: build the device graph (validate, time sort, per-node sequences S_u,
+node-pair edge sets) from device pointers, count every motif for one delta
+(star/pair sweeps, triangle kernel, reduction), copy the 36 counts back.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.  ``value`` = edges counted per second over the K timed
+steps (wall clock, bracketed by device synchronisation).  ``roofline`` is
+measured for the kernel with the largest share of GPU time, from HIP events
+the library records around every launch on the launch stream during the
+timed steps; its algorithmic bytes per launch are modelled below.
+``cpu_baseline`` is the CPU oracle (test infrastructure, paper's Algorithms
+1 and 2, OpenMP over centers) timed on this host on the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "temporal edges/s counted (exact 36 motifs)"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(name: str, m: int, n: int, n_multi_el: int, info: dict) -> float | None:
+    """Minimum bytes one launch of ``name`` must move (reads + writes), for the
+    kernels that can dominate.  Radix scatter passes read and write every
+    (key, value) pair once; the histogram passes read every key once."""
+    e2 = 2 * m
+    tbytes = 4 if info["tbits"] <= 32 else 8
+    table = {
+        "sort_time_scatter": m * (tbytes + 4) * 2,
+        "sort_time_hist": m * tbytes,
+        "sort_node_scatter": e2 * (4 + 4) * 2,
+        "sort_node_hist": e2 * 4,
+        "sort_pair_scatter": m * (8 + 4) * 2,
+        "sort_pair_hist": m * 8,
+        # S_u fill: read rank slot, perm, src/dst, t; write t, nd, r, epos
+        "fill_seq": e2 * (4 + 4 + 4 + 8 + 8 + 4 + 4 + 4),
+        "pair_keys": m * (4 + 4 + 4 + 8 + 4),
+        "entries": m * (4 + 4 + 4 + 16),
+        "time_keys": m * (8 + tbytes + 4),
+        "validate": m * 16,
+    }
+    return table.get(name)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
+                          "not supported (the path shards by center, see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2204_09236_amd as tm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec = graphgen.CONFIGS[args.workload]
+    delta = spec["deltas"][0]
+    t0 = time.time()
+    g = spec["fn"]()
+    gen_s = time.time() - t0
+    print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {gen_s:.1f}s", file=sys.stderr,
+          flush=True)
+    src = torch.from_numpy(g.src).to(dev)
+    dst = torch.from_numpy(g.dst).to(dev)
+    tt = torch.from_numpy(g.t).to(dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step():
+        G = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
+        out = G.count(delta)
+        G.free()
+        return out
+
+    for _ in range(args.warmup):
+        counts = step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    tm.prof_reset()
+    tm.prof_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        counts = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    tm.prof_enable(False)
+    prof = tm.prof_read()
+    print("[bench] timed steps done", file=sys.stderr, flush=True)
+
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = g.m * args.steps / elapsed
+
+    # graph facts for the byte model
+    with tm.build_graph(src, dst, tt, n=g.n, stream=stream) as G:
+        info = G.info()
+    tspan = int(g.t.max() - g.t.min())
+    info["tbits"] = max(tspan.bit_length(), 1)
+    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4),
+                   "avg_ms": round(v[1] / max(v[0], 1), 5)} for k, v in prof.items()}
+    gpu_ms = sum(v[1] for v in prof.values()) / args.steps
+    dominant = max(prof.items(), key=lambda kv: kv[1][1])[0] if prof else None
+    roofline = None
+    if dominant is not None:
+        launches, total_ms = prof[dominant]
+        avg_s = total_ms / launches / 1e3
+        b = algorithmic_bytes(dominant, g.m, g.n, 0, info)
+        if b is not None:
+            achieved = b / avg_s / 1e9
+            roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": None, "bytes_per_launch": b,
+                        "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        t0 = time.perf_counter()
+        want = oracle.count(g.src, g.dst, g.t, delta, n=g.n, threads=threads)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(g.m / cpu_s, 1), "unit": "edges/s", "cores": threads, "kind": "oracle",
+               "sample": f"whole {args.workload} workload (m={g.m}, delta={delta}), one run, "
+                         f"{cpu_s:.1f} s incl. building S_u and E_(v,w)",
+               "matches_gpu": bool(np.array_equal(want, counts))}
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "delta": delta,
+                   "parallelism": "single-gpu"},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "gpu_kernel_ms_per_step": round(gpu_ms, 4),
+        "kernels": kernels,
+        "motif_total": int(counts.sum()),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

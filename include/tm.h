@@ -1,0 +1,159 @@
+/*
+ * tm.h -- exact delta-temporal motif counting on one AMD Instinct MI355X
+ * (gfx950), C ABI.
+ *
+ * Problem (the paper's Problem 1, Section III): given a temporal graph -- a
+ * list of directed, timestamped edges (src, dst, t) (Definition 1) -- and a
+ * window delta, count exactly the instances of every 2- and 3-node, 3-edge
+ * delta-temporal motif (Definitions 2 and 3): three distinct edges taken in
+ * chronological order E1 < E2 < E3 with t(E3) - t(E1) <= delta whose static
+ * graph has at most three nodes.  There are 36 such motifs: 4 pair, 24 star
+ * and 8 triangle motifs (Section IV's categorisation).
+ *
+ * Conventions shared by every entry point:
+ *   - Edge id = input row index.  Edges are totally ordered by (t, id): equal
+ *     timestamps are ordered by id.  Every delta test uses t alone and is
+ *     inclusive (t_last - t_first <= delta).
+ *   - Direction bits: o = 0 (edge leaves the center), in = 1.
+ *   - Raw counters, 56 x uint64 (the paper's counters, Sections IV-A/IV-B):
+ *       [ 0,24) Star[Type][d1][d2][d3]  Type I/II/III = position of the edge
+ *               whose node pair is not shared (quadruple counter)
+ *       [24,32) Pair[d1][d2][d3]        each pair instance seen from both of
+ *               its nodes (triple counter)
+ *       [32,56) Tri[Type][d_i][d_j][d_k] each triangle instance seen from its
+ *               three vertices; Type I/II/III = the far edge e_k before e_i,
+ *               between e_i and e_j, after e_j; d_k relative to e_i's
+ *               neighbour (quadruple counter)
+ *   - Motif counts, 36 x uint64, out[6*(i-1) + (j-1)] = M_ij.  The cells the
+ *     paper's text fixes are honoured (M24 = Star[I,in,o,in], M63 =
+ *     Star[III,o,o,in], M25, M26 = time-respecting 3-cycle, M46, M55, M56,
+ *     M65, M66); the remaining placement is this library's convention:
+ *       stars:     row 1 + 2*Type + [d3 = in],  col 1 + 2*[d2 = o] + [d1 = in]
+ *       triangles: Tri[I,a,b,c] class; col 5 + [b = o];
+ *                  row by ([a = b],[c = b]): TT 1, FF 2, FT 3, TF 4
+ *       pairs:     Pair[o,d2,d3]: (o,o) M55, (in,in) M56, (in,o) M65, (o,in) M66
+ *   - Status codes: every function returns TM_OK or a negative TM_E* code;
+ *     nothing throws across the ABI.  On error, output buffers are left
+ *     untouched.  tm_strerror() names a code; tm_last_error() gives the
+ *     calling thread's last detailed message.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tm_graph tm_graph;
+
+enum {
+    TM_OK = 0,
+    TM_EINVAL = -1,     /* bad argument or input (see tm_build_graph)          */
+    TM_ENOMEM = -2,     /* device allocation failed                             */
+    TM_EHIP = -3,       /* HIP runtime error (detail in tm_last_error)          */
+    TM_EAGAIN = -4,     /* try again (reserved for queued / pending work)       */
+    TM_ENOTFOUND = -5,  /* no such object                                       */
+    TM_EINTERNAL = -6   /* a self-check of the counters failed                  */
+};
+
+enum { TM_HOST_PTRS = 0, TM_DEVICE_PTRS = 1 };
+
+/*
+ * Build the device-resident graph used by every count (delta-independent).
+ *
+ * Sequences S_u (Section IV-A: every node's incident edges (t, v, dir) in
+ * time order) are built by device radix sorts keyed by (node, t, edge id),
+ * together with the node-pair edge sets E_(v,w) of Algorithm 2 (all edges of
+ * one unordered node pair, in (t, id) order).
+ *
+ *   src, dst  int32[m], node ids in [0, n); src[k] != dst[k] (no self-loops)
+ *   t         int64[m], |t| < 2^62
+ *   m         number of edges, < 2^31 (m = 0 is allowed: all counts are 0)
+ *   n_nodes   node count; 0 means max id + 1
+ *   flags     TM_HOST_PTRS: the three arrays are host memory (copied in);
+ *             TM_DEVICE_PTRS: they are device memory on the current device,
+ *             read on `hip_stream` before this call returns
+ *   hip_stream hipStream_t used for the build and for later counts on this
+ *             graph (NULL = the null stream)
+ *   out       receives the graph handle (owned by the library until
+ *             tm_graph_free)
+ * Ownership: the caller keeps ownership of src/dst/t; they only need to stay
+ * valid during the call.
+ * Errors: TM_EINVAL for a NULL pointer (m > 0), m >= 2^31, an id outside
+ * [0, n), a negative id, a self-loop or |t| >= 2^62; TM_ENOMEM / TM_EHIP.
+ */
+int tm_build_graph(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t m,
+                   uint32_t n_nodes, int flags, void *hip_stream, tm_graph **out);
+
+/* Release a graph and its device memory.  NULL is ignored. */
+void tm_graph_free(tm_graph *g);
+
+/*
+ * Exact counts of the 36 motifs for window delta (blocking; one 448-byte
+ * device-to-host copy at the end).  delta must satisfy 0 <= delta < 2^62;
+ * delta = 0 counts only triples with equal timestamps.  out: caller-owned
+ * host memory, 36 x uint64.  TM_EINTERNAL if the merge self-checks fail.
+ * Concurrent calls on one graph are allowed (each has its own scratch).
+ */
+int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]);
+
+/* The paper's raw counters (layout above), 56 x uint64, for window delta. */
+int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]);
+
+/*
+ * tm_count_raw with explicit work partitioning; the result never depends on
+ * these, only the schedule does.
+ *   run_chunk  edges of one node-pair edge set handled by one work item of
+ *              the star/pair kernel (hub splitting); 0 = default
+ *   tri_lane_max  window products (|W_src| * |W_dst|) up to this are counted
+ *              by one lane, larger ones by a whole wavefront; 0 = default
+ */
+int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
+                       uint64_t raw[56]);
+
+/*
+ * Merge raw counters into the 36 motif counts (pair cells: the view from the
+ * first edge's source; triangle cells: orbit sum / 3).  Returns TM_EINTERNAL,
+ * leaving out untouched, if Pair[d] != Pair[not d] or the three triangle
+ * views disagree.  Pure host function.
+ */
+int tm_merge(const uint64_t raw[56], uint64_t out[36]);
+
+/*
+ * Graph facts: n nodes, m edges, number of node pairs with >= 2 edges, and
+ * the largest S_u length.  Any output pointer may be NULL.
+ */
+int tm_graph_info(const tm_graph *g, uint32_t *n, uint64_t *m, uint64_t *multi_pairs,
+                  uint64_t *max_degree);
+
+/*
+ * Copy the sequences S_u back to host memory (test and inspection aid).
+ * off: uint32[n+1] (S_u = entries off[u] .. off[u+1]-1); t: int64[2m];
+ * nbr: uint32[2m] the other endpoint; dir: uint8[2m] (0 = o, 1 = in);
+ * id: uint32[2m] edge id.  All caller-owned host buffers; any may be NULL.
+ */
+int tm_graph_sequences(const tm_graph *g, uint32_t *off, int64_t *t, uint32_t *nbr,
+                       uint8_t *dir, uint32_t *id);
+
+/*
+ * Kernel timing (tracing aid).  While enabled, every library kernel launch is
+ * bracketed by HIP events on its stream; tm_prof_read synchronises and
+ * returns, for entry i (0-based, in first-launch order), the kernel name, the
+ * number of launches and their summed duration in milliseconds.  Returns
+ * TM_ENOTFOUND past the last entry.  Not thread-safe against concurrent
+ * counting; meant for benchmarks.
+ */
+void tm_prof_enable(int on);
+void tm_prof_reset(void);
+int tm_prof_read(int i, char *name, int name_cap, uint64_t *launches, double *total_ms);
+
+const char *tm_strerror(int code);
+const char *tm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

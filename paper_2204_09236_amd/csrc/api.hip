@@ -1,0 +1,335 @@
+// C ABI of the motif-counting library: graph lifecycle, counting entry points,
+// the merge of the paper's counters into the 36 motifs, errors and tracing.
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tm_internal.h"
+
+namespace tmc {
+
+// ----------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------- scratch
+Scratch::~Scratch() {
+    if (base) (void)hipFreeAsync(base, stream);
+}
+
+int Scratch::reserve(size_t bytes, hipStream_t s) {
+    stream = s;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync((void **)&base, bytes, s);
+    if (e != hipSuccess) {
+        base = nullptr;
+        set_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EHIP;
+    }
+    cap = bytes;
+    used = 0;
+    return TM_OK;
+}
+
+// --------------------------------------------------------------- profiler
+namespace {
+struct ProfRec {
+    std::string name;
+    hipEvent_t start, stop;
+    hipStream_t stream;
+};
+struct ProfSum {
+    std::string name;
+    uint64_t launches = 0;
+    double ms = 0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_pending;
+std::vector<ProfSum> g_sums;
+thread_local hipEvent_t g_cur_start = nullptr;
+thread_local const char *g_cur_name = nullptr;
+
+void prof_drain_locked() {
+    for (ProfRec &r : g_pending) {
+        (void)hipEventSynchronize(r.stop);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, r.start, r.stop);
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+        ProfSum *slot = nullptr;
+        for (ProfSum &s : g_sums)
+            if (s.name == r.name) slot = &s;
+        if (!slot) {
+            g_sums.push_back(ProfSum{r.name, 0, 0});
+            slot = &g_sums.back();
+        }
+        slot->launches += 1;
+        slot->ms += ms;
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+void prof_begin(const char *name, hipStream_t s) {
+    if (!g_prof_on) return;
+    g_cur_name = name;
+    if (hipEventCreate(&g_cur_start) != hipSuccess) {
+        g_cur_start = nullptr;
+        return;
+    }
+    (void)hipEventRecord(g_cur_start, s);
+}
+
+void prof_end(hipStream_t s) {
+    if (!g_prof_on || !g_cur_start) return;
+    hipEvent_t stop;
+    if (hipEventCreate(&stop) != hipSuccess) return;
+    (void)hipEventRecord(stop, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending.push_back(ProfRec{g_cur_name, g_cur_start, stop, s});
+    g_cur_start = nullptr;
+}
+
+}  // namespace tmc
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char *tm_strerror(int code) {
+    switch (code) {
+        case TM_OK: return "ok";
+        case TM_EINVAL: return "invalid argument or input";
+        case TM_ENOMEM: return "out of device memory";
+        case TM_EHIP: return "HIP runtime error";
+        case TM_EAGAIN: return "try again";
+        case TM_ENOTFOUND: return "not found";
+        case TM_EINTERNAL: return "internal self-check failed";
+        default: return "unknown status";
+    }
+}
+
+const char *tm_last_error(void) { return tmc::g_last_error.c_str(); }
+
+void tm_graph_free(tm_graph *g) {
+    if (!g) return;
+    void *ps[] = {g->off, g->ent_t, g->ent_nd, g->ent_r, g->X, g->epos, g->perm, g->pair_el,
+                  g->mp_start, g->mp_end, g->mp_lo, g->mp_hi};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    delete g;
+}
+
+int tm_build_graph(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t m,
+                   uint32_t n_nodes, int flags, void *hip_stream, tm_graph **out) {
+    if (!out) {
+        tmc::set_error("out is NULL");
+        return TM_EINVAL;
+    }
+    if (m > 0 && (!src || !dst || !t)) {
+        tmc::set_error("NULL edge array");
+        return TM_EINVAL;
+    }
+    if (m >= (1ull << 31)) {
+        tmc::set_error("m must be below 2^31");
+        return TM_EINVAL;
+    }
+    if (flags != TM_HOST_PTRS && flags != TM_DEVICE_PTRS) {
+        tmc::set_error("flags must be TM_HOST_PTRS or TM_DEVICE_PTRS");
+        return TM_EINVAL;
+    }
+    if (n_nodes >= 0x80000000u) {
+        tmc::set_error("node count must be below 2^31");
+        return TM_EINVAL;
+    }
+    tm_graph *g = new (std::nothrow) tm_graph();
+    if (!g) return TM_ENOMEM;
+    g->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&g->device);
+    const int32_t *ds = src, *dd = dst;
+    const int64_t *dt = t;
+    int32_t *own_s = nullptr, *own_d = nullptr;
+    int64_t *own_t = nullptr;
+    int rc = TM_OK;
+    if (flags == TM_HOST_PTRS && m > 0) {
+        hipError_t e1 = hipMalloc((void **)&own_s, m * sizeof(int32_t));
+        hipError_t e2 = hipMalloc((void **)&own_d, m * sizeof(int32_t));
+        hipError_t e3 = hipMalloc((void **)&own_t, m * sizeof(int64_t));
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            tmc::set_error("hipMalloc of the input copy failed");
+            rc = TM_ENOMEM;
+        } else {
+            hipStream_t s = g->stream;
+            if (hipMemcpyAsync(own_s, src, m * sizeof(int32_t), hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(own_d, dst, m * sizeof(int32_t), hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(own_t, t, m * sizeof(int64_t), hipMemcpyHostToDevice, s)) {
+                tmc::set_error("host-to-device copy failed");
+                rc = TM_EHIP;
+            }
+        }
+        ds = own_s;
+        dd = own_d;
+        dt = own_t;
+    }
+    if (rc == TM_OK) rc = tmc::build_graph_device(g, ds, dd, dt, m, n_nodes, g->stream);
+    if (own_s || own_d || own_t) {
+        (void)hipStreamSynchronize(g->stream);
+        if (own_s) (void)hipFree(own_s);
+        if (own_d) (void)hipFree(own_d);
+        if (own_t) (void)hipFree(own_t);
+    }
+    if (rc != TM_OK) {
+        (void)hipStreamSynchronize(g->stream);
+        tm_graph_free(g);
+        return rc;
+    }
+    *out = g;
+    return TM_OK;
+}
+
+int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
+                       uint64_t raw[56]) {
+    if (!g || !raw) {
+        tmc::set_error("NULL graph or output");
+        return TM_EINVAL;
+    }
+    if (delta < 0 || delta >= ((int64_t)1 << 62)) {
+        tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+        return TM_EINVAL;
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    uint64_t tmp[56];
+    int rc = tmc::count_graph(g, delta, run_chunk, tri_lane_max, tmp);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc) return rc;
+    for (int i = 0; i < 56; i++) raw[i] = tmp[i];
+    return TM_OK;
+}
+
+int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]) {
+    return tm_count_raw_tuned(g, delta, 0, 0, raw);
+}
+
+// 36-cell layout: out[6*(row-1) + (col-1)] = M_{row,col}
+static int cell(int row, int col) { return 6 * (row - 1) + (col - 1); }
+
+int tm_merge(const uint64_t raw[56], uint64_t out[36]) {
+    if (!raw || !out) return TM_EINVAL;
+    uint64_t res[36] = {0};
+    for (int ty = 0; ty < 3; ty++)
+        for (int d1 = 0; d1 < 2; d1++)
+            for (int d2 = 0; d2 < 2; d2++)
+                for (int d3 = 0; d3 < 2; d3++) {
+                    const int row = 1 + 2 * ty + (d3 == 1);
+                    const int col = 1 + 2 * (d2 == 0) + (d1 == 1);
+                    res[cell(row, col)] += raw[ty * 8 + d1 * 4 + d2 * 2 + d3];
+                }
+    for (int i = 0; i < 8; i++)
+        if (raw[24 + i] != raw[24 + (7 - i)]) {
+            tmc::set_error("pair counters are not symmetric");
+            return TM_EINTERNAL;
+        }
+    // pair classes seen from the first edge's source (d1 = o)
+    res[cell(5, 5)] += raw[24 + 0];  // (o,o,o)
+    res[cell(5, 6)] += raw[24 + 3];  // (o,in,in)
+    res[cell(6, 5)] += raw[24 + 2];  // (o,in,o)
+    res[cell(6, 6)] += raw[24 + 1];  // (o,o,in)
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int c = 0; c < 2; c++) {
+                const uint64_t x = raw[32 + a * 4 + b * 2 + c];
+                const uint64_t y = raw[40 + (1 - c) * 4 + (1 - b) * 2 + (1 - a)];
+                const uint64_t z = raw[48 + c * 4 + (1 - a) * 2 + (1 - b)];
+                if (x != y || y != z) {
+                    tmc::set_error("triangle views disagree");
+                    return TM_EINTERNAL;
+                }
+                const int col = 5 + (b == 0);
+                const bool ab = a == b, cb = c == b;
+                const int row = ab ? (cb ? 1 : 4) : (cb ? 3 : 2);
+                res[cell(row, col)] += (x + y + z) / 3;
+            }
+    for (int i = 0; i < 36; i++) out[i] = res[i];
+    return TM_OK;
+}
+
+int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]) {
+    if (!out) {
+        tmc::set_error("NULL output");
+        return TM_EINVAL;
+    }
+    uint64_t raw[56];
+    int rc = tm_count_raw(g, delta, raw);
+    if (rc) return rc;
+    return tm_merge(raw, out);
+}
+
+int tm_graph_info(const tm_graph *g, uint32_t *n, uint64_t *m, uint64_t *multi_pairs,
+                  uint64_t *max_degree) {
+    if (!g) return TM_EINVAL;
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (multi_pairs) *multi_pairs = g->n_multi;
+    if (max_degree) *max_degree = g->max_degree;
+    return TM_OK;
+}
+
+int tm_graph_sequences(const tm_graph *g, uint32_t *off, int64_t *t, uint32_t *nbr, uint8_t *dir,
+                       uint32_t *id) {
+    if (!g) return TM_EINVAL;
+    const uint64_t len = 2 * g->m;
+    hipStream_t s = g->stream;
+    if (off)
+        TM_HIP_TRY(hipMemcpyAsync(off, g->off, ((uint64_t)g->n + 1) * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, s));
+    if (t && len) TM_HIP_TRY(hipMemcpyAsync(t, g->ent_t, len * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    std::vector<uint32_t> nd, rk, perm;
+    if ((nbr || dir || id) && len) {
+        nd.resize(len);
+        TM_HIP_TRY(hipMemcpyAsync(nd.data(), g->ent_nd, len * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
+    if (id && len) {
+        rk.resize(len);
+        perm.resize(g->m);
+        TM_HIP_TRY(hipMemcpyAsync(rk.data(), g->ent_r, len * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipMemcpyAsync(perm.data(), g->perm, g->m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    }
+    TM_HIP_TRY(hipStreamSynchronize(s));
+    for (uint64_t p = 0; p < len; p++) {
+        if (nbr) nbr[p] = nd[p] >> 1;
+        if (dir) dir[p] = (uint8_t)(nd[p] & 1u);
+        if (id) id[p] = perm[rk[p]];
+    }
+    return TM_OK;
+}
+
+void tm_prof_enable(int on) {
+    std::lock_guard<std::mutex> lk(tmc::g_prof_mu);
+    tmc::g_prof_on = on != 0;
+}
+
+void tm_prof_reset(void) {
+    std::lock_guard<std::mutex> lk(tmc::g_prof_mu);
+    tmc::prof_drain_locked();
+    tmc::g_sums.clear();
+}
+
+int tm_prof_read(int i, char *name, int name_cap, uint64_t *launches, double *total_ms) {
+    std::lock_guard<std::mutex> lk(tmc::g_prof_mu);
+    tmc::prof_drain_locked();
+    if (i < 0 || i >= (int)tmc::g_sums.size()) return TM_ENOTFOUND;
+    const tmc::ProfSum &s = tmc::g_sums[i];
+    if (name && name_cap > 0) {
+        size_t k = 0;
+        for (; k + 1 < (size_t)name_cap && k < s.name.size(); k++) name[k] = s.name[k];
+        name[k] = 0;
+    }
+    if (launches) *launches = s.launches;
+    if (total_ms) *total_ms = s.ms;
+    return TM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,554 @@
+// Counting kernels for one window delta.
+//
+// Star and pair motifs (the paper's FAST-Star, Section IV-A / Algorithm 1).
+// Algorithm 1 scans, for every first edge e1 of S_u, all third edges e3 inside
+// delta and reads per-neighbour counts of the edges in between.  Summed over
+// e3, its four counter updates are sums over the window W = (i, R(i)] of S_u
+// (R(i) = last position with t <= t_i + delta) that only involve the edges to
+// e1's own neighbour v -- the node-pair edge set E_(u,v) -- plus prefix counts
+// of directions along S_u.  With P_d(x) = number of dir-d entries of S_u at
+// positions <= x, and, over the E_(u,v) edges inside W:
+//   in[d]      = how many have dir d
+//   S2[d][d']  = ordered pairs k < j of them with dirs (d, d')
+//   sPm[d'][d] = sum over those with dir d' of P_d(position - 1)
+// the contributions of e1 = i (dir d_i) are, for all d, d':
+//   Pair    [d_i][d][d'] += S2[d][d']
+//   Star_II [d_i][d][d'] += sPm[d'][d] - in[d'] * P_d(i) - S2[d][d']
+//   Star_III[d_i][d][d'] += in[d] * P_d'(R) - (sPm[d][d'] + [d = d'] in[d]) - S2[d][d']
+// Star_I (e2 and e3 share the neighbour w != v) is the time mirror of Star_III
+// and is summed per third edge j instead, over the window [L(j), j) with
+// L(j) = first position with t >= t_j - delta, using the E_(u,w) edges there:
+//   Star_I[d1][d2][d_j] += sPm'[d2][d1] - in'[d2] * P_d1(L - 1) - S2'[d1][d2]
+// Each edge of E_(u,v) enters and leaves these windows once (two pointers), so
+// a node pair's work is linear in its edge count.  Only node pairs with at
+// least two edges contribute (all four sums vanish otherwise), and every such
+// pair is swept from both of its nodes.  Long pairs are cut into chunks that
+// each own a range of e1 (or e3) positions and first load the delta-window
+// that reaches into the chunk (hub splitting); every instance is counted by
+// the one chunk that owns its first (or, for Star_I, its last) edge.
+//
+// Triangle motifs (FAST-Tri, Section IV-B / Algorithm 2).  Every triangle
+// instance is counted once, by its earliest edge E1 = (s -> d): E2 and E3 are
+// the edges to the third node r inside the windows after E1 at s and at d, so
+// the instances owned by E1 are the pairs (a in W_s, b in W_d) with equal
+// neighbour r.  The class is the Type-I view at r (the vertex not on E1):
+//   a before b: Tri[I][not dir_s(a)][not dir_d(b)][o]
+//   b before a: Tri[I][not dir_d(b)][not dir_s(a)][in]
+// The paper's center-based counter Tri[3][2][2][2] counts each instance once
+// per vertex; its three views follow from the class exactly (orbit map in the
+// host merge), so no instance is enumerated three times.
+//
+// Per-lane uint64 accumulators are reduced per block, then all block partials
+// are summed by one deterministic tree reduction (no atomics on counts).
+#include "tm_internal.h"
+
+namespace tmc {
+
+namespace {
+
+struct SeqView {
+    const int64_t *t;      // ent_t
+    const uint32_t *nd;    // ent_nd
+    const uint32_t *rk;    // ent_r
+    const uint32_t *X;     // exclusive prefix of dir = in
+    const uint32_t *off;
+    const uint32_t *epos;
+};
+
+// Largest x in [p, hi) with t[x] <= lim, given t[p] <= lim (gallop, then bisect).
+__device__ inline uint32_t window_end(const int64_t *T, uint32_t p, uint32_t hi, int64_t lim) {
+    uint32_t lo = p, top = hi;
+    uint64_t step = 1;
+    while (true) {
+        const uint64_t probe = (uint64_t)lo + step;
+        if (probe >= hi) {
+            top = hi;
+            break;
+        }
+        if (T[probe] <= lim) {
+            lo = (uint32_t)probe;
+            step <<= 1;
+        } else {
+            top = (uint32_t)probe;
+            break;
+        }
+    }
+    while (top - lo > 1) {
+        const uint32_t mid = lo + (top - lo) / 2;
+        if (T[mid] <= lim) lo = mid;
+        else top = mid;
+    }
+    return lo;
+}
+
+// Smallest x in [lo_bound, p] with t[x] >= lim, given t[p] >= lim.
+__device__ inline uint32_t window_start(const int64_t *T, uint32_t p, uint32_t lo_bound,
+                                        int64_t lim) {
+    uint32_t hi = p, bot = lo_bound;
+    uint64_t step = 1;
+    bool found_low = false;
+    while (true) {
+        if ((uint64_t)hi < (uint64_t)lo_bound + step) {
+            break;
+        }
+        const uint32_t probe = (uint32_t)(hi - step);
+        if (T[probe] >= lim) {
+            hi = probe;
+            step <<= 1;
+        } else {
+            bot = probe;
+            found_low = true;
+            break;
+        }
+    }
+    // T[hi] >= lim; answer in (bot, hi] if found_low, else [lo_bound, hi]
+    uint32_t a = found_low ? bot + 1 : lo_bound, b = hi;
+    while (a < b) {
+        const uint32_t mid = a + (b - a) / 2;
+        if (T[mid] >= lim) b = mid;
+        else a = mid + 1;
+    }
+    return a;
+}
+
+// --------------------------------------------------------------- star/pair
+struct Elem {
+    int64_t t;
+    uint32_t p;    // position in S_c
+    uint32_t dir;  // 0 = o, 1 = in (relative to the center c)
+    uint32_t a0, a1;  // P_0(p-1), P_1(p-1): entries of each dir before p in S_c
+};
+
+__device__ inline Elem load_elem(const SeqView &S, uint32_t el, uint32_t side, uint32_t seg_lo,
+                                 uint32_t xbase) {
+    Elem e;
+    const uint32_t r = el & ~kOrientBit;
+    const uint32_t is_src = (el >> 31) ^ side;  // side 0: center = smaller node
+    e.p = S.epos[2 * r + (is_src ? 0 : 1)];
+    e.dir = is_src ? 0u : 1u;
+    e.t = S.t[e.p];
+    e.a1 = S.X[e.p] - xbase;
+    e.a0 = (e.p - seg_lo) - e.a1;
+    return e;
+}
+
+// Window state over the edges of one node pair inside a delta-window.
+struct Win {
+    uint64_t in[2];
+    uint64_t S2[2][2];   // S2[d][d']: ordered pairs k < j, dir k = d, dir j = d'
+    uint64_t sPm[2][2];  // sPm[d'][e]: sum over dir-d' edges of P_e(position - 1)
+    __device__ inline void clear() {
+        in[0] = in[1] = 0;
+        S2[0][0] = S2[0][1] = S2[1][0] = S2[1][1] = 0;
+        sPm[0][0] = sPm[0][1] = sPm[1][0] = sPm[1][1] = 0;
+    }
+    // append a later edge (dir d, prefix counts a0, a1)
+    __device__ inline void push(uint32_t d, uint32_t a0, uint32_t a1) {
+        const uint64_t m1 = 0ull - (uint64_t)d, m0 = ~m1;
+        // S2[x][d] += in[x] for x in {0,1}
+        S2[0][0] += in[0] & m0;
+        S2[1][0] += in[1] & m0;
+        S2[0][1] += in[0] & m1;
+        S2[1][1] += in[1] & m1;
+        in[0] += 1 & m0;
+        in[1] += 1 & m1;
+        sPm[0][0] += a0 & m0;
+        sPm[0][1] += a1 & m0;
+        sPm[1][0] += a0 & m1;
+        sPm[1][1] += a1 & m1;
+    }
+    // remove the earliest edge (dir d)
+    __device__ inline void pop(uint32_t d, uint32_t a0, uint32_t a1) {
+        const uint64_t m1 = 0ull - (uint64_t)d, m0 = ~m1;
+        in[0] -= 1 & m0;
+        in[1] -= 1 & m1;
+        // S2[d][x] -= in[x]
+        S2[0][0] -= in[0] & m0;
+        S2[0][1] -= in[1] & m0;
+        S2[1][0] -= in[0] & m1;
+        S2[1][1] -= in[1] & m1;
+        sPm[0][0] -= a0 & m0;
+        sPm[0][1] -= a1 & m0;
+        sPm[1][0] -= a0 & m1;
+        sPm[1][1] -= a1 & m1;
+    }
+};
+
+// Accumulators: [0,24) Star[T][d1][d2][d3], [24,32) Pair[d1][d2][d3]
+struct StarAcc {
+    uint64_t c[32];
+};
+
+__device__ inline void add_sel(uint64_t &lo_cell, uint64_t &hi_cell, uint64_t v, uint64_t m1) {
+    lo_cell += v & ~m1;
+    hi_cell += v & m1;
+}
+
+struct WorkItem {
+    uint32_t pair;   // index of the multi-edge node pair
+    uint32_t chunk;  // chunk index inside it
+};
+
+__global__ void __launch_bounds__(kBlock) k_star_pair(SeqView S, const uint32_t *pair_el,
+                                                      const uint32_t *mp_start,
+                                                      const uint32_t *mp_end,
+                                                      const uint32_t *mp_lo, const uint32_t *mp_hi,
+                                                      const WorkItem *items, uint64_t n_items,
+                                                      uint32_t chunk, int64_t delta,
+                                                      uint64_t *partial) {
+    StarAcc A;
+#pragma unroll
+    for (int i = 0; i < 32; i++) A.c[i] = 0;
+
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n_items;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        const WorkItem w = items[it];
+        const uint32_t rs = mp_start[w.pair], re = mp_end[w.pair];
+        const uint32_t cb = rs + w.chunk * chunk;
+        const uint32_t ce = min(re, cb + chunk);
+        for (uint32_t side = 0; side < 2; side++) {
+            const uint32_t c = side ? mp_hi[w.pair] : mp_lo[w.pair];
+            const uint32_t seg_lo = S.off[c], seg_hi = S.off[c + 1];
+            const uint32_t xbase = S.X[seg_lo];
+
+            // ---- e1 sweep: Pair, Star_II, Star_III
+            Win W;
+            W.clear();
+            uint32_t j = cb + 1;  // next pair edge to enter the window
+            for (uint32_t q = cb; q < ce; q++) {
+                const Elem eq = load_elem(S, pair_el[q], side, seg_lo, xbase);
+                if (q > cb && j > q) W.pop(eq.dir, eq.a0, eq.a1);
+                if (j <= q) j = q + 1;
+                const int64_t lim = eq.t + delta;
+                while (j < re) {
+                    const Elem ej = load_elem(S, pair_el[j], side, seg_lo, xbase);
+                    if (ej.t > lim) break;
+                    W.push(ej.dir, ej.a0, ej.a1);
+                    j++;
+                }
+                if (W.in[0] + W.in[1] == 0) continue;
+                const uint32_t R = window_end(S.t, eq.p, seg_hi, lim);
+                const uint64_t rp1 = S.X[R + 1] - xbase;
+                const uint64_t rp0 = (uint64_t)(R + 1 - seg_lo) - rp1;
+                const uint64_t rp[2] = {rp0, rp1};
+                const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0),
+                                         (uint64_t)eq.a1 + (eq.dir == 1)};
+                const uint64_t m1 = 0ull - (uint64_t)eq.dir;
+#pragma unroll
+                for (int d = 0; d < 2; d++) {
+#pragma unroll
+                    for (int dp = 0; dp < 2; dp++) {
+                        const uint64_t s2 = W.S2[d][dp];
+                        // Pair[d_i][d][d']
+                        add_sel(A.c[24 + 0 + d * 2 + dp], A.c[24 + 4 + d * 2 + dp], s2, m1);
+                        // Star_II[d_i][d][d']
+                        const uint64_t v2 = W.sPm[dp][d] - W.in[dp] * pin[d] - s2;
+                        add_sel(A.c[8 + 0 + d * 2 + dp], A.c[8 + 4 + d * 2 + dp], v2, m1);
+                        // Star_III[d_i][d][d']
+                        const uint64_t sp = W.sPm[d][dp] + (d == dp ? W.in[d] : 0ull);
+                        const uint64_t v3 = W.in[d] * rp[dp] - sp - s2;
+                        add_sel(A.c[16 + 0 + d * 2 + dp], A.c[16 + 4 + d * 2 + dp], v3, m1);
+                    }
+                }
+            }
+
+            // ---- e3 sweep: Star_I
+            W.clear();
+            uint32_t f;  // front of the window [f, q)
+            {
+                const Elem eb = load_elem(S, pair_el[cb], side, seg_lo, xbase);
+                const int64_t lim = eb.t - delta;
+                f = cb;
+                while (f > rs) {
+                    const Elem ef = load_elem(S, pair_el[f - 1], side, seg_lo, xbase);
+                    if (ef.t < lim) break;
+                    f--;
+                }
+                for (uint32_t k = f; k < cb; k++) {
+                    const Elem ek = load_elem(S, pair_el[k], side, seg_lo, xbase);
+                    W.push(ek.dir, ek.a0, ek.a1);
+                }
+            }
+            for (uint32_t q = cb; q < ce; q++) {
+                const Elem eq = load_elem(S, pair_el[q], side, seg_lo, xbase);
+                const int64_t lim = eq.t - delta;
+                while (f < q) {
+                    const Elem ef = load_elem(S, pair_el[f], side, seg_lo, xbase);
+                    if (ef.t >= lim) break;
+                    W.pop(ef.dir, ef.a0, ef.a1);
+                    f++;
+                }
+                if (W.in[0] + W.in[1] != 0) {
+                    const uint32_t L = window_start(S.t, eq.p, seg_lo, lim);
+                    const uint64_t lp1 = S.X[L] - xbase;
+                    const uint64_t lp0 = (uint64_t)(L - seg_lo) - lp1;
+                    const uint64_t lp[2] = {lp0, lp1};
+                    const uint64_t m1 = 0ull - (uint64_t)eq.dir;
+#pragma unroll
+                    for (int d1 = 0; d1 < 2; d1++) {
+#pragma unroll
+                        for (int d2 = 0; d2 < 2; d2++) {
+                            const uint64_t v1 = W.sPm[d2][d1] - W.in[d2] * lp[d1] - W.S2[d1][d2];
+                            // Star_I[d1][d2][d3 = dir of q]
+                            add_sel(A.c[0 + d1 * 4 + d2 * 2 + 0], A.c[0 + d1 * 4 + d2 * 2 + 1], v1,
+                                    m1);
+                        }
+                    }
+                }
+                W.push(eq.dir, eq.a0, eq.a1);
+            }
+        }
+    }
+
+    // block reduction of the 32 accumulators
+    __shared__ uint64_t red[kBlock / kWave][32];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        uint64_t v = A.c[i];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if (lane == 0) red[wv][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        uint64_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
+        partial[(uint64_t)blockIdx.x * 32 + threadIdx.x] = s;
+    }
+}
+
+// Work items: node pair k is cut into ceil(len / chunk) items.
+__global__ void k_item_counts(const uint32_t *mp_start, const uint32_t *mp_end, uint64_t n_multi,
+                              uint32_t chunk, uint32_t *cnt) {
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_multi;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t len = mp_end[k] - mp_start[k];
+        cnt[k] = (len + chunk - 1) / chunk;
+    }
+}
+
+__global__ void k_item_fill(const uint32_t *cnt, const uint32_t *first, uint64_t n_multi,
+                            WorkItem *items) {
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_multi;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b = first[k];
+        for (uint32_t c = 0; c < cnt[k]; c++) items[b + c] = WorkItem{(uint32_t)k, c};
+    }
+}
+
+// ---------------------------------------------------------------- triangles
+struct TriAcc {
+    uint64_t c[8];  // class (a, b, c): Tri[I][a][b][c]
+};
+
+__device__ inline void tri_add(TriAcc &T, uint32_t idx) {
+#pragma unroll
+    for (int i = 0; i < 8; i++) T.c[i] += (idx == (uint32_t)i) ? 1ull : 0ull;
+}
+
+// class of a matched pair: a from W_s (dir relative to s), b from W_d
+__device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint32_t db) {
+    return ra < rb ? ((1u - da) * 4 + (1u - db) * 2 + 0u) : ((1u - db) * 4 + (1u - da) * 2 + 1u);
+}
+
+__global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, uint64_t m, int64_t delta,
+                                                      uint32_t lane_max, uint64_t *partial) {
+    TriAcc T;
+#pragma unroll
+    for (int i = 0; i < 8; i++) T.c[i] = 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    // whole waves step through the edge ranks together
+    const uint64_t wave_id = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+    for (uint64_t base = wave_id * kWave; base < m; base += n_waves * kWave) {
+        const uint64_t r = base + lane;
+        uint32_t ps = 0, pd = 0, Rs = 0, Rd = 0;
+        bool active = false;
+        if (r < m) {
+            ps = S.epos[2 * r];
+            pd = S.epos[2 * r + 1];
+            const int64_t t1 = S.t[ps];
+            const int64_t lim = t1 + delta;
+            const uint32_t s_node = S.nd[pd] >> 1, d_node = S.nd[ps] >> 1;
+            const uint32_t s_hi = S.off[s_node + 1], d_hi = S.off[d_node + 1];
+            if (ps + 1 < s_hi && pd + 1 < d_hi && S.t[ps + 1] <= lim && S.t[pd + 1] <= lim) {
+                Rs = window_end(S.t, ps, s_hi, lim);
+                Rd = window_end(S.t, pd, d_hi, lim);
+                active = true;
+            }
+        }
+        const uint64_t ws = Rs - ps, wd = Rd - pd;
+        const bool small = active && ws * wd <= lane_max;
+        if (small) {
+            for (uint32_t a = ps + 1; a <= Rs; a++) {
+                const uint32_t nda = S.nd[a];
+                const uint32_t ra = S.rk[a];
+                for (uint32_t b = pd + 1; b <= Rd; b++) {
+                    const uint32_t ndb = S.nd[b];
+                    if ((ndb >> 1) == (nda >> 1))
+                        tri_add(T, tri_class(ra, nda & 1u, S.rk[b], ndb & 1u));
+                }
+            }
+        }
+        // large windows: the whole wave takes one edge at a time; lanes hold
+        // entries of the larger window, the smaller one is walked in order
+        uint64_t big = __ballot(active && !small);
+        while (big) {
+            const int L = __ffsll((unsigned long long)big) - 1;
+            big &= big - 1;
+            const uint32_t bps = __shfl(ps, L, kWave), bRs = __shfl(Rs, L, kWave);
+            const uint32_t bpd = __shfl(pd, L, kWave), bRd = __shfl(Rd, L, kWave);
+            const bool s_outer = (bRs - bps) <= (bRd - bpd);
+            const uint32_t o_lo = s_outer ? bps + 1 : bpd + 1, o_hi = s_outer ? bRs : bRd;
+            const uint32_t i_lo = s_outer ? bpd + 1 : bps + 1, i_hi = s_outer ? bRd : bRs;
+            for (uint32_t ib = i_lo; ib <= i_hi; ib += kWave) {
+                const uint32_t x = ib + lane;
+                const bool valid = x <= i_hi;
+                const uint32_t ndx = valid ? S.nd[x] : 0xffffffffu;
+                const uint32_t rx = valid ? S.rk[x] : 0u;
+                for (uint32_t o = o_lo; o <= o_hi; o++) {
+                    const uint32_t ndo = S.nd[o];
+                    if (valid && (ndx >> 1) == (ndo >> 1)) {
+                        const uint32_t ro = S.rk[o];
+                        const uint32_t cls = s_outer ? tri_class(ro, ndo & 1u, rx, ndx & 1u)
+                                                     : tri_class(rx, ndx & 1u, ro, ndo & 1u);
+                        tri_add(T, cls);
+                    }
+                }
+            }
+        }
+    }
+    __shared__ uint64_t red[kBlock / kWave][8];
+    const int wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        uint64_t v = T.c[i];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if (lane == 0) red[wv][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        uint64_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
+        partial[(uint64_t)blockIdx.x * 8 + threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------- reduction
+// out[c] = sum over rows of part[row][c]; one block, fixed order (integer
+// sums: exact and independent of the order anyway).
+__global__ void __launch_bounds__(kBlock) k_reduce_cols(const uint64_t *part, uint32_t rows,
+                                                        uint32_t cols, uint64_t *out) {
+    __shared__ uint64_t lds[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    for (uint32_t c = 0; c < cols; c++) {
+        uint64_t v = 0;
+        for (uint32_t r = threadIdx.x; r < rows; r += kBlock) v += part[(uint64_t)r * cols + c];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if (lane == 0) lds[wv] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t s = 0;
+            for (int q = 0; q < kBlock / kWave; q++) s += lds[q];
+            out[c] = s;
+        }
+        __syncthreads();
+    }
+}
+
+dim3 grid_for(uint64_t n, uint64_t cap) {
+    uint64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb < 1) nb = 1;
+    if (nb > cap) nb = cap;
+    return dim3((unsigned)nb);
+}
+
+}  // namespace
+
+constexpr uint32_t kDefaultRunChunk = 256;
+constexpr uint32_t kDefaultTriLaneMax = 64;
+
+int count_graph(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
+                uint64_t raw[56]) {
+    if (run_chunk == 0) run_chunk = kDefaultRunChunk;
+    if (tri_lane_max == 0) tri_lane_max = kDefaultTriLaneMax;
+    uint64_t host[40] = {0};
+    hipStream_t s = g->stream;
+    if (g->m >= 3) {
+        SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->X, g->off, g->epos};
+        const uint64_t nm = g->n_multi;
+        constexpr uint32_t kMaxStarBlocks = 2048, kMaxTriBlocks = 4096;
+        const dim3 tgrid = grid_for(g->m, kMaxTriBlocks);
+        const uint32_t nt = tgrid.x;
+        // scratch layout
+        const size_t n_tmp = scan_tmp_count(nm) + 4;
+        size_t bytes = 0;
+        auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+        bytes += up((nm + 1) * sizeof(uint32_t)) * 2;      // counts, firsts
+        bytes += up(n_tmp * sizeof(uint32_t));
+        bytes += up((uint64_t)kMaxStarBlocks * 32 * sizeof(uint64_t));
+        bytes += up((uint64_t)nt * 8 * sizeof(uint64_t));
+        bytes += up(40 * sizeof(uint64_t));
+        Scratch sc;
+        int rc = sc.reserve(bytes, s);
+        if (rc) return rc;
+        uint32_t *cnt = sc.take<uint32_t>(nm + 1);
+        uint32_t *first = sc.take<uint32_t>(nm + 1);
+        uint32_t *tmp = sc.take<uint32_t>(n_tmp);
+        uint64_t *spart = sc.take<uint64_t>((uint64_t)kMaxStarBlocks * 32);
+        uint64_t *tpart = sc.take<uint64_t>((uint64_t)nt * 8);
+        uint64_t *res = sc.take<uint64_t>(40);
+        uint64_t n_items = 0;
+        WorkItem *items = nullptr;
+        Scratch sc_items;
+        if (nm) {
+            TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s,
+                      g->mp_start, g->mp_end, nm, run_chunk, cnt);
+            rc = scan_u32_array(cnt, first, nm, tmp, s);
+            if (rc) return rc;
+            uint32_t total = 0;
+            TM_HIP_TRY(hipMemcpyAsync(&total, first + nm, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            TM_HIP_TRY(hipStreamSynchronize(s));
+            n_items = total;
+            rc = sc_items.reserve(n_items * sizeof(WorkItem) + 256, s);
+            if (rc) return rc;
+            items = sc_items.take<WorkItem>(n_items);
+            TM_LAUNCH("item_fill", k_item_fill, grid_for(nm, 4096), dim3(kBlock), 0, s, cnt, first,
+                      nm, items);
+        }
+        // one partial row per launched block; no launch means zero rows
+        const dim3 igrid = grid_for(n_items, kMaxStarBlocks);
+        const uint32_t ns = n_items ? igrid.x : 0u;
+        if (n_items) {
+            TM_LAUNCH("star_pair", k_star_pair, igrid, dim3(kBlock), 0, s, S, g->pair_el,
+                      g->mp_start, g->mp_end, g->mp_lo, g->mp_hi, items, n_items, run_chunk, delta,
+                      spart);
+        }
+        TM_LAUNCH("triangles", k_triangles, tgrid, dim3(kBlock), 0, s, S, g->m, delta, tri_lane_max,
+                  tpart);
+        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, spart, ns, 32u, res);
+        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, tpart, nt, 8u, res + 32);
+        TM_HIP_TRY(hipMemcpyAsync(host, res, 40 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipStreamSynchronize(s));
+    }
+    // raw counters: Star | Pair straight from the kernel; Tri views from the
+    // classes by the orbit Tri[I,a,b,c] = Tri[II,~c,~b,~a] = Tri[III,c,~a,~b]
+    for (int i = 0; i < 32; i++) raw[i] = host[i];
+    const uint64_t *N = host + 32;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int c = 0; c < 2; c++) {
+                const uint64_t v = N[a * 4 + b * 2 + c];
+                raw[32 + 0 * 8 + a * 4 + b * 2 + c] = v;
+                raw[32 + 1 * 8 + (1 - c) * 4 + (1 - b) * 2 + (1 - a)] = v;
+                raw[32 + 2 * 8 + c * 4 + (1 - a) * 2 + (1 - b)] = v;
+            }
+    return TM_OK;
+}
+
+}  // namespace tmc

@@ -1,0 +1,211 @@
+"""Python binding of libtm.so (ctypes).  Argument marshalling only: every step
+of the counting path runs in the library's HIP kernels.
+
+Inputs are either host numpy arrays (copied in by the library) or torch
+tensors on the GPU (read in place on the current torch stream).  Results are
+numpy uint64 arrays: ``count`` gives the 6x6 motif matrix M_ij, ``count_raw``
+the paper's 56 raw counters (Star | Pair | Tri).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtm.so")
+
+TM_OK, TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_EAGAIN, TM_ENOTFOUND, TM_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+TM_HOST_PTRS, TM_DEVICE_PTRS = 0, 1
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.tm_build_graph.argtypes = [vp, vp, vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, vp,
+                                   ctypes.POINTER(vp)]
+    lib.tm_build_graph.restype = ctypes.c_int
+    lib.tm_graph_free.argtypes = [vp]
+    lib.tm_graph_free.restype = None
+    lib.tm_count.argtypes = [vp, ctypes.c_int64, u64p]
+    lib.tm_count.restype = ctypes.c_int
+    lib.tm_count_raw.argtypes = [vp, ctypes.c_int64, u64p]
+    lib.tm_count_raw.restype = ctypes.c_int
+    lib.tm_count_raw_tuned.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, u64p]
+    lib.tm_count_raw_tuned.restype = ctypes.c_int
+    lib.tm_merge.argtypes = [u64p, u64p]
+    lib.tm_merge.restype = ctypes.c_int
+    lib.tm_graph_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), u64p, u64p, u64p]
+    lib.tm_graph_info.restype = ctypes.c_int
+    lib.tm_graph_sequences.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tm_graph_sequences.restype = ctypes.c_int
+    lib.tm_prof_enable.argtypes = [ctypes.c_int]
+    lib.tm_prof_enable.restype = None
+    lib.tm_prof_reset.argtypes = []
+    lib.tm_prof_reset.restype = None
+    lib.tm_prof_read.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, u64p,
+                                 ctypes.POINTER(ctypes.c_double)]
+    lib.tm_prof_read.restype = ctypes.c_int
+    lib.tm_strerror.argtypes = [ctypes.c_int]
+    lib.tm_strerror.restype = ctypes.c_char_p
+    lib.tm_last_error.argtypes = []
+    lib.tm_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+class TMError(RuntimeError):
+    def __init__(self, code: int):
+        detail = _lib.tm_last_error().decode(errors="replace")
+        super().__init__(f"{_lib.tm_strerror(code).decode()} ({code}): {detail}")
+        self.code = code
+
+
+def _check(rc: int) -> None:
+    if rc != TM_OK:
+        raise TMError(rc)
+
+
+def _u64(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _is_torch_device(x) -> bool:
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
+
+
+class Graph:
+    """A device-resident graph: S_u sequences and node-pair edge sets."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph was freed")
+        return self._h
+
+    def count(self, delta: int) -> np.ndarray:
+        out = np.zeros(36, dtype=np.uint64)
+        _check(_lib.tm_count(self.handle, int(delta), _u64(out)))
+        return out.reshape(6, 6)
+
+    def count_raw(self, delta: int, run_chunk: int = 0, tri_lane_max: int = 0) -> np.ndarray:
+        raw = np.zeros(56, dtype=np.uint64)
+        _check(_lib.tm_count_raw_tuned(self.handle, int(delta), int(run_chunk), int(tri_lane_max),
+                                       _u64(raw)))
+        return raw
+
+    def info(self) -> dict:
+        n = ctypes.c_uint32()
+        m, mp, md = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.tm_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(mp),
+                                  ctypes.byref(md)))
+        return {"n": n.value, "m": m.value, "multi_pairs": mp.value, "max_degree": md.value}
+
+    def sequences(self) -> dict:
+        inf = self.info()
+        n, m = inf["n"], inf["m"]
+        off = np.zeros(n + 1, np.uint32)
+        t = np.zeros(2 * m, np.int64)
+        nbr = np.zeros(2 * m, np.uint32)
+        dr = np.zeros(2 * m, np.uint8)
+        ids = np.zeros(2 * m, np.uint32)
+        _check(_lib.tm_graph_sequences(self.handle, off.ctypes.data, t.ctypes.data, nbr.ctypes.data,
+                                       dr.ctypes.data, ids.ctypes.data))
+        return {"off": off, "t": t, "nbr": nbr, "dir": dr, "id": ids}
+
+    def free(self) -> None:
+        if self._h:
+            _lib.tm_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def build_graph(src, dst, t, n: int | None = None, stream=None) -> Graph:
+    """Build the device graph.  ``src``/``dst``/``t`` are int32/int32/int64,
+    either host numpy arrays or torch tensors on the GPU (then read on
+    ``stream``, default: torch's current stream)."""
+    h = ctypes.c_void_p()
+    if _is_torch_device(src):
+        import torch
+        if not (src.dtype == torch.int32 and dst.dtype == torch.int32 and t.dtype == torch.int64):
+            raise TypeError("device inputs must be int32, int32, int64 tensors")
+        src, dst, t = src.contiguous(), dst.contiguous(), t.contiguous()
+        m = src.numel()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        _check(_lib.tm_build_graph(src.data_ptr(), dst.data_ptr(), t.data_ptr(), m,
+                                   int(n or 0), TM_DEVICE_PTRS, sp, ctypes.byref(h)))
+    else:
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        tt = np.ascontiguousarray(t, dtype=np.int64)
+        if not (s.shape == d.shape == tt.shape and s.ndim == 1):
+            raise ValueError("src, dst, t must be 1-D arrays of one length")
+        sp = ctypes.c_void_p(int(stream) if stream is not None else 0)
+        _check(_lib.tm_build_graph(s.ctypes.data, d.ctypes.data, tt.ctypes.data, s.size,
+                                   int(n or 0), TM_HOST_PTRS, sp, ctypes.byref(h)))
+    return Graph(h)
+
+
+def count(src, dst, t, delta: int, n: int | None = None) -> np.ndarray:
+    with build_graph(src, dst, t, n=n) as g:
+        return g.count(delta)
+
+
+def merge(raw) -> np.ndarray:
+    raw = np.ascontiguousarray(raw, dtype=np.uint64)
+    out = np.zeros(36, dtype=np.uint64)
+    _check(_lib.tm_merge(_u64(raw), _u64(out)))
+    return out.reshape(6, 6)
+
+
+# ---- kernel timing
+def prof_enable(on: bool = True) -> None:
+    _lib.tm_prof_enable(1 if on else 0)
+
+
+def prof_reset() -> None:
+    _lib.tm_prof_reset()
+
+
+def prof_read() -> dict:
+    """{kernel name: (launches, total ms)} for launches since the last reset."""
+    out = {}
+    i = 0
+    buf = ctypes.create_string_buffer(128)
+    while True:
+        n, ms = ctypes.c_uint64(), ctypes.c_double()
+        rc = _lib.tm_prof_read(i, buf, 128, ctypes.byref(n), ctypes.byref(ms))
+        if rc != TM_OK:
+            break
+        out[buf.value.decode()] = (n.value, ms.value)
+        i += 1
+    return out
+
+
+def library():
+    """The loaded ctypes library (for ABI checks)."""
+    return _lib

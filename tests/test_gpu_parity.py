@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Counts are integers, so the bar is bit-exact equality of all 56 raw counters
+(and hence of the 36 motif counts) on the same seeded inputs.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from motif_defs import edges, load_toy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2204_09236_amd as p
+    return p
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def gpu_raw(tm, src, dst, t, delta, n=None, **kw):
+    with tm.build_graph(src, dst, t, n=n) as g:
+        return g.count_raw(delta, **kw)
+
+
+def check(tm, src, dst, t, deltas, n=None, label=""):
+    with tm.build_graph(src, dst, t, n=n) as g:
+        for d in deltas:
+            case(f"{label} m={len(src)} n={n} delta={d}")
+            want = oracle.alg(src, dst, t, d, n=n)
+            got = g.count_raw(d)
+            np.testing.assert_array_equal(got, want, err_msg=f"{label} delta={d}")
+            np.testing.assert_array_equal(g.count(d), oracle.merge(want))
+
+
+def test_toy_graph(tm):
+    src, dst, t = load_toy()
+    check(tm, src, dst, t, [0, 1, 5, 10, 20, 100], n=5, label="toy")
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small(tm, seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(3, 10))
+    m = int(rng.integers(3, 80))
+    g = graphgen.small_random(rng, n, m, t_values=int(rng.integers(1, 15)) if seed % 2 else None,
+                              tmax=int(rng.integers(1, 80)), multi=0.3 if seed % 3 == 0 else 0.0)
+    span = int(g.t.max() - g.t.min())
+    check(tm, g.src, g.dst, g.t, sorted({0, 1, span // 3, span, span + 7}), n=n,
+          label=f"small seed={seed}")
+
+
+@pytest.mark.parametrize("seed,n,m,tv", [(1, 30, 3000, 200), (2, 200, 20000, None),
+                                          (3, 12, 5000, 50), (4, 1000, 60000, 5000)])
+def test_random_medium(tm, seed, n, m, tv):
+    rng = np.random.default_rng(seed)
+    g = graphgen.small_random(rng, n, m, t_values=tv, tmax=100000, multi=0.2)
+    check(tm, g.src, g.dst, g.t, [0, 50, 1000, 20000], n=n, label=f"medium seed={seed}")
+
+
+def test_tiny_config(tm):
+    g = graphgen.tiny()
+    check(tm, g.src, g.dst, g.t, [1000], n=g.n, label="tiny config")
+
+
+def test_sequences_match_definition(tm):
+    """S_u = every node's incident edges in (t, id) order (byte for byte)."""
+    rng = np.random.default_rng(11)
+    g = graphgen.small_random(rng, 50, 4000, t_values=300, tmax=10000, multi=0.3)
+    case("sequences m=4000")
+    with tm.build_graph(g.src, g.dst, g.t, n=50) as G:
+        seq = G.sequences()
+    m = g.m
+    ids = np.arange(m)
+    node = np.concatenate([g.src, g.dst]).astype(np.int64)
+    nbr = np.concatenate([g.dst, g.src]).astype(np.int64)
+    dr = np.concatenate([np.zeros(m), np.ones(m)]).astype(np.uint8)
+    tt = np.concatenate([g.t, g.t])
+    eid = np.concatenate([ids, ids])
+    order = np.lexsort((eid, tt, node))
+    off = np.searchsorted(node[order], np.arange(51))
+    np.testing.assert_array_equal(seq["off"], off)
+    np.testing.assert_array_equal(seq["t"], tt[order])
+    np.testing.assert_array_equal(seq["nbr"], nbr[order])
+    np.testing.assert_array_equal(seq["dir"], dr[order])
+    np.testing.assert_array_equal(seq["id"], eid[order])
+
+
+def test_partitioning_invariance(tm):
+    """Chunk size of the node-pair sweeps and the lane/wave split of the
+    triangle kernel change the schedule, never the counts."""
+    rng = np.random.default_rng(21)
+    g = graphgen.small_random(rng, 20, 6000, t_values=400, tmax=20000, multi=0.5)
+    want = oracle.alg(g.src, g.dst, g.t, 800, n=20)
+    with tm.build_graph(g.src, g.dst, g.t, n=20) as G:
+        for rc in (1, 2, 3, 7, 64, 1 << 30):
+            for lm in (1, 4, 64, 1 << 30):
+                case(f"partition run_chunk={rc} tri_lane_max={lm}")
+                np.testing.assert_array_equal(G.count_raw(800, run_chunk=rc, tri_lane_max=lm), want)
+
+
+def test_hub_pair_long_run(tm):
+    """One node pair with 8,000 edges inside one window (a long E_(v,w))
+    plus background edges: exercises chunking with large delta-halos."""
+    rng = np.random.default_rng(31)
+    k = 8000
+    src = np.where(rng.random(k) < 0.5, 0, 1).astype(np.int32)
+    dst = (1 - src).astype(np.int32)
+    t = rng.integers(0, 3000, k).astype(np.int64)
+    bg = graphgen.small_random(rng, 40, 3000, tmax=3000)
+    s = np.concatenate([src, bg.src]); d = np.concatenate([dst, bg.dst])
+    tt = np.concatenate([t, bg.t])
+    check(tm, s, d, tt, [100, 5000], n=40, label="hub pair")
+
+
+def test_star_hub(tm):
+    """A center with 6,000 edges to 150 leaves plus edges among the leaves."""
+    rng = np.random.default_rng(32)
+    k = 6000
+    leaf = rng.integers(1, 151, k).astype(np.int32)
+    out = rng.random(k) < 0.5
+    src = np.where(out, 0, leaf).astype(np.int32)
+    dst = np.where(out, leaf, 0).astype(np.int32)
+    t = rng.integers(0, 50000, k).astype(np.int64)
+    bg = graphgen.small_random(rng, 151, 8000, tmax=50000)
+    s = np.concatenate([src, bg.src]); d = np.concatenate([dst, bg.dst])
+    tt = np.concatenate([t, bg.t])
+    check(tm, s, d, tt, [0, 300, 5000], n=151, label="star hub")
+
+
+def test_all_timestamps_equal(tm):
+    rng = np.random.default_rng(41)
+    g = graphgen.small_random(rng, 15, 600, multi=0.3)
+    t = np.full(g.m, 77, np.int64)
+    check(tm, g.src, g.dst, t, [0, 10], n=15, label="all ties")
+
+
+def test_fewer_than_three_edges(tm):
+    for rows in ([], [(0, 1, 5)], [(0, 1, 5), (1, 0, 6)]):
+        src, dst, t = edges(rows) if rows else (np.zeros(0, np.int32),) * 2 + (np.zeros(0, np.int64),)
+        case(f"m={len(rows)}")
+        assert gpu_raw(tm, src, dst, t, 10, n=2).sum() == 0
+    src, dst, t = edges([(0, 1, 1), (1, 2, 2), (2, 0, 3)])
+    np.testing.assert_array_equal(gpu_raw(tm, src, dst, t, 2, n=3), oracle.alg(src, dst, t, 2, n=3))
+
+
+def test_isolated_nodes_and_large_ids(tm):
+    rng = np.random.default_rng(51)
+    g = graphgen.small_random(rng, 60, 5000, t_values=500, tmax=5000, multi=0.2)
+    ids = np.sort(rng.choice(1 << 26, 60, replace=False)).astype(np.int32)
+    src, dst = ids[g.src], ids[g.dst]
+    n = (1 << 26) + 5
+    check(tm, src, dst, g.t, [0, 200], n=n, label="sparse ids")
+
+
+def test_negative_and_extreme_times(tm):
+    rng = np.random.default_rng(52)
+    g = graphgen.small_random(rng, 25, 3000, t_values=200, tmax=4000, multi=0.2)
+    big = (1 << 62) - 10_000
+    for shift in (-big, big - 5000, -(1 << 40)):
+        t = g.t + shift
+        check(tm, g.src, g.dst, t, [0, 100, 3000], n=25, label=f"t shift {shift}")
+
+
+def test_device_pointer_input(tm):
+    import torch
+    rng = np.random.default_rng(61)
+    g = graphgen.small_random(rng, 100, 20000, t_values=2000, tmax=100000, multi=0.2)
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(g.src).to(dev)
+    d = torch.from_numpy(g.dst).to(dev)
+    t = torch.from_numpy(g.t).to(dev)
+    case("device pointers m=20000")
+    with tm.build_graph(s, d, t, n=100) as G:
+        got = G.count_raw(2000)
+    np.testing.assert_array_equal(got, oracle.alg(g.src, g.dst, g.t, 2000, n=100))
+
+
+def test_invalid_inputs(tm):
+    src, dst, t = edges([(0, 1, 1), (1, 2, 2), (2, 0, 3)])
+    for s, d, tt, n in [(src, np.array([1, 1, 0], np.int32), t, 3),          # self-loop
+                        (src, np.array([1, 5, 0], np.int32), t, 3),          # id >= n
+                        (np.array([-1, 1, 2], np.int32), dst, t, 3),         # negative id
+                        (src, dst, np.array([1, 1 << 62, 3], np.int64), 3)]:  # |t| too big
+        case("invalid input")
+        with pytest.raises(tm.TMError) as ei:
+            tm.build_graph(s, d, tt, n=n)
+        assert ei.value.code == -1
+    with tm.build_graph(src, dst, t, n=3) as G:
+        with pytest.raises(tm.TMError):
+            G.count(-1)
+
+
+def test_repeatable(tm):
+    rng = np.random.default_rng(71)
+    g = graphgen.small_random(rng, 300, 50000, t_values=5000, tmax=200000, multi=0.3)
+    case("repeat m=50000")
+    with tm.build_graph(g.src, g.dst, g.t, n=300) as G:
+        a = G.count_raw(4000)
+        b = G.count_raw(4000)
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("delta", [3600, 86400, 1_000_000])
+def test_powerlaw_scaled(tm, delta):
+    """The power-law generator at 1/50 scale (20K nodes, 400K edges)."""
+    g = graphgen.chung_lu_pareto(101, 20_000, 400_000)
+    check(tm, g.src, g.dst, g.t, [delta], n=g.n, label="powerlaw/50")
+
+
+def test_skewed_scaled(tm):
+    """The skewed generator (repeats, hub) at 1/1000 scale."""
+    g = graphgen.skewed(seed=102, n=10_000, m=300_000, top_degree=1000)
+    check(tm, g.src, g.dst, g.t, [600, 3600, 86400], n=g.n, label="skewed/1000")
+
+
+def test_powerlaw_full_size(tm):
+    """The benchmark workload at full size (1M nodes, 20M edges, delta 3600),
+    built from device pointers on the current stream as bench.py does, against
+    the oracle's counts stored by tests/golden/make_golden.py (or the oracle
+    run here if this host regenerates a different edge list)."""
+    import torch
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "powerlaw_counts.json")))
+    g = graphgen.powerlaw()
+    same_input = graphgen.edge_hash(g) == rec["edge_sha256"]
+    dev = torch.device("cuda:0")
+    s, d, t = (torch.from_numpy(a).to(dev) for a in (g.src, g.dst, g.t))
+    for key, val in rec["counts"].items():
+        delta = int(key)
+        case(f"powerlaw full m={g.m} delta={delta} stored={same_input}")
+        with tm.build_graph(s, d, t, n=g.n) as G:
+            got = G.count_raw(delta)
+        if same_input:
+            want = np.array(val["raw"], dtype=np.uint64)
+        else:
+            want = oracle.alg(g.src, g.dst, g.t, delta, n=g.n, threads=min(16, os.cpu_count()))
+        np.testing.assert_array_equal(got, want)
