@@ -38,28 +38,33 @@ def parse():
     ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--untraced", action="store_true",
+                    help="time the steps without the per-launch event tracer (no roofline)")
     return ap.parse_args()
 
 
-def algorithmic_bytes(name: str, m: int, n: int, n_multi_el: int, info: dict) -> float | None:
-    """Minimum bytes one launch of ``name`` must move (reads + writes), for the
-    kernels that can dominate.  Radix scatter passes read and write every
-    (key, value) pair once; the histogram passes read every key once."""
+def algorithmic_bytes(name: str, m: int, info: dict) -> float | None:
+    """Minimum bytes one launch of ``name`` must move (reads + writes) on this
+    workload.  Radix scatter passes read and write every (key, value) pair
+    once; histogram passes read every key once."""
     e2 = 2 * m
-    tbytes = 4 if info["tbits"] <= 32 else 8
+    tk = 4 if info["tbits"] <= 32 else 8
+    me = info["multi_pair_edges"]
     table = {
-        "sort_time_scatter": m * (tbytes + 4) * 2,
-        "sort_time_hist": m * tbytes,
-        "sort_node_scatter": e2 * (4 + 4) * 2,
+        "sort_time_scatter": m * (tk + 12) * 2,      # key + (src, dst, id)
+        "sort_time_hist": m * tk,
+        "sort_node_scatter": e2 * (4 + 8) * 2,       # node + (rank, other end, dir)
         "sort_node_hist": e2 * 4,
-        "sort_pair_scatter": m * (8 + 4) * 2,
+        "sort_pair_scatter": m * (8 + 4) * 2,        # pair key + rank
         "sort_pair_hist": m * 8,
-        # S_u fill: read rank slot, perm, src/dst, t; write t, nd, r, epos
-        "fill_seq": e2 * (4 + 4 + 4 + 8 + 8 + 4 + 4 + 4),
-        "pair_keys": m * (4 + 4 + 4 + 8 + 4),
-        "entries": m * (4 + 4 + 4 + 16),
-        "time_keys": m * (8 + tbytes + 4),
+        "fill_seq": e2 * (8 + 8 + 8 + 4 + 4 + 4),    # read value, t; write t, nd, rank, epos
+        "rank": m * (tk + 12 + 8 + 4 + 8 + 16 + 8 + 4),
+        "windows": e2 * (4 + 8 + 4),                 # center, t -> window length
+        "star_prep": 2 * me * (8 + 8 + 8 + 4 + 16),
+        "star_pair": me * 2 * (8 + 1 + 8 + 16),
+        "tri_flags": m * (8 + 4 + 4 + 4),
         "validate": m * 16,
+        "time_keys": m * (16 + tk + 12),
     }
     return table.get(name)
 
@@ -106,7 +111,7 @@ def main():
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
     tm.prof_reset()
-    tm.prof_enable(True)
+    tm.prof_enable(not args.untraced)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -133,7 +138,7 @@ def main():
     if dominant is not None:
         launches, total_ms = prof[dominant]
         avg_s = total_ms / launches / 1e3
-        b = algorithmic_bytes(dominant, g.m, g.n, 0, info)
+        b = algorithmic_bytes(dominant, g.m, info)
         if b is not None:
             achieved = b / avg_s / 1e9
             roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),

@@ -122,11 +122,12 @@ int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t 
 int tm_merge(const uint64_t raw[56], uint64_t out[36]);
 
 /*
- * Graph facts: n nodes, m edges, number of node pairs with >= 2 edges, and
- * the largest S_u length.  Any output pointer may be NULL.
+ * Graph facts: n nodes, m edges, number of node pairs with >= 2 edges and the
+ * number of edges on them, and the largest S_u length.  Any output pointer
+ * may be NULL.
  */
 int tm_graph_info(const tm_graph *g, uint32_t *n, uint64_t *m, uint64_t *multi_pairs,
-                  uint64_t *max_degree);
+                  uint64_t *multi_pair_edges, uint64_t *max_degree);
 
 /*
  * Copy the sequences S_u back to host memory (test and inspection aid).

@@ -15,18 +15,16 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 // ---------------------------------------------------------------- scratch
 Scratch::~Scratch() {
-    if (base) (void)hipFreeAsync(base, stream);
+    if (base) dev_free(base, stream);
 }
 
 int Scratch::reserve(size_t bytes, hipStream_t s) {
     stream = s;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMallocAsync((void **)&base, bytes, s);
-    if (e != hipSuccess) {
-        base = nullptr;
-        set_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EHIP;
-    }
+    void *p = nullptr;
+    const int rc = dev_alloc(&p, bytes, s);
+    if (rc) return rc;
+    base = static_cast<char *>(p);
     cap = bytes;
     used = 0;
     return TM_OK;
@@ -48,6 +46,19 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_pending;
 std::vector<ProfSum> g_sums;
+std::vector<hipEvent_t> g_event_pool;  // recycled events (creation is slow)
+
+hipEvent_t take_event() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 thread_local hipEvent_t g_cur_start = nullptr;
 thread_local const char *g_cur_name = nullptr;
 
@@ -56,8 +67,8 @@ void prof_drain_locked() {
         (void)hipEventSynchronize(r.stop);
         float ms = 0;
         (void)hipEventElapsedTime(&ms, r.start, r.stop);
-        (void)hipEventDestroy(r.start);
-        (void)hipEventDestroy(r.stop);
+        g_event_pool.push_back(r.start);
+        g_event_pool.push_back(r.stop);
         ProfSum *slot = nullptr;
         for (ProfSum &s : g_sums)
             if (s.name == r.name) slot = &s;
@@ -75,17 +86,14 @@ void prof_drain_locked() {
 void prof_begin(const char *name, hipStream_t s) {
     if (!g_prof_on) return;
     g_cur_name = name;
-    if (hipEventCreate(&g_cur_start) != hipSuccess) {
-        g_cur_start = nullptr;
-        return;
-    }
-    (void)hipEventRecord(g_cur_start, s);
+    g_cur_start = take_event();
+    if (g_cur_start) (void)hipEventRecord(g_cur_start, s);
 }
 
 void prof_end(hipStream_t s) {
     if (!g_prof_on || !g_cur_start) return;
-    hipEvent_t stop;
-    if (hipEventCreate(&stop) != hipSuccess) return;
+    hipEvent_t stop = take_event();
+    if (!stop) return;
     (void)hipEventRecord(stop, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_pending.push_back(ProfRec{g_cur_name, g_cur_start, stop, s});
@@ -114,10 +122,11 @@ const char *tm_last_error(void) { return tmc::g_last_error.c_str(); }
 
 void tm_graph_free(tm_graph *g) {
     if (!g) return;
-    void *ps[] = {g->off, g->ent_t, g->ent_nd, g->ent_r, g->X, g->epos, g->perm, g->pair_el,
-                  g->mp_start, g->mp_end, g->mp_lo, g->mp_hi};
-    for (void *p : ps)
-        if (p) (void)hipFree(p);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    for (void *p : g->allocs) tmc::dev_free(p, g->stream);
+    if (cur != g->device) (void)hipSetDevice(cur);
     delete g;
 }
 
@@ -268,12 +277,16 @@ int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]) {
 }
 
 int tm_graph_info(const tm_graph *g, uint32_t *n, uint64_t *m, uint64_t *multi_pairs,
-                  uint64_t *max_degree) {
+                  uint64_t *multi_pair_edges, uint64_t *max_degree) {
     if (!g) return TM_EINVAL;
     if (n) *n = g->n;
     if (m) *m = g->m;
     if (multi_pairs) *multi_pairs = g->n_multi;
-    if (max_degree) *max_degree = g->max_degree;
+    if (multi_pair_edges) *multi_pair_edges = g->n_me;
+    if (max_degree) {
+        const int rc = tmc::graph_max_degree(const_cast<tm_graph *>(g), max_degree);
+        if (rc) return rc;
+    }
     return TM_OK;
 }
 

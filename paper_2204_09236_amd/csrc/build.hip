@@ -1,15 +1,19 @@
-// Graph build: the per-node time-ordered sequences S_u (the paper's Section
-// IV-A input to FAST-Star; Algorithm 1 "get S_u") and the node-pair edge sets
-// E_(v,w) of Algorithm 2, both produced by stable device radix sorts.
+// Graph build: the per-node time-ordered sequences S_u (Section IV-A: every
+// node's incident edges (t, v, dir) in time order, the input of FAST-Star and
+// FAST-Tri) and the node-pair edge sets E_(v,w) of Algorithm 2, produced by
+// stable device radix sorts.  Everything here is delta-independent.
 //
-//   1. validate the edge list, find min/max t and max node id
-//   2. sort edges by t (stable, so ties stay in id order): rank r -> edge id
-//   3. emit two incident entries per edge in rank order and sort them by node
-//      (stable): S_u in (u, t, id) order, offsets from the sorted node keys
-//   4. sort edges (in rank order) by (min node, max node) (stable): every
-//      unordered node pair's edges become one run in (t, id) order; runs with
-//      at least two edges are indexed (only they can hold pair or star
-//      instances: both need two edges on one node pair)
+//   1. validate the edge list; min/max t and max node id
+//   2. sort edges by t, carrying (src, dst, id): stable, so equal timestamps
+//      stay in id order -> edge rank r in the (t, id) order
+//   3. two incident entries per edge, in rank order, sorted by node (stable),
+//      carrying (r, other endpoint, dir): S_u in (u, t, id) order
+//   4. edges (in rank order) sorted by (smaller node, larger node) (stable):
+//      each unordered node pair's edges in (t, id) order.  Only pairs with at
+//      least two edges can hold pair or star instances (both need two edges
+//      on one node pair); their edges are gathered into compact per-pair
+//      arrays with, for each of the two nodes, the edge's position in S_u and
+//      the number of dir-o / dir-in entries before it.
 #include <algorithm>
 #include <vector>
 
@@ -20,6 +24,9 @@ namespace tmc {
 namespace {
 
 constexpr int64_t kTLimit = (int64_t)1 << 62;
+constexpr uint32_t kGapFill = 64;
+constexpr uint32_t kUnset = 0xffffffffu;
+constexpr uint32_t kMaxStatBlocks = 1024;
 
 struct Stat {
     uint32_t bad;        // bit 0: id out of range / negative, bit 1: self-loop, bit 2: |t| too big
@@ -28,6 +35,7 @@ struct Stat {
     uint64_t tmax_key;
 };
 
+// Flags and extrema (not counts): block reduction, then one atomic per block.
 __global__ void __launch_bounds__(kBlock) k_validate(const int32_t *src, const int32_t *dst,
                                                      const int64_t *t, uint64_t m,
                                                      uint32_t n_limit, Stat *st) {
@@ -45,49 +53,63 @@ __global__ void __launch_bounds__(kBlock) k_validate(const int32_t *src, const i
         tmin = min(tmin, k);
         tmax = max(tmax, k);
     }
-    // wave reduction, then one atomic per wave (flags and extrema, not counts)
     for (int o = kWave / 2; o > 0; o >>= 1) {
         bad |= __shfl_xor(bad, o, kWave);
         mx = max(mx, (uint32_t)__shfl_xor(mx, o, kWave));
         tmin = min(tmin, (uint64_t)__shfl_xor(tmin, o, kWave));
         tmax = max(tmax, (uint64_t)__shfl_xor(tmax, o, kWave));
     }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (bad) atomicOr(&st->bad, bad);
-        atomicMax(&st->max_id, mx);
-        atomicMin((unsigned long long *)&st->tmin_key, (unsigned long long)tmin);
-        atomicMax((unsigned long long *)&st->tmax_key, (unsigned long long)tmax);
+    __shared__ Stat ws[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) ws[w] = Stat{bad, mx, tmin, tmax};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Stat r = ws[0];
+        for (int i = 1; i < kBlock / kWave; i++) {
+            r.bad |= ws[i].bad;
+            r.max_id = max(r.max_id, ws[i].max_id);
+            r.tmin_key = min(r.tmin_key, ws[i].tmin_key);
+            r.tmax_key = max(r.tmax_key, ws[i].tmax_key);
+        }
+        if (r.bad) atomicOr(&st->bad, r.bad);
+        atomicMax(&st->max_id, r.max_id);
+        atomicMin((unsigned long long *)&st->tmin_key, (unsigned long long)r.tmin_key);
+        atomicMax((unsigned long long *)&st->tmax_key, (unsigned long long)r.tmax_key);
     }
 }
 
 template <typename K>
-__global__ void k_time_keys(const int64_t *t, uint64_t m, int64_t tmin, K *keys, uint32_t *vals) {
+__global__ void k_time_keys(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t m,
+                            int64_t tmin, K *keys, EdgeVal *vals) {
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (uint64_t)gridDim.x * blockDim.x) {
         keys[e] = (K)(uint64_t)(t[e] - tmin);
-        vals[e] = (uint32_t)e;
+        vals[e] = EdgeVal{(uint32_t)src[e], (uint32_t)dst[e], (uint32_t)e};
     }
 }
 
-// Incident entries in rank order: slot 2r = src side (dir o), 2r+1 = dst side (dir in).
-__global__ void k_entries(const int32_t *src, const int32_t *dst, const uint32_t *perm, uint64_t m,
-                          uint32_t *nkey, uint32_t *nval) {
+// From the time-sorted edges (rank r): timestamps and ids by rank, the
+// incident entries to sort by node (slot 2r: at src, out; 2r+1: at dst, in;
+// value = r << 32 | other endpoint << 1 | dir), and the node-pair keys.
+template <typename K>
+__global__ void k_rank(const K *tkey, const EdgeVal *tval, uint64_t m, int64_t tmin, uint64_t n,
+                       int64_t *t_r, uint32_t *perm, uint32_t *nkey, NodeVal *nval,
+                       uint64_t *pkey, uint32_t *pval) {
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t e = perm[r];
-        nkey[2 * r] = (uint32_t)src[e];
-        nkey[2 * r + 1] = (uint32_t)dst[e];
-        nval[2 * r] = (uint32_t)(2 * r);
-        nval[2 * r + 1] = (uint32_t)(2 * r + 1);
+        const EdgeVal ev = tval[r];
+        const int64_t te = (int64_t)((uint64_t)tkey[r] + (uint64_t)tmin);
+        t_r[r] = te;
+        perm[r] = ev.id;
+        nkey[2 * r] = ev.src;
+        nkey[2 * r + 1] = ev.dst;
+        nval[2 * r] = NodeVal{te, (uint32_t)r, ev.dst << 1};
+        nval[2 * r + 1] = NodeVal{te, (uint32_t)r, (ev.src << 1) | 1u};
+        const uint32_t lo = min(ev.src, ev.dst), hi = max(ev.src, ev.dst);
+        pkey[r] = (uint64_t)lo * n + hi;
+        pval[r] = (uint32_t)r | (ev.src == lo ? kOrientBit : 0u);
     }
 }
-
-// off[u] = first position of node u in the node-sorted keys, atomic-free:
-// each boundary between consecutive keys fills the offsets of the (absent)
-// nodes it skips over, up to kGapFill of them; longer runs of absent nodes are
-// left marked and resolved by k_offsets_gaps with a binary search.
-constexpr uint32_t kGapFill = 64;
-constexpr uint32_t kUnset = 0xffffffffu;
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -95,6 +117,10 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
         p[i] = v;
 }
 
+// off[u] = first position of node u in the node-sorted keys, atomic-free:
+// each boundary between consecutive keys fills the offsets of the (absent)
+// nodes it skips over, up to kGapFill of them; longer runs of absent nodes are
+// left marked and resolved by k_offsets_gaps with a binary search.
 __global__ void k_offsets(const uint32_t *skey, uint64_t len, uint32_t n, uint32_t *off) {
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= len;
          p += (uint64_t)gridDim.x * blockDim.x) {
@@ -121,73 +147,74 @@ __global__ void k_offsets_gaps(const uint32_t *skey, uint64_t len, uint32_t n, u
     }
 }
 
-__global__ void k_fill_seq(const int32_t *src, const int32_t *dst, const int64_t *t,
-                           const uint32_t *perm, const uint32_t *sval, uint64_t len,
-                           int64_t *ent_t, uint32_t *ent_nd, uint32_t *ent_r, uint32_t *epos) {
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < len;
-         p += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t slot = sval[p];
-        const uint32_t r = slot >> 1, side = slot & 1u;
-        const uint32_t e = perm[r];
-        const uint32_t nbr = side ? (uint32_t)src[e] : (uint32_t)dst[e];
-        ent_t[p] = t[e];
-        ent_nd[p] = (nbr << 1) | side;
-        ent_r[p] = r;
-        epos[slot] = (uint32_t)p;
-    }
-}
-
-__global__ void k_pair_keys(const int32_t *src, const int32_t *dst, const uint32_t *perm,
-                            uint64_t m, uint64_t n, uint64_t *pkey, uint32_t *pval) {
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
-         r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t e = perm[r];
-        const uint32_t a = (uint32_t)src[e], b = (uint32_t)dst[e];
-        const uint32_t lo = min(a, b), hi = max(a, b);
-        pkey[r] = (uint64_t)lo * n + hi;
-        pval[r] = (uint32_t)r | (a == lo ? kOrientBit : 0u);
-    }
-}
-
-// Head of a run with at least two edges.
-__global__ void k_multi_heads(const uint64_t *pkey, uint64_t m, uint32_t *flag) {
+// Element g of the pair-sorted edges lies in a pair with >= 2 edges; head = first of its pair.
+__global__ void k_multi_flags(const uint64_t *pkey, uint64_t m, uint32_t *in_multi,
+                              uint32_t *multi_head) {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m;
          g += (uint64_t)gridDim.x * blockDim.x) {
-        const bool head = g == 0 || pkey[g] != pkey[g - 1];
-        const bool multi = g + 1 < m && pkey[g + 1] == pkey[g];
-        flag[g] = (head && multi) ? 1u : 0u;
+        const uint64_t k = pkey[g];
+        const bool same_prev = g > 0 && pkey[g - 1] == k;
+        const bool same_next = g + 1 < m && pkey[g + 1] == k;
+        in_multi[g] = (same_prev || same_next) ? 1u : 0u;
+        multi_head[g] = (!same_prev && same_next) ? 1u : 0u;
     }
 }
 
-__global__ void k_multi_fill(const uint64_t *pkey, uint64_t m, uint64_t n, const uint32_t *flag,
-                             const uint32_t *idx, uint32_t *mp_start, uint32_t *mp_end,
-                             uint32_t *mp_lo, uint32_t *mp_hi) {
+struct MultiOut {
+    uint32_t *mp_start, *mp_lo, *mp_hi;
+    int64_t *me_t;
+    uint2 *me_p;
+    uint4 *me_a;
+    uint8_t *me_o;
+};
+
+__global__ void k_multi_fill(const uint64_t *pkey, const uint32_t *pval, uint64_t m, uint64_t n,
+                             const uint32_t *in_multi, const uint32_t *eidx,
+                             const uint32_t *multi_head, const uint32_t *pidx,
+                             const int64_t *t_r, const uint32_t *epos, const uint32_t *X,
+                             const uint32_t *off, uint64_t n_multi, uint64_t n_me, MultiOut o) {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m;
          g += (uint64_t)gridDim.x * blockDim.x) {
-        if (!flag[g]) continue;
-        const uint32_t k = idx[g];
+        if (g == 0) o.mp_start[n_multi] = (uint32_t)n_me;
+        if (!in_multi[g]) continue;
+        const uint32_t k = eidx[g];
         const uint64_t key = pkey[g];
-        // end of the run: upper bound of key in the sorted keys
-        uint64_t lo = g + 1, hi = m;
-        while (lo < hi) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            if (pkey[mid] <= key) lo = mid + 1;
-            else hi = mid;
+        const uint32_t lo = (uint32_t)(key / n), hi = (uint32_t)(key % n);
+        if (multi_head[g]) {
+            const uint32_t q = pidx[g];
+            o.mp_start[q] = k;
+            o.mp_lo[q] = lo;
+            o.mp_hi[q] = hi;
         }
-        mp_start[k] = (uint32_t)g;
-        mp_end[k] = (uint32_t)lo;
-        mp_lo[k] = (uint32_t)(key / n);
-        mp_hi[k] = (uint32_t)(key % n);
+        const uint32_t el = pval[g];
+        const uint32_t r = el & ~kOrientBit;
+        const uint32_t src_is_lo = el >> 31;
+        // entry of this edge at lo / at hi: the src entry sits at 2r, the dst entry at 2r+1
+        const uint32_t p_lo = epos[2 * (uint64_t)r + (src_is_lo ? 0 : 1)];
+        const uint32_t p_hi = epos[2 * (uint64_t)r + (src_is_lo ? 1 : 0)];
+        const uint32_t s_lo = off[lo], s_hi = off[hi];
+        const uint32_t a1_lo = X[p_lo] - X[s_lo], a1_hi = X[p_hi] - X[s_hi];
+        o.me_t[k] = t_r[r];
+        o.me_p[k] = make_uint2(p_lo, p_hi);
+        o.me_a[k] = make_uint4(p_lo - s_lo - a1_lo, a1_lo, p_hi - s_hi - a1_hi, a1_hi);
+        o.me_o[k] = (uint8_t)src_is_lo;
     }
 }
 
-__global__ void k_max_degree(const uint32_t *off, uint32_t n, uint32_t *out) {
+__global__ void __launch_bounds__(kBlock) k_max_degree(const uint32_t *off, uint32_t n,
+                                                       uint32_t *out) {
     uint32_t mx = 0;
     for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
          u += (uint64_t)gridDim.x * blockDim.x)
         mx = max(mx, off[u + 1] - off[u]);
     for (int o = kWave / 2; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(out, mx);
+    __shared__ uint32_t ws[kBlock / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / kWave; i++) mx = max(mx, ws[i]);
+        atomicMax(out, mx);
+    }
 }
 
 int bits_for(uint64_t maxval) {
@@ -196,23 +223,11 @@ int bits_for(uint64_t maxval) {
     return b;
 }
 
-dim3 grid_for(uint64_t n) {
+dim3 grid_for(uint64_t n, uint64_t cap = 16384) {
     uint64_t nb = (n + kBlock - 1) / kBlock;
     if (nb < 1) nb = 1;
-    if (nb > 16384) nb = 16384;
+    if (nb > cap) nb = cap;
     return dim3((unsigned)nb);
-}
-
-template <typename T>
-int dmalloc(T **p, size_t count) {
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? TM_ENOMEM : TM_EHIP;
-    }
-    return TM_OK;
 }
 
 }  // namespace
@@ -223,21 +238,30 @@ int dmalloc(T **p, size_t count) {
         if (_rc) return _rc;   \
     } while (0)
 
+int graph_alloc(tm_graph *g, void **p, size_t bytes) {
+    const int rc = dev_alloc(p, bytes ? bytes : 256, g->stream);
+    if (rc) return rc;
+    g->allocs.push_back(*p);
+    return TM_OK;
+}
+
+template <typename T>
+static int galloc(tm_graph *g, T **p, size_t count) {
+    return graph_alloc(g, (void **)p, count * sizeof(T));
+}
+
 int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, const int64_t *t,
                        uint64_t m, uint32_t n_nodes, hipStream_t s) {
     g->m = m;
     // ---- 1. validation
+    Scratch st_buf;
+    TRY(st_buf.reserve(sizeof(Stat) + 256, s));
+    Stat *d_st = st_buf.take<Stat>(1);
     Stat h_st{0, 0, ~0ull, 0};
-    Stat *d_st = nullptr;
-    TRY(dmalloc(&d_st, 1));
-    struct FreeSt {
-        Stat *p;
-        ~FreeSt() { (void)hipFree(p); }
-    } free_st{d_st};
     TM_HIP_TRY(hipMemcpyAsync(d_st, &h_st, sizeof(Stat), hipMemcpyHostToDevice, s));
     if (m > 0) {
-        TM_LAUNCH("validate", k_validate, grid_for(m), dim3(kBlock), 0, s, src, dst, t, m,
-                  n_nodes ? n_nodes : 0x7fffffffu, d_st);
+        TM_LAUNCH("validate", k_validate, grid_for(m, kMaxStatBlocks), dim3(kBlock), 0, s, src, dst,
+                  t, m, n_nodes ? n_nodes : 0x7fffffffu, d_st);
     }
     TM_HIP_TRY(hipMemcpyAsync(&h_st, d_st, sizeof(Stat), hipMemcpyDeviceToHost, s));
     TM_HIP_TRY(hipStreamSynchronize(s));
@@ -246,24 +270,26 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
                   ((h_st.bad & 2) ? " self-loop" : "") + ((h_st.bad & 4) ? " |t| >= 2^62" : ""));
         return TM_EINVAL;
     }
-    uint64_t n = n_nodes ? n_nodes : (m ? (uint64_t)h_st.max_id + 1 : 0);
+    const uint64_t n = n_nodes ? n_nodes : (m ? (uint64_t)h_st.max_id + 1 : 0);
     if (n > 0x7fffffffull) {
         set_error("node count must be below 2^31");
         return TM_EINVAL;
     }
     g->n = (uint32_t)n;
     const uint64_t len = 2 * m;
-    TRY(dmalloc(&g->off, n + 1));
-    TRY(dmalloc(&g->ent_t, len));
-    TRY(dmalloc(&g->ent_nd, len));
-    TRY(dmalloc(&g->ent_r, len));
-    TRY(dmalloc(&g->X, len + 1));
-    TRY(dmalloc(&g->epos, len));
-    TRY(dmalloc(&g->perm, m));
-    TRY(dmalloc(&g->pair_el, m));
+    TRY(galloc(g, &g->off, n + 1));
+    TRY(galloc(g, &g->ent_t, len));
+    TRY(galloc(g, &g->ent_nd, len));
+    TRY(galloc(g, &g->ent_r, len));
+    TRY(galloc(g, &g->ent_c, len));
+    TRY(galloc(g, &g->X, len + 1));
+    TRY(galloc(g, &g->epos, len));
+    TRY(galloc(g, &g->perm, m));
     if (m == 0) {
         TM_HIP_TRY(hipMemsetAsync(g->off, 0, (n + 1) * sizeof(uint32_t), s));
         TM_HIP_TRY(hipMemsetAsync(g->X, 0, sizeof(uint32_t), s));
+        TRY(galloc(g, &g->mp_start, 1));
+        TM_HIP_TRY(hipMemsetAsync(g->mp_start, 0, sizeof(uint32_t), s));
         TM_HIP_TRY(hipStreamSynchronize(s));
         return TM_OK;
     }
@@ -271,102 +297,130 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     const int64_t tmax = (int64_t)(h_st.tmax_key ^ 0x8000000000000000ull);
     const int tbits = bits_for((uint64_t)(tmax - tmin));
 
-    // scratch: two key buffers (u64 of 2m) and two value buffers (u32 of 2m)
-    uint64_t *k64a = nullptr, *k64b = nullptr;
-    uint32_t *va = nullptr, *vb = nullptr, *tmp = nullptr;
-    struct FreeAll {
-        std::vector<void *> ps;
-        ~FreeAll() {
-            for (void *p : ps) (void)hipFree(p);
-        }
-    } fa;
-    TRY(dmalloc(&k64a, len));
-    fa.ps.push_back(k64a);
-    TRY(dmalloc(&k64b, len));
-    fa.ps.push_back(k64b);
-    TRY(dmalloc(&va, len));
-    fa.ps.push_back(va);
-    TRY(dmalloc(&vb, len));
-    fa.ps.push_back(vb);
+    // ---- scratch (stream-ordered, released when this function returns)
+    // KA, KB: 8 bytes x 2m each   (time keys, node keys)
+    // VA, VB: 16 bytes x 2m each  (EdgeVal of m, NodeVal of 2m)
+    // PKA, PKB: u64 x m; PVA, PVB: u32 x m   (pair sort)
+    // TR: i64 x m                 (timestamps by rank)
+    // TMP: scan / histogram scratch
     const size_t ntmp = std::max(radix_tmp_count(len), scan_tmp_count(len)) + 16;
-    TRY(dmalloc(&tmp, ntmp));
-    fa.ps.push_back(tmp);
+    Scratch sc;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t bytes = 2 * up(8 * len) + 2 * up(16 * len) + 2 * up(8 * m) + 2 * up(4 * m) +
+                         up(8 * m) + up(4 * ntmp);
+    TRY(sc.reserve(bytes, s));
+    char *KA = sc.take<char>(8 * len), *KB = sc.take<char>(8 * len);
+    char *VA = sc.take<char>(16 * len), *VB = sc.take<char>(16 * len);
+    uint64_t *PKA = sc.take<uint64_t>(m), *PKB = sc.take<uint64_t>(m);
+    uint32_t *PVA = sc.take<uint32_t>(m), *PVB = sc.take<uint32_t>(m);
+    int64_t *TR = sc.take<int64_t>(m);
+    uint32_t *tmp = sc.take<uint32_t>(ntmp);
 
-    // ---- 2. sort edges by t (stable): perm[r] = edge id of rank r
-    uint32_t *vals = va, *vals_alt = vb;
-    if (tbits <= 32) {
-        uint32_t *keys = reinterpret_cast<uint32_t *>(k64a);
-        uint32_t *keys_alt = reinterpret_cast<uint32_t *>(k64b);
-        TM_LAUNCH("time_keys", k_time_keys<uint32_t>, grid_for(m), dim3(kBlock), 0, s, t, m, tmin,
-                  keys, vals);
-        TRY(radix_sort_u32(&keys, &keys_alt, &vals, &vals_alt, m, tbits, tmp, s, "sort_time_hist",
-                           "sort_time_scatter"));
-    } else {
-        uint64_t *keys = k64a, *keys_alt = k64b;
-        TM_LAUNCH("time_keys", k_time_keys<uint64_t>, grid_for(m), dim3(kBlock), 0, s, t, m, tmin,
-                  keys, vals);
-        TRY(radix_sort_u64(&keys, &keys_alt, &vals, &vals_alt, m, tbits, tmp, s, "sort_time_hist",
-                           "sort_time_scatter"));
-    }
-    TM_HIP_TRY(hipMemcpyAsync(g->perm, vals, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-
-    // ---- 3. incident entries sorted by node (stable over rank order)
+    // ---- 2. time sort carrying (src, dst, id); rank-ordered arrays
+    // The sorted time data ends in one of (KA, VA) / (KB, VB); the node keys
+    // and values go to the other buffers.
+    uint32_t *nkey = nullptr;
+    NodeVal *nval = nullptr;
     {
-        uint32_t *keys = reinterpret_cast<uint32_t *>(k64a);
-        uint32_t *keys_alt = reinterpret_cast<uint32_t *>(k64b);
-        uint32_t *v = va, *v_alt = vb;
-        TM_LAUNCH("entries", k_entries, grid_for(m), dim3(kBlock), 0, s, src, dst, g->perm, m, keys,
-                  v);
-        TRY(radix_sort_u32(&keys, &keys_alt, &v, &v_alt, len, bits_for(n - 1), tmp, s,
-                           "sort_node_hist", "sort_node_scatter"));
+        EdgeVal *ev = reinterpret_cast<EdgeVal *>(VA), *ev_alt = reinterpret_cast<EdgeVal *>(VB);
+        auto other_k = [&](const void *p) {
+            return reinterpret_cast<uint32_t *>(static_cast<const char *>(p) == KA ? KB : KA);
+        };
+        auto other_v = [&](const void *p) {
+            return reinterpret_cast<NodeVal *>(static_cast<const char *>(p) == VA ? VB : VA);
+        };
+        if (tbits <= 32) {
+            uint32_t *k = reinterpret_cast<uint32_t *>(KA), *k_alt = reinterpret_cast<uint32_t *>(KB);
+            TM_LAUNCH("time_keys", k_time_keys<uint32_t>, grid_for(m), dim3(kBlock), 0, s, src, dst,
+                      t, m, tmin, k, ev);
+            TRY(radix_sort_u32_edge(&k, &k_alt, &ev, &ev_alt, m, tbits, tmp, s, "sort_time_hist",
+                                    "sort_time_scatter"));
+            nkey = other_k(k);
+            nval = other_v(ev);
+            TM_LAUNCH("rank", k_rank<uint32_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, tmin, n,
+                      TR, g->perm, nkey, nval, PKA, PVA);
+        } else {
+            uint64_t *k = reinterpret_cast<uint64_t *>(KA), *k_alt = reinterpret_cast<uint64_t *>(KB);
+            TM_LAUNCH("time_keys", k_time_keys<uint64_t>, grid_for(m), dim3(kBlock), 0, s, src, dst,
+                      t, m, tmin, k, ev);
+            TRY(radix_sort_u64_edge(&k, &k_alt, &ev, &ev_alt, m, tbits, tmp, s, "sort_time_hist",
+                                    "sort_time_scatter"));
+            nkey = other_k(k);
+            nval = other_v(ev);
+            TM_LAUNCH("rank", k_rank<uint64_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, tmin, n,
+                      TR, g->perm, nkey, nval, PKA, PVA);
+        }
+    }
+
+    // ---- 3. node sort -> S_u (the last pass writes the sequence arrays and epos)
+    {
+        uint32_t *k_alt = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(nkey) == KA ? KB : KA);
+        NodeVal *v_alt = reinterpret_cast<NodeVal *>(reinterpret_cast<char *>(nval) == VA ? VB : VA);
+        const SeqOut so{g->ent_c, g->ent_t, g->ent_nd, g->ent_r, g->epos};
+        TRY(radix_sort_nodes(nkey, k_alt, nval, v_alt, len, bits_for(n - 1), tmp, s, so));
         TM_LAUNCH("offsets_fill", k_fill_u32, grid_for(n + 1), dim3(kBlock), 0, s, g->off, n + 1,
                   kUnset);
-        TM_LAUNCH("offsets", k_offsets, grid_for(len + 1), dim3(kBlock), 0, s, keys, len,
+        TM_LAUNCH("offsets", k_offsets, grid_for(len + 1), dim3(kBlock), 0, s, g->ent_c, len,
                   (uint32_t)n, g->off);
-        TM_LAUNCH("offsets_gaps", k_offsets_gaps, grid_for(n + 1), dim3(kBlock), 0, s, keys, len,
+        TM_LAUNCH("offsets_gaps", k_offsets_gaps, grid_for(n + 1), dim3(kBlock), 0, s, g->ent_c, len,
                   (uint32_t)n, g->off);
-        TM_LAUNCH("fill_seq", k_fill_seq, grid_for(len), dim3(kBlock), 0, s, src, dst, t, g->perm, v,
-                  len, g->ent_t, g->ent_nd, g->ent_r, g->epos);
         TRY(scan_dirbits(g->ent_nd, g->X, len, tmp, s));
     }
 
-    // ---- 4. node-pair edge sets
+    // ---- 4. node-pair edge sets; the edges of pairs with >= 2 edges
     {
-        uint64_t *keys = k64a, *keys_alt = k64b;
-        uint32_t *v = va, *v_alt = vb;
-        TM_LAUNCH("pair_keys", k_pair_keys, grid_for(m), dim3(kBlock), 0, s, src, dst, g->perm, m,
-                  n, keys, v);
-        TRY(radix_sort_u64(&keys, &keys_alt, &v, &v_alt, m, bits_for(n * n - 1), tmp, s,
+        uint64_t *k = PKA, *k_alt = PKB;
+        uint32_t *v = PVA, *v_alt = PVB;
+        TRY(radix_sort_u64(&k, &k_alt, &v, &v_alt, m, bits_for(n * n - 1), tmp, s,
                            "sort_pair_hist", "sort_pair_scatter"));
-        TM_HIP_TRY(hipMemcpyAsync(g->pair_el, v, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-        uint32_t *flag = v_alt;            // free value buffer
-        uint32_t *idx = reinterpret_cast<uint32_t *>(keys_alt);  // free key buffer (>= m + 1 u32)
-        TM_LAUNCH("multi_heads", k_multi_heads, grid_for(m), dim3(kBlock), 0, s, keys, m, flag);
-        TRY(scan_u32_array(flag, idx, m, tmp, s));
-        uint32_t n_multi = 0;
-        TM_HIP_TRY(hipMemcpyAsync(&n_multi, idx + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        // flags and their scans reuse the (now free) node-sort buffers
+        uint32_t *in_multi = reinterpret_cast<uint32_t *>(KA);
+        uint32_t *head = reinterpret_cast<uint32_t *>(KB);
+        uint32_t *eidx = reinterpret_cast<uint32_t *>(VA);
+        uint32_t *pidx = reinterpret_cast<uint32_t *>(VB);
+        TM_LAUNCH("multi_flags", k_multi_flags, grid_for(m), dim3(kBlock), 0, s, k, m, in_multi,
+                  head);
+        TRY(scan_u32_array(in_multi, eidx, m, tmp, s));
+        TRY(scan_u32_array(head, pidx, m, tmp, s));
+        uint32_t counts[2] = {0, 0};
+        TM_HIP_TRY(hipMemcpyAsync(&counts[0], eidx + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipMemcpyAsync(&counts[1], pidx + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
-        g->n_multi = n_multi;
-        TRY(dmalloc(&g->mp_start, n_multi));
-        TRY(dmalloc(&g->mp_end, n_multi));
-        TRY(dmalloc(&g->mp_lo, n_multi));
-        TRY(dmalloc(&g->mp_hi, n_multi));
-        if (n_multi) {
-            TM_LAUNCH("multi_fill", k_multi_fill, grid_for(m), dim3(kBlock), 0, s, keys, m, n, flag,
-                      idx, g->mp_start, g->mp_end, g->mp_lo, g->mp_hi);
-        }
+        g->n_me = counts[0];
+        g->n_multi = counts[1];
+        TRY(galloc(g, &g->mp_start, g->n_multi + 1));
+        TRY(galloc(g, &g->mp_lo, g->n_multi));
+        TRY(galloc(g, &g->mp_hi, g->n_multi));
+        TRY(galloc(g, &g->me_t, g->n_me));
+        TRY(galloc(g, &g->me_p, g->n_me));
+        TRY(galloc(g, &g->me_a, g->n_me));
+        TRY(galloc(g, &g->me_o, g->n_me));
+        MultiOut o{g->mp_start, g->mp_lo, g->mp_hi, g->me_t, g->me_p, g->me_a, g->me_o};
+        TM_LAUNCH("multi_fill", k_multi_fill, grid_for(m), dim3(kBlock), 0, s, k, v, m, n, in_multi,
+                  eidx, head, pidx, TR, g->epos, g->X, g->off, g->n_multi, g->n_me, o);
     }
-    // ---- facts
-    {
-        uint32_t *d_mx = tmp;
+
+    return TM_OK;
+}
+
+int graph_max_degree(tm_graph *g, uint64_t *out) {
+    if (!g->max_degree_known) {
+        hipStream_t s = g->stream;
+        Scratch sc;
+        TRY(sc.reserve(256, s));
+        uint32_t *d_mx = sc.take<uint32_t>(1);
         TM_HIP_TRY(hipMemsetAsync(d_mx, 0, sizeof(uint32_t), s));
-        TM_LAUNCH("max_degree", k_max_degree, grid_for(n), dim3(kBlock), 0, s, g->off, (uint32_t)n,
-                  d_mx);
+        if (g->n) {
+            TM_LAUNCH("max_degree", k_max_degree, grid_for(g->n, kMaxStatBlocks), dim3(kBlock), 0, s,
+                      g->off, g->n, d_mx);
+        }
         uint32_t mx = 0;
         TM_HIP_TRY(hipMemcpyAsync(&mx, d_mx, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
         g->max_degree = mx;
+        g->max_degree_known = true;
     }
+    *out = g->max_degree;
     return TM_OK;
 }
 

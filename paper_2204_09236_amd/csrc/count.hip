@@ -40,6 +40,8 @@
 //
 // Per-lane uint64 accumulators are reduced per block, then all block partials
 // are summed by one deterministic tree reduction (no atomics on counts).
+#include <algorithm>
+
 #include "tm_internal.h"
 
 namespace tmc {
@@ -50,6 +52,7 @@ struct SeqView {
     const int64_t *t;      // ent_t
     const uint32_t *nd;    // ent_nd
     const uint32_t *rk;    // ent_r
+    const uint32_t *c;     // ent_c
     const uint32_t *X;     // exclusive prefix of dir = in
     const uint32_t *off;
     const uint32_t *epos;
@@ -111,25 +114,59 @@ __device__ inline uint32_t window_start(const int64_t *T, uint32_t p, uint32_t l
     return a;
 }
 
-// --------------------------------------------------------------- star/pair
-struct Elem {
-    int64_t t;
-    uint32_t p;    // position in S_c
-    uint32_t dir;  // 0 = o, 1 = in (relative to the center c)
-    uint32_t a0, a1;  // P_0(p-1), P_1(p-1): entries of each dir before p in S_c
-};
+// ------------------------------------------------------------ window sizes
+// Wf[p] = R(p) - p: how many later entries of the same S_u lie within delta.
+__global__ void __launch_bounds__(kBlock) k_windows(SeqView S, uint64_t len, int64_t delta,
+                                                    uint32_t *Wf) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < len;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t hi = S.off[S.c[p] + 1];
+        const int64_t lim = S.t[p] + delta;
+        uint32_t w = 0;
+        if (p + 1 < hi && S.t[p + 1] <= lim)
+            w = window_end(S.t, (uint32_t)p, hi, lim) - (uint32_t)p;
+        Wf[p] = w;
+    }
+}
 
-__device__ inline Elem load_elem(const SeqView &S, uint32_t el, uint32_t side, uint32_t seg_lo,
-                                 uint32_t xbase) {
-    Elem e;
-    const uint32_t r = el & ~kOrientBit;
-    const uint32_t is_src = (el >> 31) ^ side;  // side 0: center = smaller node
-    e.p = S.epos[2 * r + (is_src ? 0 : 1)];
-    e.dir = is_src ? 0u : 1u;
-    e.t = S.t[e.p];
-    e.a1 = S.X[e.p] - xbase;
-    e.a0 = (e.p - seg_lo) - e.a1;
-    return e;
+// --------------------------------------------------------------- star/pair
+// Per element (edge of a multi-edge node pair) and side (center = smaller /
+// larger node): P_0, P_1 of S_c at the window end R and just before the
+// window start L:  w = (P_0(R), P_1(R), P_0(L-1), P_1(L-1)).
+__global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me_p,
+                                                      const uint4 *me_a, const int64_t *me_t,
+                                                      const uint32_t *Wf, uint64_t n_me,
+                                                      int64_t delta, uint4 *me_w) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n_me;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = i >> 1;
+        const uint32_t side = (uint32_t)(i & 1);
+        const uint2 pp = me_p[k];
+        const uint4 aa = me_a[k];
+        const uint32_t p = side ? pp.y : pp.x;
+        const uint32_t a0 = side ? aa.z : aa.x, a1 = side ? aa.w : aa.y;
+        const uint32_t seg_lo = p - (a0 + a1);
+        const int64_t tp = me_t[k];
+        // The sweeps read these only for an element whose pair has another
+        // edge within delta after it (window end) or before it (window start);
+        // that edge is then its neighbour in the element array.
+        const bool need_r = k + 1 < n_me && me_t[k + 1] - tp <= delta;
+        const bool need_l = k > 0 && tp - me_t[k - 1] <= delta;
+        if (!need_r && !need_l) continue;
+        const uint32_t xp = S.X[p];
+        uint32_t rp0 = 0, rp1 = 0, lp0 = 0, lp1 = 0;
+        if (need_r) {
+            const uint32_t R = p + Wf[p];
+            rp1 = a1 + (S.X[R + 1] - xp);
+            rp0 = (a0 + a1) + (R - p) + 1 - rp1;
+        }
+        if (need_l) {
+            const uint32_t L = window_start(S.t, p, seg_lo, tp - delta);
+            lp1 = a1 - (xp - S.X[L]);
+            lp0 = (L - seg_lo) - lp1;
+        }
+        me_w[i] = make_uint4(rp0, rp1, lp0, lp1);
+    }
 }
 
 // Window state over the edges of one node pair inside a delta-window.
@@ -145,7 +182,6 @@ struct Win {
     // append a later edge (dir d, prefix counts a0, a1)
     __device__ inline void push(uint32_t d, uint32_t a0, uint32_t a1) {
         const uint64_t m1 = 0ull - (uint64_t)d, m0 = ~m1;
-        // S2[x][d] += in[x] for x in {0,1}
         S2[0][0] += in[0] & m0;
         S2[1][0] += in[1] & m0;
         S2[0][1] += in[0] & m1;
@@ -162,7 +198,6 @@ struct Win {
         const uint64_t m1 = 0ull - (uint64_t)d, m0 = ~m1;
         in[0] -= 1 & m0;
         in[1] -= 1 & m1;
-        // S2[d][x] -= in[x]
         S2[0][0] -= in[0] & m0;
         S2[0][1] -= in[1] & m0;
         S2[1][0] -= in[0] & m1;
@@ -189,48 +224,78 @@ struct WorkItem {
     uint32_t chunk;  // chunk index inside it
 };
 
-__global__ void __launch_bounds__(kBlock) k_star_pair(SeqView S, const uint32_t *pair_el,
-                                                      const uint32_t *mp_start,
-                                                      const uint32_t *mp_end,
-                                                      const uint32_t *mp_lo, const uint32_t *mp_hi,
-                                                      const WorkItem *items, uint64_t n_items,
-                                                      uint32_t chunk, int64_t delta,
-                                                      uint64_t *partial) {
+// One element of a pair seen from one side.
+struct El {
+    int64_t t;
+    uint32_t dir, a0, a1;
+};
+
+__device__ inline El load_el(const int64_t *me_t, const uint8_t *me_o, const uint4 *me_a,
+                             uint32_t k, uint32_t side) {
+    El e;
+    e.t = me_t[k];
+    const uint32_t is_src = (uint32_t)me_o[k] ^ side;  // side 0: center = smaller node
+    e.dir = 1u - is_src;
+    const uint4 aa = me_a[k];
+    e.a0 = side ? aa.z : aa.x;
+    e.a1 = side ? aa.w : aa.y;
+    return e;
+}
+
+struct StarArgs {
+    const uint32_t *mp_start;
+    const int64_t *me_t;
+    const uint8_t *me_o;
+    const uint4 *me_a;
+    const uint4 *me_w;
+    const uint32_t *first;  // n_multi + 1: first work item of each pair (exclusive scan)
+    uint64_t n_multi;
+    uint32_t chunk;
+    int64_t delta;
+};
+
+// Work item -> (pair, chunk): the pair is the last one whose first item is <= it.
+__device__ inline WorkItem item_of(const uint32_t *first, uint64_t n_multi, uint32_t it) {
+    uint64_t lo = 0, hi = n_multi;  // first[lo] <= it < first[hi]
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (first[mid] <= it) lo = mid;
+        else hi = mid;
+    }
+    return WorkItem{(uint32_t)lo, it - first[lo]};
+}
+
+__global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *partial) {
     StarAcc A;
 #pragma unroll
     for (int i = 0; i < 32; i++) A.c[i] = 0;
 
+    const uint64_t n_items = a.first[a.n_multi];
     for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n_items;
          it += (uint64_t)gridDim.x * blockDim.x) {
-        const WorkItem w = items[it];
-        const uint32_t rs = mp_start[w.pair], re = mp_end[w.pair];
-        const uint32_t cb = rs + w.chunk * chunk;
-        const uint32_t ce = min(re, cb + chunk);
+        const WorkItem w = item_of(a.first, a.n_multi, (uint32_t)it);
+        const uint32_t rs = a.mp_start[w.pair], re = a.mp_start[w.pair + 1];
+        const uint32_t cb = rs + w.chunk * a.chunk;
+        const uint32_t ce = min(re, cb + a.chunk);
         for (uint32_t side = 0; side < 2; side++) {
-            const uint32_t c = side ? mp_hi[w.pair] : mp_lo[w.pair];
-            const uint32_t seg_lo = S.off[c], seg_hi = S.off[c + 1];
-            const uint32_t xbase = S.X[seg_lo];
-
             // ---- e1 sweep: Pair, Star_II, Star_III
             Win W;
             W.clear();
             uint32_t j = cb + 1;  // next pair edge to enter the window
             for (uint32_t q = cb; q < ce; q++) {
-                const Elem eq = load_elem(S, pair_el[q], side, seg_lo, xbase);
+                const El eq = load_el(a.me_t, a.me_o, a.me_a, q, side);
                 if (q > cb && j > q) W.pop(eq.dir, eq.a0, eq.a1);
                 if (j <= q) j = q + 1;
-                const int64_t lim = eq.t + delta;
+                const int64_t lim = eq.t + a.delta;
                 while (j < re) {
-                    const Elem ej = load_elem(S, pair_el[j], side, seg_lo, xbase);
+                    const El ej = load_el(a.me_t, a.me_o, a.me_a, j, side);
                     if (ej.t > lim) break;
                     W.push(ej.dir, ej.a0, ej.a1);
                     j++;
                 }
                 if (W.in[0] + W.in[1] == 0) continue;
-                const uint32_t R = window_end(S.t, eq.p, seg_hi, lim);
-                const uint64_t rp1 = S.X[R + 1] - xbase;
-                const uint64_t rp0 = (uint64_t)(R + 1 - seg_lo) - rp1;
-                const uint64_t rp[2] = {rp0, rp1};
+                const uint4 ww = a.me_w[2 * (uint64_t)q + side];
+                const uint64_t rp[2] = {ww.x, ww.y};
                 const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0),
                                          (uint64_t)eq.a1 + (eq.dir == 1)};
                 const uint64_t m1 = 0ull - (uint64_t)eq.dir;
@@ -256,33 +321,26 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(SeqView S, const uint32_t 
             W.clear();
             uint32_t f;  // front of the window [f, q)
             {
-                const Elem eb = load_elem(S, pair_el[cb], side, seg_lo, xbase);
-                const int64_t lim = eb.t - delta;
+                const int64_t lim = a.me_t[cb] - a.delta;
                 f = cb;
-                while (f > rs) {
-                    const Elem ef = load_elem(S, pair_el[f - 1], side, seg_lo, xbase);
-                    if (ef.t < lim) break;
-                    f--;
-                }
+                while (f > rs && a.me_t[f - 1] >= lim) f--;
                 for (uint32_t k = f; k < cb; k++) {
-                    const Elem ek = load_elem(S, pair_el[k], side, seg_lo, xbase);
+                    const El ek = load_el(a.me_t, a.me_o, a.me_a, k, side);
                     W.push(ek.dir, ek.a0, ek.a1);
                 }
             }
             for (uint32_t q = cb; q < ce; q++) {
-                const Elem eq = load_elem(S, pair_el[q], side, seg_lo, xbase);
-                const int64_t lim = eq.t - delta;
+                const El eq = load_el(a.me_t, a.me_o, a.me_a, q, side);
+                const int64_t lim = eq.t - a.delta;
                 while (f < q) {
-                    const Elem ef = load_elem(S, pair_el[f], side, seg_lo, xbase);
+                    const El ef = load_el(a.me_t, a.me_o, a.me_a, f, side);
                     if (ef.t >= lim) break;
                     W.pop(ef.dir, ef.a0, ef.a1);
                     f++;
                 }
                 if (W.in[0] + W.in[1] != 0) {
-                    const uint32_t L = window_start(S.t, eq.p, seg_lo, lim);
-                    const uint64_t lp1 = S.X[L] - xbase;
-                    const uint64_t lp0 = (uint64_t)(L - seg_lo) - lp1;
-                    const uint64_t lp[2] = {lp0, lp1};
+                    const uint4 ww = a.me_w[2 * (uint64_t)q + side];
+                    const uint64_t lp[2] = {ww.z, ww.w};
                     const uint64_t m1 = 0ull - (uint64_t)eq.dir;
 #pragma unroll
                     for (int d1 = 0; d1 < 2; d1++) {
@@ -320,25 +378,36 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(SeqView S, const uint32_t 
 }
 
 // Work items: node pair k is cut into ceil(len / chunk) items.
-__global__ void k_item_counts(const uint32_t *mp_start, const uint32_t *mp_end, uint64_t n_multi,
-                              uint32_t chunk, uint32_t *cnt) {
+__global__ void k_item_counts(const uint32_t *mp_start, uint64_t n_multi, uint32_t chunk,
+                              uint32_t *cnt) {
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_multi;
          k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t len = mp_end[k] - mp_start[k];
+        const uint32_t len = mp_start[k + 1] - mp_start[k];
         cnt[k] = (len + chunk - 1) / chunk;
     }
 }
 
-__global__ void k_item_fill(const uint32_t *cnt, const uint32_t *first, uint64_t n_multi,
-                            WorkItem *items) {
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_multi;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t b = first[k];
-        for (uint32_t c = 0; c < cnt[k]; c++) items[b + c] = WorkItem{(uint32_t)k, c};
+// ---------------------------------------------------------------- triangles
+// Candidate first edges: both windows after the edge (at its source and at
+// its destination) hold at least one entry.
+__global__ void k_tri_flags(const uint2 *epos2, const uint32_t *Wf, uint64_t m, uint32_t *flag) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint2 e = epos2[r];
+        flag[r] = (Wf[e.x] != 0 && Wf[e.y] != 0) ? 1u : 0u;
     }
 }
 
-// ---------------------------------------------------------------- triangles
+__global__ void k_tri_compact(const uint2 *epos2, const uint32_t *Wf, const uint32_t *flag,
+                              const uint32_t *idx, uint64_t m, uint4 *cand) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        if (!flag[r]) continue;
+        const uint2 e = epos2[r];
+        cand[idx[r]] = make_uint4(e.x, e.y, Wf[e.x], Wf[e.y]);
+    }
+}
+
 struct TriAcc {
     uint64_t c[8];  // class (a, b, c): Tri[I][a][b][c]
 };
@@ -353,39 +422,34 @@ __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint
     return ra < rb ? ((1u - da) * 4 + (1u - db) * 2 + 0u) : ((1u - db) * 4 + (1u - da) * 2 + 1u);
 }
 
-__global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, uint64_t m, int64_t delta,
-                                                      uint32_t lane_max, uint64_t *partial) {
+__global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
+                                                      const uint32_t *n_cand, uint32_t lane_max,
+                                                      uint64_t *partial) {
+    const uint64_t nc = *n_cand;
     TriAcc T;
 #pragma unroll
     for (int i = 0; i < 8; i++) T.c[i] = 0;
     const int lane = threadIdx.x & (kWave - 1);
-    // whole waves step through the edge ranks together
+    // whole waves step through the candidates together
     const uint64_t wave_id = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
-    for (uint64_t base = wave_id * kWave; base < m; base += n_waves * kWave) {
-        const uint64_t r = base + lane;
-        uint32_t ps = 0, pd = 0, Rs = 0, Rd = 0;
-        bool active = false;
-        if (r < m) {
-            ps = S.epos[2 * r];
-            pd = S.epos[2 * r + 1];
-            const int64_t t1 = S.t[ps];
-            const int64_t lim = t1 + delta;
-            const uint32_t s_node = S.nd[pd] >> 1, d_node = S.nd[ps] >> 1;
-            const uint32_t s_hi = S.off[s_node + 1], d_hi = S.off[d_node + 1];
-            if (ps + 1 < s_hi && pd + 1 < d_hi && S.t[ps + 1] <= lim && S.t[pd + 1] <= lim) {
-                Rs = window_end(S.t, ps, s_hi, lim);
-                Rd = window_end(S.t, pd, d_hi, lim);
-                active = true;
-            }
+    for (uint64_t base = wave_id * kWave; base < nc; base += n_waves * kWave) {
+        const uint64_t ci = base + lane;
+        uint32_t ps = 0, pd = 0, ws = 0, wd = 0;
+        const bool active = ci < nc;
+        if (active) {
+            const uint4 c = cand[ci];
+            ps = c.x;
+            pd = c.y;
+            ws = c.z;
+            wd = c.w;
         }
-        const uint64_t ws = Rs - ps, wd = Rd - pd;
-        const bool small = active && ws * wd <= lane_max;
+        const bool small = active && (uint64_t)ws * wd <= lane_max;
         if (small) {
-            for (uint32_t a = ps + 1; a <= Rs; a++) {
+            for (uint32_t a = ps + 1; a <= ps + ws; a++) {
                 const uint32_t nda = S.nd[a];
                 const uint32_t ra = S.rk[a];
-                for (uint32_t b = pd + 1; b <= Rd; b++) {
+                for (uint32_t b = pd + 1; b <= pd + wd; b++) {
                     const uint32_t ndb = S.nd[b];
                     if ((ndb >> 1) == (nda >> 1))
                         tri_add(T, tri_class(ra, nda & 1u, S.rk[b], ndb & 1u));
@@ -398,11 +462,11 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, uint64_t m, int
         while (big) {
             const int L = __ffsll((unsigned long long)big) - 1;
             big &= big - 1;
-            const uint32_t bps = __shfl(ps, L, kWave), bRs = __shfl(Rs, L, kWave);
-            const uint32_t bpd = __shfl(pd, L, kWave), bRd = __shfl(Rd, L, kWave);
-            const bool s_outer = (bRs - bps) <= (bRd - bpd);
-            const uint32_t o_lo = s_outer ? bps + 1 : bpd + 1, o_hi = s_outer ? bRs : bRd;
-            const uint32_t i_lo = s_outer ? bpd + 1 : bps + 1, i_hi = s_outer ? bRd : bRs;
+            const uint32_t bps = __shfl(ps, L, kWave), bws = __shfl(ws, L, kWave);
+            const uint32_t bpd = __shfl(pd, L, kWave), bwd = __shfl(wd, L, kWave);
+            const bool s_outer = bws <= bwd;
+            const uint32_t o_lo = s_outer ? bps + 1 : bpd + 1, o_hi = s_outer ? bps + bws : bpd + bwd;
+            const uint32_t i_lo = s_outer ? bpd + 1 : bps + 1, i_hi = s_outer ? bpd + bwd : bps + bws;
             for (uint32_t ib = i_lo; ib <= i_hi; ib += kWave) {
                 const uint32_t x = ib + lane;
                 const bool valid = x <= i_hi;
@@ -439,25 +503,26 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, uint64_t m, int
 }
 
 // ---------------------------------------------------------------- reduction
-// out[c] = sum over rows of part[row][c]; one block, fixed order (integer
-// sums: exact and independent of the order anyway).
+// Column sums of part[rows][cols] (cols divides kBlock), in two stages with
+// fixed shapes: block b of the first stage sums rows b, b + gridDim.x, ...
+// into stage[b][cols]; one block then sums the stage rows.  Thread t handles
+// column t % cols, so consecutive threads read consecutive words.  Integer
+// sums: exact and order-independent, no atomics.
+constexpr uint32_t kReduceBlocks = 64;
+
 __global__ void __launch_bounds__(kBlock) k_reduce_cols(const uint64_t *part, uint32_t rows,
                                                         uint32_t cols, uint64_t *out) {
-    __shared__ uint64_t lds[kBlock / kWave];
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    for (uint32_t c = 0; c < cols; c++) {
-        uint64_t v = 0;
-        for (uint32_t r = threadIdx.x; r < rows; r += kBlock) v += part[(uint64_t)r * cols + c];
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if (lane == 0) lds[wv] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t s = 0;
-            for (int q = 0; q < kBlock / kWave; q++) s += lds[q];
-            out[c] = s;
-        }
-        __syncthreads();
+    __shared__ uint64_t lds[kBlock];
+    const uint32_t c = threadIdx.x % cols, g = threadIdx.x / cols, groups = kBlock / cols;
+    uint64_t v = 0;
+    for (uint32_t r = blockIdx.x + g * gridDim.x; r < rows; r += groups * gridDim.x)
+        v += part[(uint64_t)r * cols + c];
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < cols) {
+        uint64_t s = 0;
+        for (uint32_t q = 0; q < groups; q++) s += lds[q * cols + threadIdx.x];
+        out[(uint64_t)blockIdx.x * cols + threadIdx.x] = s;
     }
 }
 
@@ -470,7 +535,7 @@ dim3 grid_for(uint64_t n, uint64_t cap) {
 
 }  // namespace
 
-constexpr uint32_t kDefaultRunChunk = 256;
+constexpr uint32_t kDefaultRunChunk = 8;
 constexpr uint32_t kDefaultTriLaneMax = 64;
 
 int count_graph(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
@@ -480,59 +545,71 @@ int count_graph(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lan
     uint64_t host[40] = {0};
     hipStream_t s = g->stream;
     if (g->m >= 3) {
-        SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->X, g->off, g->epos};
-        const uint64_t nm = g->n_multi;
-        constexpr uint32_t kMaxStarBlocks = 2048, kMaxTriBlocks = 4096;
-        const dim3 tgrid = grid_for(g->m, kMaxTriBlocks);
-        const uint32_t nt = tgrid.x;
-        // scratch layout
-        const size_t n_tmp = scan_tmp_count(nm) + 4;
-        size_t bytes = 0;
+        SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos};
+        const uint64_t m = g->m, len = 2 * m;
+        const uint64_t nm = g->n_multi, nme = g->n_me;
+        constexpr uint32_t kMaxStarBlocks = 8192, kMaxTriBlocks = 4096;
+        // work items <= elements of multi-edge pairs: one lane per item at most
+        const uint32_t kStarBlocks = grid_for(nme, kMaxStarBlocks).x;
+        const dim3 tgrid = grid_for(m, kMaxTriBlocks);
+        // Work counts stay on the device (kernels read them), so the only
+        // host synchronisation is the final copy of the 40 counters.  Buffers
+        // are sized by upper bounds: triangle candidates <= m; the star grid
+        // covers the work items (<= elements of multi-edge pairs).
+        const size_t n_tmp = scan_tmp_count(std::max<uint64_t>(m, nm)) + 4;
         auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-        bytes += up((nm + 1) * sizeof(uint32_t)) * 2;      // counts, firsts
-        bytes += up(n_tmp * sizeof(uint32_t));
-        bytes += up((uint64_t)kMaxStarBlocks * 32 * sizeof(uint64_t));
-        bytes += up((uint64_t)nt * 8 * sizeof(uint64_t));
-        bytes += up(40 * sizeof(uint64_t));
+        const size_t bytes = up(len * 4)                      // Wf
+                             + up(2 * nme * sizeof(uint4))    // me_w
+                             + up((nm + 1) * 4) * 2           // item counts, firsts
+                             + up(m * 4) + up((m + 1) * 4)    // triangle flags, index
+                             + up(m * sizeof(uint4))          // candidates
+                             + up(n_tmp * 4) + up((uint64_t)kStarBlocks * 32 * 8) +
+                             up((uint64_t)tgrid.x * 8 * 8) + up(kReduceBlocks * 40 * 8) + up(40 * 8);
         Scratch sc;
         int rc = sc.reserve(bytes, s);
         if (rc) return rc;
+        uint32_t *Wf = sc.take<uint32_t>(len);
+        uint4 *me_w = sc.take<uint4>(2 * nme);
         uint32_t *cnt = sc.take<uint32_t>(nm + 1);
         uint32_t *first = sc.take<uint32_t>(nm + 1);
+        uint32_t *tflag = sc.take<uint32_t>(m);
+        uint32_t *tidx = sc.take<uint32_t>(m + 1);
+        uint4 *cand = sc.take<uint4>(m);
         uint32_t *tmp = sc.take<uint32_t>(n_tmp);
-        uint64_t *spart = sc.take<uint64_t>((uint64_t)kMaxStarBlocks * 32);
-        uint64_t *tpart = sc.take<uint64_t>((uint64_t)nt * 8);
+        uint64_t *spart = sc.take<uint64_t>((uint64_t)kStarBlocks * 32);
+        uint64_t *tpart = sc.take<uint64_t>((uint64_t)tgrid.x * 8);
+        uint64_t *stage = sc.take<uint64_t>(kReduceBlocks * 40);
         uint64_t *res = sc.take<uint64_t>(40);
-        uint64_t n_items = 0;
-        WorkItem *items = nullptr;
-        Scratch sc_items;
+
+        TM_LAUNCH("windows", k_windows, grid_for(len, 16384), dim3(kBlock), 0, s, S, len, delta, Wf);
+
+        // ---- star / pair
         if (nm) {
+            TM_LAUNCH("star_prep", k_star_prep, grid_for(2 * nme, 16384), dim3(kBlock), 0, s, S,
+                      g->me_p, g->me_a, g->me_t, Wf, nme, delta, me_w);
             TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s,
-                      g->mp_start, g->mp_end, nm, run_chunk, cnt);
+                      g->mp_start, nm, run_chunk, cnt);
             rc = scan_u32_array(cnt, first, nm, tmp, s);
             if (rc) return rc;
-            uint32_t total = 0;
-            TM_HIP_TRY(hipMemcpyAsync(&total, first + nm, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-            TM_HIP_TRY(hipStreamSynchronize(s));
-            n_items = total;
-            rc = sc_items.reserve(n_items * sizeof(WorkItem) + 256, s);
-            if (rc) return rc;
-            items = sc_items.take<WorkItem>(n_items);
-            TM_LAUNCH("item_fill", k_item_fill, grid_for(nm, 4096), dim3(kBlock), 0, s, cnt, first,
-                      nm, items);
+            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, me_w, first, nm, run_chunk, delta};
+            TM_LAUNCH("star_pair", k_star_pair, dim3(kStarBlocks), dim3(kBlock), 0, s, sa, spart);
         }
-        // one partial row per launched block; no launch means zero rows
-        const dim3 igrid = grid_for(n_items, kMaxStarBlocks);
-        const uint32_t ns = n_items ? igrid.x : 0u;
-        if (n_items) {
-            TM_LAUNCH("star_pair", k_star_pair, igrid, dim3(kBlock), 0, s, S, g->pair_el,
-                      g->mp_start, g->mp_end, g->mp_lo, g->mp_hi, items, n_items, run_chunk, delta,
-                      spart);
-        }
-        TM_LAUNCH("triangles", k_triangles, tgrid, dim3(kBlock), 0, s, S, g->m, delta, tri_lane_max,
-                  tpart);
-        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, spart, ns, 32u, res);
-        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, tpart, nt, 8u, res + 32);
+        // ---- triangles: candidate first edges, then matching
+        TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
+                  reinterpret_cast<const uint2 *>(g->epos), Wf, m, tflag);
+        rc = scan_u32_array(tflag, tidx, m, tmp, s);
+        if (rc) return rc;
+        TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
+                  reinterpret_cast<const uint2 *>(g->epos), Wf, tflag, tidx, m, cand);
+        TM_LAUNCH("triangles", k_triangles, tgrid, dim3(kBlock), 0, s, S, cand, tidx + m,
+                  tri_lane_max, tpart);
+        TM_LAUNCH("reduce", k_reduce_cols, dim3(kReduceBlocks), dim3(kBlock), 0, s, spart,
+                  nm ? kStarBlocks : 0u, 32u, stage);
+        TM_LAUNCH("reduce", k_reduce_cols, dim3(kReduceBlocks), dim3(kBlock), 0, s, tpart, tgrid.x, 8u,
+                  stage + kReduceBlocks * 32);
+        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, stage, kReduceBlocks, 32u, res);
+        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, stage + kReduceBlocks * 32,
+                  kReduceBlocks, 8u, res + 32);
         TM_HIP_TRY(hipMemcpyAsync(host, res, 40 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
     }

@@ -134,10 +134,30 @@ int scan_impl(L ld, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
 // [w*1024, (w+1)*1024) of the tile and walks it in 16 rounds of 64, so the
 // order inside the tile is (wave, round, lane) = input order and a per-wave
 // running digit count gives stable ranks without block barriers.
-constexpr int kRadixItems = 16;
+constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kBlock * kRadixItems;
 constexpr int kWaves = kBlock / kWave;
+static_assert(kBlock == 256, "radix kernels map one thread to each 8-bit digit");
 
+// Digit of a key and the lanes of this wave that share it (ballot matching).
+template <typename K>
+__device__ inline uint64_t digit_peers(K key, int shift, bool valid, uint32_t *digit) {
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    *digit = d;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+    }
+    return peers;
+}
+
+// Per-block digit histogram.  Each wave keeps its own sub-histogram; the
+// lowest lane of every group of equal digits adds the group size, so no two
+// lanes of a wave touch one counter (skewed keys, e.g. a hub's node id, do
+// not serialise on LDS atomics).
 template <typename K>
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const K *keys, uint64_t n, int shift,
                                                        uint32_t *hist, uint32_t nb) {
@@ -146,36 +166,66 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const K *keys, uint64_t n
     for (int i = threadIdx.x; i < kWaves * 256; i += kBlock) (&h[0][0])[i] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kRadixTile + (uint64_t)w * (kRadixItems * kWave);
+    const uint64_t lt = lanemask_lt(lane);
 #pragma unroll 4
     for (int i = 0; i < kRadixItems; i++) {
-        uint64_t idx = base + (uint64_t)i * kWave + lane;
-        if (idx < n) {
-            uint32_t d = (uint32_t)(keys[idx] >> shift) & 255u;
-            atomicAdd(&h[w][d], 1u);
-        }
+        const uint64_t idx = base + (uint64_t)i * kWave + lane;
+        const bool valid = idx < n;
+        const K key = valid ? keys[idx] : K(0);
+        uint32_t d;
+        const uint64_t peers = digit_peers(key, shift, valid, &d);
+        if (valid && __popcll(peers & lt) == 0) h[w][d] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    if (threadIdx.x < 256) {
-        uint32_t s = 0;
+    uint32_t s = 0;
 #pragma unroll
-        for (int q = 0; q < kWaves; q++) s += h[q][threadIdx.x];
-        hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = s;
-    }
+    for (int q = 0; q < kWaves; q++) s += h[q][threadIdx.x];
+    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = s;
 }
 
-template <typename K>
-__global__ void __launch_bounds__(kBlock) k_radix_scatter(const K *kin, const uint32_t *vin,
-                                                          K *kout, uint32_t *vout, uint64_t n,
-                                                          int shift, const uint32_t *offs,
-                                                          uint32_t nb) {
+// Stable scatter of one digit pass.  Ranks come from per-wave running digit
+// counts (tile order = (wave, round, lane) = input order); the tile is then
+// staged in LDS in digit order so that the global writes of each digit's run
+// are contiguous.
+template <typename K, typename V>
+struct PairOut {
+    K *kout;
+    V *vout;
+    __device__ inline void operator()(uint32_t pos, K k, const V &v) const {
+        kout[pos] = k;
+        vout[pos] = v;
+    }
+};
+
+struct SeqWrite {
+    SeqOut o;
+    __device__ inline void operator()(uint32_t pos, uint32_t k, const NodeVal &v) const {
+        o.ent_c[pos] = k;
+        o.ent_t[pos] = v.t;
+        o.ent_nd[pos] = v.nd;
+        o.ent_r[pos] = v.r;
+        o.epos[2 * (uint64_t)v.r + (v.nd & 1u)] = pos;
+    }
+};
+
+template <typename K, typename V, typename Out>
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const K *kin, const V *vin, Out out,
+                                                          uint64_t n, int shift,
+                                                          const uint32_t *offs, uint32_t nb) {
     __shared__ uint32_t wh[kWaves][256];
+    __shared__ uint32_t blk_off[256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t scan_lds[kBlock / kWave];
+    __shared__ K s_key[kRadixTile];
+    __shared__ V s_val[kRadixTile];
     const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     for (int i = threadIdx.x; i < kWaves * 256; i += kBlock) (&wh[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kRadixTile + (uint64_t)w * (kRadixItems * kWave);
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kRadixTile;
+    const uint64_t base = tile0 + (uint64_t)w * (kRadixItems * kWave);
     const uint64_t lt = lanemask_lt(lane);
     K key[kRadixItems];
-    uint32_t val[kRadixItems];
     uint32_t rank[kRadixItems];
     uint32_t dig[kRadixItems];
 #pragma unroll
@@ -183,16 +233,9 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K *kin, const ui
         const uint64_t idx = base + (uint64_t)i * kWave + lane;
         const bool valid = idx < n;
         key[i] = valid ? kin[idx] : K(0);
-        val[i] = valid ? vin[idx] : 0u;
-        const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+        uint32_t d;
+        const uint64_t peers = digit_peers(key[i], shift, valid, &d);
         dig[i] = d;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
         const uint32_t below = __popcll(peers & lt);
         const uint32_t cnt = __popcll(peers);
         uint32_t run = 0;
@@ -203,14 +246,25 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K *kin, const ui
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // exclusive prefix over waves, offset by this block's global digit base
-    if (threadIdx.x < 256) {
-        uint32_t run = offs[(uint64_t)threadIdx.x * nb + blockIdx.x];
+    // digit totals of the tile -> exclusive prefix over digits (one thread per digit)
+    {
+        const int d = threadIdx.x;
+        uint32_t c[kWaves];
+        uint32_t tot = 0;
 #pragma unroll
         for (int q = 0; q < kWaves; q++) {
-            uint32_t c = wh[q][threadIdx.x];
-            wh[q][threadIdx.x] = run;
-            run += c;
+            c[q] = wh[q][d];
+            tot += c[q];
+        }
+        uint32_t total;
+        const uint32_t excl = block_incl_scan(tot, &total, scan_lds) - tot;
+        blk_off[d] = excl;
+        gbase[d] = offs[(uint64_t)d * nb + blockIdx.x];
+        uint32_t run = excl;
+#pragma unroll
+        for (int q = 0; q < kWaves; q++) {
+            wh[q][d] = run;
+            run += c[q];
         }
     }
     __syncthreads();
@@ -218,15 +272,24 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K *kin, const ui
     for (int i = 0; i < kRadixItems; i++) {
         const uint64_t idx = base + (uint64_t)i * kWave + lane;
         if (idx < n) {
-            const uint32_t pos = wh[w][dig[i]] + rank[i];
-            kout[pos] = key[i];
-            vout[pos] = val[i];
+            // values are not held in registers: read straight into their slot
+            const uint32_t x = wh[w][dig[i]] + rank[i];
+            s_key[x] = key[i];
+            s_val[x] = vin[idx];
         }
+    }
+    __syncthreads();
+    const uint32_t cnt_tile = (uint32_t)min<uint64_t>((uint64_t)kRadixTile, n - tile0);
+    for (uint32_t x = threadIdx.x; x < cnt_tile; x += kBlock) {
+        const K k = s_key[x];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = gbase[d] + (x - blk_off[d]);
+        out(pos, k, s_val[x]);
     }
 }
 
-template <typename K>
-int radix_impl(K **keys, K **keys_alt, uint32_t **vals, uint32_t **vals_alt, uint64_t n, int bits,
+template <typename K, typename V>
+int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits,
                uint32_t *tmp, hipStream_t s, const char *hist_name, const char *scatter_name) {
     if (n <= 1 || bits <= 0) return TM_OK;
     const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
@@ -238,12 +301,12 @@ int radix_impl(K **keys, K **keys_alt, uint32_t **vals, uint32_t **vals_alt, uin
                   hist, (uint32_t)nb);
         int rc = scan_impl(LoadArray{hist}, hist, nh, stmp, s);
         if (rc) return rc;
-        TM_LAUNCH(scatter_name, k_radix_scatter<K>, dim3(nb), dim3(kBlock), 0, s, *keys, *vals,
-                  *keys_alt, *vals_alt, n, shift, hist, (uint32_t)nb);
+        TM_LAUNCH(scatter_name, (k_radix_scatter<K, V, PairOut<K, V>>), dim3(nb), dim3(kBlock), 0, s,
+                  *keys, *vals, (PairOut<K, V>{*keys_alt, *vals_alt}), n, shift, hist, (uint32_t)nb);
         K *tk = *keys;
         *keys = *keys_alt;
         *keys_alt = tk;
-        uint32_t *tv = *vals;
+        V *tv = *vals;
         *vals = *vals_alt;
         *vals_alt = tv;
     }
@@ -274,18 +337,48 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
     return scan_impl(LoadDirBit{ent_nd}, out, n, tmp, s);
 }
 
-int radix_sort_u32(uint32_t **keys, uint32_t **keys_alt, uint32_t **vals, uint32_t **vals_alt,
-                   uint64_t n, int bits, uint32_t *tmp, hipStream_t s, const char *hist_name,
-                   const char *scatter_name) {
-    return radix_impl<uint32_t>(keys, keys_alt, vals, vals_alt, n, bits, tmp, s, hist_name,
-                                scatter_name);
-}
+#define TM_RADIX_INST(NAME, K, V)                                                             \
+    int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, uint32_t *tmp, \
+             hipStream_t s, const char *hist_name, const char *scatter_name) {                    \
+        return radix_impl<K, V>(keys, keys_alt, vals, vals_alt, n, bits, tmp, s, hist_name,      \
+                                scatter_name);                                                   \
+    }
+TM_RADIX_INST(radix_sort_u32, uint32_t, uint32_t)
+TM_RADIX_INST(radix_sort_u64, uint64_t, uint32_t)
+TM_RADIX_INST(radix_sort_u32_v64, uint32_t, uint64_t)
+TM_RADIX_INST(radix_sort_u32_edge, uint32_t, EdgeVal)
+TM_RADIX_INST(radix_sort_u64_edge, uint64_t, EdgeVal)
+#undef TM_RADIX_INST
 
-int radix_sort_u64(uint64_t **keys, uint64_t **keys_alt, uint32_t **vals, uint32_t **vals_alt,
-                   uint64_t n, int bits, uint32_t *tmp, hipStream_t s, const char *hist_name,
-                   const char *scatter_name) {
-    return radix_impl<uint64_t>(keys, keys_alt, vals, vals_alt, n, bits, tmp, s, hist_name,
-                                scatter_name);
+int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
+                     uint64_t n, int bits, uint32_t *tmp, hipStream_t s, SeqOut so) {
+    if (n == 0) return TM_OK;
+    if (bits < 1) bits = 1;
+    const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    const uint64_t nh = nb * 256;
+    uint32_t *hist = tmp;
+    uint32_t *stmp = tmp + nh + 1;
+    for (int shift = 0; shift < bits; shift += 8) {
+        TM_LAUNCH("sort_node_hist", k_radix_hist<uint32_t>, dim3(nb), dim3(kBlock), 0, s, keys, n,
+                  shift, hist, (uint32_t)nb);
+        int rc = scan_impl(LoadArray{hist}, hist, nh, stmp, s);
+        if (rc) return rc;
+        if (shift + 8 >= bits) {
+            TM_LAUNCH("sort_node_scatter", (k_radix_scatter<uint32_t, NodeVal, SeqWrite>), dim3(nb),
+                      dim3(kBlock), 0, s, keys, vals, SeqWrite{so}, n, shift, hist, (uint32_t)nb);
+        } else {
+            TM_LAUNCH("sort_node_scatter", (k_radix_scatter<uint32_t, NodeVal, PairOut<uint32_t, NodeVal>>),
+                      dim3(nb), dim3(kBlock), 0, s, keys, vals,
+                      (PairOut<uint32_t, NodeVal>{keys_alt, vals_alt}), n, shift, hist, (uint32_t)nb);
+            uint32_t *tk = keys;
+            keys = keys_alt;
+            keys_alt = tk;
+            NodeVal *tv = vals;
+            vals = vals_alt;
+            vals_alt = tv;
+        }
+    }
+    return TM_OK;
 }
 
 int fill_iota(uint32_t *p, uint64_t n, hipStream_t s) {

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "tm.h"
 
@@ -48,9 +49,14 @@ void prof_end(hipStream_t s);
         }                                                                             \
     } while (0)
 
-// ------------------------------------------------------- device workspace
-// A bump allocator over one stream-ordered allocation; everything taken from
-// it is released together.
+// ------------------------------------------------------- device memory
+// Caching allocator (mem.hip): blocks are reused across calls; a block freed
+// on one stream and reused on another is ordered by an event.
+int dev_alloc(void **out, size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+
+// A bump allocator over one cached block; everything taken from it is
+// released together (to the cache) at scope exit.
 struct Scratch {
     hipStream_t stream = nullptr;
     char *base = nullptr;
@@ -78,13 +84,42 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
 // pass, ping-ponging between the two buffers; *keys / *vals point at the
 // sorted data on return.  tmp must hold radix_tmp_count(n) u32.
 size_t radix_tmp_count(uint64_t n);
+// An edge carried through the time sort: endpoints and input index.
+struct EdgeVal {
+    uint32_t src, dst, id;
+};
+
+// An incident entry carried through the node sort: timestamp, edge rank and
+// (other endpoint << 1 | dir).
+struct NodeVal {
+    int64_t t;
+    uint32_t r, nd;
+};
+
+// Where the node sort's last pass writes: the sequence arrays S_u directly,
+// plus each edge's two positions (epos[2r + dir]).
+struct SeqOut {
+    uint32_t *ent_c;
+    int64_t *ent_t;
+    uint32_t *ent_nd;
+    uint32_t *ent_r;
+    uint32_t *epos;
+};
+
 // hist_name / scatter_name label the two kernels of each pass for the tracer.
-int radix_sort_u32(uint32_t **keys, uint32_t **keys_alt, uint32_t **vals, uint32_t **vals_alt,
-                   uint64_t n, int bits, uint32_t *tmp, hipStream_t s, const char *hist_name,
-                   const char *scatter_name);
-int radix_sort_u64(uint64_t **keys, uint64_t **keys_alt, uint32_t **vals, uint32_t **vals_alt,
-                   uint64_t n, int bits, uint32_t *tmp, hipStream_t s, const char *hist_name,
-                   const char *scatter_name);
+#define TM_RADIX_DECL(NAME, K, V)                                                              \
+    int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, uint32_t *tmp, \
+             hipStream_t s, const char *hist_name, const char *scatter_name);
+TM_RADIX_DECL(radix_sort_u32, uint32_t, uint32_t)
+TM_RADIX_DECL(radix_sort_u64, uint64_t, uint32_t)
+TM_RADIX_DECL(radix_sort_u32_v64, uint32_t, uint64_t)
+TM_RADIX_DECL(radix_sort_u32_edge, uint32_t, EdgeVal)
+TM_RADIX_DECL(radix_sort_u64_edge, uint64_t, EdgeVal)
+#undef TM_RADIX_DECL
+// Node sort: (node, NodeVal) pairs on bits [0, bits); the last pass writes
+// SeqOut instead of the ping-pong buffers (at least one pass always runs).
+int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
+                     uint64_t n, int bits, uint32_t *tmp, hipStream_t s, SeqOut out);
 
 int fill_iota(uint32_t *p, uint64_t n, hipStream_t s);
 
@@ -97,27 +132,34 @@ struct tm_graph {
     uint32_t n = 0;
     uint64_t m = 0;
     uint64_t max_degree = 0;
+    bool max_degree_known = false;
+    std::vector<void *> allocs;  // every device buffer below (stream-ordered allocations)
     // S_u for all u, (u, t, id) order: 2m entries
     uint32_t *off = nullptr;     // n + 1
     int64_t *ent_t = nullptr;    // timestamp
     uint32_t *ent_nd = nullptr;  // (other endpoint << 1) | dir
     uint32_t *ent_r = nullptr;   // edge rank in the global (t, id) order
+    uint32_t *ent_c = nullptr;   // the center u the entry belongs to
     uint32_t *X = nullptr;       // 2m + 1: exclusive prefix count of dir = in entries
     uint32_t *epos = nullptr;    // 2m: position of edge rank r's src entry (2r) and dst entry (2r+1)
     uint32_t *perm = nullptr;    // m: edge id of rank r
-    // node-pair edge sets: all edges sorted by (min node, max node, t, id)
-    uint32_t *pair_el = nullptr;  // m: rank | kOrientBit if src is the smaller node
-    // node pairs with at least two edges (the only ones that hold pair or star instances)
-    uint64_t n_multi = 0;
-    uint32_t *mp_start = nullptr;  // n_multi: first index in pair_el
-    uint32_t *mp_end = nullptr;    // n_multi: one past the last
+    // node pairs with at least two edges (the only ones that hold pair or star
+    // instances) and their edges ("elements"), pair by pair in (t, id) order
+    uint64_t n_multi = 0, n_me = 0;
+    uint32_t *mp_start = nullptr;  // n_multi + 1: first element of each pair
     uint32_t *mp_lo = nullptr;     // n_multi: smaller node
     uint32_t *mp_hi = nullptr;     // n_multi: larger node
+    int64_t *me_t = nullptr;       // n_me: timestamp
+    uint2 *me_p = nullptr;         // n_me: position in S_lo, in S_hi
+    uint4 *me_a = nullptr;         // n_me: (#o, #in) entries before it in S_lo, then in S_hi
+    uint8_t *me_o = nullptr;       // n_me: 1 if the edge leaves the smaller node
 };
 
 namespace tmc {
 int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, const int64_t *t,
                        uint64_t m, uint32_t n_nodes, hipStream_t s);
+// Largest S_u length (computed on first use).
+int graph_max_degree(tm_graph *g, uint64_t *out);
 // Counts into raw[56] (host), see tm.h for the layout.
 int count_graph(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
                 uint64_t raw[56]);

@@ -41,7 +41,7 @@ def _load():
     lib.tm_count_raw_tuned.restype = ctypes.c_int
     lib.tm_merge.argtypes = [u64p, u64p]
     lib.tm_merge.restype = ctypes.c_int
-    lib.tm_graph_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), u64p, u64p, u64p]
+    lib.tm_graph_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), u64p, u64p, u64p, u64p]
     lib.tm_graph_info.restype = ctypes.c_int
     lib.tm_graph_sequences.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tm_graph_sequences.restype = ctypes.c_int
@@ -107,10 +107,11 @@ class Graph:
 
     def info(self) -> dict:
         n = ctypes.c_uint32()
-        m, mp, md = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        m, mp, me, md = (ctypes.c_uint64() for _ in range(4))
         _check(_lib.tm_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(mp),
-                                  ctypes.byref(md)))
-        return {"n": n.value, "m": m.value, "multi_pairs": mp.value, "max_degree": md.value}
+                                  ctypes.byref(me), ctypes.byref(md)))
+        return {"n": n.value, "m": m.value, "multi_pairs": mp.value, "multi_pair_edges": me.value,
+                "max_degree": md.value}
 
     def sequences(self) -> dict:
         inf = self.info()
