@@ -87,6 +87,35 @@ enum { TM_HOST_PTRS = 0, TM_DEVICE_PTRS = 1 };
 int tm_build_graph(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t m,
                    uint32_t n_nodes, int flags, void *hip_stream, tm_graph **out);
 
+/*
+ * Batched build: G independent temporal graphs built as one device object
+ * (one sort pipeline for all of them).  Graph i's edges are rows
+ * edge_off[i] .. edge_off[i+1]-1 of src/dst/t, with node ids local to that
+ * graph: in [0, node_count[i]), or any non-negative id when node_count[i] is
+ * 0 (then the graph has max id + 1 nodes).  Graphs do not interact: counts
+ * are per graph.  edge_off (G + 1 entries, edge_off[0] = 0, non-decreasing)
+ * and node_count (G entries) are host arrays; src/dst/t follow `flags` as in
+ * tm_build_graph.  Limits: total edges < 2^31, total nodes < 2^31, and
+ * ceil(log2 G) plus the largest per-graph time-range bit width <= 64.
+ * Errors as tm_build_graph; an invalid edge names its graph in
+ * tm_last_error.  tm_build_graph is the case G = 1.
+ */
+int tm_build_batch(const int32_t *src, const int32_t *dst, const int64_t *t,
+                   const uint64_t *edge_off, const uint32_t *node_count, uint32_t G, int flags,
+                   void *hip_stream, tm_graph **out);
+
+/* Number of graphs held by g (1 for tm_build_graph). */
+uint32_t tm_graph_count(const tm_graph *g);
+
+/*
+ * Count every graph of a batch, graph i with window deltas[i] (host array of
+ * G values, 0 <= delta < 2^62), into out[i] (36 motif counts) or raw[i] (56
+ * raw counters).  All graphs go through the same kernel launches; per-graph
+ * results are exact and identical to counting each graph alone.
+ */
+int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]);
+int tm_count_batch_raw(tm_graph *g, const int64_t *deltas, uint64_t (*raw)[56]);
+
 /* Release a graph and its device memory.  NULL is ignored. */
 void tm_graph_free(tm_graph *g);
 
@@ -95,7 +124,8 @@ void tm_graph_free(tm_graph *g);
  * device-to-host copy at the end).  delta must satisfy 0 <= delta < 2^62;
  * delta = 0 counts only triples with equal timestamps.  out: caller-owned
  * host memory, 36 x uint64.  TM_EINTERNAL if the merge self-checks fail.
- * Concurrent calls on one graph are allowed (each has its own scratch).
+ * TM_EINVAL if g holds a batch of several graphs (use tm_count_batch).
+ * Concurrent calls on one graph are allowed; they run one after another.
  */
 int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]);
 

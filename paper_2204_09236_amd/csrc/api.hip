@@ -120,6 +120,8 @@ const char *tm_strerror(int code) {
 
 const char *tm_last_error(void) { return tmc::g_last_error.c_str(); }
 
+uint32_t tm_graph_count(const tm_graph *g) { return g ? g->G : 0; }
+
 void tm_graph_free(tm_graph *g) {
     if (!g) return;
     int cur = 0;
@@ -130,26 +132,42 @@ void tm_graph_free(tm_graph *g) {
     delete g;
 }
 
-int tm_build_graph(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t m,
-                   uint32_t n_nodes, int flags, void *hip_stream, tm_graph **out) {
+static int build_common(const int32_t *src, const int32_t *dst, const int64_t *t,
+                        const uint64_t *edge_off, const uint32_t *node_count, uint32_t G, int flags,
+                        void *hip_stream, tm_graph **out) {
     if (!out) {
         tmc::set_error("out is NULL");
         return TM_EINVAL;
     }
+    if (G == 0 || !edge_off || !node_count) {
+        tmc::set_error("a batch needs G >= 1 graphs and its edge offsets and node counts");
+        return TM_EINVAL;
+    }
+    if (edge_off[0] != 0) {
+        tmc::set_error("edge offsets must start at 0");
+        return TM_EINVAL;
+    }
+    for (uint32_t i = 0; i < G; i++) {
+        if (edge_off[i + 1] < edge_off[i]) {
+            tmc::set_error("edge offsets must be non-decreasing");
+            return TM_EINVAL;
+        }
+        if (node_count[i] >= 0x80000000u) {
+            tmc::set_error("node counts must be below 2^31");
+            return TM_EINVAL;
+        }
+    }
+    const uint64_t m = edge_off[G];
     if (m > 0 && (!src || !dst || !t)) {
         tmc::set_error("NULL edge array");
         return TM_EINVAL;
     }
     if (m >= (1ull << 31)) {
-        tmc::set_error("m must be below 2^31");
+        tmc::set_error("the number of edges must be below 2^31");
         return TM_EINVAL;
     }
     if (flags != TM_HOST_PTRS && flags != TM_DEVICE_PTRS) {
         tmc::set_error("flags must be TM_HOST_PTRS or TM_DEVICE_PTRS");
-        return TM_EINVAL;
-    }
-    if (n_nodes >= 0x80000000u) {
-        tmc::set_error("node count must be below 2^31");
         return TM_EINVAL;
     }
     tm_graph *g = new (std::nothrow) tm_graph();
@@ -158,36 +176,28 @@ int tm_build_graph(const int32_t *src, const int32_t *dst, const int64_t *t, uin
     (void)hipGetDevice(&g->device);
     const int32_t *ds = src, *dd = dst;
     const int64_t *dt = t;
-    int32_t *own_s = nullptr, *own_d = nullptr;
-    int64_t *own_t = nullptr;
+    void *own = nullptr;
     int rc = TM_OK;
     if (flags == TM_HOST_PTRS && m > 0) {
-        hipError_t e1 = hipMalloc((void **)&own_s, m * sizeof(int32_t));
-        hipError_t e2 = hipMalloc((void **)&own_d, m * sizeof(int32_t));
-        hipError_t e3 = hipMalloc((void **)&own_t, m * sizeof(int64_t));
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-            tmc::set_error("hipMalloc of the input copy failed");
-            rc = TM_ENOMEM;
-        } else {
+        rc = tmc::dev_alloc(&own, m * 16, g->stream);
+        if (rc == TM_OK) {
+            int32_t *os = static_cast<int32_t *>(own);
+            int32_t *od = os + m;
+            int64_t *ot = reinterpret_cast<int64_t *>(od + m);
             hipStream_t s = g->stream;
-            if (hipMemcpyAsync(own_s, src, m * sizeof(int32_t), hipMemcpyHostToDevice, s) ||
-                hipMemcpyAsync(own_d, dst, m * sizeof(int32_t), hipMemcpyHostToDevice, s) ||
-                hipMemcpyAsync(own_t, t, m * sizeof(int64_t), hipMemcpyHostToDevice, s)) {
+            if (hipMemcpyAsync(os, src, m * 4, hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(od, dst, m * 4, hipMemcpyHostToDevice, s) ||
+                hipMemcpyAsync(ot, t, m * 8, hipMemcpyHostToDevice, s)) {
                 tmc::set_error("host-to-device copy failed");
                 rc = TM_EHIP;
             }
+            ds = os;
+            dd = od;
+            dt = ot;
         }
-        ds = own_s;
-        dd = own_d;
-        dt = own_t;
     }
-    if (rc == TM_OK) rc = tmc::build_graph_device(g, ds, dd, dt, m, n_nodes, g->stream);
-    if (own_s || own_d || own_t) {
-        (void)hipStreamSynchronize(g->stream);
-        if (own_s) (void)hipFree(own_s);
-        if (own_d) (void)hipFree(own_d);
-        if (own_t) (void)hipFree(own_t);
-    }
+    if (rc == TM_OK) rc = tmc::build_graph_device(g, ds, dd, dt, edge_off, node_count, G, g->stream);
+    if (own) tmc::dev_free(own, g->stream);
     if (rc != TM_OK) {
         (void)hipStreamSynchronize(g->stream);
         tm_graph_free(g);
@@ -197,25 +207,78 @@ int tm_build_graph(const int32_t *src, const int32_t *dst, const int64_t *t, uin
     return TM_OK;
 }
 
-int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
-                       uint64_t raw[56]) {
-    if (!g || !raw) {
-        tmc::set_error("NULL graph or output");
+int tm_build_graph(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t m,
+                   uint32_t n_nodes, int flags, void *hip_stream, tm_graph **out) {
+    if (m >= (1ull << 31)) {
+        tmc::set_error("m must be below 2^31");
         return TM_EINVAL;
     }
-    if (delta < 0 || delta >= ((int64_t)1 << 62)) {
-        tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+    const uint64_t eoff[2] = {0, m};
+    const uint32_t ncount[1] = {n_nodes};
+    return build_common(src, dst, t, eoff, ncount, 1, flags, hip_stream, out);
+}
+
+int tm_build_batch(const int32_t *src, const int32_t *dst, const int64_t *t,
+                   const uint64_t *edge_off, const uint32_t *node_count, uint32_t G, int flags,
+                   void *hip_stream, tm_graph **out) {
+    return build_common(src, dst, t, edge_off, node_count, G, flags, hip_stream, out);
+}
+
+static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
+                        uint32_t tri_lane_max, uint64_t *raw) {
+    if (!g || !raw || !deltas) {
+        tmc::set_error("NULL graph, deltas or output");
         return TM_EINVAL;
     }
+    for (uint32_t i = 0; i < g->G; i++)
+        if (deltas[i] < 0 || deltas[i] >= ((int64_t)1 << 62)) {
+            tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+            return TM_EINVAL;
+        }
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
-    uint64_t tmp[56];
-    int rc = tmc::count_graph(g, delta, run_chunk, tri_lane_max, tmp);
+    std::vector<uint64_t> tmp((size_t)g->G * 56);
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        rc = tmc::count_graph(g, deltas, run_chunk, tri_lane_max, tmp.data());
+    }
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc) return rc;
-    for (int i = 0; i < 56; i++) raw[i] = tmp[i];
+    for (size_t i = 0; i < tmp.size(); i++) raw[i] = tmp[i];
     return TM_OK;
+}
+
+int tm_count_batch_raw(tm_graph *g, const int64_t *deltas, uint64_t (*raw)[56]) {
+    return count_common(g, deltas, 0, 0, raw ? &raw[0][0] : nullptr);
+}
+
+int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]) {
+    if (!g || !out) {
+        tmc::set_error("NULL graph or output");
+        return TM_EINVAL;
+    }
+    std::vector<uint64_t> raw((size_t)g->G * 56);
+    int rc = count_common(g, deltas, 0, 0, raw.data());
+    if (rc) return rc;
+    std::vector<uint64_t> res((size_t)g->G * 36);
+    for (uint32_t i = 0; i < g->G; i++) {
+        rc = tm_merge(raw.data() + (size_t)i * 56, res.data() + (size_t)i * 36);
+        if (rc) return rc;
+    }
+    for (uint32_t i = 0; i < g->G; i++)
+        for (int c = 0; c < 36; c++) out[i][c] = res[(size_t)i * 36 + c];
+    return TM_OK;
+}
+
+int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
+                       uint64_t raw[56]) {
+    if (g && g->G != 1) {
+        tmc::set_error("a batch of several graphs is counted with tm_count_batch");
+        return TM_EINVAL;
+    }
+    return count_common(g, &delta, run_chunk, tri_lane_max, raw);
 }
 
 int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]) {

@@ -27,6 +27,7 @@ constexpr int64_t kTLimit = (int64_t)1 << 62;
 constexpr uint32_t kGapFill = 64;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr uint32_t kMaxStatBlocks = 1024;
+constexpr uint64_t kEntryTile = 8192, kElemTile = 8192;
 
 struct Stat {
     uint32_t bad;        // bit 0: id out of range / negative, bit 1: self-loop, bit 2: |t| too big
@@ -35,56 +36,71 @@ struct Stat {
     uint64_t tmax_key;
 };
 
-// Flags and extrema (not counts): block reduction, then one atomic per block.
+// Flags and extrema (not counts) per graph.  Edge tiles lie inside one graph;
+// each block reduces its tile, then updates its graph's record atomically.
 __global__ void __launch_bounds__(kBlock) k_validate(const int32_t *src, const int32_t *dst,
-                                                     const int64_t *t, uint64_t m,
-                                                     uint32_t n_limit, Stat *st) {
-    uint32_t bad = 0, mx = 0;
-    uint64_t tmin = ~0ull, tmax = 0;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        const int32_t a = src[e], b = dst[e];
-        const int64_t te = t[e];
-        if (a < 0 || b < 0 || (uint32_t)a >= n_limit || (uint32_t)b >= n_limit) bad |= 1u;
-        if (a == b) bad |= 2u;
-        if (te >= kTLimit || te <= -kTLimit) bad |= 4u;
-        mx = max(mx, (uint32_t)max(a, b));
-        const uint64_t k = (uint64_t)te ^ 0x8000000000000000ull;
-        tmin = min(tmin, k);
-        tmax = max(tmax, k);
-    }
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        bad |= __shfl_xor(bad, o, kWave);
-        mx = max(mx, (uint32_t)__shfl_xor(mx, o, kWave));
-        tmin = min(tmin, (uint64_t)__shfl_xor(tmin, o, kWave));
-        tmax = max(tmax, (uint64_t)__shfl_xor(tmax, o, kWave));
-    }
+                                                     const int64_t *t, const Tile *tiles,
+                                                     uint32_t n_tiles, const uint32_t *n_limit,
+                                                     Stat *st) {
     __shared__ Stat ws[kBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    if (lane == 0) ws[w] = Stat{bad, mx, tmin, tmax};
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Stat r = ws[0];
-        for (int i = 1; i < kBlock / kWave; i++) {
-            r.bad |= ws[i].bad;
-            r.max_id = max(r.max_id, ws[i].max_id);
-            r.tmin_key = min(r.tmin_key, ws[i].tmin_key);
-            r.tmax_key = max(r.tmax_key, ws[i].tmax_key);
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const Tile tl = tiles[ti];
+        const uint32_t lim = n_limit[tl.g];
+        uint32_t bad = 0, mx = 0;
+        uint64_t tmin = ~0ull, tmax = 0;
+        for (uint64_t e = tl.b + threadIdx.x; e < tl.e; e += blockDim.x) {
+            const int32_t a = src[e], b = dst[e];
+            const int64_t te = t[e];
+            if (a < 0 || b < 0 || (uint32_t)a >= lim || (uint32_t)b >= lim) bad |= 1u;
+            if (a == b) bad |= 2u;
+            if (te >= kTLimit || te <= -kTLimit) bad |= 4u;
+            mx = max(mx, (uint32_t)max(a, b));
+            const uint64_t k = (uint64_t)te ^ 0x8000000000000000ull;
+            tmin = min(tmin, k);
+            tmax = max(tmax, k);
         }
-        if (r.bad) atomicOr(&st->bad, r.bad);
-        atomicMax(&st->max_id, r.max_id);
-        atomicMin((unsigned long long *)&st->tmin_key, (unsigned long long)r.tmin_key);
-        atomicMax((unsigned long long *)&st->tmax_key, (unsigned long long)r.tmax_key);
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            bad |= __shfl_xor(bad, o, kWave);
+            mx = max(mx, (uint32_t)__shfl_xor(mx, o, kWave));
+            tmin = min(tmin, (uint64_t)__shfl_xor(tmin, o, kWave));
+            tmax = max(tmax, (uint64_t)__shfl_xor(tmax, o, kWave));
+        }
+        if (lane == 0) ws[w] = Stat{bad, mx, tmin, tmax};
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Stat r = ws[0];
+            for (int i = 1; i < kBlock / kWave; i++) {
+                r.bad |= ws[i].bad;
+                r.max_id = max(r.max_id, ws[i].max_id);
+                r.tmin_key = min(r.tmin_key, ws[i].tmin_key);
+                r.tmax_key = max(r.tmax_key, ws[i].tmax_key);
+            }
+            Stat *d = st + tl.g;
+            if (r.bad) atomicOr(&d->bad, r.bad);
+            atomicMax(&d->max_id, r.max_id);
+            atomicMin((unsigned long long *)&d->tmin_key, (unsigned long long)r.tmin_key);
+            atomicMax((unsigned long long *)&d->tmax_key, (unsigned long long)r.tmax_key);
+        }
+        __syncthreads();
     }
 }
 
+// Time-sort key = (graph << tbits) | (t - tmin of the graph); the value
+// carries the endpoints as union-graph node ids (local id + graph's node base).
 template <typename K>
-__global__ void k_time_keys(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t m,
-                            int64_t tmin, K *keys, EdgeVal *vals) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        keys[e] = (K)(uint64_t)(t[e] - tmin);
-        vals[e] = EdgeVal{(uint32_t)src[e], (uint32_t)dst[e], (uint32_t)e};
+__global__ void k_time_keys(const int32_t *src, const int32_t *dst, const int64_t *t,
+                            const Tile *tiles, uint32_t n_tiles, const int64_t *tmin,
+                            const uint32_t *node_base, int tbits, K *keys, EdgeVal *vals) {
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const Tile tl = tiles[ti];
+        const int64_t t0 = tmin[tl.g];
+        const uint32_t nb = node_base[tl.g];
+        const uint64_t gk = (uint64_t)tl.g << tbits;
+        for (uint64_t e = tl.b + threadIdx.x; e < tl.e; e += blockDim.x) {
+            keys[e] = (K)(gk | (uint64_t)(t[e] - t0));
+            vals[e] = EdgeVal{(uint32_t)src[e] + nb, (uint32_t)dst[e] + nb, (uint32_t)e};
+        }
     }
 }
 
@@ -92,13 +108,16 @@ __global__ void k_time_keys(const int32_t *src, const int32_t *dst, const int64_
 // incident entries to sort by node (slot 2r: at src, out; 2r+1: at dst, in;
 // value = r << 32 | other endpoint << 1 | dir), and the node-pair keys.
 template <typename K>
-__global__ void k_rank(const K *tkey, const EdgeVal *tval, uint64_t m, int64_t tmin, uint64_t n,
-                       int64_t *t_r, uint32_t *perm, uint32_t *nkey, NodeVal *nval,
-                       uint64_t *pkey, uint32_t *pval) {
+__global__ void k_rank(const K *tkey, const EdgeVal *tval, uint64_t m, const int64_t *tmin,
+                       int tbits, uint64_t n, int64_t *t_r, uint32_t *perm, uint32_t *nkey,
+                       NodeVal *nval, uint64_t *pkey, uint32_t *pval) {
+    const uint64_t tmask = tbits >= 64 ? ~0ull : ((1ull << tbits) - 1);
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (uint64_t)gridDim.x * blockDim.x) {
         const EdgeVal ev = tval[r];
-        const int64_t te = (int64_t)((uint64_t)tkey[r] + (uint64_t)tmin);
+        const uint64_t key = (uint64_t)tkey[r];
+        const uint32_t gi = tbits >= 64 ? 0u : (uint32_t)(key >> tbits);
+        const int64_t te = (int64_t)((key & tmask) + (uint64_t)tmin[gi]);
         t_r[r] = te;
         perm[r] = ev.id;
         nkey[2 * r] = ev.src;
@@ -201,6 +220,25 @@ __global__ void k_multi_fill(const uint64_t *pkey, const uint32_t *pval, uint64_
     }
 }
 
+// Per graph: first S_u position, first multi-edge pair and its first element.
+__global__ void k_graph_ranges(const uint32_t *off, const uint32_t *node_base, uint32_t G,
+                               const uint32_t *mp_lo, uint64_t n_multi, const uint32_t *mp_start,
+                               uint32_t *ent_off, uint32_t *mpb, uint32_t *me_off) {
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t nb = node_base[g];
+        ent_off[g] = off[nb];
+        uint64_t a = 0, b = n_multi;  // first pair whose smaller node is >= nb
+        while (a < b) {
+            const uint64_t mid = a + (b - a) / 2;
+            if (mp_lo[mid] < nb) a = mid + 1;
+            else b = mid;
+        }
+        mpb[g] = (uint32_t)a;
+        me_off[g] = mp_start[a];
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_max_degree(const uint32_t *off, uint32_t n,
                                                        uint32_t *out) {
     uint32_t mx = 0;
@@ -250,32 +288,87 @@ static int galloc(tm_graph *g, T **p, size_t count) {
     return graph_alloc(g, (void **)p, count * sizeof(T));
 }
 
+// Tiles of at most `cap` items over per-graph ranges [bound[g], bound[g+1]).
+static std::vector<Tile> make_tiles(const std::vector<uint64_t> &bound, uint64_t cap) {
+    std::vector<Tile> tiles;
+    for (size_t gi = 0; gi + 1 < bound.size(); gi++)
+        for (uint64_t b = bound[gi]; b < bound[gi + 1]; b += cap)
+            tiles.push_back(Tile{(uint32_t)gi, (uint32_t)b, (uint32_t)std::min(bound[gi + 1], b + cap)});
+    return tiles;
+}
+
+static int upload_tiles(tm_graph *g, const std::vector<Tile> &tiles, Tile **out, uint32_t *count,
+                        hipStream_t s) {
+    *count = (uint32_t)tiles.size();
+    TRY(galloc(g, out, std::max<size_t>(tiles.size(), 1)));
+    if (!tiles.empty())
+        TM_HIP_TRY(hipMemcpyAsync(*out, tiles.data(), tiles.size() * sizeof(Tile),
+                                  hipMemcpyHostToDevice, s));
+    return TM_OK;
+}
+
 int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, const int64_t *t,
-                       uint64_t m, uint32_t n_nodes, hipStream_t s) {
+                       const uint64_t *eoff, const uint32_t *ncount, uint32_t G, hipStream_t s) {
+    const uint64_t m = eoff[G];
     g->m = m;
-    // ---- 1. validation
-    Scratch st_buf;
-    TRY(st_buf.reserve(sizeof(Stat) + 256, s));
-    Stat *d_st = st_buf.take<Stat>(1);
-    Stat h_st{0, 0, ~0ull, 0};
-    TM_HIP_TRY(hipMemcpyAsync(d_st, &h_st, sizeof(Stat), hipMemcpyHostToDevice, s));
-    if (m > 0) {
-        TM_LAUNCH("validate", k_validate, grid_for(m, kMaxStatBlocks), dim3(kBlock), 0, s, src, dst,
-                  t, m, n_nodes ? n_nodes : 0x7fffffffu, d_st);
+    g->G = G;
+    g->h_eoff.assign(eoff, eoff + G + 1);
+    // ---- 1. per-graph validation
+    std::vector<Stat> h_st(G, Stat{0, 0, ~0ull, 0});
+    std::vector<uint32_t> h_lim(G);
+    for (uint32_t i = 0; i < G; i++) h_lim[i] = ncount[i] ? ncount[i] : 0x7fffffffu;
+    const std::vector<Tile> etiles = make_tiles(g->h_eoff, 1u << 16);
+    {
+        Scratch vs;
+        TRY(vs.reserve(G * sizeof(Stat) + G * 4 + etiles.size() * sizeof(Tile) + 1024, s));
+        Stat *d_st = vs.take<Stat>(G);
+        uint32_t *d_lim = vs.take<uint32_t>(G);
+        Tile *d_et = vs.take<Tile>(std::max<size_t>(etiles.size(), 1));
+        TM_HIP_TRY(hipMemcpyAsync(d_st, h_st.data(), G * sizeof(Stat), hipMemcpyHostToDevice, s));
+        TM_HIP_TRY(hipMemcpyAsync(d_lim, h_lim.data(), G * 4, hipMemcpyHostToDevice, s));
+        if (!etiles.empty()) {
+            TM_HIP_TRY(hipMemcpyAsync(d_et, etiles.data(), etiles.size() * sizeof(Tile),
+                                      hipMemcpyHostToDevice, s));
+            TM_LAUNCH("validate", k_validate,
+                      dim3((unsigned)std::min<size_t>(etiles.size(), kMaxStatBlocks)), dim3(kBlock), 0,
+                      s, src, dst, t, d_et, (uint32_t)etiles.size(), d_lim, d_st);
+        }
+        TM_HIP_TRY(hipMemcpyAsync(h_st.data(), d_st, G * sizeof(Stat), hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipStreamSynchronize(s));
     }
-    TM_HIP_TRY(hipMemcpyAsync(&h_st, d_st, sizeof(Stat), hipMemcpyDeviceToHost, s));
-    TM_HIP_TRY(hipStreamSynchronize(s));
-    if (h_st.bad) {
-        set_error(std::string("invalid edge list:") + ((h_st.bad & 1) ? " node id out of range" : "") +
-                  ((h_st.bad & 2) ? " self-loop" : "") + ((h_st.bad & 4) ? " |t| >= 2^62" : ""));
+    std::vector<uint32_t> node_base(G + 1, 0);
+    std::vector<int64_t> tmin_g(G, 0);
+    int tbits = 0;
+    for (uint32_t i = 0; i < G; i++) {
+        if (h_st[i].bad) {
+            const uint32_t bad = h_st[i].bad;
+            set_error(std::string("invalid edge list") + (G > 1 ? " (graph " + std::to_string(i) + ")" : "") +
+                      ":" + ((bad & 1) ? " node id out of range" : "") + ((bad & 2) ? " self-loop" : "") +
+                      ((bad & 4) ? " |t| >= 2^62" : ""));
+            return TM_EINVAL;
+        }
+        const bool has_edges = eoff[i + 1] > eoff[i];
+        const uint64_t ni = ncount[i] ? ncount[i] : (has_edges ? (uint64_t)h_st[i].max_id + 1 : 0);
+        if ((uint64_t)node_base[i] + ni > 0x7fffffffull) {
+            set_error("total node count must be below 2^31");
+            return TM_EINVAL;
+        }
+        node_base[i + 1] = node_base[i] + (uint32_t)ni;
+        if (has_edges) {
+            const int64_t lo = (int64_t)(h_st[i].tmin_key ^ 0x8000000000000000ull);
+            const int64_t hi = (int64_t)(h_st[i].tmax_key ^ 0x8000000000000000ull);
+            tmin_g[i] = lo;
+            tbits = std::max(tbits, bits_for((uint64_t)(hi - lo)));
+        }
+    }
+    const int gbits = bits_for(G - 1);
+    if (gbits + tbits > 64) {
+        set_error("graph index and time range do not fit one 64-bit sort key");
         return TM_EINVAL;
     }
-    const uint64_t n = n_nodes ? n_nodes : (m ? (uint64_t)h_st.max_id + 1 : 0);
-    if (n > 0x7fffffffull) {
-        set_error("node count must be below 2^31");
-        return TM_EINVAL;
-    }
+    const uint64_t n = node_base[G];
     g->n = (uint32_t)n;
+    g->h_node_base = node_base;
     const uint64_t len = 2 * m;
     TRY(galloc(g, &g->off, n + 1));
     TRY(galloc(g, &g->ent_t, len));
@@ -285,17 +378,35 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     TRY(galloc(g, &g->X, len + 1));
     TRY(galloc(g, &g->epos, len));
     TRY(galloc(g, &g->perm, m));
+    TRY(galloc(g, &g->d_eoff, G + 1));
+    {
+        std::vector<uint32_t> e32(G + 1);
+        for (uint32_t i = 0; i <= G; i++) e32[i] = (uint32_t)eoff[i];
+        TM_HIP_TRY(hipMemcpyAsync(g->d_eoff, e32.data(), (G + 1) * 4, hipMemcpyHostToDevice, s));
+    }
     if (m == 0) {
         TM_HIP_TRY(hipMemsetAsync(g->off, 0, (n + 1) * sizeof(uint32_t), s));
         TM_HIP_TRY(hipMemsetAsync(g->X, 0, sizeof(uint32_t), s));
         TRY(galloc(g, &g->mp_start, 1));
         TM_HIP_TRY(hipMemsetAsync(g->mp_start, 0, sizeof(uint32_t), s));
+        TRY(galloc(g, &g->d_mpb, G + 1));
+        TM_HIP_TRY(hipMemsetAsync(g->d_mpb, 0, (G + 1) * sizeof(uint32_t), s));
+        g->h_ent_off.assign(G + 1, 0);
+        g->h_mpb.assign(G + 1, 0);
+        g->h_me_off.assign(G + 1, 0);
         TM_HIP_TRY(hipStreamSynchronize(s));
         return TM_OK;
     }
-    const int64_t tmin = (int64_t)(h_st.tmin_key ^ 0x8000000000000000ull);
-    const int64_t tmax = (int64_t)(h_st.tmax_key ^ 0x8000000000000000ull);
-    const int tbits = bits_for((uint64_t)(tmax - tmin));
+    const int kbits = gbits + tbits;
+    uint32_t *d_nb = nullptr;
+    TRY(galloc(g, &d_nb, G + 1));
+    g->d_node_base = d_nb;
+    TM_HIP_TRY(hipMemcpyAsync(d_nb, node_base.data(), (G + 1) * 4, hipMemcpyHostToDevice, s));
+    TRY(galloc(g, &g->d_tmin, G));
+    TM_HIP_TRY(hipMemcpyAsync(g->d_tmin, tmin_g.data(), G * 8, hipMemcpyHostToDevice, s));
+    Tile *d_etiles = nullptr;
+    uint32_t n_etiles = 0;
+    TRY(upload_tiles(g, etiles, &d_etiles, &n_etiles, s));
 
     // ---- scratch (stream-ordered, released when this function returns)
     // KA, KB: 8 bytes x 2m each   (time keys, node keys)
@@ -303,7 +414,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     // PKA, PKB: u64 x m; PVA, PVB: u32 x m   (pair sort)
     // TR: i64 x m                 (timestamps by rank)
     // TMP: scan / histogram scratch
-    const size_t ntmp = std::max(radix_tmp_count(len), scan_tmp_count(len)) + 16;
+    const size_t ntmp = std::max({radix_tmp_count(len), scan_tmp_count(len), (size_t)3 * (G + 1)}) + 16;
     Scratch sc;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t bytes = 2 * up(8 * len) + 2 * up(16 * len) + 2 * up(8 * m) + 2 * up(4 * m) +
@@ -329,26 +440,27 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         auto other_v = [&](const void *p) {
             return reinterpret_cast<NodeVal *>(static_cast<const char *>(p) == VA ? VB : VA);
         };
-        if (tbits <= 32) {
+        const dim3 tgrid((unsigned)std::min<uint32_t>(n_etiles, 4096));
+        if (kbits <= 32) {
             uint32_t *k = reinterpret_cast<uint32_t *>(KA), *k_alt = reinterpret_cast<uint32_t *>(KB);
-            TM_LAUNCH("time_keys", k_time_keys<uint32_t>, grid_for(m), dim3(kBlock), 0, s, src, dst,
-                      t, m, tmin, k, ev);
-            TRY(radix_sort_u32_edge(&k, &k_alt, &ev, &ev_alt, m, tbits, tmp, s, "sort_time_hist",
+            TM_LAUNCH("time_keys", k_time_keys<uint32_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
+                      d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
+            TRY(radix_sort_u32_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, s, "sort_time_hist",
                                     "sort_time_scatter"));
             nkey = other_k(k);
             nval = other_v(ev);
-            TM_LAUNCH("rank", k_rank<uint32_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, tmin, n,
-                      TR, g->perm, nkey, nval, PKA, PVA);
+            TM_LAUNCH("rank", k_rank<uint32_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, g->d_tmin,
+                      G > 1 ? tbits : 64, n, TR, g->perm, nkey, nval, PKA, PVA);
         } else {
             uint64_t *k = reinterpret_cast<uint64_t *>(KA), *k_alt = reinterpret_cast<uint64_t *>(KB);
-            TM_LAUNCH("time_keys", k_time_keys<uint64_t>, grid_for(m), dim3(kBlock), 0, s, src, dst,
-                      t, m, tmin, k, ev);
-            TRY(radix_sort_u64_edge(&k, &k_alt, &ev, &ev_alt, m, tbits, tmp, s, "sort_time_hist",
+            TM_LAUNCH("time_keys", k_time_keys<uint64_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
+                      d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
+            TRY(radix_sort_u64_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, s, "sort_time_hist",
                                     "sort_time_scatter"));
             nkey = other_k(k);
             nval = other_v(ev);
-            TM_LAUNCH("rank", k_rank<uint64_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, tmin, n,
-                      TR, g->perm, nkey, nval, PKA, PVA);
+            TM_LAUNCH("rank", k_rank<uint64_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, g->d_tmin,
+                      G > 1 ? tbits : 64, n, TR, g->perm, nkey, nval, PKA, PVA);
         }
     }
 
@@ -398,6 +510,31 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         MultiOut o{g->mp_start, g->mp_lo, g->mp_hi, g->me_t, g->me_p, g->me_a, g->me_o};
         TM_LAUNCH("multi_fill", k_multi_fill, grid_for(m), dim3(kBlock), 0, s, k, v, m, n, in_multi,
                   eidx, head, pidx, TR, g->epos, g->X, g->off, g->n_multi, g->n_me, o);
+    }
+
+    // ---- 5. per-graph ranges and the static work tiles
+    {
+        uint32_t *r3 = tmp;  // 3 x (G + 1)
+        TRY(galloc(g, &g->d_mpb, G + 1));
+        TM_LAUNCH("graph_ranges", k_graph_ranges, grid_for(G + 1), dim3(kBlock), 0, s, g->off, d_nb, G,
+                  g->mp_lo, g->n_multi, g->mp_start, r3, g->d_mpb, r3 + 2 * (G + 1));
+        std::vector<uint32_t> h(3 * (G + 1));
+        TM_HIP_TRY(hipMemcpyAsync(h.data(), r3, (G + 1) * 4, hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipMemcpyAsync(h.data() + (G + 1), g->d_mpb, (G + 1) * 4, hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipMemcpyAsync(h.data() + 2 * (G + 1), r3 + 2 * (G + 1), (G + 1) * 4,
+                                  hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipStreamSynchronize(s));
+        g->h_ent_off.assign(h.begin(), h.begin() + (G + 1));
+        g->h_mpb.assign(h.begin() + (G + 1), h.begin() + 2 * (G + 1));
+        g->h_me_off.assign(h.begin() + 2 * (G + 1), h.end());
+        std::vector<uint64_t> eb(G + 1), mb(G + 1);
+        for (uint32_t i = 0; i <= G; i++) {
+            eb[i] = g->h_ent_off[i];
+            mb[i] = 2 * (uint64_t)g->h_me_off[i];  // element sides
+        }
+        TRY(upload_tiles(g, make_tiles(eb, kEntryTile), &g->t_entries, &g->n_t_entries, s));
+        TRY(upload_tiles(g, make_tiles(mb, kElemTile), &g->t_elems, &g->n_t_elems, s));
+        TM_HIP_TRY(hipStreamSynchronize(s));
     }
 
     return TM_OK;

@@ -41,6 +41,7 @@
 // Per-lane uint64 accumulators are reduced per block, then all block partials
 // are summed by one deterministic tree reduction (no atomics on counts).
 #include <algorithm>
+#include <vector>
 
 #include "tm_internal.h"
 
@@ -115,17 +116,20 @@ __device__ inline uint32_t window_start(const int64_t *T, uint32_t p, uint32_t l
 }
 
 // ------------------------------------------------------------ window sizes
-// Wf[p] = R(p) - p: how many later entries of the same S_u lie within delta.
-__global__ void __launch_bounds__(kBlock) k_windows(SeqView S, uint64_t len, int64_t delta,
-                                                    uint32_t *Wf) {
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < len;
-         p += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t hi = S.off[S.c[p] + 1];
-        const int64_t lim = S.t[p] + delta;
-        uint32_t w = 0;
-        if (p + 1 < hi && S.t[p + 1] <= lim)
-            w = window_end(S.t, (uint32_t)p, hi, lim) - (uint32_t)p;
-        Wf[p] = w;
+// Wf[p] = R(p) - p: how many later entries of the same S_u lie within delta
+// (the delta of the graph the entry belongs to; tiles never straddle graphs).
+__global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
+                                                    const int64_t *deltas, uint32_t *Wf) {
+    for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const Tile tl = tiles[ti];
+        const int64_t delta = deltas[tl.g];
+        for (uint32_t p = tl.b + threadIdx.x; p < tl.e; p += blockDim.x) {
+            const uint32_t hi = S.off[S.c[p] + 1];
+            const int64_t lim = S.t[p] + delta;
+            uint32_t w = 0;
+            if (p + 1 < hi && S.t[p + 1] <= lim) w = window_end(S.t, p, hi, lim) - p;
+            Wf[p] = w;
+        }
     }
 }
 
@@ -136,9 +140,12 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, uint64_t len, int
 __global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me_p,
                                                       const uint4 *me_a, const int64_t *me_t,
                                                       const uint32_t *Wf, uint64_t n_me,
-                                                      int64_t delta, uint4 *me_w) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n_me;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+                                                      const Tile *tiles, uint32_t n_tiles,
+                                                      const int64_t *deltas, uint4 *me_w) {
+  for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+    const Tile tl = tiles[ti];
+    const int64_t delta = deltas[tl.g];
+    for (uint64_t i = tl.b + threadIdx.x; i < tl.e; i += blockDim.x) {
         const uint64_t k = i >> 1;
         const uint32_t side = (uint32_t)(i & 1);
         const uint2 pp = me_p[k];
@@ -167,6 +174,7 @@ __global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me
         }
         me_w[i] = make_uint4(rp0, rp1, lp0, lp1);
     }
+  }
 }
 
 // Window state over the edges of one node pair inside a delta-window.
@@ -248,11 +256,25 @@ struct StarArgs {
     const uint8_t *me_o;
     const uint4 *me_a;
     const uint4 *me_w;
-    const uint32_t *first;  // n_multi + 1: first work item of each pair (exclusive scan)
+    const uint32_t *first;   // n_multi + 1: first work item of each pair (exclusive scan)
     uint64_t n_multi;
+    const uint32_t *mpb;     // G + 1: multi-edge pair bounds per graph
+    const uint32_t *tfirst;  // G + 1: first item tile of each graph
+    uint32_t G;
+    const int64_t *deltas;
     uint32_t chunk;
-    int64_t delta;
 };
+
+// Largest i in [0, n) with a[i] <= x, for ascending a with a[0] <= x.
+__device__ inline uint32_t last_le(const uint32_t *a, uint32_t n, uint32_t x) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (a[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 // Work item -> (pair, chunk): the pair is the last one whose first item is <= it.
 __device__ inline WorkItem item_of(const uint32_t *first, uint64_t n_multi, uint32_t it) {
@@ -265,15 +287,22 @@ __device__ inline WorkItem item_of(const uint32_t *first, uint64_t n_multi, uint
     return WorkItem{(uint32_t)lo, it - first[lo]};
 }
 
+// One block per item tile (kItemTile items of one graph); one partial row
+// of 32 counters per tile.
+constexpr uint32_t kItemTile = 1024;
+
 __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *partial) {
+  const uint32_t n_tiles = a.tfirst[a.G];
+  for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+    const uint32_t gi = last_le(a.tfirst, a.G + 1, ti);
+    const int64_t delta = a.deltas[gi];
+    const uint32_t ib = a.first[a.mpb[gi]] + (ti - a.tfirst[gi]) * kItemTile;
+    const uint32_t ie = min(a.first[a.mpb[gi + 1]], ib + kItemTile);
     StarAcc A;
 #pragma unroll
     for (int i = 0; i < 32; i++) A.c[i] = 0;
-
-    const uint64_t n_items = a.first[a.n_multi];
-    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n_items;
-         it += (uint64_t)gridDim.x * blockDim.x) {
-        const WorkItem w = item_of(a.first, a.n_multi, (uint32_t)it);
+    for (uint32_t it = ib + threadIdx.x; it < ie; it += blockDim.x) {
+        const WorkItem w = item_of(a.first, a.n_multi, it);
         const uint32_t rs = a.mp_start[w.pair], re = a.mp_start[w.pair + 1];
         const uint32_t cb = rs + w.chunk * a.chunk;
         const uint32_t ce = min(re, cb + a.chunk);
@@ -286,7 +315,7 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
                 const El eq = load_el(a.me_t, a.me_o, a.me_a, q, side);
                 if (q > cb && j > q) W.pop(eq.dir, eq.a0, eq.a1);
                 if (j <= q) j = q + 1;
-                const int64_t lim = eq.t + a.delta;
+                const int64_t lim = eq.t + delta;
                 while (j < re) {
                     const El ej = load_el(a.me_t, a.me_o, a.me_a, j, side);
                     if (ej.t > lim) break;
@@ -321,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
             W.clear();
             uint32_t f;  // front of the window [f, q)
             {
-                const int64_t lim = a.me_t[cb] - a.delta;
+                const int64_t lim = a.me_t[cb] - delta;
                 f = cb;
                 while (f > rs && a.me_t[f - 1] >= lim) f--;
                 for (uint32_t k = f; k < cb; k++) {
@@ -331,7 +360,7 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
             }
             for (uint32_t q = cb; q < ce; q++) {
                 const El eq = load_el(a.me_t, a.me_o, a.me_a, q, side);
-                const int64_t lim = eq.t - a.delta;
+                const int64_t lim = eq.t - delta;
                 while (f < q) {
                     const El ef = load_el(a.me_t, a.me_o, a.me_a, f, side);
                     if (ef.t >= lim) break;
@@ -358,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
         }
     }
 
-    // block reduction of the 32 accumulators
+    // block reduction of the 32 accumulators into this tile's row
     __shared__ uint64_t red[kBlock / kWave][32];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
 #pragma unroll
@@ -373,8 +402,10 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
         uint64_t s = 0;
 #pragma unroll
         for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
-        partial[(uint64_t)blockIdx.x * 32 + threadIdx.x] = s;
+        partial[(uint64_t)ti * 32 + threadIdx.x] = s;
     }
+    __syncthreads();
+  }
 }
 
 // Work items: node pair k is cut into ceil(len / chunk) items.
@@ -422,21 +453,28 @@ __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint
     return ra < rb ? ((1u - da) * 4 + (1u - db) * 2 + 0u) : ((1u - db) * 4 + (1u - da) * 2 + 1u);
 }
 
+// One block per candidate tile (kCandTile candidates of one graph); waves
+// take 64 candidates at a time; one partial row of 8 counters per tile.
+constexpr uint32_t kCandTile = 1024;
+
 __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
-                                                      const uint32_t *n_cand, uint32_t lane_max,
-                                                      uint64_t *partial) {
-    const uint64_t nc = *n_cand;
+                                                      const uint32_t *tidx, const uint32_t *eoff,
+                                                      const uint32_t *ctfirst, uint32_t G,
+                                                      uint32_t lane_max, uint64_t *partial) {
+  const uint32_t n_tiles = ctfirst[G];
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t wv = threadIdx.x / kWave;
+  for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+    const uint32_t gi = last_le(ctfirst, G + 1, ti);
+    const uint32_t cb = tidx[eoff[gi]] + (ti - ctfirst[gi]) * kCandTile;
+    const uint32_t ce = min(tidx[eoff[gi + 1]], cb + kCandTile);
     TriAcc T;
 #pragma unroll
     for (int i = 0; i < 8; i++) T.c[i] = 0;
-    const int lane = threadIdx.x & (kWave - 1);
-    // whole waves step through the candidates together
-    const uint64_t wave_id = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
-    for (uint64_t base = wave_id * kWave; base < nc; base += n_waves * kWave) {
-        const uint64_t ci = base + lane;
+    for (uint32_t base = cb + wv * kWave; base < ce; base += kBlock) {
+        const uint32_t ci = base + lane;
         uint32_t ps = 0, pd = 0, ws = 0, wd = 0;
-        const bool active = ci < nc;
+        const bool active = ci < ce;
         if (active) {
             const uint4 c = cand[ci];
             ps = c.x;
@@ -485,7 +523,6 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
         }
     }
     __shared__ uint64_t red[kBlock / kWave][8];
-    const int wv = threadIdx.x / kWave;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         uint64_t v = T.c[i];
@@ -498,31 +535,48 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
         uint64_t s = 0;
 #pragma unroll
         for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
-        partial[(uint64_t)blockIdx.x * 8 + threadIdx.x] = s;
+        partial[(uint64_t)ti * 8 + threadIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Per graph: item tiles (star/pair) and candidate tiles (triangles).
+__global__ void k_graph_tiles(const uint32_t *first, const uint32_t *mpb, const uint32_t *tidx,
+                              const uint32_t *eoff, uint32_t G, uint32_t *n_item_tiles,
+                              uint32_t *n_cand_tiles) {
+    for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G; gi += gridDim.x * blockDim.x) {
+        const uint32_t items = first[mpb[gi + 1]] - first[mpb[gi]];
+        const uint32_t cands = tidx[eoff[gi + 1]] - tidx[eoff[gi]];
+        n_item_tiles[gi] = (items + kItemTile - 1) / kItemTile;
+        n_cand_tiles[gi] = (cands + kCandTile - 1) / kCandTile;
     }
 }
 
-// ---------------------------------------------------------------- reduction
-// Column sums of part[rows][cols] (cols divides kBlock), in two stages with
-// fixed shapes: block b of the first stage sums rows b, b + gridDim.x, ...
-// into stage[b][cols]; one block then sums the stage rows.  Thread t handles
-// column t % cols, so consecutive threads read consecutive words.  Integer
-// sums: exact and order-independent, no atomics.
-constexpr uint32_t kReduceBlocks = 64;
-
-__global__ void __launch_bounds__(kBlock) k_reduce_cols(const uint64_t *part, uint32_t rows,
-                                                        uint32_t cols, uint64_t *out) {
+// Per graph: sum its star/pair tile rows and its triangle tile rows (block
+// per graph, thread t on column t % cols; integer sums, no atomics).
+__global__ void __launch_bounds__(kBlock) k_graph_sums(const uint64_t *spart, const uint32_t *tfirst,
+                                                       const uint64_t *tpart,
+                                                       const uint32_t *ctfirst, uint32_t G,
+                                                       uint64_t *out) {
     __shared__ uint64_t lds[kBlock];
-    const uint32_t c = threadIdx.x % cols, g = threadIdx.x / cols, groups = kBlock / cols;
-    uint64_t v = 0;
-    for (uint32_t r = blockIdx.x + g * gridDim.x; r < rows; r += groups * gridDim.x)
-        v += part[(uint64_t)r * cols + c];
-    lds[threadIdx.x] = v;
-    __syncthreads();
-    if (threadIdx.x < cols) {
-        uint64_t s = 0;
-        for (uint32_t q = 0; q < groups; q++) s += lds[q * cols + threadIdx.x];
-        out[(uint64_t)blockIdx.x * cols + threadIdx.x] = s;
+    for (uint32_t gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        for (int pass = 0; pass < 2; pass++) {
+            const uint32_t cols = pass == 0 ? 32u : 8u;
+            const uint64_t *part = pass == 0 ? spart : tpart;
+            const uint32_t *fr = pass == 0 ? tfirst : ctfirst;
+            const uint32_t c = threadIdx.x % cols, grp = threadIdx.x / cols, groups = kBlock / cols;
+            uint64_t v = 0;
+            for (uint32_t r = fr[gi] + grp; r < fr[gi + 1]; r += groups) v += part[(uint64_t)r * cols + c];
+            lds[threadIdx.x] = v;
+            __syncthreads();
+            if (threadIdx.x < cols) {
+                uint64_t sum = 0;
+                for (uint32_t q = 0; q < groups; q++) sum += lds[q * cols + threadIdx.x];
+                out[(uint64_t)gi * 40 + (pass == 0 ? 0 : 32) + threadIdx.x] = sum;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -538,36 +592,36 @@ dim3 grid_for(uint64_t n, uint64_t cap) {
 constexpr uint32_t kDefaultRunChunk = 8;
 constexpr uint32_t kDefaultTriLaneMax = 64;
 
-int count_graph(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t raw[56]) {
+int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32_t tri_lane_max,
+                uint64_t *raw) {
     if (run_chunk == 0) run_chunk = kDefaultRunChunk;
     if (tri_lane_max == 0) tri_lane_max = kDefaultTriLaneMax;
-    uint64_t host[40] = {0};
+    const uint32_t G = g->G;
+    std::vector<uint64_t> host((size_t)G * 40, 0);
     hipStream_t s = g->stream;
     if (g->m >= 3) {
         SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos};
         const uint64_t m = g->m, len = 2 * m;
         const uint64_t nm = g->n_multi, nme = g->n_me;
-        constexpr uint32_t kMaxStarBlocks = 8192, kMaxTriBlocks = 4096;
-        // work items <= elements of multi-edge pairs: one lane per item at most
-        const uint32_t kStarBlocks = grid_for(nme, kMaxStarBlocks).x;
-        const dim3 tgrid = grid_for(m, kMaxTriBlocks);
-        // Work counts stay on the device (kernels read them), so the only
-        // host synchronisation is the final copy of the 40 counters.  Buffers
-        // are sized by upper bounds: triangle candidates <= m; the star grid
-        // covers the work items (<= elements of multi-edge pairs).
-        const size_t n_tmp = scan_tmp_count(std::max<uint64_t>(m, nm)) + 4;
+        // Every work count stays on the device (kernels read it), so the only
+        // host synchronisation is the final copy of the counters.  Partial
+        // rows are bounded by (work / tile + one per graph).
+        const uint64_t max_itiles = nme / kItemTile + G + 1, max_ctiles = m / kCandTile + G + 1;
+        const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
         auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-        const size_t bytes = up(len * 4)                      // Wf
+        const size_t bytes = up(G * 8)                        // deltas
+                             + up(len * 4)                    // Wf
                              + up(2 * nme * sizeof(uint4))    // me_w
                              + up((nm + 1) * 4) * 2           // item counts, firsts
                              + up(m * 4) + up((m + 1) * 4)    // triangle flags, index
                              + up(m * sizeof(uint4))          // candidates
-                             + up(n_tmp * 4) + up((uint64_t)kStarBlocks * 32 * 8) +
-                             up((uint64_t)tgrid.x * 8 * 8) + up(kReduceBlocks * 40 * 8) + up(40 * 8);
+                             + up((G + 1) * 4) * 4            // per-graph tile counts / firsts
+                             + up(n_tmp * 4) + up(max_itiles * 32 * 8) + up(max_ctiles * 8 * 8) +
+                             up((size_t)G * 40 * 8);
         Scratch sc;
         int rc = sc.reserve(bytes, s);
         if (rc) return rc;
+        int64_t *deltas = sc.take<int64_t>(G);
         uint32_t *Wf = sc.take<uint32_t>(len);
         uint4 *me_w = sc.take<uint4>(2 * nme);
         uint32_t *cnt = sc.take<uint32_t>(nm + 1);
@@ -575,56 +629,73 @@ int count_graph(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lan
         uint32_t *tflag = sc.take<uint32_t>(m);
         uint32_t *tidx = sc.take<uint32_t>(m + 1);
         uint4 *cand = sc.take<uint4>(m);
+        uint32_t *n_itiles = sc.take<uint32_t>(G + 1);
+        uint32_t *tfirst = sc.take<uint32_t>(G + 1);
+        uint32_t *n_ctiles = sc.take<uint32_t>(G + 1);
+        uint32_t *ctfirst = sc.take<uint32_t>(G + 1);
         uint32_t *tmp = sc.take<uint32_t>(n_tmp);
-        uint64_t *spart = sc.take<uint64_t>((uint64_t)kStarBlocks * 32);
-        uint64_t *tpart = sc.take<uint64_t>((uint64_t)tgrid.x * 8);
-        uint64_t *stage = sc.take<uint64_t>(kReduceBlocks * 40);
-        uint64_t *res = sc.take<uint64_t>(40);
+        uint64_t *spart = sc.take<uint64_t>(max_itiles * 32);
+        uint64_t *tpart = sc.take<uint64_t>(max_ctiles * 8);
+        uint64_t *res = sc.take<uint64_t>((size_t)G * 40);
+        TM_HIP_TRY(hipMemcpyAsync(deltas, h_deltas, G * 8, hipMemcpyHostToDevice, s));
 
-        TM_LAUNCH("windows", k_windows, grid_for(len, 16384), dim3(kBlock), 0, s, S, len, delta, Wf);
-
-        // ---- star / pair
+        TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock),
+                  0, s, S, g->t_entries, g->n_t_entries, deltas, Wf);
+        // ---- star / pair: work items (pair, chunk)
         if (nm) {
-            TM_LAUNCH("star_prep", k_star_prep, grid_for(2 * nme, 16384), dim3(kBlock), 0, s, S,
-                      g->me_p, g->me_a, g->me_t, Wf, nme, delta, me_w);
+            TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
+                      dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, Wf, nme, g->t_elems,
+                      g->n_t_elems, deltas, me_w);
             TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s,
                       g->mp_start, nm, run_chunk, cnt);
             rc = scan_u32_array(cnt, first, nm, tmp, s);
-            if (rc) return rc;
-            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, me_w, first, nm, run_chunk, delta};
-            TM_LAUNCH("star_pair", k_star_pair, dim3(kStarBlocks), dim3(kBlock), 0, s, sa, spart);
+        } else {
+            rc = scan_u32_array(cnt, first, 0, tmp, s);  // first[0] = 0
         }
-        // ---- triangles: candidate first edges, then matching
+        if (rc) return rc;
+        // ---- triangles: candidate first edges
         TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
                   reinterpret_cast<const uint2 *>(g->epos), Wf, m, tflag);
         rc = scan_u32_array(tflag, tidx, m, tmp, s);
         if (rc) return rc;
         TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
                   reinterpret_cast<const uint2 *>(g->epos), Wf, tflag, tidx, m, cand);
-        TM_LAUNCH("triangles", k_triangles, tgrid, dim3(kBlock), 0, s, S, cand, tidx + m,
-                  tri_lane_max, tpart);
-        TM_LAUNCH("reduce", k_reduce_cols, dim3(kReduceBlocks), dim3(kBlock), 0, s, spart,
-                  nm ? kStarBlocks : 0u, 32u, stage);
-        TM_LAUNCH("reduce", k_reduce_cols, dim3(kReduceBlocks), dim3(kBlock), 0, s, tpart, tgrid.x, 8u,
-                  stage + kReduceBlocks * 32);
-        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, stage, kReduceBlocks, 32u, res);
-        TM_LAUNCH("reduce", k_reduce_cols, dim3(1), dim3(kBlock), 0, s, stage + kReduceBlocks * 32,
-                  kReduceBlocks, 8u, res + 32);
-        TM_HIP_TRY(hipMemcpyAsync(host, res, 40 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        // ---- per-graph work tiles
+        TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, first, g->d_mpb,
+                  tidx, g->d_eoff, G, n_itiles, n_ctiles);
+        rc = scan_u32_array(n_itiles, tfirst, G, tmp, s);
+        if (rc) return rc;
+        rc = scan_u32_array(n_ctiles, ctfirst, G, tmp, s);
+        if (rc) return rc;
+        if (nm) {
+            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, me_w, first, nm,
+                        g->d_mpb, tfirst, G, deltas, run_chunk};
+            TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(max_itiles, 8192)),
+                      dim3(kBlock), 0, s, sa, spart);
+        }
+        TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(max_ctiles, 8192)),
+                  dim3(kBlock), 0, s, S, cand, tidx, g->d_eoff, ctfirst, G, tri_lane_max, tpart);
+        TM_LAUNCH("graph_sums", k_graph_sums, dim3(std::min<uint32_t>(G, 8192)), dim3(kBlock), 0, s,
+                  spart, tfirst, tpart, ctfirst, G, res);
+        TM_HIP_TRY(hipMemcpyAsync(host.data(), res, (size_t)G * 40 * 8, hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
     }
-    // raw counters: Star | Pair straight from the kernel; Tri views from the
-    // classes by the orbit Tri[I,a,b,c] = Tri[II,~c,~b,~a] = Tri[III,c,~a,~b]
-    for (int i = 0; i < 32; i++) raw[i] = host[i];
-    const uint64_t *N = host + 32;
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++)
-            for (int c = 0; c < 2; c++) {
-                const uint64_t v = N[a * 4 + b * 2 + c];
-                raw[32 + 0 * 8 + a * 4 + b * 2 + c] = v;
-                raw[32 + 1 * 8 + (1 - c) * 4 + (1 - b) * 2 + (1 - a)] = v;
-                raw[32 + 2 * 8 + c * 4 + (1 - a) * 2 + (1 - b)] = v;
-            }
+    // raw counters per graph: Star | Pair straight from the kernels; Tri views
+    // from the classes by the orbit Tri[I,a,b,c] = Tri[II,~c,~b,~a] = Tri[III,c,~a,~b]
+    for (uint32_t gi = 0; gi < G; gi++) {
+        const uint64_t *h = host.data() + (size_t)gi * 40;
+        uint64_t *rw = raw + (size_t)gi * 56;
+        for (int i = 0; i < 32; i++) rw[i] = h[i];
+        const uint64_t *N = h + 32;
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int c = 0; c < 2; c++) {
+                    const uint64_t v = N[a * 4 + b * 2 + c];
+                    rw[32 + 0 * 8 + a * 4 + b * 2 + c] = v;
+                    rw[32 + 1 * 8 + (1 - c) * 4 + (1 - b) * 2 + (1 - a)] = v;
+                    rw[32 + 2 * 8 + c * 4 + (1 - a) * 2 + (1 - b)] = v;
+                }
+    }
     return TM_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -84,6 +85,11 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
 // pass, ping-ponging between the two buffers; *keys / *vals point at the
 // sorted data on return.  tmp must hold radix_tmp_count(n) u32.
 size_t radix_tmp_count(uint64_t n);
+// A range [b, e) of work items that all belong to graph g of a batch.
+struct Tile {
+    uint32_t g, b, e;
+};
+
 // An edge carried through the time sort: endpoints and input index.
 struct EdgeVal {
     uint32_t src, dst, id;
@@ -127,8 +133,22 @@ int fill_iota(uint32_t *p, uint64_t n, hipStream_t s);
 
 // ------------------------------------------------------------------ graph
 struct tm_graph {
+    // A graph is a batch of G independent temporal graphs stored as one union
+    // graph: graph i's nodes are [node_base[i], node_base[i+1]), its edge
+    // ranks (time order within the graph) [eoff[i], eoff[i+1]).
+    uint32_t G = 1;
+    std::vector<uint64_t> h_eoff;
+    std::vector<uint32_t> h_node_base, h_ent_off, h_mpb, h_me_off;
+    uint32_t *d_eoff = nullptr;       // G + 1 edge-rank bounds
+    uint32_t *d_node_base = nullptr;  // G + 1
+    uint32_t *d_mpb = nullptr;        // G + 1 multi-edge pair bounds
+    int64_t *d_tmin = nullptr;        // G
+    tmc::Tile *t_entries = nullptr;   // S_u entries, per graph
+    tmc::Tile *t_elems = nullptr;     // multi-pair element sides (2 per element), per graph
+    uint32_t n_t_entries = 0, n_t_elems = 0;
     int device = 0;
     hipStream_t stream = nullptr;
+    std::mutex mu;  // counts on one graph run one at a time
     uint32_t n = 0;
     uint64_t m = 0;
     uint64_t max_degree = 0;
@@ -156,11 +176,16 @@ struct tm_graph {
 };
 
 namespace tmc {
+// Builds G graphs at once: edges of graph i are rows [eoff[i], eoff[i+1]) of
+// src/dst/t with node ids local to the graph (< ncount[i], or any id when
+// ncount[i] == 0).  eoff and ncount are host arrays.
 int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, const int64_t *t,
-                       uint64_t m, uint32_t n_nodes, hipStream_t s);
+                       const uint64_t *eoff, const uint32_t *ncount, uint32_t G, hipStream_t s);
 // Largest S_u length (computed on first use).
 int graph_max_degree(tm_graph *g, uint64_t *out);
 // Counts into raw[56] (host), see tm.h for the layout.
-int count_graph(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t raw[56]);
+// Counts every graph of the batch with its own delta (host array of G) into
+// raw[G * 56] (host).
+int count_graph(tm_graph *g, const int64_t *deltas, uint32_t run_chunk, uint32_t tri_lane_max,
+                uint64_t *raw);
 }  // namespace tmc

@@ -52,6 +52,15 @@ def _load():
     lib.tm_prof_read.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, u64p,
                                  ctypes.POINTER(ctypes.c_double)]
     lib.tm_prof_read.restype = ctypes.c_int
+    lib.tm_build_batch.argtypes = [vp, vp, vp, u64p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32,
+                                   ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.tm_build_batch.restype = ctypes.c_int
+    lib.tm_graph_count.argtypes = [vp]
+    lib.tm_graph_count.restype = ctypes.c_uint32
+    lib.tm_count_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), u64p]
+    lib.tm_count_batch.restype = ctypes.c_int
+    lib.tm_count_batch_raw.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), u64p]
+    lib.tm_count_batch_raw.restype = ctypes.c_int
     lib.tm_strerror.argtypes = [ctypes.c_int]
     lib.tm_strerror.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = []
@@ -104,6 +113,31 @@ class Graph:
         _check(_lib.tm_count_raw_tuned(self.handle, int(delta), int(run_chunk), int(tri_lane_max),
                                        _u64(raw)))
         return raw
+
+    @property
+    def num_graphs(self) -> int:
+        return int(_lib.tm_graph_count(self.handle))
+
+    def _deltas(self, deltas) -> np.ndarray:
+        d = np.ascontiguousarray(np.broadcast_to(np.asarray(deltas, dtype=np.int64),
+                                                 (self.num_graphs,)))
+        return d
+
+    def count_batch(self, deltas) -> np.ndarray:
+        """(G, 6, 6) motif counts, graph i with window deltas[i]."""
+        d = self._deltas(deltas)
+        out = np.zeros((d.size, 36), dtype=np.uint64)
+        _check(_lib.tm_count_batch(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   _u64(out)))
+        return out.reshape(-1, 6, 6)
+
+    def count_batch_raw(self, deltas) -> np.ndarray:
+        """(G, 56) raw counters, graph i with window deltas[i]."""
+        d = self._deltas(deltas)
+        out = np.zeros((d.size, 56), dtype=np.uint64)
+        _check(_lib.tm_count_batch_raw(self.handle,
+                                       d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _u64(out)))
+        return out
 
     def info(self) -> dict:
         n = ctypes.c_uint32()
@@ -168,6 +202,55 @@ def build_graph(src, dst, t, n: int | None = None, stream=None) -> Graph:
         sp = ctypes.c_void_p(int(stream) if stream is not None else 0)
         _check(_lib.tm_build_graph(s.ctypes.data, d.ctypes.data, tt.ctypes.data, s.size,
                                    int(n or 0), TM_HOST_PTRS, sp, ctypes.byref(h)))
+    return Graph(h)
+
+
+def build_batch(graphs, stream=None) -> Graph:
+    """Build G independent graphs as one device object.  ``graphs`` is a list
+    of (src, dst, t) or (src, dst, t, n) host arrays with node ids local to
+    each graph (n = 0 or missing: max id + 1)."""
+    srcs, dsts, ts, ns = [], [], [], []
+    for gr in graphs:
+        srcs.append(np.ascontiguousarray(gr[0], dtype=np.int32))
+        dsts.append(np.ascontiguousarray(gr[1], dtype=np.int32))
+        ts.append(np.ascontiguousarray(gr[2], dtype=np.int64))
+        ns.append(int(gr[3]) if len(gr) > 3 and gr[3] is not None else 0)
+    off = np.zeros(len(graphs) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([a.size for a in srcs])
+    src = np.concatenate(srcs) if srcs else np.zeros(0, np.int32)
+    dst = np.concatenate(dsts) if dsts else np.zeros(0, np.int32)
+    t = np.concatenate(ts) if ts else np.zeros(0, np.int64)
+    return build_batch_arrays(src, dst, t, off, np.asarray(ns, dtype=np.uint32), stream=stream)
+
+
+def build_batch_arrays(src, dst, t, edge_off, node_count, stream=None) -> Graph:
+    """Batched build from concatenated arrays (host numpy or GPU torch
+    tensors) with host ``edge_off`` (G + 1) and ``node_count`` (G)."""
+    off = np.ascontiguousarray(edge_off, dtype=np.uint64)
+    nc = np.ascontiguousarray(node_count, dtype=np.uint32)
+    G = nc.size
+    if off.size != G + 1:
+        raise ValueError("edge_off needs G + 1 entries")
+    h = ctypes.c_void_p()
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    ncp = nc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    if _is_torch_device(src):
+        import torch
+        if not (src.dtype == torch.int32 and dst.dtype == torch.int32 and t.dtype == torch.int64):
+            raise TypeError("device inputs must be int32, int32, int64 tensors")
+        src, dst, t = src.contiguous(), dst.contiguous(), t.contiguous()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        _check(_lib.tm_build_batch(src.data_ptr(), dst.data_ptr(), t.data_ptr(), offp, ncp, G,
+                                   TM_DEVICE_PTRS, sp, ctypes.byref(h)))
+    else:
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        tt = np.ascontiguousarray(t, dtype=np.int64)
+        sp = ctypes.c_void_p(int(stream) if stream is not None else 0)
+        _check(_lib.tm_build_batch(s.ctypes.data, d.ctypes.data, tt.ctypes.data, offp, ncp, G,
+                                   TM_HOST_PTRS, sp, ctypes.byref(h)))
     return Graph(h)
 
 

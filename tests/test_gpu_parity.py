@@ -246,3 +246,83 @@ def test_powerlaw_full_size(tm):
         else:
             want = oracle.alg(g.src, g.dst, g.t, delta, n=g.n, threads=min(16, os.cpu_count()))
         np.testing.assert_array_equal(got, want)
+
+
+# --------------------------------------------------------------------------
+# batches: many graphs, one build, one count, per-graph delta
+
+def _batch_graphs(seed, G, lo=0, hi=400):
+    rng = np.random.default_rng(seed)
+    graphs, deltas = [], []
+    for i in range(G):
+        m = int(rng.integers(lo, hi))
+        n = int(rng.integers(2, 25))
+        g = graphgen.small_random(rng, n, m, t_values=int(rng.integers(1, 60)) if i % 2 else None,
+                                  tmax=int(rng.integers(1, 3000)), multi=0.3 if i % 3 == 0 else 0.0)
+        graphs.append((g.src, g.dst, g.t, n if i % 4 else 0))
+        deltas.append(int(rng.integers(0, 400)))
+    return graphs, deltas
+
+
+@pytest.mark.parametrize("seed,G", [(1, 1), (2, 7), (3, 64), (4, 300)])
+def test_batch_matches_oracle_per_graph(tm, seed, G):
+    graphs, deltas = _batch_graphs(seed, G)
+    case(f"batch G={G} seed={seed}")
+    with tm.build_batch(graphs) as B:
+        assert B.num_graphs == G
+        raw = B.count_batch_raw(deltas)
+        grids = B.count_batch(deltas)
+    for i, (s, d, t, n) in enumerate(graphs):
+        want = oracle.alg(s, d, t, deltas[i], n=n or None)
+        np.testing.assert_array_equal(raw[i], want, err_msg=f"graph {i}")
+        np.testing.assert_array_equal(grids[i], oracle.merge(want))
+
+
+def test_batch_equals_single_graph_counts(tm):
+    """A graph counted alone and the same graph inside a batch of uneven
+    graphs (with empty and tiny members) give identical counts."""
+    graphs, deltas = _batch_graphs(9, 40, lo=0, hi=2000)
+    graphs.append((np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int64), 5))
+    deltas.append(10)
+    big = graphgen.chung_lu_pareto(77, 3000, 60_000)
+    graphs.insert(5, (big.src, big.dst, big.t, big.n))
+    deltas.insert(5, 86400)
+    with tm.build_batch(graphs) as B:
+        raw = B.count_batch_raw(deltas)
+    for i, (s, d, t, n) in enumerate(graphs):
+        case(f"batch member {i} alone m={len(s)}")
+        with tm.build_graph(s, d, t, n=n or None) as G1:
+            np.testing.assert_array_equal(G1.count_raw(deltas[i]), raw[i], err_msg=f"graph {i}")
+
+
+def test_batch_device_pointers_and_repeat(tm):
+    import torch
+    graphs, deltas = _batch_graphs(12, 100, lo=50, hi=1500)
+    src = np.concatenate([g[0] for g in graphs]); dst = np.concatenate([g[1] for g in graphs])
+    t = np.concatenate([g[2] for g in graphs])
+    off = np.zeros(len(graphs) + 1, np.uint64)
+    off[1:] = np.cumsum([len(g[0]) for g in graphs])
+    ncount = np.array([g[3] for g in graphs], np.uint32)
+    dev = torch.device("cuda:0")
+    case("batch device pointers G=100")
+    with tm.build_batch_arrays(torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev),
+                               torch.from_numpy(t).to(dev), off, ncount) as B:
+        a = B.count_batch_raw(deltas)
+        b = B.count_batch_raw(deltas)
+        c = B.count_batch_raw([0] * len(graphs))
+    np.testing.assert_array_equal(a, b)
+    for i, (s, d, tt, n) in enumerate(graphs):
+        np.testing.assert_array_equal(a[i], oracle.alg(s, d, tt, deltas[i], n=n or None))
+        np.testing.assert_array_equal(c[i], oracle.alg(s, d, tt, 0, n=n or None))
+
+
+def test_batch_invalid_member(tm):
+    graphs, deltas = _batch_graphs(13, 5, lo=10, hi=50)
+    s, d, t, n = graphs[3]
+    d = d.copy()
+    d[0] = s[0]                                     # self-loop in graph 3
+    graphs[3] = (s, d, t, n)
+    case("batch invalid member")
+    with pytest.raises(tm.TMError) as ei:
+        tm.build_batch(graphs)
+    assert ei.value.code == -1 and "graph 3" in str(ei.value)
