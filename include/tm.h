@@ -116,6 +116,27 @@ uint32_t tm_graph_count(const tm_graph *g);
 int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]);
 int tm_count_batch_raw(tm_graph *g, const int64_t *deltas, uint64_t (*raw)[56]);
 
+/*
+ * tm_count_batch_raw with explicit execution choices; results never depend
+ * on them.  run_chunk / tri_lane_max as in tm_count_raw_tuned (0 = the
+ * graph's tuned values, else the autotuner table's, else defaults);
+ * use_graph = 1 replays the count as one captured hipGraph (captured on the
+ * first call for these parameters and kept with the graph), 0 launches the
+ * kernels one by one.  tm_count_batch / tm_count_batch_raw use the graph.
+ */
+int tm_count_batch_raw_ex(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
+                          uint32_t tri_lane_max, int use_graph, uint64_t (*raw)[56]);
+
+/*
+ * Autotuner: times the count of g (graph i with deltas[i]) over a grid of
+ * partition parameters, keeps the fastest on g (used by later counts that
+ * pass 0) and in a process-wide table keyed by the graph's shape (later
+ * graphs of that shape default to it).  Outputs (any may be NULL): the chosen
+ * run_chunk, tri_lane_max and its time in milliseconds.
+ */
+int tm_autotune(tm_graph *g, const int64_t *deltas, uint32_t *run_chunk, uint32_t *tri_lane_max,
+                float *best_ms);
+
 /* Release a graph and its device memory.  NULL is ignored. */
 void tm_graph_free(tm_graph *g);
 

@@ -1,5 +1,6 @@
 // C ABI of the motif-counting library: graph lifecycle, counting entry points,
 // the merge of the paper's counters into the 36 motifs, errors and tracing.
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -28,6 +29,40 @@ int Scratch::reserve(size_t bytes, hipStream_t s) {
     cap = bytes;
     used = 0;
     return TM_OK;
+}
+
+// ------------------------------------------------------- autotuner table
+namespace {
+std::mutex g_tune_mu;
+std::map<uint64_t, std::pair<uint32_t, uint32_t>> g_tune;
+
+int ilog2(uint64_t x) {
+    int b = 0;
+    while (x > 1) {
+        x >>= 1;
+        b++;
+    }
+    return b;
+}
+
+uint64_t shape_key(const tm_graph *g) {
+    return ((uint64_t)ilog2(g->m + 1) << 16) | ((uint64_t)ilog2(g->n_me + 1) << 8) |
+           (uint64_t)ilog2(g->G);
+}
+}  // namespace
+
+void tune_table_lookup(const tm_graph *g, uint32_t *run_chunk, uint32_t *tri_lane_max) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(shape_key(g));
+    if (it != g_tune.end()) {
+        *run_chunk = it->second.first;
+        *tri_lane_max = it->second.second;
+    }
+}
+
+void tune_table_store(const tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[shape_key(g)] = {run_chunk, tri_lane_max};
 }
 
 // --------------------------------------------------------------- profiler
@@ -61,6 +96,7 @@ hipEvent_t take_event() {
 }
 thread_local hipEvent_t g_cur_start = nullptr;
 thread_local const char *g_cur_name = nullptr;
+thread_local bool g_capturing = false;
 
 void prof_drain_locked() {
     for (ProfRec &r : g_pending) {
@@ -83,15 +119,17 @@ void prof_drain_locked() {
 }
 }  // namespace
 
+void set_capturing(bool on) { g_capturing = on; }
+
 void prof_begin(const char *name, hipStream_t s) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_capturing) return;
     g_cur_name = name;
     g_cur_start = take_event();
     if (g_cur_start) (void)hipEventRecord(g_cur_start, s);
 }
 
 void prof_end(hipStream_t s) {
-    if (!g_prof_on || !g_cur_start) return;
+    if (!g_prof_on || g_capturing || !g_cur_start) return;
     hipEvent_t stop = take_event();
     if (!stop) return;
     (void)hipEventRecord(stop, s);
@@ -127,6 +165,7 @@ void tm_graph_free(tm_graph *g) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
+    tmc::plan_release(g);
     for (void *p : g->allocs) tmc::dev_free(p, g->stream);
     if (cur != g->device) (void)hipSetDevice(cur);
     delete g;
@@ -225,7 +264,7 @@ int tm_build_batch(const int32_t *src, const int32_t *dst, const int64_t *t,
 }
 
 static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
-                        uint32_t tri_lane_max, uint64_t *raw) {
+                        uint32_t tri_lane_max, uint64_t *raw, bool use_graph) {
     if (!g || !raw || !deltas) {
         tmc::set_error("NULL graph, deltas or output");
         return TM_EINVAL;
@@ -242,7 +281,7 @@ static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
     int rc;
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        rc = tmc::count_graph(g, deltas, run_chunk, tri_lane_max, tmp.data());
+        rc = tmc::count_graph(g, deltas, run_chunk, tri_lane_max, tmp.data(), use_graph);
     }
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc) return rc;
@@ -250,8 +289,37 @@ static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
     return TM_OK;
 }
 
+int tm_count_batch_raw_ex(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
+                          uint32_t tri_lane_max, int use_graph, uint64_t (*raw)[56]) {
+    return count_common(g, deltas, run_chunk, tri_lane_max, raw ? &raw[0][0] : nullptr,
+                        use_graph != 0);
+}
+
+int tm_autotune(tm_graph *g, const int64_t *deltas, uint32_t *run_chunk, uint32_t *tri_lane_max,
+                float *best_ms) {
+    if (!g || !deltas) {
+        tmc::set_error("NULL graph or deltas");
+        return TM_EINVAL;
+    }
+    for (uint32_t i = 0; i < g->G; i++)
+        if (deltas[i] < 0 || deltas[i] >= ((int64_t)1 << 62)) {
+            tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+            return TM_EINVAL;
+        }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        rc = tmc::autotune(g, deltas, run_chunk, tri_lane_max, best_ms);
+    }
+    if (cur != g->device) (void)hipSetDevice(cur);
+    return rc;
+}
+
 int tm_count_batch_raw(tm_graph *g, const int64_t *deltas, uint64_t (*raw)[56]) {
-    return count_common(g, deltas, 0, 0, raw ? &raw[0][0] : nullptr);
+    return count_common(g, deltas, 0, 0, raw ? &raw[0][0] : nullptr, true);
 }
 
 int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]) {
@@ -260,7 +328,7 @@ int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]) {
         return TM_EINVAL;
     }
     std::vector<uint64_t> raw((size_t)g->G * 56);
-    int rc = count_common(g, deltas, 0, 0, raw.data());
+    int rc = count_common(g, deltas, 0, 0, raw.data(), true);
     if (rc) return rc;
     std::vector<uint64_t> res((size_t)g->G * 36);
     for (uint32_t i = 0; i < g->G; i++) {
@@ -278,7 +346,7 @@ int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t 
         tmc::set_error("a batch of several graphs is counted with tm_count_batch");
         return TM_EINVAL;
     }
-    return count_common(g, &delta, run_chunk, tri_lane_max, raw);
+    return count_common(g, &delta, run_chunk, tri_lane_max, raw, false);
 }
 
 int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]) {

@@ -592,93 +592,208 @@ dim3 grid_for(uint64_t n, uint64_t cap) {
 constexpr uint32_t kDefaultRunChunk = 8;
 constexpr uint32_t kDefaultTriLaneMax = 64;
 
+// ---------------------------------------------------------------- driver
+// Device workspace of one count: carved from one block, either per call or
+// kept in the graph's plan for captured replays.
+struct Workspace {
+    int64_t *deltas;
+    uint32_t *Wf;
+    uint4 *me_w;
+    uint32_t *cnt, *first, *tflag, *tidx;
+    uint4 *cand;
+    uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
+    uint64_t *spart, *tpart, *res;
+    uint64_t max_itiles, max_ctiles;
+};
+
+static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
+    const uint32_t G = g->G;
+    const uint64_t m = g->m, len = 2 * m, nm = g->n_multi, nme = g->n_me;
+    w->max_itiles = nme / kItemTile + G + 1;
+    w->max_ctiles = m / kCandTile + G + 1;
+    const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return up(G * 8) + up(len * 4) + up(2 * nme * sizeof(uint4)) + up((nm + 1) * 4) * 2 +
+           up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
+           up(n_tmp * 4) + up(w->max_itiles * 32 * 8) + up(w->max_ctiles * 8 * 8) +
+           up((size_t)G * 40 * 8) + 4096;
+}
+
+static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
+    const uint32_t G = g->G;
+    const uint64_t m = g->m, len = 2 * m, nm = g->n_multi, nme = g->n_me;
+    const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
+    w->deltas = sc.take<int64_t>(G);
+    w->Wf = sc.take<uint32_t>(len);
+    w->me_w = sc.take<uint4>(2 * nme);
+    w->cnt = sc.take<uint32_t>(nm + 1);
+    w->first = sc.take<uint32_t>(nm + 1);
+    w->tflag = sc.take<uint32_t>(m);
+    w->tidx = sc.take<uint32_t>(m + 1);
+    w->cand = sc.take<uint4>(m);
+    w->n_itiles = sc.take<uint32_t>(G + 1);
+    w->tfirst = sc.take<uint32_t>(G + 1);
+    w->n_ctiles = sc.take<uint32_t>(G + 1);
+    w->ctfirst = sc.take<uint32_t>(G + 1);
+    w->tmp = sc.take<uint32_t>(n_tmp);
+    w->spart = sc.take<uint64_t>(w->max_itiles * 32);
+    w->tpart = sc.take<uint64_t>(w->max_ctiles * 8);
+    w->res = sc.take<uint64_t>((size_t)G * 40);
+}
+
+// Every kernel of one count, deltas already in w.deltas, counters to w.res
+// (G x 40).  No host synchronisation, memset or allocation: capturable.
+static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
+                         uint32_t tri_lane_max, hipStream_t s) {
+    const uint32_t G = g->G;
+    SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos};
+    const uint64_t m = g->m, nm = g->n_multi, nme = g->n_me;
+    int rc;
+    TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
+              s, S, g->t_entries, g->n_t_entries, w.deltas, w.Wf);
+    // ---- star / pair: work items (pair, chunk)
+    if (nm) {
+        TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
+                  dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, w.Wf, nme, g->t_elems,
+                  g->n_t_elems, w.deltas, w.me_w);
+        TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
+                  nm, run_chunk, w.cnt);
+    }
+    rc = scan_u32_array(w.cnt, w.first, nm, w.tmp, s);
+    if (rc) return rc;
+    // ---- triangles: candidate first edges
+    TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
+              reinterpret_cast<const uint2 *>(g->epos), w.Wf, m, w.tflag);
+    rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
+    if (rc) return rc;
+    TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
+              reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.tflag, w.tidx, m, w.cand);
+    // ---- per-graph work tiles
+    TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, w.first, g->d_mpb,
+              w.tidx, g->d_eoff, G, w.n_itiles, w.n_ctiles);
+    rc = scan_u32_array(w.n_itiles, w.tfirst, G, w.tmp, s);
+    if (rc) return rc;
+    rc = scan_u32_array(w.n_ctiles, w.ctfirst, G, w.tmp, s);
+    if (rc) return rc;
+    if (nm) {
+        StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w, w.first, nm,
+                    g->d_mpb, w.tfirst, G, w.deltas, run_chunk};
+        TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
+                  dim3(kBlock), 0, s, sa, w.spart);
+    }
+    TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
+              dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max, w.tpart);
+    TM_LAUNCH("graph_sums", k_graph_sums, dim3(std::min<uint32_t>(G, 8192)), dim3(kBlock), 0, s,
+              w.spart, w.tfirst, w.tpart, w.ctfirst, G, w.res);
+    return TM_OK;
+}
+
+// Captured count sequence of one graph object, replayed on a private stream.
+struct Plan {
+    Scratch mem;
+    Workspace w;
+    uint32_t run_chunk = 0, tri_lane_max = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev = nullptr;
+};
+
+void plan_release(tm_graph *g) {
+    Plan *p = g->plan;
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ev) (void)hipEventDestroy(p->ev);
+    {
+        // the workspace returns to the cache on the plan's stream
+        Scratch tmp;
+        std::swap(tmp.base, p->mem.base);
+        tmp.stream = p->stream;
+        tmp.cap = p->mem.cap;
+    }
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+    g->plan = nullptr;
+}
+
+static int plan_prepare(tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max) {
+    Plan *p = g->plan;
+    if (p && p->exec && p->run_chunk == run_chunk && p->tri_lane_max == tri_lane_max) return TM_OK;
+    plan_release(g);
+    p = new (std::nothrow) Plan();
+    if (!p) return TM_ENOMEM;
+    g->plan = p;
+    TM_HIP_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+    TM_HIP_TRY(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
+    const size_t bytes = workspace_bytes(g, &p->w);
+    int rc = p->mem.reserve(bytes, p->stream);
+    if (rc) return rc;
+    workspace_carve(g, p->mem, &p->w);
+    p->run_chunk = run_chunk;
+    p->tri_lane_max = tri_lane_max;
+    TM_HIP_TRY(hipStreamSynchronize(p->stream));
+    TM_HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    set_capturing(true);
+    rc = enqueue_count(g, p->w, run_chunk, tri_lane_max, p->stream);
+    set_capturing(false);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        return TM_EHIP;
+    }
+    p->graph = graph;
+    TM_HIP_TRY(hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0));
+    return TM_OK;
+}
+
+// Partition parameters used when a call passes 0: the graph's tuned values,
+// else the autotuner table's entry for graphs of this shape, else defaults.
+static void resolve_params(const tm_graph *g, uint32_t *run_chunk, uint32_t *tri_lane_max) {
+    uint32_t rc = g->tuned_run_chunk, tl = g->tuned_tri_lane_max;
+    if (!rc || !tl) tune_table_lookup(g, &rc, &tl);
+    if (*run_chunk == 0) *run_chunk = rc ? rc : kDefaultRunChunk;
+    if (*tri_lane_max == 0) *tri_lane_max = tl ? tl : kDefaultTriLaneMax;
+}
+
 int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t *raw) {
-    if (run_chunk == 0) run_chunk = kDefaultRunChunk;
-    if (tri_lane_max == 0) tri_lane_max = kDefaultTriLaneMax;
+                uint64_t *raw, bool use_graph) {
+    resolve_params(g, &run_chunk, &tri_lane_max);
     const uint32_t G = g->G;
     std::vector<uint64_t> host((size_t)G * 40, 0);
-    hipStream_t s = g->stream;
     if (g->m >= 3) {
-        SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos};
-        const uint64_t m = g->m, len = 2 * m;
-        const uint64_t nm = g->n_multi, nme = g->n_me;
-        // Every work count stays on the device (kernels read it), so the only
-        // host synchronisation is the final copy of the counters.  Partial
-        // rows are bounded by (work / tile + one per graph).
-        const uint64_t max_itiles = nme / kItemTile + G + 1, max_ctiles = m / kCandTile + G + 1;
-        const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
-        auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-        const size_t bytes = up(G * 8)                        // deltas
-                             + up(len * 4)                    // Wf
-                             + up(2 * nme * sizeof(uint4))    // me_w
-                             + up((nm + 1) * 4) * 2           // item counts, firsts
-                             + up(m * 4) + up((m + 1) * 4)    // triangle flags, index
-                             + up(m * sizeof(uint4))          // candidates
-                             + up((G + 1) * 4) * 4            // per-graph tile counts / firsts
-                             + up(n_tmp * 4) + up(max_itiles * 32 * 8) + up(max_ctiles * 8 * 8) +
-                             up((size_t)G * 40 * 8);
-        Scratch sc;
-        int rc = sc.reserve(bytes, s);
-        if (rc) return rc;
-        int64_t *deltas = sc.take<int64_t>(G);
-        uint32_t *Wf = sc.take<uint32_t>(len);
-        uint4 *me_w = sc.take<uint4>(2 * nme);
-        uint32_t *cnt = sc.take<uint32_t>(nm + 1);
-        uint32_t *first = sc.take<uint32_t>(nm + 1);
-        uint32_t *tflag = sc.take<uint32_t>(m);
-        uint32_t *tidx = sc.take<uint32_t>(m + 1);
-        uint4 *cand = sc.take<uint4>(m);
-        uint32_t *n_itiles = sc.take<uint32_t>(G + 1);
-        uint32_t *tfirst = sc.take<uint32_t>(G + 1);
-        uint32_t *n_ctiles = sc.take<uint32_t>(G + 1);
-        uint32_t *ctfirst = sc.take<uint32_t>(G + 1);
-        uint32_t *tmp = sc.take<uint32_t>(n_tmp);
-        uint64_t *spart = sc.take<uint64_t>(max_itiles * 32);
-        uint64_t *tpart = sc.take<uint64_t>(max_ctiles * 8);
-        uint64_t *res = sc.take<uint64_t>((size_t)G * 40);
-        TM_HIP_TRY(hipMemcpyAsync(deltas, h_deltas, G * 8, hipMemcpyHostToDevice, s));
-
-        TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock),
-                  0, s, S, g->t_entries, g->n_t_entries, deltas, Wf);
-        // ---- star / pair: work items (pair, chunk)
-        if (nm) {
-            TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
-                      dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, Wf, nme, g->t_elems,
-                      g->n_t_elems, deltas, me_w);
-            TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s,
-                      g->mp_start, nm, run_chunk, cnt);
-            rc = scan_u32_array(cnt, first, nm, tmp, s);
+        if (use_graph) {
+            int rc = plan_prepare(g, run_chunk, tri_lane_max);
+            if (rc) return rc;
+            Plan *p = g->plan;
+            // order after earlier work on the graph's stream, run, copy back
+            TM_HIP_TRY(hipEventRecord(p->ev, g->stream));
+            TM_HIP_TRY(hipStreamWaitEvent(p->stream, p->ev, 0));
+            TM_HIP_TRY(hipMemcpyAsync(p->w.deltas, h_deltas, G * 8, hipMemcpyHostToDevice, p->stream));
+            TM_HIP_TRY(hipGraphLaunch(p->exec, p->stream));
+            TM_HIP_TRY(hipMemcpyAsync(host.data(), p->w.res, (size_t)G * 40 * 8,
+                                      hipMemcpyDeviceToHost, p->stream));
+            TM_HIP_TRY(hipStreamSynchronize(p->stream));
         } else {
-            rc = scan_u32_array(cnt, first, 0, tmp, s);  // first[0] = 0
+            hipStream_t s = g->stream;
+            Workspace w;
+            const size_t bytes = workspace_bytes(g, &w);
+            Scratch sc;
+            int rc = sc.reserve(bytes, s);
+            if (rc) return rc;
+            workspace_carve(g, sc, &w);
+            TM_HIP_TRY(hipMemcpyAsync(w.deltas, h_deltas, G * 8, hipMemcpyHostToDevice, s));
+            rc = enqueue_count(g, w, run_chunk, tri_lane_max, s);
+            if (rc) return rc;
+            TM_HIP_TRY(hipMemcpyAsync(host.data(), w.res, (size_t)G * 40 * 8, hipMemcpyDeviceToHost, s));
+            TM_HIP_TRY(hipStreamSynchronize(s));
         }
-        if (rc) return rc;
-        // ---- triangles: candidate first edges
-        TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
-                  reinterpret_cast<const uint2 *>(g->epos), Wf, m, tflag);
-        rc = scan_u32_array(tflag, tidx, m, tmp, s);
-        if (rc) return rc;
-        TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
-                  reinterpret_cast<const uint2 *>(g->epos), Wf, tflag, tidx, m, cand);
-        // ---- per-graph work tiles
-        TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, first, g->d_mpb,
-                  tidx, g->d_eoff, G, n_itiles, n_ctiles);
-        rc = scan_u32_array(n_itiles, tfirst, G, tmp, s);
-        if (rc) return rc;
-        rc = scan_u32_array(n_ctiles, ctfirst, G, tmp, s);
-        if (rc) return rc;
-        if (nm) {
-            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, me_w, first, nm,
-                        g->d_mpb, tfirst, G, deltas, run_chunk};
-            TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(max_itiles, 8192)),
-                      dim3(kBlock), 0, s, sa, spart);
-        }
-        TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(max_ctiles, 8192)),
-                  dim3(kBlock), 0, s, S, cand, tidx, g->d_eoff, ctfirst, G, tri_lane_max, tpart);
-        TM_LAUNCH("graph_sums", k_graph_sums, dim3(std::min<uint32_t>(G, 8192)), dim3(kBlock), 0, s,
-                  spart, tfirst, tpart, ctfirst, G, res);
-        TM_HIP_TRY(hipMemcpyAsync(host.data(), res, (size_t)G * 40 * 8, hipMemcpyDeviceToHost, s));
-        TM_HIP_TRY(hipStreamSynchronize(s));
     }
     // raw counters per graph: Star | Pair straight from the kernels; Tri views
     // from the classes by the orbit Tri[I,a,b,c] = Tri[II,~c,~b,~a] = Tri[III,c,~a,~b]
@@ -696,6 +811,63 @@ int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32
                     rw[32 + 2 * 8 + c * 4 + (1 - a) * 2 + (1 - b)] = v;
                 }
     }
+    return TM_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+// Times the eager count of this graph (its own deltas) for a grid of
+// partition parameters (work-item chunk of the star/pair sweeps, lane/wave
+// split of the triangle matching) and keeps the fastest.  The result is
+// stored on the graph and in a process-wide table keyed by the graph's shape
+// (log2 of edges, of multi-pair edges, and of the graph count), which later
+// graphs of that shape use by default.
+int autotune(tm_graph *g, const int64_t *h_deltas, uint32_t *best_chunk, uint32_t *best_lane,
+             float *best_ms) {
+    static const uint32_t chunks[] = {2, 4, 8, 16, 32, 64};
+    static const uint32_t lanes[] = {8, 32, 64, 256, 1024};
+    uint32_t bc = kDefaultRunChunk, bl = kDefaultTriLaneMax;
+    float bt = 0;
+    if (g->m >= 3) {
+        hipStream_t s = g->stream;
+        Workspace w;
+        Scratch sc;
+        int rc = sc.reserve(workspace_bytes(g, &w), s);
+        if (rc) return rc;
+        workspace_carve(g, sc, &w);
+        TM_HIP_TRY(hipMemcpyAsync(w.deltas, h_deltas, g->G * 8, hipMemcpyHostToDevice, s));
+        hipEvent_t e0, e1;
+        TM_HIP_TRY(hipEventCreate(&e0));
+        TM_HIP_TRY(hipEventCreate(&e1));
+        bt = -1;
+        for (uint32_t c : chunks)
+            for (uint32_t l : lanes) {
+                float tbest = -1;
+                for (int rep = 0; rep < 2 && rc == TM_OK; rep++) {
+                    (void)hipEventRecord(e0, s);
+                    rc = enqueue_count(g, w, c, l, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (tbest < 0 || ms < tbest) tbest = ms;
+                }
+                if (rc) break;
+                if (bt < 0 || tbest < bt) {
+                    bt = tbest;
+                    bc = c;
+                    bl = l;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+    }
+    g->tuned_run_chunk = bc;
+    g->tuned_tri_lane_max = bl;
+    tune_table_store(g, bc, bl);
+    if (best_chunk) *best_chunk = bc;
+    if (best_lane) *best_lane = bl;
+    if (best_ms) *best_ms = bt;
     return TM_OK;
 }
 

@@ -115,11 +115,14 @@ __global__ void __launch_bounds__(kBlock) k_tile_scan(L ld, uint64_t n, const ui
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[np];
 }
 
+__global__ void k_set_zero(uint32_t *p) { *p = 0; }
+
 template <typename L>
 int scan_impl(L ld, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
     const uint64_t nb = (n + kTile - 1) / kTile;
     if (nb == 0) {
-        TM_HIP_TRY(hipMemsetAsync(out, 0, sizeof(uint32_t), s));
+        // a kernel, not a memset: this may run inside a captured graph
+        TM_LAUNCH("scan_empty", k_set_zero, dim3(1), dim3(1), 0, s, out);
         return TM_OK;
     }
     TM_LAUNCH("scan_tile_sum", (k_tile_sum<L>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp);

@@ -37,6 +37,8 @@ void set_error(const std::string &msg);
 // can bracket them with events on their stream.
 void prof_begin(const char *name, hipStream_t s);
 void prof_end(hipStream_t s);
+// While a stream is being captured into a hipGraph the tracer stays silent.
+void set_capturing(bool on);
 
 #define TM_LAUNCH(name, kernel, grid, block, shm, stream, ...)                       \
     do {                                                                              \
@@ -132,6 +134,10 @@ int fill_iota(uint32_t *p, uint64_t n, hipStream_t s);
 }  // namespace tmc
 
 // ------------------------------------------------------------------ graph
+namespace tmc {
+struct Plan;
+}
+
 struct tm_graph {
     // A graph is a batch of G independent temporal graphs stored as one union
     // graph: graph i's nodes are [node_base[i], node_base[i+1]), its edge
@@ -149,6 +155,10 @@ struct tm_graph {
     int device = 0;
     hipStream_t stream = nullptr;
     std::mutex mu;  // counts on one graph run one at a time
+    // captured count sequence for repeated counts (see count.hip)
+    tmc::Plan *plan = nullptr;
+    // partition parameters picked by the autotuner (0 = not tuned)
+    uint32_t tuned_run_chunk = 0, tuned_tri_lane_max = 0;
     uint32_t n = 0;
     uint64_t m = 0;
     uint64_t max_degree = 0;
@@ -185,7 +195,14 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
 int graph_max_degree(tm_graph *g, uint64_t *out);
 // Counts into raw[56] (host), see tm.h for the layout.
 // Counts every graph of the batch with its own delta (host array of G) into
-// raw[G * 56] (host).
+// raw[G * 56] (host).  use_graph: replay the count as a captured hipGraph
+// (captured on first use for these partition parameters, then reused).
 int count_graph(tm_graph *g, const int64_t *deltas, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t *raw);
+                uint64_t *raw, bool use_graph);
+void plan_release(tm_graph *g);
+// Autotuner (count.hip) and its process-wide table (api.hip).
+int autotune(tm_graph *g, const int64_t *deltas, uint32_t *best_chunk, uint32_t *best_lane,
+             float *best_ms);
+void tune_table_lookup(const tm_graph *g, uint32_t *run_chunk, uint32_t *tri_lane_max);
+void tune_table_store(const tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max);
 }  // namespace tmc

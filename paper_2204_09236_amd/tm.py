@@ -61,6 +61,12 @@ def _load():
     lib.tm_count_batch.restype = ctypes.c_int
     lib.tm_count_batch_raw.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), u64p]
     lib.tm_count_batch_raw.restype = ctypes.c_int
+    lib.tm_count_batch_raw_ex.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.c_int, u64p]
+    lib.tm_count_batch_raw_ex.restype = ctypes.c_int
+    lib.tm_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]
+    lib.tm_autotune.restype = ctypes.c_int
     lib.tm_strerror.argtypes = [ctypes.c_int]
     lib.tm_strerror.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = []
@@ -138,6 +144,23 @@ class Graph:
         _check(_lib.tm_count_batch_raw(self.handle,
                                        d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _u64(out)))
         return out
+
+    def count_batch_raw_ex(self, deltas, run_chunk: int = 0, tri_lane_max: int = 0,
+                           use_graph: bool = True) -> np.ndarray:
+        d = self._deltas(deltas)
+        out = np.zeros((d.size, 56), dtype=np.uint64)
+        _check(_lib.tm_count_batch_raw_ex(self.handle,
+                                          d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          int(run_chunk), int(tri_lane_max), 1 if use_graph else 0,
+                                          _u64(out)))
+        return out
+
+    def autotune(self, deltas) -> dict:
+        d = self._deltas(deltas)
+        c, l, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
+        _check(_lib.tm_autotune(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                ctypes.byref(c), ctypes.byref(l), ctypes.byref(ms)))
+        return {"run_chunk": c.value, "tri_lane_max": l.value, "ms": ms.value}
 
     def info(self) -> dict:
         n = ctypes.c_uint32()

@@ -326,3 +326,40 @@ def test_batch_invalid_member(tm):
     with pytest.raises(tm.TMError) as ei:
         tm.build_batch(graphs)
     assert ei.value.code == -1 and "graph 3" in str(ei.value)
+
+
+def test_batch_graph_replays_match_eager(tm):
+    """The captured hipGraph of a batch count, replayed several times with
+    other eager GPU work and synchronisations in between, gives the eager
+    result on every replay."""
+    import torch
+    graphs, deltas = _batch_graphs(21, 80, lo=20, hi=1500)
+    rng = np.random.default_rng(5)
+    with tm.build_batch(graphs) as B:
+        for rep in range(4):
+            ds = deltas if rep % 2 == 0 else list(rng.integers(0, 600, len(graphs)))
+            case(f"graph replay {rep}")
+            replay = B.count_batch_raw_ex(ds, use_graph=True)
+            x = torch.randn(1 << 20, device="cuda")          # unrelated eager work
+            _ = (x * 2).sum().item()
+            torch.cuda.synchronize()
+            eager = B.count_batch_raw_ex(ds, use_graph=False)
+            np.testing.assert_array_equal(replay, eager)
+            if rep == 0:
+                for i, (s, d, t, n) in enumerate(graphs):
+                    np.testing.assert_array_equal(replay[i], oracle.alg(s, d, t, ds[i], n=n or None))
+        for rc, lm in ((3, 16), (1, 1)):
+            case(f"graph replay params {rc} {lm}")
+            np.testing.assert_array_equal(B.count_batch_raw_ex(deltas, rc, lm, True),
+                                          B.count_batch_raw_ex(deltas, rc, lm, False))
+
+
+def test_autotune_then_count(tm):
+    g = graphgen.chung_lu_pareto(88, 5000, 150_000)
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        case("autotune")
+        best = G.autotune([86400])
+        assert best["run_chunk"] in (2, 4, 8, 16, 32, 64)
+        assert best["tri_lane_max"] in (8, 32, 64, 256, 1024)
+        assert best["ms"] > 0
+        np.testing.assert_array_equal(G.count_raw(86400), oracle.alg(g.src, g.dst, g.t, 86400, n=g.n))
