@@ -35,7 +35,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "tiny", "batch"])
+    ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "tiny", "batch", "serve"])
+    ap.add_argument("--serve-pool", type=int, default=128, help="graphs in the serving pool")
+    ap.add_argument("--serve-mhi", type=float, default=5e6,
+                    help="largest edge count of a pool graph (log-uniform from 1e3)")
+    ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="arrival window per rate (at most --serve-max requests)")
+    ap.add_argument("--serve-max", type=int, default=1000)
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-mhi", type=float, default=2e6,
                     help="largest per-graph edge count of the batch workload (log-uniform from 1e3)")
@@ -165,6 +172,104 @@ def bench_batch(args):
         sys.exit(1)
 
 
+def bench_serve(args):
+    """Serving: Poisson arrivals of (pool graph, delta) requests at each rate;
+    keyed graphs stay resident after their first request.  Latency = done -
+    submit on the server's clock; edges/s = edges of the completed requests /
+    (last done - first submit).  Every result is compared with the same
+    request counted alone."""
+    import math
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2204_09236_amd as tm
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(4)
+    ms = np.rint(np.exp(rng.uniform(math.log(1e3), math.log(args.serve_mhi), args.serve_pool)))
+    kids = np.random.SeedSequence(4).spawn(args.serve_pool)
+    spec = [graphgen.BatchItem(int(m), max(3, int(m) // 20), 0, kids[i]) for i, m in enumerate(ms)]
+    t0 = time.time()
+    with mp.get_context("fork").Pool(args.procs) as pool_:
+        pool = pool_.map(_gen_batch_member, spec, chunksize=2)
+    print(f"[bench] serving pool: {len(pool)} graphs, {int(ms.sum())} edges, generated in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    budget = int(0.7 * torch.cuda.get_device_properties(0).total_memory)
+    S = tm.Server(budget, max_inflight=16)
+    alone_graphs = {}
+    rows = []
+    sent = set()
+    for rate in rates:
+        n_req = int(min(args.serve_max, max(20, rate * args.serve_seconds)))
+        gaps = rng.exponential(1.0 / rate, n_req)
+        reqs = [(int(rng.integers(0, len(pool))),
+                 int(round(math.exp(rng.uniform(math.log(60), math.log(86400))))))
+                for _ in range(n_req)]
+        outstanding, done = {}, {}
+        start = time.perf_counter()
+        t_next = start
+        for i, (gi, delta) in enumerate(reqs):
+            t_next += gaps[i]
+            while True:      # poll finished requests until the next arrival
+                for tk in list(outstanding):
+                    rc, out, times = S.poll(tk)
+                    if rc != tm.tm.TM_EAGAIN:
+                        done[outstanding.pop(tk)] = (rc, out, times)
+                if time.perf_counter() >= t_next:
+                    break
+                time.sleep(min(2e-4, max(0.0, t_next - time.perf_counter())))
+            src, dst, t, n = pool[gi]
+            if gi in sent:
+                tk = S.submit(delta, key=gi + 1)
+            else:
+                tk = S.submit(delta, src, dst, t, n=n, key=gi + 1)
+                sent.add(gi)
+            outstanding[tk] = i
+        for tk, i in outstanding.items():
+            done[i] = S.wait(tk)
+        lat = np.array([(done[i][2][2] - done[i][2][0]) / 1e6 for i in range(n_req)])
+        first_submit = min(done[i][2][0] for i in range(n_req))
+        last_done = max(done[i][2][2] for i in range(n_req))
+        edges = sum(pool[gi][0].size for gi, _ in reqs)
+        ok = all(done[i][0] == 0 for i in range(n_req))
+        same = ok
+        if ok:
+            for i, (gi, delta) in enumerate(reqs):
+                if gi not in alone_graphs:
+                    src, dst, t, n = pool[gi]
+                    alone_graphs[gi] = tm.build_graph(src, dst, t, n=n)
+                if not np.array_equal(done[i][1], alone_graphs[gi].count(delta)):
+                    same = False
+                    break
+        row = {"rate": rate, "requests": n_req, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "edges_per_s": round(edges / ((last_done - first_submit) / 1e9), 1),
+               "all_ok": ok, "identical_to_alone": same}
+        rows.append(row)
+        print(f"[bench] serve rate {rate}: {row}", file=sys.stderr, flush=True)
+    st = S.stats()
+    S.close()
+    for G in alone_graphs.values():
+        G.free()
+    line = {
+        "metric": "p50/p99 request latency and edges/s, served (exact 36 motifs)",
+        "value": rows[-1]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": len(rows),
+        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "serve", "pool_graphs": len(pool), "pool_edges": int(ms.sum()),
+                   "m_range": [1000, args.serve_mhi], "delta_range": [60, 86400],
+                   "budget_bytes": budget, "max_inflight": 16, "parallelism": "single-gpu"},
+        "rates": rows, "server_stats": st,
+    }
+    print(json.dumps(line))
+    if not all(r["identical_to_alone"] for r in rows):
+        sys.exit(1)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -175,6 +280,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

@@ -201,6 +201,51 @@ void tm_prof_enable(int on);
 void tm_prof_reset(void);
 int tm_prof_read(int i, char *name, int name_cap, uint64_t *launches, double *total_ms);
 
+/*
+ * Serving.  A server counts requests (graph, delta) as they arrive, on the
+ * current device, with continuous batching: a scheduler thread admits
+ * pending requests oldest first while at most max_inflight counts are in
+ * flight and the device bytes of resident graphs and running counts stay
+ * within hbm_budget_bytes; counts run asynchronously and overlap on the
+ * device; a request that arrives while others run is admitted as soon as a
+ * slot and memory free up.  Anonymous requests admitted together are built
+ * as one batch.  Keyed graphs (graph_key != 0) stay resident after their
+ * first request (least recently used idle graphs are evicted when the
+ * budget is short), so later requests only count.  Results are identical to
+ * counting each request alone.
+ *
+ * tm_server_create: budget > 0, max_inflight > 0, max_queue > 0 (pending
+ *   requests beyond it are refused with TM_EAGAIN: back-pressure).
+ * tm_submit: graph_key = 0 -> the edges (host arrays, copied before the call
+ *   returns; same rules as tm_build_graph) are the request's graph;
+ *   graph_key != 0 -> the resident graph of that key, or the edges given
+ *   here become it (edges may be NULL if the key is resident or an earlier
+ *   request carries them; given edges are ignored for a resident key).
+ *   TM_EINVAL for bad arguments, TM_ENOTFOUND for an unknown key without
+ *   edges, TM_EAGAIN when the queue is full.  A request that can never fit
+ *   the budget completes with TM_ENOMEM; an invalid edge list completes with
+ *   TM_EINVAL without affecting other requests.
+ * tm_poll: TM_EAGAIN while pending; otherwise the request's final status
+ *   (TM_OK: out holds the 36 counts) and the ticket is released.
+ *   times_ns (optional): submit, start (admitted), done, steady-clock ns.
+ * tm_wait: as tm_poll but blocks up to timeout_ms.
+ * tm_server_stats: [queued, in flight, resident graphs, resident bytes,
+ *   in-flight bytes, completed, failed, budget].
+ * tm_server_destroy: finishes the counts in flight, drops pending requests
+ *   and frees everything.
+ */
+typedef struct tm_server tm_server;
+typedef uint64_t tm_ticket;
+int tm_server_create(uint64_t hbm_budget_bytes, uint32_t max_inflight, uint32_t max_queue,
+                     tm_server **out);
+int tm_submit(tm_server *s, uint64_t graph_key, const int32_t *src, const int32_t *dst,
+              const int64_t *t, uint64_t m, uint32_t n_nodes, int64_t delta, tm_ticket *out);
+int tm_poll(tm_server *s, tm_ticket tk, uint64_t out[36], uint64_t times_ns[3]);
+int tm_wait(tm_server *s, tm_ticket tk, uint64_t out[36], uint64_t times_ns[3],
+            uint32_t timeout_ms);
+int tm_server_stats(tm_server *s, uint64_t stats[8]);
+void tm_server_destroy(tm_server *s);
+
 const char *tm_strerror(int code);
 const char *tm_last_error(void);
 

@@ -688,6 +688,11 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
     return TM_OK;
 }
 
+size_t count_workspace_bytes(const tm_graph *g) {
+    Workspace w;
+    return workspace_bytes(g, &w);
+}
+
 // Captured count sequence of one graph object, replayed on a private stream.
 struct Plan {
     Scratch mem;
@@ -762,6 +767,52 @@ static void resolve_params(const tm_graph *g, uint32_t *run_chunk, uint32_t *tri
     if (*tri_lane_max == 0) *tri_lane_max = tl ? tl : kDefaultTriLaneMax;
 }
 
+// Raw counters (G x 56) from the kernels' per-graph counters (G x 40):
+// Star | Pair as counted; the Tri views from the classes by the orbit
+// Tri[I,a,b,c] = Tri[II,~c,~b,~a] = Tri[III,c,~a,~b].
+void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw) {
+    for (uint32_t gi = 0; gi < G; gi++) {
+        const uint64_t *h = res40 + (size_t)gi * 40;
+        uint64_t *rw = raw + (size_t)gi * 56;
+        for (int i = 0; i < 32; i++) rw[i] = h[i];
+        const uint64_t *N = h + 32;
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int c = 0; c < 2; c++) {
+                    const uint64_t v = N[a * 4 + b * 2 + c];
+                    rw[32 + 0 * 8 + a * 4 + b * 2 + c] = v;
+                    rw[32 + 1 * 8 + (1 - c) * 4 + (1 - b) * 2 + (1 - a)] = v;
+                    rw[32 + 2 * 8 + c * 4 + (1 - a) * 2 + (1 - b)] = v;
+                }
+    }
+}
+
+// Asynchronous count through the graph's captured plan: deltas are read from
+// pinned host memory, the G x 40 counters land in pinned host memory, and
+// `done` is recorded after the copy.  Returns without waiting.
+int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,
+                      hipEvent_t done) {
+    const uint32_t G = g->G;
+    if (g->m < 3) {
+        for (size_t i = 0; i < (size_t)G * 40; i++) pinned_res[i] = 0;
+        TM_HIP_TRY(hipEventRecord(done, g->stream));
+        return TM_OK;
+    }
+    uint32_t run_chunk = 0, tri_lane_max = 0;
+    resolve_params(g, &run_chunk, &tri_lane_max);
+    int rc = plan_prepare(g, run_chunk, tri_lane_max);
+    if (rc) return rc;
+    Plan *p = g->plan;
+    TM_HIP_TRY(hipEventRecord(p->ev, g->stream));
+    TM_HIP_TRY(hipStreamWaitEvent(p->stream, p->ev, 0));
+    TM_HIP_TRY(hipMemcpyAsync(p->w.deltas, pinned_deltas, G * 8, hipMemcpyHostToDevice, p->stream));
+    TM_HIP_TRY(hipGraphLaunch(p->exec, p->stream));
+    TM_HIP_TRY(hipMemcpyAsync(pinned_res, p->w.res, (size_t)G * 40 * 8, hipMemcpyDeviceToHost,
+                              p->stream));
+    TM_HIP_TRY(hipEventRecord(done, p->stream));
+    return TM_OK;
+}
+
 int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32_t tri_lane_max,
                 uint64_t *raw, bool use_graph) {
     resolve_params(g, &run_chunk, &tri_lane_max);
@@ -795,22 +846,7 @@ int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32
             TM_HIP_TRY(hipStreamSynchronize(s));
         }
     }
-    // raw counters per graph: Star | Pair straight from the kernels; Tri views
-    // from the classes by the orbit Tri[I,a,b,c] = Tri[II,~c,~b,~a] = Tri[III,c,~a,~b]
-    for (uint32_t gi = 0; gi < G; gi++) {
-        const uint64_t *h = host.data() + (size_t)gi * 40;
-        uint64_t *rw = raw + (size_t)gi * 56;
-        for (int i = 0; i < 32; i++) rw[i] = h[i];
-        const uint64_t *N = h + 32;
-        for (int a = 0; a < 2; a++)
-            for (int b = 0; b < 2; b++)
-                for (int c = 0; c < 2; c++) {
-                    const uint64_t v = N[a * 4 + b * 2 + c];
-                    rw[32 + 0 * 8 + a * 4 + b * 2 + c] = v;
-                    rw[32 + 1 * 8 + (1 - c) * 4 + (1 - b) * 2 + (1 - a)] = v;
-                    rw[32 + 2 * 8 + c * 4 + (1 - a) * 2 + (1 - b)] = v;
-                }
-    }
+    raw_from_counters(host.data(), G, raw);
     return TM_OK;
 }
 

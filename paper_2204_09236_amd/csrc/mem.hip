@@ -104,6 +104,27 @@ int dev_alloc(void **out, size_t bytes, hipStream_t s) {
     return TM_OK;
 }
 
+size_t dev_block_size(void *p) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache &c = g_cache[dev];
+    auto it = c.live.find(p);
+    return it == c.live.end() ? 0 : it->second;
+}
+
+size_t graph_bytes(const tm_graph *g) {
+    size_t b = 0;
+    for (void *p : g->allocs) b += dev_block_size(p);
+    return b;
+}
+
+size_t build_peak_bytes(uint64_t m, uint64_t n, uint32_t G) {
+    // scratch (sort buffers, ranks, scans) + the graph's own arrays, both
+    // bounded per edge; see the buffer layout of the build
+    return (size_t)m * 230 + (size_t)n * 8 + (size_t)G * 64 + ((size_t)64 << 20);
+}
+
 void dev_free(void *p, hipStream_t s) {
     if (!p) return;
     int dev = 0;

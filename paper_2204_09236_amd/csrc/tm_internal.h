@@ -200,6 +200,15 @@ int graph_max_degree(tm_graph *g, uint64_t *out);
 int count_graph(tm_graph *g, const int64_t *deltas, uint32_t run_chunk, uint32_t tri_lane_max,
                 uint64_t *raw, bool use_graph);
 void plan_release(tm_graph *g);
+void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw);
+int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,
+                      hipEvent_t done);
+// Device bytes held by a graph (its buffers; not the per-count workspace).
+size_t graph_bytes(const tm_graph *g);
+// Device bytes one count of g needs for its workspace.
+size_t count_workspace_bytes(const tm_graph *g);
+// Upper bound of device bytes a build of m edges uses at its peak.
+size_t build_peak_bytes(uint64_t m, uint64_t n, uint32_t G);
 // Autotuner (count.hip) and its process-wide table (api.hip).
 int autotune(tm_graph *g, const int64_t *deltas, uint32_t *best_chunk, uint32_t *best_lane,
              float *best_ms);

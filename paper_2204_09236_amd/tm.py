@@ -67,6 +67,20 @@ def _load():
     lib.tm_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]
     lib.tm_autotune.restype = ctypes.c_int
+    lib.tm_server_create.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.POINTER(vp)]
+    lib.tm_server_create.restype = ctypes.c_int
+    lib.tm_submit.argtypes = [vp, ctypes.c_uint64, vp, vp, vp, ctypes.c_uint64, ctypes.c_uint32,
+                              ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.tm_submit.restype = ctypes.c_int
+    lib.tm_poll.argtypes = [vp, ctypes.c_uint64, u64p, u64p]
+    lib.tm_poll.restype = ctypes.c_int
+    lib.tm_wait.argtypes = [vp, ctypes.c_uint64, u64p, u64p, ctypes.c_uint32]
+    lib.tm_wait.restype = ctypes.c_int
+    lib.tm_server_stats.argtypes = [vp, u64p]
+    lib.tm_server_stats.restype = ctypes.c_int
+    lib.tm_server_destroy.argtypes = [vp]
+    lib.tm_server_destroy.restype = None
     lib.tm_strerror.argtypes = [ctypes.c_int]
     lib.tm_strerror.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = []
@@ -287,6 +301,69 @@ def merge(raw) -> np.ndarray:
     out = np.zeros(36, dtype=np.uint64)
     _check(_lib.tm_merge(_u64(raw), _u64(out)))
     return out.reshape(6, 6)
+
+
+class Server:
+    """Request loop with continuous batching (see tm.h: tm_server_*)."""
+
+    def __init__(self, budget_bytes: int, max_inflight: int = 16, max_queue: int = 1 << 20):
+        h = ctypes.c_void_p()
+        _check(_lib.tm_server_create(int(budget_bytes), int(max_inflight), int(max_queue),
+                                     ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, delta: int, src=None, dst=None, t=None, n: int = 0, key: int = 0) -> int:
+        """Queue a request; returns its ticket.  Raises TMError (code
+        TM_EAGAIN when the queue is full)."""
+        tk = ctypes.c_uint64()
+        if src is None:
+            _check(_lib.tm_submit(self._h, int(key), None, None, None, 0, int(n), int(delta),
+                                  ctypes.byref(tk)))
+        else:
+            s = np.ascontiguousarray(src, dtype=np.int32)
+            d = np.ascontiguousarray(dst, dtype=np.int32)
+            tt = np.ascontiguousarray(t, dtype=np.int64)
+            _check(_lib.tm_submit(self._h, int(key), s.ctypes.data, d.ctypes.data, tt.ctypes.data,
+                                  s.size, int(n), int(delta), ctypes.byref(tk)))
+        return tk.value
+
+    def poll(self, ticket: int):
+        """(status, 6x6 counts or None, (submit, start, done) ns); status
+        TM_EAGAIN while pending.  A final status releases the ticket."""
+        out = np.zeros(36, dtype=np.uint64)
+        times = np.zeros(3, dtype=np.uint64)
+        rc = _lib.tm_poll(self._h, int(ticket), _u64(out), _u64(times))
+        return rc, (out.reshape(6, 6) if rc == TM_OK else None), tuple(int(x) for x in times)
+
+    def wait(self, ticket: int, timeout_ms: int = 600000):
+        out = np.zeros(36, dtype=np.uint64)
+        times = np.zeros(3, dtype=np.uint64)
+        rc = _lib.tm_wait(self._h, int(ticket), _u64(out), _u64(times), int(timeout_ms))
+        return rc, (out.reshape(6, 6) if rc == TM_OK else None), tuple(int(x) for x in times)
+
+    def stats(self) -> dict:
+        st = np.zeros(8, dtype=np.uint64)
+        _check(_lib.tm_server_stats(self._h, _u64(st)))
+        keys = ["queued", "in_flight", "resident_graphs", "resident_bytes", "in_flight_bytes",
+                "completed", "failed", "budget"]
+        return {k: int(v) for k, v in zip(keys, st)}
+
+    def close(self) -> None:
+        if self._h:
+            _lib.tm_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- kernel timing
