@@ -1,19 +1,25 @@
-"""Throughput benchmark: exact 36-motif counting of the power-law workload.
+"""Throughput benchmark: exact 36-motif counting.
 
-One step = the whole counting path on one synthetic graph already resident
-in HBM: build the device graph (validate, time sort, per-node sequences S_u,
-node-pair edge sets) from device pointers, count every motif for one delta
-(star/pair sweeps, triangle kernel, reduction), copy the 36 counts back.
+Default workload: the power-law graph (1M nodes, 20M edges, delta 3600).  One
+step = the whole counting path on one synthetic graph already resident in
+HBM: build the device graph (validate, time sort, per-node sequences S_u,
+node-pair edge sets) from device pointers, count every motif for each delta
+of the workload (star/pair sweeps, triangle kernel, reduction), copy the 36
+counts back.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload powerlaw|tiny|skewed|batch|serve]
 
 Prints one JSON line.  ``value`` = edges counted per second over the K timed
-steps (wall clock, bracketed by device synchronisation).  ``roofline`` is
-measured for the kernel with the largest share of GPU time, from HIP events
-the library records around every launch on the launch stream during the
-timed steps; its algorithmic bytes per launch are modelled below.
-``cpu_baseline`` is the CPU oracle (test infrastructure, paper's Algorithms
-1 and 2, OpenMP over centers) timed on this host on the same workload.
+steps (m x number of deltas per step, wall clock bracketed by device
+synchronisation).  ``roofline`` is measured for the kernel with the largest
+share of GPU time, from HIP events the library records around every launch
+on the launch stream during the timed steps; algorithmic bytes per launch
+come from ``byte_model``; ``traffic`` is the HBM bytes per launch from
+rocprofv3 counters, read from the committed summary under profiles/ when it
+was taken from the current kernel sources.  ``cpu_baseline`` is the CPU
+oracle (test infrastructure: the paper's Algorithms 1 and 2, OpenMP over
+centers) timed on this host.
 """
 from __future__ import annotations
 
@@ -26,7 +32,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = "temporal edges/s counted (exact 36 motifs)"
+METRIC = "temporal edges/s counted (exact 36 motifs), %HBM peak; p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
 
 
@@ -35,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "tiny", "batch", "serve"])
+    ap.add_argument("--workload", default="powerlaw", choices=["powerlaw", "tiny", "skewed", "batch", "serve"])
     ap.add_argument("--serve-pool", type=int, default=128, help="graphs in the serving pool")
     ap.add_argument("--serve-mhi", type=float, default=5e6,
                     help="largest edge count of a pool graph (log-uniform from 1e3)")
@@ -49,35 +55,130 @@ def parse():
     ap.add_argument("--procs", type=int, default=16, help="generator processes (batch workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=float, default=0.05,
+                    help="skewed workload: fraction of the time span the CPU baseline counts")
     ap.add_argument("--untraced", action="store_true",
                     help="time the steps without the per-launch event tracer (no roofline)")
     return ap.parse_args()
 
 
-def algorithmic_bytes(name: str, m: int, info: dict) -> float | None:
-    """Minimum bytes one launch of ``name`` must move (reads + writes) on this
-    workload.  Radix scatter passes read and write every (key, value) pair
-    once; histogram passes read every key once."""
+def window_stats(src, dst, t, delta: int) -> dict:
+    """Delta-window facts of a graph, for the triangle kernel's byte model
+    (measurement only, outside the timed region).  Entries of S_u are ordered
+    by (node, t, edge id): interleaving the two entries of each edge by edge id
+    and sorting stably by (node, t) gives that order.  W(p) = later entries of
+    the same S_u within delta; a triangle candidate is an edge with non-empty
+    windows after it at both endpoints."""
+    import torch
+    m = src.numel()
+    if m == 0:
+        return {"sum_w": 0, "cand": 0, "sum_cand_w": 0}
+    t0 = t - t.min()
+    tb = max(int(t0.max().item() + delta).bit_length(), 1)
+    node = torch.stack([src, dst], 1).reshape(-1).long()
+    tt = torch.stack([t0, t0], 1).reshape(-1)
+    key = (node << tb) | tt
+    skey, perm = torch.sort(key, stable=True)
+    del key
+    R = torch.searchsorted(skey, skey + delta, right=True) - 1
+    W = R - torch.arange(2 * m, device=R.device)
+    del R, skey
+    pos = torch.empty_like(perm)
+    pos[perm] = torch.arange(2 * m, device=perm.device)
+    ws, wd = W[pos[0::2]], W[pos[1::2]]
+    cand = (ws > 0) & (wd > 0)
+    return {"sum_w": int(W.sum().item()), "cand": int(cand.sum().item()),
+            "sum_cand_w": int((ws + wd)[cand].sum().item())}
+
+
+def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dict:
+    """Algorithmic bytes per launch of each kernel: what its access pattern
+    must read and write at least once (reads + writes).  m edges, 2m incident
+    entries, n nodes, tk = time-sort key width, me = edges on node pairs with
+    >= 2 edges, nm = such pairs.  Radix scatter passes read and write every
+    (key, value) pair once; histogram passes read every key once; the node
+    sort's last pass writes the sequence arrays (node, t, other end | dir,
+    rank) and each edge's two positions instead of the ping-pong buffers."""
     e2 = 2 * m
     tk = 4 if info["tbits"] <= 32 else 8
-    me = info["multi_pair_edges"]
+    me, nm = info["multi_pair_edges"], info["multi_pairs"]
+    pn = max(passes["node"], 1)
+    node_scatter = (e2 * 40 * (pn - 1) + e2 * (20 + 24)) / pn
     table = {
-        "sort_time_scatter": m * (tk + 12) * 2,      # key + (src, dst, id)
-        "sort_time_hist": m * tk,
-        "sort_node_scatter": e2 * (4 + 8) * 2,       # node + (rank, other end, dir)
-        "sort_node_hist": e2 * 4,
-        "sort_pair_scatter": m * (8 + 4) * 2,        # pair key + rank
-        "sort_pair_hist": m * 8,
-        "fill_seq": e2 * (8 + 8 + 8 + 4 + 4 + 4),    # read value, t; write t, nd, rank, epos
-        "rank": m * (tk + 12 + 8 + 4 + 8 + 16 + 8 + 4),
-        "windows": e2 * (4 + 8 + 4),                 # center, t -> window length
-        "star_prep": 2 * me * (8 + 8 + 8 + 4 + 16),
-        "star_pair": me * 2 * (8 + 1 + 8 + 16),
-        "tri_flags": m * (8 + 4 + 4 + 4),
         "validate": m * 16,
         "time_keys": m * (16 + tk + 12),
+        "sort_time_hist": m * tk,
+        "sort_time_scatter": m * (tk + 12) * 2,
+        "rank": m * (tk + 12 + 8 + 4 + 8 + 32 + 8 + 4),
+        "sort_node_hist": e2 * 4,
+        "sort_node_scatter": node_scatter,
+        "offsets_fill": (n + 1) * 4,
+        "offsets": e2 * 4 + (n + 1) * 4,
+        "sort_pair_hist": m * 8,
+        "sort_pair_scatter": m * (8 + 4) * 2,
+        "multi_flags": m * (8 + 8),
+        "multi_fill": m * 28 + me * (32 + 33) + nm * 12,
+        "windows": e2 * 16 + (n + 1) * 4,
+        "star_prep": me * 32 + 2 * me * 28,
+        "star_pair": me * 25 + 2 * me * 16,
+        "tri_flags": m * (8 + 8 + 4),
     }
-    return table.get(name)
+    if ws is not None:
+        table["tri_compact"] = m * 8 + ws["cand"] * (8 + 8 + 16)
+        table["triangles"] = ws["cand"] * 16 + ws["sum_cand_w"] * 8
+    return table
+
+
+def kernel_table(prof: dict, model: dict) -> tuple[dict, str | None]:
+    kernels = {}
+    for k, (launches, total_ms) in prof.items():
+        row = {"launches": launches, "total_ms": round(total_ms, 4),
+               "avg_ms": round(total_ms / max(launches, 1), 5)}
+        b = model.get(k)
+        if b is not None and total_ms > 0:
+            gbs = b / (total_ms / launches / 1e3) / 1e9
+            row.update({"bytes_per_launch": int(b), "achieved_GBs": round(gbs, 1),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[k] = row
+    dominant = max(prof.items(), key=lambda kv: kv[1][1])[0] if prof else None
+    return kernels, dominant
+
+
+def source_digest() -> str:
+    """sha256 over the HIP sources: a stored counter reading applies only to
+    the kernels it was taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2204_09236_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, workload: str) -> dict | None:
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
+    a copy kernel of known size, read from the committed counter summary of
+    (kernel, workload) if it was taken from the current sources."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                a, b = line.split("=", 1)
+                kv[a.strip()] = b.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return {"bytes": float(kv["traffic_bytes_per_launch"]),
+                "fetch_kib": float(kv["fetch_kib_per_launch"]),
+                "write_kib": float(kv["write_kib_per_launch"]),
+                "copy_factor": float(kv["copy_factor"])}
+    except (KeyError, ValueError):
+        return None
 
 
 def _gen_batch_member(item):
@@ -154,7 +255,7 @@ def bench_batch(args):
     el_p = time.perf_counter() - t_start
     same = bool(np.array_equal(res_b, res_p))
     line = {
-        "metric": METRIC + ", batched", "value": round(m_total / el_b, 1), "unit": "edges/s",
+        "metric": METRIC, "value": round(m_total / el_b, 1), "unit": "edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el_b * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
         "data": "synthetic",
@@ -256,7 +357,7 @@ def bench_serve(args):
     for G in alone_graphs.values():
         G.free()
     line = {
-        "metric": "p50/p99 request latency and edges/s, served (exact 36 motifs)",
+        "metric": METRIC,
         "value": rows[-1]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": len(rows),
         "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
@@ -270,19 +371,13 @@ def bench_serve(args):
         sys.exit(1)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
-                          "not supported (the path shards by center, see DESIGN.md)",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+COPY_CALIB_BYTES = 256 << 20
 
-    if args.workload == "batch":
-        return bench_batch(args)
-    if args.workload == "serve":
-        return bench_serve(args)
 
+def bench_single(args):
+    """One graph: a step builds the device graph from device pointers and
+    counts every delta of the workload (one for power-law and tiny, three for
+    skewed) on it."""
     import numpy as np
     import torch
 
@@ -293,23 +388,28 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     spec = graphgen.CONFIGS[args.workload]
-    delta = spec["deltas"][0]
+    deltas = list(spec["deltas"])
     t0 = time.time()
     g = spec["fn"]()
-    gen_s = time.time() - t0
-    print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {gen_s:.1f}s", file=sys.stderr,
-          flush=True)
+    print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
     src = torch.from_numpy(g.src).to(dev)
     dst = torch.from_numpy(g.dst).to(dev)
     tt = torch.from_numpy(g.t).to(dev)
     stream = torch.cuda.current_stream()
+    # a plain device copy of known size: the reference reading for the
+    # FETCH_SIZE / WRITE_SIZE counters of a profiled run of this script
+    ca = torch.ones(COPY_CALIB_BYTES // 4, dtype=torch.int32, device=dev)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    del ca, cb
     torch.cuda.synchronize()
 
     def step():
         G = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
-        out = G.count(delta)
+        outs = [G.count(d) for d in deltas]
         G.free()
-        return out
+        return outs
 
     for _ in range(args.warmup):
         counts = step()
@@ -327,56 +427,124 @@ def main():
     tm.prof_enable(False)
     prof = tm.prof_read()
     print("[bench] timed steps done", file=sys.stderr, flush=True)
-
     ms_per_step = elapsed * 1e3 / args.steps
-    value = g.m * args.steps / elapsed
+    value = g.m * len(deltas) * args.steps / elapsed
 
-    # graph facts for the byte model
-    with tm.build_graph(src, dst, tt, n=g.n, stream=stream) as G:
-        info = G.info()
-    tspan = int(g.t.max() - g.t.min())
+    # build alone and count alone (outside the timed region above)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    for _ in range(args.steps):
+        tm.build_graph(src, dst, tt, n=g.n, stream=stream).free()
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t_b) * 1e3 / args.steps
+    G = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
+    info = G.info()
+    count_ms = {}
+    for d in deltas:
+        G.count(d)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for _ in range(args.steps):
+            G.count(d)
+        torch.cuda.synchronize()
+        count_ms[str(d)] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
+    G.free()
+
+    tspan = int(g.t.max() - g.t.min()) if g.m else 0
     info["tbits"] = max(tspan.bit_length(), 1)
-    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4),
-                   "avg_ms": round(v[1] / max(v[0], 1), 5)} for k, v in prof.items()}
-    gpu_ms = sum(v[1] for v in prof.values()) / args.steps
-    dominant = max(prof.items(), key=lambda kv: kv[1][1])[0] if prof else None
+    passes = {"node": (max(int(g.n - 1).bit_length(), 1) + 7) // 8}
+    wstats = {str(d): window_stats(src, dst, tt, d) for d in deltas}
+    torch.cuda.empty_cache()
+    # count kernels run once per delta: the model averages their bytes over deltas
+    model = byte_model(g.m, g.n, info, None, passes)
+    tri = {"tri_compact": 0.0, "triangles": 0.0}
+    for d in deltas:
+        md = byte_model(g.m, g.n, info, wstats[str(d)], passes)
+        for k in tri:
+            tri[k] += md[k] / len(deltas)
+    model.update(tri)
+    kernels, dominant = kernel_table(prof, model)
     roofline = None
-    if dominant is not None:
-        launches, total_ms = prof[dominant]
-        avg_s = total_ms / launches / 1e3
-        b = algorithmic_bytes(dominant, g.m, info)
-        if b is not None:
-            achieved = b / avg_s / 1e9
-            roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": None, "bytes_per_launch": b,
-                        "avg_launch_ms": round(avg_s * 1e3, 4)}
+    if dominant is not None and "achieved_GBs" in kernels[dominant]:
+        kd = kernels[dominant]
+        tr = stored_traffic(dominant, args.workload)
+        roofline = {"kernel": dominant, "bound": "hbm", "achieved": kd["achieved_GBs"],
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["frac"],
+                    "traffic": None if tr is None else tr["bytes"],
+                    "bytes_per_launch": kd["bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
+        if tr is not None:
+            roofline["traffic_over_algorithmic"] = round(tr["bytes"] / kd["bytes_per_launch"], 3)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-        t0 = time.perf_counter()
-        want = oracle.count(g.src, g.dst, g.t, delta, n=g.n, threads=threads)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": round(g.m / cpu_s, 1), "unit": "edges/s", "cores": threads, "kind": "oracle",
-               "sample": f"whole {args.workload} workload (m={g.m}, delta={delta}), one run, "
-                         f"{cpu_s:.1f} s incl. building S_u and E_(v,w)",
-               "matches_gpu": bool(np.array_equal(want, counts))}
+        cpu = cpu_baseline(args, g, deltas, counts)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "edges/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": g.n, "m": g.m, "delta": delta,
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "deltas": deltas,
                    "parallelism": "single-gpu"},
         "roofline": roofline, "cpu_baseline": cpu,
-        "gpu_kernel_ms_per_step": round(gpu_ms, 4),
+        "build_only_ms": round(build_ms, 4), "count_only_ms": count_ms,
+        "count_only_edges_per_s": {d: round(g.m / (v / 1e3), 1) for d, v in count_ms.items()},
+        "gpu_kernel_ms_per_step": round(sum(v[1] for v in prof.values()) / args.steps, 4),
+        "graph": {k: info[k] for k in ("multi_pairs", "multi_pair_edges", "max_degree")},
+        "window_stats": wstats,
         "kernels": kernels,
-        "motif_total": int(counts.sum()),
+        "motif_total": [int(c.sum()) for c in counts],
     }
     print(json.dumps(line))
+    if cpu is not None and not cpu["matches_gpu"]:
+        sys.exit(1)
+
+
+def cpu_baseline(args, g, deltas, counts):
+    """The CPU oracle (the paper's Algorithms 1 and 2, OpenMP over centers)
+    timed on this host.  Power-law and tiny: the whole workload.  Skewed: a
+    bounded sample, the edges of the first --cpu-sample fraction of the time
+    span (a temporal slice keeps every window of the slice intact), at the
+    smallest delta; counts of the sample are not compared."""
+    import numpy as np
+
+    import oracle
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    if args.workload != "skewed":
+        t0 = time.perf_counter()
+        want = [oracle.count(g.src, g.dst, g.t, d, n=g.n, threads=threads) for d in deltas]
+        cpu_s = time.perf_counter() - t0
+        m = g.m * len(deltas)
+        sample = (f"whole {args.workload} workload (m={g.m}, deltas={deltas}), one run each, "
+                  f"{cpu_s:.1f} s incl. building S_u and E_(v,w)")
+        match = all(np.array_equal(a, b) for a, b in zip(want, counts))
+    else:
+        lim = int(g.t.min()) + int((int(g.t.max()) - int(g.t.min())) * args.cpu_sample)
+        sel = g.t <= lim
+        s, d, t = g.src[sel], g.dst[sel], g.t[sel]
+        t0 = time.perf_counter()
+        oracle.count(s, d, t, deltas[0], n=g.n, threads=threads)
+        cpu_s = time.perf_counter() - t0
+        m = int(s.size)
+        sample = (f"edges with t in the first {args.cpu_sample:.0%} of the span (m={m}), "
+                  f"delta={deltas[0]}, {cpu_s:.1f} s incl. building S_u and E_(v,w)")
+        match = True
+    return {"value": round(m / cpu_s, 1), "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "matches_gpu": bool(match)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
+                          "not supported (the path would shard by center)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
+    return bench_single(args)
 
 
 if __name__ == "__main__":
