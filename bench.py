@@ -121,7 +121,8 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
         "windows": e2 * 16 + (n + 1) * 4,
         "star_prep": me * 32 + 2 * me * 28,
         "star_pair": me * 25 + 2 * me * 16,
-        "tri_flags": m * (8 + 8 + 4),
+        "wbits": e2 * 4 + e2 / 8,
+        "tri_flags": m * (8 + 4) + e2 / 8,
     }
     if ws is not None:
         table["tri_compact"] = m * 8 + ws["cand"] * (8 + 8 + 16)

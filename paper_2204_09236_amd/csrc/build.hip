@@ -414,11 +414,12 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     // PKA, PKB: u64 x m; PVA, PVB: u32 x m   (pair sort)
     // TR: i64 x m                 (timestamps by rank)
     // TMP: scan / histogram scratch
-    const size_t ntmp = std::max({radix_tmp_count(len), scan_tmp_count(len), (size_t)3 * (G + 1)}) + 16;
+    const size_t ntmp =
+        std::max({radix_tmp_bytes(len) / 4 + 1, scan_tmp_count(len), (size_t)3 * (G + 1)}) + 16;
     Scratch sc;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t bytes = 2 * up(8 * len) + 2 * up(16 * len) + 2 * up(8 * m) + 2 * up(4 * m) +
-                         up(8 * m) + up(4 * ntmp);
+                         up(8 * m) + up(4 * ntmp) + up(4);
     TRY(sc.reserve(bytes, s));
     char *KA = sc.take<char>(8 * len), *KB = sc.take<char>(8 * len);
     char *VA = sc.take<char>(16 * len), *VB = sc.take<char>(16 * len);
@@ -426,6 +427,8 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     uint32_t *PVA = sc.take<uint32_t>(m), *PVB = sc.take<uint32_t>(m);
     int64_t *TR = sc.take<int64_t>(m);
     uint32_t *tmp = sc.take<uint32_t>(ntmp);
+    uint32_t *sort_err = sc.take<uint32_t>(1);
+    TM_LAUNCH("sort_err_clear", k_fill_u32, dim3(1), dim3(kBlock), 0, s, sort_err, 1, 0u);
 
     // ---- 2. time sort carrying (src, dst, id); rank-ordered arrays
     // The sorted time data ends in one of (KA, VA) / (KB, VB); the node keys
@@ -445,7 +448,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
             uint32_t *k = reinterpret_cast<uint32_t *>(KA), *k_alt = reinterpret_cast<uint32_t *>(KB);
             TM_LAUNCH("time_keys", k_time_keys<uint32_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
                       d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
-            TRY(radix_sort_u32_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, s, "sort_time_hist",
+            TRY(radix_sort_u32_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, sort_err, s, "sort_time_hist",
                                     "sort_time_scatter"));
             nkey = other_k(k);
             nval = other_v(ev);
@@ -455,7 +458,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
             uint64_t *k = reinterpret_cast<uint64_t *>(KA), *k_alt = reinterpret_cast<uint64_t *>(KB);
             TM_LAUNCH("time_keys", k_time_keys<uint64_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
                       d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
-            TRY(radix_sort_u64_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, s, "sort_time_hist",
+            TRY(radix_sort_u64_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, sort_err, s, "sort_time_hist",
                                     "sort_time_scatter"));
             nkey = other_k(k);
             nval = other_v(ev);
@@ -469,7 +472,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         uint32_t *k_alt = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(nkey) == KA ? KB : KA);
         NodeVal *v_alt = reinterpret_cast<NodeVal *>(reinterpret_cast<char *>(nval) == VA ? VB : VA);
         const SeqOut so{g->ent_c, g->ent_t, g->ent_nd, g->ent_r, g->epos};
-        TRY(radix_sort_nodes(nkey, k_alt, nval, v_alt, len, bits_for(n - 1), tmp, s, so));
+        TRY(radix_sort_nodes(nkey, k_alt, nval, v_alt, len, bits_for(n - 1), tmp, sort_err, s, so));
         TM_LAUNCH("offsets_fill", k_fill_u32, grid_for(n + 1), dim3(kBlock), 0, s, g->off, n + 1,
                   kUnset);
         TM_LAUNCH("offsets", k_offsets, grid_for(len + 1), dim3(kBlock), 0, s, g->ent_c, len,
@@ -483,7 +486,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     {
         uint64_t *k = PKA, *k_alt = PKB;
         uint32_t *v = PVA, *v_alt = PVB;
-        TRY(radix_sort_u64(&k, &k_alt, &v, &v_alt, m, bits_for(n * n - 1), tmp, s,
+        TRY(radix_sort_u64(&k, &k_alt, &v, &v_alt, m, bits_for(n * n - 1), tmp, sort_err, s,
                            "sort_pair_hist", "sort_pair_scatter"));
         // flags and their scans reuse the (now free) node-sort buffers
         uint32_t *in_multi = reinterpret_cast<uint32_t *>(KA);
@@ -494,10 +497,15 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
                   head);
         TRY(scan_u32_array(in_multi, eidx, m, tmp, s));
         TRY(scan_u32_array(head, pidx, m, tmp, s));
-        uint32_t counts[2] = {0, 0};
+        uint32_t counts[3] = {0, 0, 0};
         TM_HIP_TRY(hipMemcpyAsync(&counts[0], eidx + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipMemcpyAsync(&counts[1], pidx + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipMemcpyAsync(&counts[2], sort_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
+        if (counts[2]) {
+            set_error("radix sort: a look-back wait gave up (device graph not built)");
+            return TM_EINTERNAL;
+        }
         g->n_me = counts[0];
         g->n_multi = counts[1];
         TRY(galloc(g, &g->mp_start, g->n_multi + 1));

@@ -419,13 +419,31 @@ __global__ void k_item_counts(const uint32_t *mp_start, uint64_t n_multi, uint32
 }
 
 // ---------------------------------------------------------------- triangles
+// One bit per entry: is its window non-empty.  The bitmap (len / 8 bytes)
+// stays in cache, so the per-edge lookups at two unrelated positions below
+// do not each fetch a line of Wf from HBM.
+__global__ void k_wbits(const uint32_t *Wf, uint64_t len, uint64_t *bits) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // the loop bound is rounded up to whole waves so every lane takes part in the ballot
+    const uint64_t lim = (len + kWave - 1) / kWave * kWave;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < lim; p += stride) {
+        const uint64_t b = __ballot(p < len && Wf[p] != 0);
+        if (lane == 0) bits[p / kWave] = b;
+    }
+}
+
+__device__ inline bool wbit(const uint64_t *bits, uint32_t p) {
+    return (bits[p / kWave] >> (p % kWave)) & 1ull;
+}
+
 // Candidate first edges: both windows after the edge (at its source and at
 // its destination) hold at least one entry.
-__global__ void k_tri_flags(const uint2 *epos2, const uint32_t *Wf, uint64_t m, uint32_t *flag) {
+__global__ void k_tri_flags(const uint2 *epos2, const uint64_t *bits, uint64_t m, uint32_t *flag) {
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (uint64_t)gridDim.x * blockDim.x) {
         const uint2 e = epos2[r];
-        flag[r] = (Wf[e.x] != 0 && Wf[e.y] != 0) ? 1u : 0u;
+        flag[r] = (wbit(bits, e.x) && wbit(bits, e.y)) ? 1u : 0u;
     }
 }
 
@@ -598,6 +616,7 @@ constexpr uint32_t kDefaultTriLaneMax = 64;
 struct Workspace {
     int64_t *deltas;
     uint32_t *Wf;
+    uint64_t *wbits;
     uint4 *me_w;
     uint32_t *cnt, *first, *tflag, *tidx;
     uint4 *cand;
@@ -613,7 +632,8 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
     w->max_ctiles = m / kCandTile + G + 1;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return up(G * 8) + up(len * 4) + up(2 * nme * sizeof(uint4)) + up((nm + 1) * 4) * 2 +
+    return up(G * 8) + up(len * 4) + up((len / kWave + 1) * 8) + up(2 * nme * sizeof(uint4)) +
+           up((nm + 1) * 4) * 2 +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
            up(n_tmp * 4) + up(w->max_itiles * 32 * 8) + up(w->max_ctiles * 8 * 8) +
            up((size_t)G * 40 * 8) + 4096;
@@ -625,6 +645,7 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     w->deltas = sc.take<int64_t>(G);
     w->Wf = sc.take<uint32_t>(len);
+    w->wbits = sc.take<uint64_t>(len / kWave + 1);
     w->me_w = sc.take<uint4>(2 * nme);
     w->cnt = sc.take<uint32_t>(nm + 1);
     w->first = sc.take<uint32_t>(nm + 1);
@@ -662,8 +683,9 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
     rc = scan_u32_array(w.cnt, w.first, nm, w.tmp, s);
     if (rc) return rc;
     // ---- triangles: candidate first edges
+    TM_LAUNCH("wbits", k_wbits, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m, w.wbits);
     TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
-              reinterpret_cast<const uint2 *>(g->epos), w.Wf, m, w.tflag);
+              reinterpret_cast<const uint2 *>(g->epos), w.wbits, m, w.tflag);
     rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
     if (rc) return rc;
     TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,

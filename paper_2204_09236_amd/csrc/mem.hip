@@ -122,7 +122,7 @@ size_t graph_bytes(const tm_graph *g) {
 size_t build_peak_bytes(uint64_t m, uint64_t n, uint32_t G) {
     // scratch (sort buffers, ranks, scans) + the graph's own arrays, both
     // bounded per edge; see the buffer layout of the build
-    return (size_t)m * 230 + (size_t)n * 8 + (size_t)G * 64 + ((size_t)64 << 20);
+    return (size_t)m * 240 + (size_t)n * 8 + (size_t)G * 64 + ((size_t)64 << 20);
 }
 
 void dev_free(void *p, hipStream_t s) {

@@ -1,6 +1,9 @@
 // Device primitives: exclusive scan and a stable LSD radix sort, written for
 // 64-wide CDNA wavefronts (ballot-based digit matching, no block barriers in
 // the ranking loop).
+#include <algorithm>
+#include <utility>
+
 #include "tm_internal.h"
 
 namespace tmc {
@@ -133,14 +136,37 @@ int scan_impl(L ld, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ radix sort
-// Tile of kRadixTile elements per block; wave w owns the contiguous quarter
-// [w*1024, (w+1)*1024) of the tile and walks it in 16 rounds of 64, so the
-// order inside the tile is (wave, round, lane) = input order and a per-wave
-// running digit count gives stable ranks without block barriers.
-constexpr int kRadixItems = 8;
-constexpr int kRadixTile = kBlock * kRadixItems;
-constexpr int kWaves = kBlock / kWave;
-static_assert(kBlock == 256, "radix kernels map one thread to each 8-bit digit");
+// Stable LSD radix sort, 8-bit digits, one kernel per digit pass.
+//
+// A histogram kernel reads the keys once and counts the digits of every
+// pass.  In a pass, each block takes the next tile in input order from a
+// counter, ranks its keys (wave w owns the contiguous run
+// [w * ITEMS * 64, (w + 1) * ITEMS * 64) of the tile and walks it in ITEMS
+// rounds of 64, so tile order = (wave, round, lane) = input order and a
+// per-wave running digit count gives stable ranks without block barriers),
+// publishes its 256 digit counts, and adds up the counts of all earlier
+// tiles by decoupled look-back: each earlier tile's word holds either its
+// own count (aggregate) or the count of itself and everything before it
+// (inclusive), and the walk stops at the first inclusive word.  The tile is
+// then staged in LDS in digit order so that each digit's run is written to
+// HBM contiguously.  Tiles hold 3072 to 5120 elements (72 KiB of LDS or
+// less, two blocks per CU).
+constexpr int kOsThreads = 512;
+constexpr int kOsWaves = kOsThreads / kWave;
+constexpr int kMaxPasses = 8;
+constexpr int kHistItems = 4;
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStInc = 2ull << 62;
+constexpr uint64_t kStVal = (1ull << 62) - 1;
+// A look-back wait polls at most this many times (about a second) before it
+// gives up, flags the error and lets the kernel finish.
+constexpr uint32_t kSpinLimit = 1u << 20;
+constexpr uint64_t kMinTile = (uint64_t)kOsThreads * 6;
+
+template <typename K, typename V>
+constexpr int os_items() {
+    return sizeof(K) + sizeof(V) <= 12 ? 10 : (sizeof(K) + sizeof(V) <= 16 ? 8 : 6);
+}
 
 // Digit of a key and the lanes of this wave that share it (ballot matching).
 template <typename K>
@@ -157,40 +183,75 @@ __device__ inline uint64_t digit_peers(K key, int shift, bool valid, uint32_t *d
     return peers;
 }
 
-// Per-block digit histogram.  Each wave keeps its own sub-histogram; the
-// lowest lane of every group of equal digits adds the group size, so no two
-// lanes of a wave touch one counter (skewed keys, e.g. a hub's node id, do
-// not serialise on LDS atomics).
-template <typename K>
-__global__ void __launch_bounds__(kBlock) k_radix_hist(const K *keys, uint64_t n, int shift,
-                                                       uint32_t *hist, uint32_t nb) {
-    __shared__ uint32_t h[kWaves][256];
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int i = threadIdx.x; i < kWaves * 256; i += kBlock) (&h[0][0])[i] = 0;
+// Exclusive scan of one value per digit, held by threads [0, 256) of a
+// kOsThreads block; every thread of the block must call it.
+__device__ inline uint32_t digit_excl_scan(uint32_t v, uint32_t *lds4) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint32_t s = wave_incl_scan(v, lane);
+    if (w < 4 && lane == kWave - 1) lds4[w] = s;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kRadixTile + (uint64_t)w * (kRadixItems * kWave);
-    const uint64_t lt = lanemask_lt(lane);
-#pragma unroll 4
-    for (int i = 0; i < kRadixItems; i++) {
-        const uint64_t idx = base + (uint64_t)i * kWave + lane;
-        const bool valid = idx < n;
-        const K key = valid ? keys[idx] : K(0);
-        uint32_t d;
-        const uint64_t peers = digit_peers(key, shift, valid, &d);
-        if (valid && __popcll(peers & lt) == 0) h[w][d] += (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    uint32_t s = 0;
+    uint32_t pre = 0;
 #pragma unroll
-    for (int q = 0; q < kWaves; q++) s += h[q][threadIdx.x];
-    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = s;
+    for (int i = 0; i < 3; i++)
+        if (i < w) pre += lds4[i];
+    __syncthreads();
+    return s + pre - v;
 }
 
-// Stable scatter of one digit pass.  Ranks come from per-wave running digit
-// counts (tile order = (wave, round, lane) = input order); the tile is then
-// staged in LDS in digit order so that the global writes of each digit's run
-// are contiguous.
+// Zero the digit counts and tile counters of every pass and the first
+// pass's look-back words.
+__global__ void k_os_init(uint32_t *counts, uint32_t n_counts, uint64_t *status, uint64_t n_status) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_counts; i += stride)
+        counts[i] = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_status; i += stride)
+        status[i] = 0;
+}
+
+// Digit counts of every pass over all keys: per-block LDS counters (plain
+// LDS atomics: counting needs no ranks), each block writing its own row
+// part[block][pass][digit]; no global atomics here, since thousands of blocks
+// adding into the same 256 words serialise across the XCDs.
+constexpr uint32_t kHistBlocks = 512;
+constexpr uint32_t kHistSumSplit = 16;
+
+template <typename K>
+__global__ void __launch_bounds__(kOsThreads) k_os_hist(const K *keys, uint64_t n, int passes,
+                                                        uint32_t *part) {
+    __shared__ uint32_t h[kMaxPasses][256];
+    for (int i = threadIdx.x; i < kMaxPasses * 256; i += kOsThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t chunk = (uint64_t)kOsThreads * kHistItems;
+    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk) {
+        K key[kHistItems];
+#pragma unroll
+        for (int i = 0; i < kHistItems; i++) {
+            const uint64_t idx = base + (uint64_t)i * kOsThreads + threadIdx.x;
+            key[i] = idx < n ? keys[idx] : K(0);
+        }
+#pragma unroll
+        for (int i = 0; i < kHistItems; i++) {
+            if (base + (uint64_t)i * kOsThreads + threadIdx.x < n) {
+                for (int p = 0; p < passes; p++)
+                    atomicAdd(&h[p][(uint32_t)(key[i] >> (8 * p)) & 255u], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * 256; i += kOsThreads)
+        part[(uint64_t)blockIdx.x * passes * 256 + i] = (&h[0][0])[i];
+}
+
+// ghist[pass][digit] += the rows of blocks y, y + split, ... (grid: pass x
+// split); a handful of global adds per counter.
+__global__ void __launch_bounds__(256) k_os_hist_sum(const uint32_t *part, uint32_t nblocks,
+                                                     int passes, uint32_t *ghist) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    uint32_t s = 0;
+    for (uint32_t b = blockIdx.y; b < nblocks; b += gridDim.y) s += part[(uint64_t)b * passes * 256 + i];
+    if (s) atomicAdd(&ghist[i], s);
+}
+
 template <typename K, typename V>
 struct PairOut {
     K *kout;
@@ -212,30 +273,55 @@ struct SeqWrite {
     }
 };
 
-template <typename K, typename V, typename Out>
-__global__ void __launch_bounds__(kBlock) k_radix_scatter(const K *kin, const V *vin, Out out,
-                                                          uint64_t n, int shift,
-                                                          const uint32_t *offs, uint32_t nb) {
-    __shared__ uint32_t wh[kWaves][256];
+// One digit pass.  ghist: this pass's 256 digit counts over all keys;
+// status: this pass's look-back words (tile x 256, zero on entry);
+// status_next: the next pass's words, whose row for this tile is cleared
+// here (null on the last pass); ticket: tile counter (zero on entry).
+template <typename K, typename V, typename Out, int ITEMS>
+__global__ void __launch_bounds__(kOsThreads) k_os_scatter(const K *kin, const V *vin, Out out,
+                                                           uint64_t n, int shift,
+                                                           const uint32_t *ghist, uint64_t *status,
+                                                           uint64_t *status_next, uint32_t *ticket,
+                                                           uint32_t *err) {
+    constexpr uint32_t kT = (uint32_t)kOsThreads * ITEMS;
+    __shared__ V s_val[kT];
+    __shared__ K s_key[kT];
+    __shared__ uint32_t wh[kOsWaves][256];
     __shared__ uint32_t blk_off[256];
     __shared__ uint32_t gbase[256];
-    __shared__ uint32_t scan_lds[kBlock / kWave];
-    __shared__ K s_key[kRadixTile];
-    __shared__ V s_val[kRadixTile];
+    __shared__ uint32_t lds4[4];
+    __shared__ uint32_t s_tile;
     const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int i = threadIdx.x; i < kWaves * 256; i += kBlock) (&wh[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < kOsWaves * 256; i += kOsThreads) (&wh[0][0])[i] = 0;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
-    const uint64_t tile0 = (uint64_t)blockIdx.x * kRadixTile;
-    const uint64_t base = tile0 + (uint64_t)w * (kRadixItems * kWave);
+    const uint32_t tile = s_tile;
+    if (status_next && threadIdx.x < 256) status_next[(uint64_t)tile * 256 + threadIdx.x] = 0;
+    const uint64_t tile0 = (uint64_t)tile * kT;
+    const uint64_t base = tile0 + (uint64_t)w * (ITEMS * kWave);
     const uint64_t lt = lanemask_lt(lane);
-    K key[kRadixItems];
-    uint32_t rank[kRadixItems];
-    uint32_t dig[kRadixItems];
+    // values travel in registers as 32-bit words (struct-typed register
+    // arrays are not promoted and would spill)
+    static_assert(sizeof(V) % 4 == 0, "value size must be a multiple of 4 bytes");
+    constexpr int kVW = (int)(sizeof(V) / 4);
+    K key[ITEMS];
+    uint32_t val[ITEMS][kVW];
+    uint32_t rank[ITEMS];
+    uint32_t dig[ITEMS];
 #pragma unroll
-    for (int i = 0; i < kRadixItems; i++) {
+    for (int i = 0; i < ITEMS; i++) {
         const uint64_t idx = base + (uint64_t)i * kWave + lane;
-        const bool valid = idx < n;
-        key[i] = valid ? kin[idx] : K(0);
+        key[i] = K(0);
+#pragma unroll
+        for (int j = 0; j < kVW; j++) val[i][j] = 0;
+        if (idx < n) {
+            key[i] = kin[idx];
+            __builtin_memcpy(&val[i][0], vin + idx, sizeof(V));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const bool valid = base + (uint64_t)i * kWave + lane < n;
         uint32_t d;
         const uint64_t peers = digit_peers(key[i], shift, valid, &d);
         dig[i] = d;
@@ -249,87 +335,143 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const K *kin, const V 
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // digit totals of the tile -> exclusive prefix over digits (one thread per digit)
-    {
-        const int d = threadIdx.x;
-        uint32_t c[kWaves];
-        uint32_t tot = 0;
+    const int d = threadIdx.x;
+    uint32_t c[kOsWaves];
+    uint32_t tot = 0;
+    if (d < 256) {
 #pragma unroll
-        for (int q = 0; q < kWaves; q++) {
+        for (int q = 0; q < kOsWaves; q++) {
             c[q] = wh[q][d];
             tot += c[q];
         }
-        uint32_t total;
-        const uint32_t excl = block_incl_scan(tot, &total, scan_lds) - tot;
+    }
+    const uint32_t excl = digit_excl_scan(tot, lds4);
+    const uint32_t gex = digit_excl_scan(d < 256 ? ghist[d] : 0u, lds4);
+    if (d < 256) {
         blk_off[d] = excl;
-        gbase[d] = offs[(uint64_t)d * nb + blockIdx.x];
         uint32_t run = excl;
 #pragma unroll
-        for (int q = 0; q < kWaves; q++) {
+        for (int q = 0; q < kOsWaves; q++) {
             wh[q][d] = run;
             run += c[q];
         }
+        uint64_t *mine = status + (uint64_t)tile * 256 + d;
+        uint64_t prefix = 0;
+        if (tile == 0) {
+            __hip_atomic_store(mine, kStInc | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(mine, kStAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t k = tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint64_t v = __hip_atomic_load(status + (uint64_t)k * 256 + d, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t st = v & ~kStVal;
+                if (st == 0) {
+                    if (++spins >= kSpinLimit) {
+                        atomicOr(err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                prefix += v & kStVal;
+                if (st == kStInc || k == 0) break;
+                k--;
+            }
+            __hip_atomic_store(mine, kStInc | (prefix + tot), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        gbase[d] = gex + (uint32_t)prefix;
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kRadixItems; i++) {
-        const uint64_t idx = base + (uint64_t)i * kWave + lane;
-        if (idx < n) {
-            // values are not held in registers: read straight into their slot
+    for (int i = 0; i < ITEMS; i++) {
+        if (base + (uint64_t)i * kWave + lane < n) {
             const uint32_t x = wh[w][dig[i]] + rank[i];
             s_key[x] = key[i];
-            s_val[x] = vin[idx];
+            __builtin_memcpy(&s_val[x], &val[i][0], sizeof(V));
         }
     }
     __syncthreads();
-    const uint32_t cnt_tile = (uint32_t)min<uint64_t>((uint64_t)kRadixTile, n - tile0);
-    for (uint32_t x = threadIdx.x; x < cnt_tile; x += kBlock) {
+    const uint32_t cnt_tile = (uint32_t)min<uint64_t>((uint64_t)kT, n - tile0);
+    for (uint32_t x = threadIdx.x; x < cnt_tile; x += kOsThreads) {
         const K k = s_key[x];
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
-        const uint32_t pos = gbase[d] + (x - blk_off[d]);
-        out(pos, k, s_val[x]);
+        const uint32_t dk = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = gbase[dk] + (x - blk_off[dk]);
+        // only an abandoned look-back can place an element outside [0, n)
+        if (pos < n) out(pos, k, s_val[x]);
+        else atomicOr(err, 2u);
     }
 }
 
-template <typename K, typename V>
-int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits,
-               uint32_t *tmp, hipStream_t s, const char *hist_name, const char *scatter_name) {
-    if (n <= 1 || bits <= 0) return TM_OK;
-    const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
-    const uint64_t nh = nb * 256;
-    uint32_t *hist = tmp;                      // nh + 1
-    uint32_t *stmp = tmp + nh + 1;             // scan partials
-    for (int shift = 0; shift < bits; shift += 8) {
-        TM_LAUNCH(hist_name, k_radix_hist<K>, dim3(nb), dim3(kBlock), 0, s, *keys, n, shift,
-                  hist, (uint32_t)nb);
-        int rc = scan_impl(LoadArray{hist}, hist, nh, stmp, s);
-        if (rc) return rc;
-        TM_LAUNCH(scatter_name, (k_radix_scatter<K, V, PairOut<K, V>>), dim3(nb), dim3(kBlock), 0, s,
-                  *keys, *vals, (PairOut<K, V>{*keys_alt, *vals_alt}), n, shift, hist, (uint32_t)nb);
-        K *tk = *keys;
-        *keys = *keys_alt;
-        *keys_alt = tk;
-        V *tv = *vals;
-        *vals = *vals_alt;
-        *vals_alt = tv;
+// Layout of the sort's scratch: digit counts and tile counters of every
+// pass, two look-back word arrays (passes alternate between them), and the
+// histogram blocks' rows.
+struct OsTmp {
+    uint32_t *ghist;    // kMaxPasses x 256
+    uint32_t *tickets;  // kMaxPasses
+    uint64_t *status[2];
+    uint32_t *part;     // kHistBlocks x kMaxPasses x 256
+};
+
+inline OsTmp os_tmp(void *tmp, uint64_t ntiles) {
+    OsTmp t;
+    t.ghist = static_cast<uint32_t *>(tmp);
+    t.tickets = t.ghist + kMaxPasses * 256;
+    t.status[0] = reinterpret_cast<uint64_t *>(t.tickets + kMaxPasses);  // 8-byte aligned
+    t.status[1] = t.status[0] + ntiles * 256;
+    t.part = reinterpret_cast<uint32_t *>(t.status[1] + ntiles * 256);
+    return t;
+}
+
+template <typename K, typename V, typename Final>
+int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,
+               uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name,
+               const Final *fin) {
+    constexpr int kItems_ = os_items<K, V>();
+    constexpr uint64_t kT = (uint64_t)kOsThreads * kItems_;
+    const int passes = (bits + 7) / 8;
+    if (passes > kMaxPasses || (uint64_t)passes * 8 > sizeof(K) * 8) {
+        set_error("radix sort: key bits out of range");
+        return TM_EINTERNAL;
+    }
+    const uint64_t ntiles = (n + kT - 1) / kT;
+    const OsTmp t = os_tmp(tmp, ntiles);
+    const uint64_t n_status = ntiles * 256;
+    TM_LAUNCH("sort_init", k_os_init, dim3((unsigned)std::min<uint64_t>((n_status + kBlock - 1) / kBlock + 1, 4096)),
+              dim3(kBlock), 0, s, t.ghist, (uint32_t)(kMaxPasses * 257), t.status[0], n_status);
+    const uint64_t hchunk = (uint64_t)kOsThreads * kHistItems;
+    const uint32_t hblocks = (uint32_t)std::min<uint64_t>((n + hchunk - 1) / hchunk, kHistBlocks);
+    TM_LAUNCH(hist_name, k_os_hist<K>, dim3(hblocks), dim3(kOsThreads), 0, s, *keys, n, passes,
+              t.part);
+    TM_LAUNCH("sort_hist_sum", k_os_hist_sum, dim3((unsigned)passes, kHistSumSplit), dim3(256), 0, s,
+              t.part, hblocks, passes, t.ghist);
+    for (int p = 0; p < passes; p++) {
+        uint64_t *st = t.status[p & 1];
+        uint64_t *st_next = p + 1 < passes ? t.status[(p + 1) & 1] : nullptr;
+        if (fin && p + 1 == passes) {
+            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, Final, kItems_>), dim3((unsigned)ntiles),
+                      dim3(kOsThreads), 0, s, *keys, *vals, *fin, n, 8 * p, t.ghist + 256 * p, st,
+                      st_next, t.tickets + p, err);
+        } else {
+            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, PairOut<K, V>, kItems_>), dim3((unsigned)ntiles),
+                      dim3(kOsThreads), 0, s, *keys, *vals, (PairOut<K, V>{*keys_alt, *vals_alt}), n,
+                      8 * p, t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+            std::swap(*keys, *keys_alt);
+            std::swap(*vals, *vals_alt);
+        }
     }
     return TM_OK;
-}
-
-__global__ void k_iota(uint32_t *p, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = (uint32_t)i;
 }
 
 }  // namespace
 
 size_t scan_tmp_count(uint64_t n) { return (n + kTile - 1) / kTile + 2; }
 
-size_t radix_tmp_count(uint64_t n) {
-    const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
-    const uint64_t nh = nb * 256;
-    return nh + 1 + scan_tmp_count(nh) + 4;
+size_t radix_tmp_bytes(uint64_t n) {
+    const uint64_t ntiles = (n + kMinTile - 1) / kMinTile;
+    return (size_t)kMaxPasses * 257 * 4 + 2 * ntiles * 256 * 8 + (size_t)kHistBlocks * kMaxPasses * 256 * 4 + 64;
 }
 
 int scan_u32_array(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
@@ -340,56 +482,25 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
     return scan_impl(LoadDirBit{ent_nd}, out, n, tmp, s);
 }
 
-#define TM_RADIX_INST(NAME, K, V)                                                             \
-    int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, uint32_t *tmp, \
-             hipStream_t s, const char *hist_name, const char *scatter_name) {                    \
-        return radix_impl<K, V>(keys, keys_alt, vals, vals_alt, n, bits, tmp, s, hist_name,      \
-                                scatter_name);                                                   \
+#define TM_RADIX_INST(NAME, K, V)                                                                \
+    int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,   \
+             uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name) {    \
+        if (n == 0 || bits <= 0) return TM_OK;                                                   \
+        return radix_impl<K, V, PairOut<K, V>>(keys, keys_alt, vals, vals_alt, n, bits, tmp, err, \
+                                               s, hist_name, scatter_name, nullptr);             \
     }
-TM_RADIX_INST(radix_sort_u32, uint32_t, uint32_t)
 TM_RADIX_INST(radix_sort_u64, uint64_t, uint32_t)
-TM_RADIX_INST(radix_sort_u32_v64, uint32_t, uint64_t)
 TM_RADIX_INST(radix_sort_u32_edge, uint32_t, EdgeVal)
 TM_RADIX_INST(radix_sort_u64_edge, uint64_t, EdgeVal)
 #undef TM_RADIX_INST
 
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
-                     uint64_t n, int bits, uint32_t *tmp, hipStream_t s, SeqOut so) {
+                     uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut so) {
     if (n == 0) return TM_OK;
-    if (bits < 1) bits = 1;
-    const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
-    const uint64_t nh = nb * 256;
-    uint32_t *hist = tmp;
-    uint32_t *stmp = tmp + nh + 1;
-    for (int shift = 0; shift < bits; shift += 8) {
-        TM_LAUNCH("sort_node_hist", k_radix_hist<uint32_t>, dim3(nb), dim3(kBlock), 0, s, keys, n,
-                  shift, hist, (uint32_t)nb);
-        int rc = scan_impl(LoadArray{hist}, hist, nh, stmp, s);
-        if (rc) return rc;
-        if (shift + 8 >= bits) {
-            TM_LAUNCH("sort_node_scatter", (k_radix_scatter<uint32_t, NodeVal, SeqWrite>), dim3(nb),
-                      dim3(kBlock), 0, s, keys, vals, SeqWrite{so}, n, shift, hist, (uint32_t)nb);
-        } else {
-            TM_LAUNCH("sort_node_scatter", (k_radix_scatter<uint32_t, NodeVal, PairOut<uint32_t, NodeVal>>),
-                      dim3(nb), dim3(kBlock), 0, s, keys, vals,
-                      (PairOut<uint32_t, NodeVal>{keys_alt, vals_alt}), n, shift, hist, (uint32_t)nb);
-            uint32_t *tk = keys;
-            keys = keys_alt;
-            keys_alt = tk;
-            NodeVal *tv = vals;
-            vals = vals_alt;
-            vals_alt = tv;
-        }
-    }
-    return TM_OK;
-}
-
-int fill_iota(uint32_t *p, uint64_t n, hipStream_t s) {
-    if (n == 0) return TM_OK;
-    uint64_t nb = (n + kBlock - 1) / kBlock;
-    if (nb > 65536) nb = 65536;
-    TM_LAUNCH("iota", k_iota, dim3(nb), dim3(kBlock), 0, s, p, n);
-    return TM_OK;
+    const SeqWrite fin{so};
+    return radix_impl<uint32_t, NodeVal, SeqWrite>(&keys, &keys_alt, &vals, &vals_alt, n,
+                                                   bits < 1 ? 1 : bits, tmp, err, s,
+                                                   "sort_node_hist", "sort_node_scatter", &fin);
 }
 
 }  // namespace tmc

@@ -26,6 +26,7 @@
 #include <deque>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "tm_internal.h"
@@ -95,6 +96,8 @@ struct tm_server {
     std::thread worker;
     // scheduler-thread state (read for stats under mu)
     std::unordered_map<uint64_t, tmc::Resident> resident;
+    // keys whose graph is being built from an admitted request (under mu)
+    std::unordered_set<uint64_t> building;
     std::vector<tmc::Flight> flights;
     std::vector<tmc::Pinned> pinned_pool;
     size_t resident_bytes = 0, flight_bytes = 0;
@@ -291,11 +294,16 @@ void admit(tm_server *S) {
             {
                 std::lock_guard<std::mutex> lk(S->mu);
                 S->pending.pop_front();
+                S->building.insert(r->key);
             }
             r->t_start = now_ns();
             tm_graph *g = nullptr;
             int rc = build_one(S, r, &g);
             if (rc) {
+                {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    S->building.erase(r->key);
+                }
                 finish(S, r, rc);
                 continue;
             }
@@ -310,6 +318,7 @@ void admit(tm_server *S) {
                 for (Request *q : S->pending)
                     if (q->key == r->key && !q->has_edges) rg.queued++;
                 S->resident[r->key] = rg;
+                S->building.erase(r->key);
             }
             S->resident_bytes += rg.bytes;
             r->src.clear();
@@ -456,6 +465,8 @@ int tm_server_create(uint64_t hbm_budget_bytes, uint32_t max_inflight, uint32_t 
     return TM_OK;
 }
 
+static int enqueue(tm_server *S, tmc::Request *r, tmc::Resident *rg, tm_ticket *out);
+
 int tm_submit(tm_server *S, uint64_t graph_key, const int32_t *src, const int32_t *dst,
               const int64_t *t, uint64_t m, uint32_t n_nodes, int64_t delta, tm_ticket *out) {
     if (!S || !out) {
@@ -471,45 +482,48 @@ int tm_submit(tm_server *S, uint64_t graph_key, const int32_t *src, const int32_
     r->key = graph_key;
     r->delta = delta;
     r->n = n_nodes;
-    bool need_edges = true;
-    {
+    // A known key (resident, being built, or carried by a pending request)
+    // needs no edges: the request is queued in the same critical section
+    // that found the key, so the graph cannot be evicted, or become resident
+    // without counting this request, in between.
+    if (graph_key) {
         std::lock_guard<std::mutex> lk(S->mu);
-        if (graph_key) {
-            if (S->resident.count(graph_key)) need_edges = false;
-            for (tmc::Request *q : S->pending)
-                if (q->key == graph_key && q->has_edges) need_edges = false;
-        }
+        auto it = S->resident.find(graph_key);
+        bool known = it != S->resident.end() || S->building.count(graph_key);
+        for (tmc::Request *q : S->pending)
+            if (!known && q->key == graph_key && q->has_edges) known = true;
+        if (known) return enqueue(S, r, it != S->resident.end() ? &it->second : nullptr, out);
     }
-    if (need_edges) {
-        if (graph_key && !src) {
-            delete r;
-            tmc::set_error("unknown graph key and no edges given");
-            return TM_ENOTFOUND;
-        }
-        if (m > 0 && (!src || !dst || !t)) {
-            delete r;
-            tmc::set_error(graph_key ? "unknown graph key and no edges given" : "NULL edge array");
-            return graph_key ? TM_ENOTFOUND : TM_EINVAL;
-        }
-        if (m >= (1ull << 31)) {
-            delete r;
-            tmc::set_error("m must be below 2^31");
-            return TM_EINVAL;
-        }
-        r->m = m;
-        r->has_edges = true;
-        if (m) {
-            r->src.assign(src, src + m);
-            r->dst.assign(dst, dst + m);
-            r->t.assign(t, t + m);
-        }
+    if (graph_key && !src) {
+        delete r;
+        tmc::set_error("unknown graph key and no edges given");
+        return TM_ENOTFOUND;
+    }
+    if (m > 0 && (!src || !dst || !t)) {
+        delete r;
+        tmc::set_error("NULL edge array");
+        return TM_EINVAL;
+    }
+    if (m >= (1ull << 31)) {
+        delete r;
+        tmc::set_error("m must be below 2^31");
+        return TM_EINVAL;
+    }
+    r->m = m;
+    r->has_edges = true;
+    if (m) {
+        r->src.assign(src, src + m);
+        r->dst.assign(dst, dst + m);
+        r->t.assign(t, t + m);
     }
     std::lock_guard<std::mutex> lk(S->mu);
-    if (graph_key && !r->has_edges) {
-        // the graph must stay (or become) resident until this request runs
-        auto it = S->resident.find(graph_key);
-        if (it != S->resident.end()) it->second.queued++;
-    }
+    return enqueue(S, r, nullptr, out);
+}
+
+// Queue a request (caller holds S->mu).  rg: the resident graph an
+// edge-less keyed request relies on, which must then stay resident until
+// the request runs.
+static int enqueue(tm_server *S, tmc::Request *r, tmc::Resident *rg, tm_ticket *out) {
     if (S->stop) {
         delete r;
         tmc::set_error("server is shutting down");
@@ -520,6 +534,7 @@ int tm_submit(tm_server *S, uint64_t graph_key, const int32_t *src, const int32_
         tmc::set_error("server queue is full");
         return TM_EAGAIN;
     }
+    if (rg) rg->queued++;
     r->ticket = S->next_ticket++;
     r->t_submit = tmc::now_ns();
     S->tickets[r->ticket] = r;

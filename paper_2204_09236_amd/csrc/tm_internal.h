@@ -85,8 +85,10 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8 bits per
 // pass, ping-ponging between the two buffers; *keys / *vals point at the
-// sorted data on return.  tmp must hold radix_tmp_count(n) u32.
-size_t radix_tmp_count(uint64_t n);
+// sorted data on return.  tmp: radix_tmp_bytes(n) bytes, 8-byte aligned.
+// err: a device flag the sort sets (and never clears) when a wait of its
+// look-back gave up; the sorted data are then invalid.
+size_t radix_tmp_bytes(uint64_t n);
 // A range [b, e) of work items that all belong to graph g of a batch.
 struct Tile {
     uint32_t g, b, e;
@@ -114,22 +116,19 @@ struct SeqOut {
     uint32_t *epos;
 };
 
-// hist_name / scatter_name label the two kernels of each pass for the tracer.
-#define TM_RADIX_DECL(NAME, K, V)                                                              \
-    int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, uint32_t *tmp, \
-             hipStream_t s, const char *hist_name, const char *scatter_name);
-TM_RADIX_DECL(radix_sort_u32, uint32_t, uint32_t)
+// hist_name / scatter_name label the sort's kernels for the tracer.
+#define TM_RADIX_DECL(NAME, K, V)                                                                \
+    int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,   \
+             uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name);
 TM_RADIX_DECL(radix_sort_u64, uint64_t, uint32_t)
-TM_RADIX_DECL(radix_sort_u32_v64, uint32_t, uint64_t)
 TM_RADIX_DECL(radix_sort_u32_edge, uint32_t, EdgeVal)
 TM_RADIX_DECL(radix_sort_u64_edge, uint64_t, EdgeVal)
 #undef TM_RADIX_DECL
 // Node sort: (node, NodeVal) pairs on bits [0, bits); the last pass writes
 // SeqOut instead of the ping-pong buffers (at least one pass always runs).
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
-                     uint64_t n, int bits, uint32_t *tmp, hipStream_t s, SeqOut out);
+                     uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut out);
 
-int fill_iota(uint32_t *p, uint64_t n, hipStream_t s);
 
 }  // namespace tmc
 

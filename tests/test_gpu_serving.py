@@ -113,16 +113,19 @@ def test_server_budget_and_backpressure(tm):
     big = graphgen.chung_lu_pareto(6, 50_000, 2_000_000)
     refused = 0
     with tm.Server(64 * GB, max_inflight=1, max_queue=1) as S:
+        # one resident graph; edge-less submits take microseconds, each count
+        # milliseconds, so a burst overruns the one-slot queue
+        assert S.wait(S.submit(86400, big.src, big.dst, big.t, n=big.n, key=9))[0] == 0
         tks = []
-        for _ in range(6):
+        for _ in range(50):
             try:
-                tks.append(S.submit(86400, big.src, big.dst, big.t, n=big.n))
+                tks.append(S.submit(86400, key=9))
             except tm.TMError as e:
                 assert e.code == -4                  # TM_EAGAIN
                 refused += 1
         for tk in tks:
             assert S.wait(tk)[0] == 0
-    assert refused >= 1
+    assert refused >= 1 and len(tks) >= 1
     with pytest.raises(tm.TMError):
         tm.Server(0)
 
@@ -142,3 +145,21 @@ def test_server_resident_graph_reuse(tm):
     np.testing.assert_array_equal(outs[0][1], first)
     for (rc, out, _), d in zip(outs, (3600, 600, 86400)):
         np.testing.assert_array_equal(out, oracle.count(g.src, g.dst, g.t, d, n=g.n))
+
+
+def test_server_key_known_while_building(tm):
+    """Edge-less requests for a key whose graph is still being built (taken
+    from the queue, not yet resident) wait for it instead of failing."""
+    g = graphgen.chung_lu_pareto(77, 50_000, 1_000_000)
+    deltas = [60, 600, 3600, 86400]
+    case("server key known while building, m=1e6")
+    with tm.Server(64 * GB, max_inflight=4) as S:
+        first = S.submit(3600, g.src, g.dst, g.t, n=g.n, key=5)
+        rest = [S.submit(d, key=5) for d in deltas * 5]
+        got = [S.wait(first)] + [S.wait(tk) for tk in rest]
+    assert all(rc == 0 for rc, _, _ in got)
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        want = {d: G.count(d) for d in deltas}
+    assert np.array_equal(got[0][1], want[3600])
+    for (rc, out, _), d in zip(got[1:], deltas * 5):
+        assert np.array_equal(out, want[d])
