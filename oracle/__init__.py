@@ -25,7 +25,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
+# The mutation tests point this at a deliberately broken copy of the oracle
+# to show that the pins in tests/test_oracle.py reject it.
+_LIB_PATH = os.environ.get("TM_ORACLE_LIB") or _DEFAULT_LIB
 _SOURCES = [os.path.join(_HERE, "tm_oracle.c"), os.path.join(_HERE, "tm_brute.c")]
 _lib = None
 
@@ -33,21 +36,26 @@ _lib = None
 OK, EINVAL, ENOMEM, EINTERNAL = 0, -1, -2, -6
 
 
+def compile_lib(sources, out_path: str) -> str:
+    """gcc -O3 -fopenmp shared library from the given C sources."""
+    tmp = out_path + ".tmp"
+    cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp] + list(sources)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out_path)
+    return out_path
+
+
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (portable -O3, OpenMP)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-o", tmp] + _SOURCES
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    if force or not os.path.exists(_DEFAULT_LIB):
+        compile_lib(_SOURCES, _DEFAULT_LIB)
+    return _DEFAULT_LIB
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        if not os.path.exists(_LIB_PATH) and _LIB_PATH == _DEFAULT_LIB:
             build()
         lib = ctypes.CDLL(_LIB_PATH)
         p32 = ctypes.POINTER(ctypes.c_int32)

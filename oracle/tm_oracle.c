@@ -46,7 +46,10 @@
  * index order [type][d1][d2][d3] with o = 0, in = 1.
  * Motif layout (36 x u64): out[6*(row-1) + (col-1)] = M_{row,col}; see
  * oracle_layout_* below.  Only some cells of the paper's Figure 2 are fixed by
- * its text; the rest is a convention that honours all of them.
+ * its text; the rest is a convention that honours all of them.  The class
+ * counts themselves are pinned (brute force of the definition, closed forms,
+ * the paper's worked examples); the grid positions of the cells the text does
+ * not fix are parity unpinned against the paper.
  */
 #include <stdint.h>
 #include <stdlib.h>
