@@ -87,8 +87,10 @@ def window_stats(src, dst, t, delta: int) -> dict:
     pos[perm] = torch.arange(2 * m, device=perm.device)
     ws, wd = W[pos[0::2]], W[pos[1::2]]
     cand = (ws > 0) & (wd > 0)
-    return {"sum_w": int(W.sum().item()), "cand": int(cand.sum().item()),
-            "sum_cand_w": int((ws + wd)[cand].sum().item())}
+    return {"sum_w": int(W.sum().item()), "max_w": int(W.max().item()),
+            "cand": int(cand.sum().item()),
+            "sum_cand_w": int((ws + wd)[cand].sum().item()),
+            "sum_cand_prod": int((ws * wd)[cand].sum().item())}
 
 
 def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dict:
@@ -490,6 +492,7 @@ def bench_single(args):
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, g, deltas, counts)
+    golden = golden_check(args.workload, g, deltas, counts)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "edges/s", "n_gpus": 1,
@@ -498,7 +501,7 @@ def bench_single(args):
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "deltas": deltas,
                    "parallelism": "single-gpu"},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "golden": golden,
         "build_only_ms": round(build_ms, 4), "count_only_ms": count_ms,
         "pcie_inclusive": {"ms_per_step": round(host_ms, 3),
                            "edges_per_s": round(g.m * len(deltas) / (host_ms / 1e3), 1),
@@ -511,8 +514,30 @@ def bench_single(args):
         "motif_total": [int(c.sum()) for c in counts],
     }
     print(json.dumps(line))
-    if cpu is not None and not cpu["matches_gpu"]:
+    if (cpu is not None and not cpu["matches_gpu"]) or (golden is not None and not golden["match"]):
         sys.exit(1)
+
+
+def golden_check(workload, g, deltas, counts):
+    """Compare with the oracle's stored counts for this workload
+    (tests/golden/<workload>_counts.json, written by make_golden.py from the
+    oracle alone) when the regenerated input has the stored sha256."""
+    import numpy as np
+
+    import graphgen
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_counts.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("edge_sha256") != graphgen.edge_hash(g):
+        return {"match": None, "note": "input differs from the stored one; not compared"}
+    ok = True
+    for d, c in zip(deltas, counts):
+        want = rec["counts"].get(str(d))
+        if want is None or not np.array_equal(np.array(want["grid"], dtype=np.uint64), c):
+            ok = False
+    return {"match": ok, "deltas": deltas, "source": os.path.relpath(path, ROOT)}
 
 
 def cpu_baseline(args, g, deltas, counts):

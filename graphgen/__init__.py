@@ -30,6 +30,8 @@ from __future__ import annotations
 
 import hashlib
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -65,17 +67,29 @@ def edge_hash(g: EdgeList) -> str:
 # building blocks
 
 def _inverse_cdf_sample(rng: np.random.Generator, weights: np.ndarray, size: int) -> np.ndarray:
-    """Draw ``size`` indices with probability proportional to ``weights``."""
+    """Draw ``size`` indices with probability proportional to ``weights``.
+
+    The uniforms are drawn from ``rng`` in order, chunk by chunk; the
+    lookups of a group of chunks run on threads (numpy releases the GIL in
+    searchsorted), which changes nothing in the result."""
     cdf = np.cumsum(weights, dtype=np.float64)
     cdf /= cdf[-1]
     out = np.empty(size, dtype=np.int32)
     step = 1 << 24                     # bounded temporaries for the 300M-edge case
     last = weights.shape[0] - 1
-    for b in range(0, size, step):
-        u = rng.random(min(step, size - b))
+    workers = max(1, min(16, os.cpu_count() or 1))
+
+    def lookup(job):
+        b, u = job
         idx = np.searchsorted(cdf, u, side="right")
         np.minimum(idx, last, out=idx)
         out[b:b + idx.shape[0]] = idx
+
+    starts = list(range(0, size, step))
+    with ThreadPoolExecutor(workers) as ex:
+        for g in range(0, len(starts), workers):
+            jobs = [(b, rng.random(min(step, size - b))) for b in starts[g:g + workers]]
+            list(ex.map(lookup, jobs))
     return out
 
 

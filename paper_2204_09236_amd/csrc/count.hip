@@ -474,6 +474,7 @@ __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint
 // One block per candidate tile (kCandTile candidates of one graph); waves
 // take 64 candidates at a time; one partial row of 8 counters per tile.
 constexpr uint32_t kCandTile = 1024;
+constexpr int kRegWin = 8;
 
 __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
                                                       const uint32_t *tidx, const uint32_t *eoff,
@@ -502,13 +503,38 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
         }
         const bool small = active && (uint64_t)ws * wd <= lane_max;
         if (small) {
-            for (uint32_t a = ps + 1; a <= ps + ws; a++) {
-                const uint32_t nda = S.nd[a];
-                const uint32_t ra = S.rk[a];
-                for (uint32_t b = pd + 1; b <= pd + wd; b++) {
+            // the smaller window, if it has at most kRegWin entries, is held in
+            // registers and the larger one streamed once
+            const bool s_reg = ws <= wd;
+            const uint32_t rp = s_reg ? ps : pd, rw = s_reg ? ws : wd;
+            const uint32_t lp = s_reg ? pd : ps, lw = s_reg ? wd : ws;
+            if (rw <= kRegWin) {
+                uint32_t rn[kRegWin], rr[kRegWin];
+#pragma unroll
+                for (int k = 0; k < kRegWin; k++) {
+                    const bool v = (uint32_t)k < rw;
+                    rn[k] = v ? S.nd[rp + 1 + k] : 0xffffffffu;  // matches no neighbour
+                    rr[k] = v ? S.rk[rp + 1 + k] : 0u;
+                }
+                for (uint32_t b = lp + 1; b <= lp + lw; b++) {
                     const uint32_t ndb = S.nd[b];
-                    if ((ndb >> 1) == (nda >> 1))
-                        tri_add(T, tri_class(ra, nda & 1u, S.rk[b], ndb & 1u));
+                    const uint32_t rb = S.rk[b];
+#pragma unroll
+                    for (int k = 0; k < kRegWin; k++) {
+                        if ((rn[k] >> 1) == (ndb >> 1))
+                            tri_add(T, s_reg ? tri_class(rr[k], rn[k] & 1u, rb, ndb & 1u)
+                                             : tri_class(rb, ndb & 1u, rr[k], rn[k] & 1u));
+                    }
+                }
+            } else {
+                for (uint32_t a = ps + 1; a <= ps + ws; a++) {
+                    const uint32_t nda = S.nd[a];
+                    const uint32_t ra = S.rk[a];
+                    for (uint32_t b = pd + 1; b <= pd + wd; b++) {
+                        const uint32_t ndb = S.nd[b];
+                        if ((ndb >> 1) == (nda >> 1))
+                            tri_add(T, tri_class(ra, nda & 1u, S.rk[b], ndb & 1u));
+                    }
                 }
             }
         }
@@ -523,18 +549,26 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
             const bool s_outer = bws <= bwd;
             const uint32_t o_lo = s_outer ? bps + 1 : bpd + 1, o_hi = s_outer ? bps + bws : bpd + bwd;
             const uint32_t i_lo = s_outer ? bpd + 1 : bps + 1, i_hi = s_outer ? bpd + bwd : bps + bws;
+            // both windows travel in 64-entry chunks, one coalesced load each;
+            // the outer chunk's entries are broadcast from registers
             for (uint32_t ib = i_lo; ib <= i_hi; ib += kWave) {
                 const uint32_t x = ib + lane;
                 const bool valid = x <= i_hi;
                 const uint32_t ndx = valid ? S.nd[x] : 0xffffffffu;
                 const uint32_t rx = valid ? S.rk[x] : 0u;
-                for (uint32_t o = o_lo; o <= o_hi; o++) {
-                    const uint32_t ndo = S.nd[o];
-                    if (valid && (ndx >> 1) == (ndo >> 1)) {
-                        const uint32_t ro = S.rk[o];
-                        const uint32_t cls = s_outer ? tri_class(ro, ndo & 1u, rx, ndx & 1u)
-                                                     : tri_class(rx, ndx & 1u, ro, ndo & 1u);
-                        tri_add(T, cls);
+                for (uint32_t ob = o_lo; ob <= o_hi; ob += kWave) {
+                    const uint32_t y = ob + lane;
+                    const uint32_t ndy = y <= o_hi ? S.nd[y] : 0u;
+                    const uint32_t ry = y <= o_hi ? S.rk[y] : 0u;
+                    const uint32_t cnt = min((uint32_t)kWave, o_hi - ob + 1);
+                    for (uint32_t k = 0; k < cnt; k++) {
+                        const uint32_t ndo = (uint32_t)__builtin_amdgcn_readlane((int)ndy, (int)k);
+                        const uint32_t ro = (uint32_t)__builtin_amdgcn_readlane((int)ry, (int)k);
+                        if (valid && (ndx >> 1) == (ndo >> 1)) {
+                            const uint32_t cls = s_outer ? tri_class(ro, ndo & 1u, rx, ndx & 1u)
+                                                         : tri_class(rx, ndx & 1u, ro, ndo & 1u);
+                            tri_add(T, cls);
+                        }
                     }
                 }
             }

@@ -225,6 +225,14 @@ def test_skewed_scaled(tm):
     check(tm, g.src, g.dst, g.t, [600, 3600, 86400], n=g.n, label="skewed/1000")
 
 
+def test_skewed_hub_heavy(tm):
+    """The skewed generator at 1/100 scale (100K nodes, 3M edges, 20 % repeats)
+    with a hub of ~1.2e5 incident edges: long node-pair runs that the hub
+    split cuts into many chunks, and wide triangle windows at delta 86400."""
+    g = graphgen.skewed(seed=103, n=100_000, m=3_000_000, top_degree=100_000)
+    check(tm, g.src, g.dst, g.t, [600, 3600, 86400], n=g.n, label="skewed/100 hub-heavy")
+
+
 def test_powerlaw_full_size(tm):
     """The benchmark workload at full size (1M nodes, 20M edges, delta 3600),
     built from device pointers on the current stream as bench.py does, against
