@@ -475,6 +475,20 @@ __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint
 // take 64 candidates at a time; one partial row of 8 counters per tile.
 constexpr uint32_t kCandTile = 1024;
 constexpr int kRegWin = 8;
+// Wide candidates whose smaller window exceeds kHashMin entries are joined
+// through an LDS hash table of at most 2 * kHashChunk slots per wave (load
+// factor <= 1/2, so every probe sequence ends at an empty slot).
+constexpr uint32_t kHashMin = 32;
+constexpr uint32_t kHashChunk = 256;
+constexpr uint32_t kEmptyKey = 0xffffffffu;  // node ids are below 2^31
+constexpr uint32_t kHashMul = 2654435761u;   // Knuth's multiplicative constant
+
+// Order this wave's LDS writes before its later LDS reads (all lanes).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
                                                       const uint32_t *tidx, const uint32_t *eoff,
@@ -483,6 +497,8 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
   const uint32_t n_tiles = ctfirst[G];
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t wv = threadIdx.x / kWave;
+  __shared__ uint32_t hkey[kBlock / kWave][2 * kHashChunk];
+  __shared__ uint32_t hval[kBlock / kWave][2 * kHashChunk];
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const uint32_t gi = last_le(ctfirst, G + 1, ti);
     const uint32_t cb = tidx[eoff[gi]] + (ti - ctfirst[gi]) * kCandTile;
@@ -538,8 +554,7 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                 }
             }
         }
-        // large windows: the whole wave takes one edge at a time; lanes hold
-        // entries of the larger window, the smaller one is walked in order
+        // large windows: the whole wave takes one edge at a time
         uint64_t big = __ballot(active && !small);
         while (big) {
             const int L = __ffsll((unsigned long long)big) - 1;
@@ -549,6 +564,46 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
             const bool s_outer = bws <= bwd;
             const uint32_t o_lo = s_outer ? bps + 1 : bpd + 1, o_hi = s_outer ? bps + bws : bpd + bwd;
             const uint32_t i_lo = s_outer ? bpd + 1 : bps + 1, i_hi = s_outer ? bpd + bwd : bps + bws;
+            if (o_hi - o_lo + 1 > kHashMin) {
+                // hash join: the smaller window, kHashChunk entries at a time,
+                // goes into an open-addressing table in this wave's LDS (one
+                // slot per entry, key = neighbour, value = rank << 1 | dir);
+                // every entry of the larger window probes it.  Work is linear in
+                // the two windows plus the matches instead of their product.
+                uint32_t *hk = hkey[wv], *hv = hval[wv];
+                for (uint32_t cb = o_lo; cb <= o_hi; cb += kHashChunk) {
+                    const uint32_t ce = min(o_hi, cb + kHashChunk - 1);
+                    uint32_t hbits = 6;
+                    while ((1u << hbits) < 2 * (ce - cb + 1)) hbits++;
+                    const uint32_t hmask = (1u << hbits) - 1, hshift = 32 - hbits;
+                    for (uint32_t q = lane; q <= hmask; q += kWave) hk[q] = kEmptyKey;
+                    wave_lds_sync();
+                    for (uint32_t y = cb + lane; y <= ce; y += kWave) {
+                        const uint32_t nd = S.nd[y];
+                        const uint32_t key = nd >> 1;
+                        uint32_t h = (key * kHashMul) >> hshift;
+                        while (atomicCAS(&hk[h], kEmptyKey, key) != kEmptyKey) h = (h + 1) & hmask;
+                        hv[h] = (S.rk[y] << 1) | (nd & 1u);
+                    }
+                    wave_lds_sync();
+                    for (uint32_t x = i_lo + lane; x <= i_hi; x += kWave) {
+                        const uint32_t nd = S.nd[x];
+                        const uint32_t key = nd >> 1;
+                        const uint32_t rx = S.rk[x];
+                        for (uint32_t h = (key * kHashMul) >> hshift;; h = (h + 1) & hmask) {
+                            const uint32_t k = hk[h];
+                            if (k == kEmptyKey) break;
+                            if (k == key) {
+                                const uint32_t v = hv[h];
+                                tri_add(T, s_outer ? tri_class(v >> 1, v & 1u, rx, nd & 1u)
+                                                   : tri_class(rx, nd & 1u, v >> 1, v & 1u));
+                            }
+                        }
+                    }
+                    wave_lds_sync();
+                }
+                continue;
+            }
             // both windows travel in 64-entry chunks, one coalesced load each;
             // the outer chunk's entries are broadcast from registers
             for (uint32_t ib = i_lo; ib <= i_hi; ib += kWave) {
