@@ -238,18 +238,6 @@ struct El {
     uint32_t dir, a0, a1;
 };
 
-__device__ inline El load_el(const int64_t *me_t, const uint8_t *me_o, const uint4 *me_a,
-                             uint32_t k, uint32_t side) {
-    El e;
-    e.t = me_t[k];
-    const uint32_t is_src = (uint32_t)me_o[k] ^ side;  // side 0: center = smaller node
-    e.dir = 1u - is_src;
-    const uint4 aa = me_a[k];
-    e.a0 = side ? aa.z : aa.x;
-    e.a1 = side ? aa.w : aa.y;
-    return e;
-}
-
 struct StarArgs {
     const uint32_t *mp_start;
     const int64_t *me_t;
@@ -257,7 +245,9 @@ struct StarArgs {
     const uint4 *me_a;
     const uint4 *me_w;
     const uint32_t *first;   // n_multi + 1: first work item of each pair (exclusive scan)
+    const uint32_t *ipair;   // work item -> its pair
     uint64_t n_multi;
+    uint64_t n_me;
     const uint32_t *mpb;     // G + 1: multi-edge pair bounds per graph
     const uint32_t *tfirst;  // G + 1: first item tile of each graph
     uint32_t G;
@@ -276,33 +266,93 @@ __device__ inline uint32_t last_le(const uint32_t *a, uint32_t n, uint32_t x) {
     return lo;
 }
 
-// Work item -> (pair, chunk): the pair is the last one whose first item is <= it.
-__device__ inline WorkItem item_of(const uint32_t *first, uint64_t n_multi, uint32_t it) {
-    uint64_t lo = 0, hi = n_multi;  // first[lo] <= it < first[hi]
-    while (hi - lo > 1) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (first[mid] <= it) lo = mid;
-        else hi = mid;
-    }
-    return WorkItem{(uint32_t)lo, it - first[lo]};
-}
+// One block per item tile (kItemTile items of one graph, one per thread);
+// one partial row of 32 counters per tile.  The tile's items cover one
+// contiguous range of elements; that range and kStageHalo elements on each
+// side are first copied into LDS with coalesced loads, so the sequential
+// window sweeps read LDS.  Elements outside the staged range (long delta
+// halos of hub pairs, or ranges beyond the stage capacity when chunks are
+// long) are read from global memory, so the result does not depend on the
+// staging.
+constexpr uint32_t kItemTile = kBlock;
 
-// One block per item tile (kItemTile items of one graph); one partial row
-// of 32 counters per tile.
-constexpr uint32_t kItemTile = 1024;
+__device__ inline WorkItem item_at(const StarArgs &a, uint32_t it) {
+    const uint32_t p = a.ipair[it];
+    return WorkItem{p, it - a.first[p]};
+}
+constexpr uint32_t kStageHalo = 64;
+constexpr uint32_t kStageCap = 1024 + 2 * kStageHalo;
+
+struct ElemView {
+    uint32_t lo, hi;  // staged element range
+    const int64_t *st;
+    const uint8_t *so;
+    const uint4 *sa, *sw;
+    const int64_t *gt;
+    const uint8_t *go;
+    const uint4 *ga, *gw;
+    __device__ inline bool staged(uint32_t k) const { return k - lo < hi - lo; }
+    __device__ inline int64_t t(uint32_t k) const { return staged(k) ? st[k - lo] : gt[k]; }
+    __device__ inline El el(uint32_t k, uint32_t side) const {
+        int64_t tt;
+        uint32_t o;
+        uint4 aa;
+        if (staged(k)) {
+            tt = st[k - lo];
+            o = so[k - lo];
+            aa = sa[k - lo];
+        } else {
+            tt = gt[k];
+            o = go[k];
+            aa = ga[k];
+        }
+        El e;
+        e.t = tt;
+        e.dir = 1u - (o ^ side);  // side 0: center = smaller node
+        e.a0 = side ? aa.z : aa.x;
+        e.a1 = side ? aa.w : aa.y;
+        return e;
+    }
+    __device__ inline uint4 w(uint32_t k, uint32_t side) const {
+        return staged(k) ? sw[2 * (k - lo) + side] : gw[2 * (uint64_t)k + side];
+    }
+};
 
 __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *partial) {
+  __shared__ int64_t s_t[kStageCap];
+  __shared__ uint4 s_a[kStageCap];
+  __shared__ uint4 s_w[2 * kStageCap];
+  __shared__ uint8_t s_o[kStageCap];
+  __shared__ uint64_t red[kBlock / kWave][32];
   const uint32_t n_tiles = a.tfirst[a.G];
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const uint32_t gi = last_le(a.tfirst, a.G + 1, ti);
     const int64_t delta = a.deltas[gi];
     const uint32_t ib = a.first[a.mpb[gi]] + (ti - a.tfirst[gi]) * kItemTile;
     const uint32_t ie = min(a.first[a.mpb[gi + 1]], ib + kItemTile);
+    // element range of the tile's items, plus halos, clipped to the capacity
+    const WorkItem w0 = item_at(a, ib);
+    const WorkItem w1 = item_at(a, ie - 1);
+    const uint32_t eb = a.mp_start[w0.pair] + w0.chunk * a.chunk;
+    const uint32_t ee = min(a.mp_start[w1.pair + 1], a.mp_start[w1.pair] + (w1.chunk + 1) * a.chunk);
+    const uint32_t lo = eb - min(eb, kStageHalo);
+    const uint32_t hi = (uint32_t)min<uint64_t>(min<uint64_t>(a.n_me, (uint64_t)ee + kStageHalo),
+                                                (uint64_t)lo + kStageCap);
+    __syncthreads();  // the previous tile's sweeps are done with the stage
+    for (uint32_t k = lo + threadIdx.x; k < hi; k += kBlock) {
+        s_t[k - lo] = a.me_t[k];
+        s_o[k - lo] = a.me_o[k];
+        s_a[k - lo] = a.me_a[k];
+        s_w[2 * (k - lo)] = a.me_w[2 * (uint64_t)k];
+        s_w[2 * (k - lo) + 1] = a.me_w[2 * (uint64_t)k + 1];
+    }
+    __syncthreads();
+    const ElemView V{lo, hi, s_t, s_o, s_a, s_w, a.me_t, a.me_o, a.me_a, a.me_w};
     StarAcc A;
 #pragma unroll
     for (int i = 0; i < 32; i++) A.c[i] = 0;
     for (uint32_t it = ib + threadIdx.x; it < ie; it += blockDim.x) {
-        const WorkItem w = item_of(a.first, a.n_multi, it);
+        const WorkItem w = item_at(a, it);
         const uint32_t rs = a.mp_start[w.pair], re = a.mp_start[w.pair + 1];
         const uint32_t cb = rs + w.chunk * a.chunk;
         const uint32_t ce = min(re, cb + a.chunk);
@@ -312,18 +362,18 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
             W.clear();
             uint32_t j = cb + 1;  // next pair edge to enter the window
             for (uint32_t q = cb; q < ce; q++) {
-                const El eq = load_el(a.me_t, a.me_o, a.me_a, q, side);
+                const El eq = V.el(q, side);
                 if (q > cb && j > q) W.pop(eq.dir, eq.a0, eq.a1);
                 if (j <= q) j = q + 1;
                 const int64_t lim = eq.t + delta;
                 while (j < re) {
-                    const El ej = load_el(a.me_t, a.me_o, a.me_a, j, side);
+                    const El ej = V.el(j, side);
                     if (ej.t > lim) break;
                     W.push(ej.dir, ej.a0, ej.a1);
                     j++;
                 }
                 if (W.in[0] + W.in[1] == 0) continue;
-                const uint4 ww = a.me_w[2 * (uint64_t)q + side];
+                const uint4 ww = V.w(q, side);
                 const uint64_t rp[2] = {ww.x, ww.y};
                 const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0),
                                          (uint64_t)eq.a1 + (eq.dir == 1)};
@@ -350,25 +400,25 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
             W.clear();
             uint32_t f;  // front of the window [f, q)
             {
-                const int64_t lim = a.me_t[cb] - delta;
+                const int64_t lim = V.t(cb) - delta;
                 f = cb;
-                while (f > rs && a.me_t[f - 1] >= lim) f--;
+                while (f > rs && V.t(f - 1) >= lim) f--;
                 for (uint32_t k = f; k < cb; k++) {
-                    const El ek = load_el(a.me_t, a.me_o, a.me_a, k, side);
+                    const El ek = V.el(k, side);
                     W.push(ek.dir, ek.a0, ek.a1);
                 }
             }
             for (uint32_t q = cb; q < ce; q++) {
-                const El eq = load_el(a.me_t, a.me_o, a.me_a, q, side);
+                const El eq = V.el(q, side);
                 const int64_t lim = eq.t - delta;
                 while (f < q) {
-                    const El ef = load_el(a.me_t, a.me_o, a.me_a, f, side);
+                    const El ef = V.el(f, side);
                     if (ef.t >= lim) break;
                     W.pop(ef.dir, ef.a0, ef.a1);
                     f++;
                 }
                 if (W.in[0] + W.in[1] != 0) {
-                    const uint4 ww = a.me_w[2 * (uint64_t)q + side];
+                    const uint4 ww = V.w(q, side);
                     const uint64_t lp[2] = {ww.z, ww.w};
                     const uint64_t m1 = 0ull - (uint64_t)eq.dir;
 #pragma unroll
@@ -388,7 +438,6 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
     }
 
     // block reduction of the 32 accumulators into this tile's row
-    __shared__ uint64_t red[kBlock / kWave][32];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
 #pragma unroll
     for (int i = 0; i < 32; i++) {
@@ -404,8 +453,32 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
         for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
         partial[(uint64_t)ti * 32 + threadIdx.x] = s;
     }
-    __syncthreads();
   }
+}
+
+// item -> pair.  Every pair has at least one item, so first[] strictly
+// increases; a thread fills kItemsPerThread consecutive items, finding the
+// first one's pair by binary search and walking forward from there (long hub
+// pairs do not serialise one thread).
+constexpr uint32_t kItemsPerThread = 32;
+
+__global__ void k_item_pairs(const uint32_t *first, uint64_t n_multi, uint32_t *ipair) {
+    const uint64_t n_items = first[n_multi];
+    for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kItemsPerThread;
+         base < n_items; base += (uint64_t)gridDim.x * blockDim.x * kItemsPerThread) {
+        uint64_t lo = 0, hi = n_multi;  // first[lo] <= base < first[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (first[mid] <= base) lo = mid;
+            else hi = mid;
+        }
+        uint64_t p = lo;
+        const uint64_t end = min(base + kItemsPerThread, n_items);
+        for (uint64_t it = base; it < end; it++) {
+            while (first[p + 1] <= it) p++;
+            ipair[it] = (uint32_t)p;
+        }
+    }
 }
 
 // Work items: node pair k is cut into ceil(len / chunk) items.
@@ -660,30 +733,46 @@ __global__ void k_graph_tiles(const uint32_t *first, const uint32_t *mpb, const 
     }
 }
 
-// Per graph: sum its star/pair tile rows and its triangle tile rows (block
-// per graph, thread t on column t % cols; integer sums, no atomics).
+// Per graph: sum its star/pair tile rows and its triangle tile rows.  Each
+// graph's rows are split over kSumSplit blocks (a single graph can have
+// hundreds of thousands of rows); block (graph, part) writes one partial row
+// of 40, and k_graph_sums_fin adds the parts.  Integer sums, no atomics.
+constexpr uint32_t kSumSplit = 16;
+
 __global__ void __launch_bounds__(kBlock) k_graph_sums(const uint64_t *spart, const uint32_t *tfirst,
                                                        const uint64_t *tpart,
                                                        const uint32_t *ctfirst, uint32_t G,
-                                                       uint64_t *out) {
+                                                       uint64_t *gpart) {
     __shared__ uint64_t lds[kBlock];
-    for (uint32_t gi = blockIdx.x; gi < G; gi += gridDim.x) {
+    for (uint64_t bi = blockIdx.x; bi < (uint64_t)G * kSumSplit; bi += gridDim.x) {
+        const uint32_t gi = (uint32_t)(bi / kSumSplit), sp = (uint32_t)(bi % kSumSplit);
         for (int pass = 0; pass < 2; pass++) {
             const uint32_t cols = pass == 0 ? 32u : 8u;
             const uint64_t *part = pass == 0 ? spart : tpart;
             const uint32_t *fr = pass == 0 ? tfirst : ctfirst;
             const uint32_t c = threadIdx.x % cols, grp = threadIdx.x / cols, groups = kBlock / cols;
             uint64_t v = 0;
-            for (uint32_t r = fr[gi] + grp; r < fr[gi + 1]; r += groups) v += part[(uint64_t)r * cols + c];
+            for (uint32_t r = fr[gi] + sp * groups + grp; r < fr[gi + 1]; r += groups * kSumSplit)
+                v += part[(uint64_t)r * cols + c];
             lds[threadIdx.x] = v;
             __syncthreads();
             if (threadIdx.x < cols) {
                 uint64_t sum = 0;
                 for (uint32_t q = 0; q < groups; q++) sum += lds[q * cols + threadIdx.x];
-                out[(uint64_t)gi * 40 + (pass == 0 ? 0 : 32) + threadIdx.x] = sum;
+                gpart[bi * 40 + (pass == 0 ? 0 : 32) + threadIdx.x] = sum;
             }
             __syncthreads();
         }
+    }
+}
+
+__global__ void k_graph_sums_fin(const uint64_t *gpart, uint32_t G, uint64_t *out) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)G * 40;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t gi = i / 40, c = i % 40;
+        uint64_t sum = 0;
+        for (uint32_t sp = 0; sp < kSumSplit; sp++) sum += gpart[(gi * kSumSplit + sp) * 40 + c];
+        out[i] = sum;
     }
 }
 
@@ -696,8 +785,8 @@ dim3 grid_for(uint64_t n, uint64_t cap) {
 
 }  // namespace
 
-constexpr uint32_t kDefaultRunChunk = 8;
-constexpr uint32_t kDefaultTriLaneMax = 64;
+constexpr uint32_t kDefaultRunChunk = 4;
+constexpr uint32_t kDefaultTriLaneMax = 16;
 
 // ---------------------------------------------------------------- driver
 // Device workspace of one count: carved from one block, either per call or
@@ -707,10 +796,10 @@ struct Workspace {
     uint32_t *Wf;
     uint64_t *wbits;
     uint4 *me_w;
-    uint32_t *cnt, *first, *tflag, *tidx;
+    uint32_t *cnt, *first, *ipair, *tflag, *tidx;
     uint4 *cand;
     uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
-    uint64_t *spart, *tpart, *res;
+    uint64_t *spart, *tpart, *gpart, *res;
     uint64_t max_itiles, max_ctiles;
 };
 
@@ -722,7 +811,7 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     return up(G * 8) + up(len * 4) + up((len / kWave + 1) * 8) + up(2 * nme * sizeof(uint4)) +
-           up((nm + 1) * 4) * 2 +
+           up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * kSumSplit * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
            up(n_tmp * 4) + up(w->max_itiles * 32 * 8) + up(w->max_ctiles * 8 * 8) +
            up((size_t)G * 40 * 8) + 4096;
@@ -738,6 +827,7 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->me_w = sc.take<uint4>(2 * nme);
     w->cnt = sc.take<uint32_t>(nm + 1);
     w->first = sc.take<uint32_t>(nm + 1);
+    w->ipair = sc.take<uint32_t>(nme + 1);
     w->tflag = sc.take<uint32_t>(m);
     w->tidx = sc.take<uint32_t>(m + 1);
     w->cand = sc.take<uint4>(m);
@@ -748,6 +838,7 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->tmp = sc.take<uint32_t>(n_tmp);
     w->spart = sc.take<uint64_t>(w->max_itiles * 32);
     w->tpart = sc.take<uint64_t>(w->max_ctiles * 8);
+    w->gpart = sc.take<uint64_t>((size_t)G * kSumSplit * 40);
     w->res = sc.take<uint64_t>((size_t)G * 40);
 }
 
@@ -787,15 +878,19 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
     rc = scan_u32_array(w.n_ctiles, w.ctfirst, G, w.tmp, s);
     if (rc) return rc;
     if (nm) {
-        StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w, w.first, nm,
+        TM_LAUNCH("item_pairs", k_item_pairs, grid_for(nme / kItemsPerThread + 1, 4096), dim3(kBlock),
+                  0, s, w.first, nm, w.ipair);
+        StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w, w.first, w.ipair, nm, nme,
                     g->d_mpb, w.tfirst, G, w.deltas, run_chunk};
         TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
                   dim3(kBlock), 0, s, sa, w.spart);
     }
     TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
               dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max, w.tpart);
-    TM_LAUNCH("graph_sums", k_graph_sums, dim3(std::min<uint32_t>(G, 8192)), dim3(kBlock), 0, s,
-              w.spart, w.tfirst, w.tpart, w.ctfirst, G, w.res);
+    TM_LAUNCH("graph_sums", k_graph_sums, dim3((unsigned)std::min<uint64_t>((uint64_t)G * kSumSplit, 16384)),
+              dim3(kBlock), 0, s, w.spart, w.tfirst, w.tpart, w.ctfirst, G, w.gpart);
+    TM_LAUNCH("graph_sums_fin", k_graph_sums_fin, grid_for((uint64_t)G * 40, 4096), dim3(kBlock), 0, s,
+              w.gpart, G, w.res);
     return TM_OK;
 }
 
