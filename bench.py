@@ -147,16 +147,29 @@ def kernel_table(prof: dict, model: dict) -> tuple[dict, str | None]:
     return kernels, dominant
 
 
-def source_digest() -> str:
-    """sha256 over the HIP sources: a stored counter reading applies only to
-    the kernels it was taken from."""
+COUNT_KERNELS = ("windows", "star_prep", "item_counts", "item_pairs", "star_pair", "wbits",
+                 "tri_flags", "tri_compact", "triangles", "graph_tiles", "graph_sums",
+                 "graph_sums_fin")
+
+
+def kernel_sources(kernel: str) -> list[str]:
+    """The HIP source files that define a traced kernel."""
+    if kernel.startswith("sort_") or kernel.startswith("scan_"):
+        return ["prim.hip", "tm_internal.h"]
+    if kernel in COUNT_KERNELS:
+        return ["count.hip", "tm_internal.h"]
+    return ["build.hip", "tm_internal.h"]
+
+
+def source_digest(kernel: str) -> str:
+    """sha256 over the sources of one kernel: a stored counter reading
+    applies only to the code it was taken from."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2204_09236_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in kernel_sources(kernel):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -173,7 +186,7 @@ def stored_traffic(kernel: str, workload: str) -> dict | None:
             if "=" in line and not line.startswith("#"):
                 a, b = line.split("=", 1)
                 kv[a.strip()] = b.strip()
-    if kv.get("source_digest") != source_digest():
+    if kv.get("source_digest") != source_digest(kernel):
         return None
     try:
         return {"bytes": float(kv["traffic_bytes_per_launch"]),
