@@ -149,8 +149,7 @@ int scan_impl(L ld, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
 // own count (aggregate) or the count of itself and everything before it
 // (inclusive), and the walk stops at the first inclusive word.  The tile is
 // then staged in LDS in digit order so that each digit's run is written to
-// HBM contiguously.  Tiles hold 3072 to 5120 elements (72 KiB of LDS or
-// less, two blocks per CU).
+// HBM contiguously.
 constexpr int kOsThreads = 512;
 constexpr int kOsWaves = kOsThreads / kWave;
 constexpr int kMaxPasses = 8;
@@ -162,6 +161,16 @@ constexpr uint64_t kStVal = (1ull << 62) - 1;
 // gives up, flags the error and lets the kernel finish.
 constexpr uint32_t kSpinLimit = 1u << 20;
 constexpr uint64_t kMinTile = (uint64_t)kOsThreads * 6;
+
+// Block size and items per thread of a pass, by element type: the node
+// sort's 20-byte elements run in 1024-thread blocks with 6144-element tiles
+// (one block per CU, 141 KiB of LDS); the others in 512-thread blocks with
+// 3072-5120-element tiles (two blocks per CU).  Measured on gfx950: longer
+// digit runs per tile pay more than occupancy for the node sort.
+template <typename K, typename V>
+constexpr int os_threads() {
+    return sizeof(V) == sizeof(NodeVal) && sizeof(K) == 4 ? 1024 : kOsThreads;
+}
 
 template <typename K, typename V>
 constexpr int os_items() {
@@ -184,7 +193,7 @@ __device__ inline uint64_t digit_peers(K key, int shift, bool valid, uint32_t *d
 }
 
 // Exclusive scan of one value per digit, held by threads [0, 256) of a
-// kOsThreads block; every thread of the block must call it.
+// block of at least 256 threads; every thread of the block must call it.
 __device__ inline uint32_t digit_excl_scan(uint32_t v, uint32_t *lds4) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const uint32_t s = wave_incl_scan(v, lane);
@@ -277,22 +286,23 @@ struct SeqWrite {
 // status: this pass's look-back words (tile x 256, zero on entry);
 // status_next: the next pass's words, whose row for this tile is cleared
 // here (null on the last pass); ticket: tile counter (zero on entry).
-template <typename K, typename V, typename Out, int ITEMS>
-__global__ void __launch_bounds__(kOsThreads) k_os_scatter(const K *kin, const V *vin, Out out,
+template <typename K, typename V, typename Out, int THREADS, int ITEMS>
+__global__ void __launch_bounds__(THREADS) k_os_scatter(const K *kin, const V *vin, Out out,
                                                            uint64_t n, int shift,
                                                            const uint32_t *ghist, uint64_t *status,
                                                            uint64_t *status_next, uint32_t *ticket,
                                                            uint32_t *err) {
-    constexpr uint32_t kT = (uint32_t)kOsThreads * ITEMS;
+    constexpr uint32_t kT = (uint32_t)THREADS * ITEMS;
+    constexpr int kWv = THREADS / kWave;
     __shared__ V s_val[kT];
     __shared__ K s_key[kT];
-    __shared__ uint32_t wh[kOsWaves][256];
+    __shared__ uint32_t wh[kWv][256];
     __shared__ uint32_t blk_off[256];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t lds4[4];
     __shared__ uint32_t s_tile;
     const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (int i = threadIdx.x; i < kOsWaves * 256; i += kOsThreads) (&wh[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < kWv * 256; i += THREADS) (&wh[0][0])[i] = 0;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -336,11 +346,11 @@ __global__ void __launch_bounds__(kOsThreads) k_os_scatter(const K *kin, const V
     }
     __syncthreads();
     const int d = threadIdx.x;
-    uint32_t c[kOsWaves];
+    uint32_t c[kWv];
     uint32_t tot = 0;
     if (d < 256) {
 #pragma unroll
-        for (int q = 0; q < kOsWaves; q++) {
+        for (int q = 0; q < kWv; q++) {
             c[q] = wh[q][d];
             tot += c[q];
         }
@@ -351,7 +361,7 @@ __global__ void __launch_bounds__(kOsThreads) k_os_scatter(const K *kin, const V
         blk_off[d] = excl;
         uint32_t run = excl;
 #pragma unroll
-        for (int q = 0; q < kOsWaves; q++) {
+        for (int q = 0; q < kWv; q++) {
             wh[q][d] = run;
             run += c[q];
         }
@@ -395,7 +405,7 @@ __global__ void __launch_bounds__(kOsThreads) k_os_scatter(const K *kin, const V
     }
     __syncthreads();
     const uint32_t cnt_tile = (uint32_t)min<uint64_t>((uint64_t)kT, n - tile0);
-    for (uint32_t x = threadIdx.x; x < cnt_tile; x += kOsThreads) {
+    for (uint32_t x = threadIdx.x; x < cnt_tile; x += THREADS) {
         const K k = s_key[x];
         const uint32_t dk = (uint32_t)(k >> shift) & 255u;
         const uint32_t pos = gbase[dk] + (x - blk_off[dk]);
@@ -430,7 +440,8 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
                uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name,
                const Final *fin) {
     constexpr int kItems_ = os_items<K, V>();
-    constexpr uint64_t kT = (uint64_t)kOsThreads * kItems_;
+    constexpr int kThr = os_threads<K, V>();
+    constexpr uint64_t kT = (uint64_t)kThr * kItems_;
     const int passes = (bits + 7) / 8;
     if (passes > kMaxPasses || (uint64_t)passes * 8 > sizeof(K) * 8) {
         set_error("radix sort: key bits out of range");
@@ -451,12 +462,13 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
         uint64_t *st = t.status[p & 1];
         uint64_t *st_next = p + 1 < passes ? t.status[(p + 1) & 1] : nullptr;
         if (fin && p + 1 == passes) {
-            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, Final, kItems_>), dim3((unsigned)ntiles),
-                      dim3(kOsThreads), 0, s, *keys, *vals, *fin, n, 8 * p, t.ghist + 256 * p, st,
+            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, Final, kThr, kItems_>), dim3((unsigned)ntiles),
+                      dim3(kThr), 0, s, *keys, *vals, *fin, n, 8 * p, t.ghist + 256 * p, st,
                       st_next, t.tickets + p, err);
         } else {
-            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, PairOut<K, V>, kItems_>), dim3((unsigned)ntiles),
-                      dim3(kOsThreads), 0, s, *keys, *vals, (PairOut<K, V>{*keys_alt, *vals_alt}), n,
+            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, PairOut<K, V>, kThr, kItems_>),
+                      dim3((unsigned)ntiles), dim3(kThr), 0, s, *keys, *vals,
+                      (PairOut<K, V>{*keys_alt, *vals_alt}), n,
                       8 * p, t.ghist + 256 * p, st, st_next, t.tickets + p, err);
             std::swap(*keys, *keys_alt);
             std::swap(*vals, *vals_alt);
