@@ -26,7 +26,7 @@ namespace {
 constexpr int64_t kTLimit = (int64_t)1 << 62;
 constexpr uint32_t kGapFill = 64;
 constexpr uint32_t kUnset = 0xffffffffu;
-constexpr uint32_t kMaxStatBlocks = 1024;
+constexpr uint32_t kMaxStatBlocks = 4096;
 constexpr uint64_t kEntryTile = 8192, kElemTile = 8192;
 
 struct Stat {
@@ -317,7 +317,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     std::vector<Stat> h_st(G, Stat{0, 0, ~0ull, 0});
     std::vector<uint32_t> h_lim(G);
     for (uint32_t i = 0; i < G; i++) h_lim[i] = ncount[i] ? ncount[i] : 0x7fffffffu;
-    const std::vector<Tile> etiles = make_tiles(g->h_eoff, 1u << 16);
+    const std::vector<Tile> etiles = make_tiles(g->h_eoff, 1u << 13);
     {
         Scratch vs;
         TRY(vs.reserve(G * sizeof(Stat) + G * 4 + etiles.size() * sizeof(Tile) + 1024, s));

@@ -116,19 +116,76 @@ __device__ inline uint32_t window_start(const int64_t *T, uint32_t p, uint32_t l
 }
 
 // ------------------------------------------------------------ window sizes
+constexpr int kWinUnroll = 4;
+
 // Wf[p] = R(p) - p: how many later entries of the same S_u lie within delta
 // (the delta of the graph the entry belongs to; tiles never straddle graphs).
+// A wave takes 64 consecutive entries and holds the (center, t) keys of
+// those and of the next 64 in registers.  Entries are sorted by (center, t),
+// so "key <= (c_p, t_p + delta)" holds on a prefix of the entries after p:
+// each lane finds the end of that prefix by binary search over the 128
+// register-held keys (lane shuffles, no memory round trips), and only a
+// window that runs past them continues with a gallop in global memory.
 __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
-                                                    const int64_t *deltas, uint32_t *Wf) {
+                                                    uint64_t len, const int64_t *deltas,
+                                                    uint32_t *Wf) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const Tile tl = tiles[ti];
         const int64_t delta = deltas[tl.g];
-        for (uint32_t p = tl.b + threadIdx.x; p < tl.e; p += blockDim.x) {
-            const uint32_t hi = S.off[S.c[p] + 1];
-            const int64_t lim = S.t[p] + delta;
-            uint32_t w = 0;
-            if (p + 1 < hi && S.t[p + 1] <= lim) w = window_end(S.t, p, hi, lim) - p;
-            Wf[p] = w;
+        // each wave walks its own contiguous span of the tile, kWinUnroll
+        // chunks of 64 per step (their loads issued together), carrying the
+        // last chunk's keys into the next step
+        const uint32_t span = ((tl.e - tl.b + nw - 1) / nw + kWave - 1) / kWave * kWave;
+        const uint32_t w_b = tl.b + wv * span, w_e = min(tl.e, w_b + span);
+        if (w_b >= w_e) continue;
+        uint32_t cc[kWinUnroll + 1];
+        int64_t tt[kWinUnroll + 1];
+        uint64_t q0 = (uint64_t)w_b + lane;
+        cc[0] = q0 < len ? S.c[q0] : 0xffffffffu;
+        tt[0] = q0 < len ? S.t[q0] : 0;
+        for (uint32_t b0 = w_b; b0 < w_e; b0 += kWinUnroll * kWave) {
+#pragma unroll
+            for (int u = 1; u <= kWinUnroll; u++) {
+                const uint64_t q = q0 + (uint64_t)u * kWave;
+                cc[u] = q < len ? S.c[q] : 0xffffffffu;
+                tt[u] = q < len ? S.t[q] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kWinUnroll; u++) {
+                const uint32_t base = b0 + (uint32_t)u * kWave;
+                if (base >= w_e) break;
+                const uint64_t qa = (uint64_t)base + lane;
+                const uint32_t ca = cc[u], cb = cc[u + 1];
+                const int64_t ta = tt[u], tb = tt[u + 1];
+                const int64_t lim = ta + delta;
+                // last k in [lane, 128) with key(base + k) <= (ca, lim)
+                uint32_t lo = (uint32_t)lane, hi = 2 * kWave;
+#pragma unroll
+                for (int step = 0; step < 7; step++) {
+                    const uint32_t mid = (lo + hi) / 2;
+                    const int src = (int)(mid & (kWave - 1));
+                    const uint32_t c1 = __shfl(ca, src, kWave), c2 = __shfl(cb, src, kWave);
+                    const int64_t t1 = __shfl(ta, src, kWave), t2 = __shfl(tb, src, kWave);
+                    const uint32_t cm = mid < kWave ? c1 : c2;
+                    const int64_t tm = mid < kWave ? t1 : t2;
+                    const bool ok = cm < ca || (cm == ca && tm <= lim);
+                    if (hi - lo > 1) {
+                        if (ok) lo = mid;
+                        else hi = mid;
+                    }
+                }
+                if (qa < w_e) {
+                    uint64_t R = (uint64_t)base + lo;
+                    if (lo == 2 * kWave - 1)  // the window may run past the registers
+                        R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
+                    Wf[qa] = (uint32_t)(R - qa);
+                }
+            }
+            cc[0] = cc[kWinUnroll];
+            tt[0] = tt[kWinUnroll];
+            q0 += (uint64_t)kWinUnroll * kWave;
         }
     }
 }
@@ -851,7 +908,7 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
     const uint64_t m = g->m, nm = g->n_multi, nme = g->n_me;
     int rc;
     TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
-              s, S, g->t_entries, g->n_t_entries, w.deltas, w.Wf);
+              s, S, g->t_entries, g->n_t_entries, 2 * m, w.deltas, w.Wf);
     // ---- star / pair: work items (pair, chunk)
     if (nm) {
         TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
