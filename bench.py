@@ -475,6 +475,18 @@ def bench_single(args):
             G.count(d)
         torch.cuda.synchronize()
         count_ms[str(d)] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
+    # one family at a time (tm_count_masked), as the paper times its
+    # pair-only and triangle-only variants
+    family_ms = {}
+    for name, fam in (("stars+pairs", tm.STARS | tm.PAIRS), ("pairs", tm.PAIRS),
+                      ("triangles", tm.TRIANGLES)):
+        G.count(deltas[0], families=fam)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for _ in range(args.steps):
+            G.count(deltas[0], families=fam)
+        torch.cuda.synchronize()
+        family_ms[name] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
     G.free()
 
     tspan = int(g.t.max() - g.t.min()) if g.m else 0
@@ -516,6 +528,7 @@ def bench_single(args):
                    "parallelism": "single-gpu"},
         "roofline": roofline, "cpu_baseline": cpu, "golden": golden,
         "build_only_ms": round(build_ms, 4), "count_only_ms": count_ms,
+        "count_only_family_ms": {"delta": deltas[0], **family_ms},
         "pcie_inclusive": {"ms_per_step": round(host_ms, 3),
                            "edges_per_s": round(g.m * len(deltas) / (host_ms / 1e3), 1),
                            "note": "inputs in host memory, copied in by tm_build_graph"},

@@ -60,6 +60,10 @@ enum {
 
 enum { TM_HOST_PTRS = 0, TM_DEVICE_PTRS = 1 };
 
+/* Motif families (the paper's categories, Section IV: stars, pairs,
+ * triangles), for tm_count_masked. */
+enum { TM_STARS = 1, TM_PAIRS = 2, TM_TRIANGLES = 4, TM_ALL_MOTIFS = 7 };
+
 /*
  * Build the device-resident graph used by every count (delta-independent).
  *
@@ -149,6 +153,20 @@ void tm_graph_free(tm_graph *g);
  * Concurrent calls on one graph are allowed; they run one after another.
  */
 int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]);
+
+/*
+ * tm_count restricted to some motif families.  The problem statement lets
+ * users pick the motif types they need (Section III); the paper times its
+ * pair-only and triangle-only variants separately (Section V).
+ * families: a nonzero OR of TM_STARS (the 24 star cells), TM_PAIRS (the 4
+ * pair cells) and TM_TRIANGLES (the 8 triangle cells).  The selected cells
+ * equal tm_count's; the others are 0.  Kernels that only serve unselected
+ * families do not run: triangles only skip the star/pair sweeps, stars and
+ * pairs only skip the triangle kernels, pairs only also skip the Star_I
+ * sweep.  TM_EINVAL for families == 0 or bits beyond TM_ALL_MOTIFS; other
+ * errors as tm_count.
+ */
+int tm_count_masked(tm_graph *g, int64_t delta, uint32_t families, uint64_t out[36]);
 
 /* The paper's raw counters (layout above), 56 x uint64, for window delta. */
 int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]);

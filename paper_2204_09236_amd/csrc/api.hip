@@ -264,7 +264,8 @@ int tm_build_batch(const int32_t *src, const int32_t *dst, const int64_t *t,
 }
 
 static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
-                        uint32_t tri_lane_max, uint64_t *raw, bool use_graph) {
+                        uint32_t tri_lane_max, uint64_t *raw, bool use_graph,
+                        uint32_t families = TM_ALL_MOTIFS) {
     if (!g || !raw || !deltas) {
         tmc::set_error("NULL graph, deltas or output");
         return TM_EINVAL;
@@ -281,7 +282,7 @@ static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
     int rc;
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        rc = tmc::count_graph(g, deltas, run_chunk, tri_lane_max, tmp.data(), use_graph);
+        rc = tmc::count_graph(g, deltas, run_chunk, tri_lane_max, tmp.data(), use_graph, families);
     }
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc) return rc;
@@ -403,6 +404,25 @@ int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]) {
     }
     uint64_t raw[56];
     int rc = tm_count_raw(g, delta, raw);
+    if (rc) return rc;
+    return tm_merge(raw, out);
+}
+
+int tm_count_masked(tm_graph *g, int64_t delta, uint32_t families, uint64_t out[36]) {
+    if (!out) {
+        tmc::set_error("NULL output");
+        return TM_EINVAL;
+    }
+    if (families == 0 || (families & ~(uint32_t)TM_ALL_MOTIFS)) {
+        tmc::set_error("families must be a nonzero OR of TM_STARS, TM_PAIRS, TM_TRIANGLES");
+        return TM_EINVAL;
+    }
+    if (g && g->G != 1) {
+        tmc::set_error("a batch of several graphs is counted with tm_count_batch");
+        return TM_EINVAL;
+    }
+    uint64_t raw[56];
+    int rc = count_common(g, &delta, 0, 0, raw, false, families);
     if (rc) return rc;
     return tm_merge(raw, out);
 }

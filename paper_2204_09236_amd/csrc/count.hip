@@ -310,6 +310,7 @@ struct StarArgs {
     uint32_t G;
     const int64_t *deltas;
     uint32_t chunk;
+    int star_i;              // run the Star_I sweep (stars requested)
 };
 
 // Largest i in [0, n) with a[i] <= x, for ascending a with a[0] <= x.
@@ -454,6 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
             }
 
             // ---- e3 sweep: Star_I
+            if (!a.star_i) continue;
             W.clear();
             uint32_t f;  // front of the window [f, q)
             {
@@ -779,12 +781,13 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
 }
 
 // Per graph: item tiles (star/pair) and candidate tiles (triangles).
+// A family that is not counted gets no tiles (its arrays are not read).
 __global__ void k_graph_tiles(const uint32_t *first, const uint32_t *mpb, const uint32_t *tidx,
-                              const uint32_t *eoff, uint32_t G, uint32_t *n_item_tiles,
-                              uint32_t *n_cand_tiles) {
+                              const uint32_t *eoff, uint32_t G, int star_pair, int tri,
+                              uint32_t *n_item_tiles, uint32_t *n_cand_tiles) {
     for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G; gi += gridDim.x * blockDim.x) {
-        const uint32_t items = first[mpb[gi + 1]] - first[mpb[gi]];
-        const uint32_t cands = tidx[eoff[gi + 1]] - tidx[eoff[gi]];
+        const uint32_t items = star_pair ? first[mpb[gi + 1]] - first[mpb[gi]] : 0u;
+        const uint32_t cands = tri ? tidx[eoff[gi + 1]] - tidx[eoff[gi]] : 0u;
         n_item_tiles[gi] = (items + kItemTile - 1) / kItemTile;
         n_cand_tiles[gi] = (cands + kCandTile - 1) / kCandTile;
     }
@@ -902,10 +905,13 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
 // Every kernel of one count, deltas already in w.deltas, counters to w.res
 // (G x 40).  No host synchronisation, memset or allocation: capturable.
 static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
-                         uint32_t tri_lane_max, hipStream_t s) {
+                         uint32_t tri_lane_max, uint32_t families, hipStream_t s) {
     const uint32_t G = g->G;
     SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos};
-    const uint64_t m = g->m, nm = g->n_multi, nme = g->n_me;
+    const uint64_t m = g->m, nme = g->n_me;
+    const bool do_sp = (families & (TM_STARS | TM_PAIRS)) != 0;
+    const bool do_tri = (families & TM_TRIANGLES) != 0;
+    const uint64_t nm = do_sp ? g->n_multi : 0;
     int rc;
     TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
               s, S, g->t_entries, g->n_t_entries, 2 * m, w.deltas, w.Wf);
@@ -917,19 +923,23 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
         TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
                   nm, run_chunk, w.cnt);
     }
-    rc = scan_u32_array(w.cnt, w.first, nm, w.tmp, s);
-    if (rc) return rc;
+    if (do_sp) {
+        rc = scan_u32_array(w.cnt, w.first, nm, w.tmp, s);
+        if (rc) return rc;
+    }
     // ---- triangles: candidate first edges
-    TM_LAUNCH("wbits", k_wbits, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m, w.wbits);
-    TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
-              reinterpret_cast<const uint2 *>(g->epos), w.wbits, m, w.tflag);
-    rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
-    if (rc) return rc;
-    TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
-              reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.tflag, w.tidx, m, w.cand);
+    if (do_tri) {
+        TM_LAUNCH("wbits", k_wbits, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m, w.wbits);
+        TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
+                  reinterpret_cast<const uint2 *>(g->epos), w.wbits, m, w.tflag);
+        rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
+        if (rc) return rc;
+        TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
+                  reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.tflag, w.tidx, m, w.cand);
+    }
     // ---- per-graph work tiles
     TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, w.first, g->d_mpb,
-              w.tidx, g->d_eoff, G, w.n_itiles, w.n_ctiles);
+              w.tidx, g->d_eoff, G, (int)do_sp, (int)do_tri, w.n_itiles, w.n_ctiles);
     rc = scan_u32_array(w.n_itiles, w.tfirst, G, w.tmp, s);
     if (rc) return rc;
     rc = scan_u32_array(w.n_ctiles, w.ctfirst, G, w.tmp, s);
@@ -938,12 +948,16 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
         TM_LAUNCH("item_pairs", k_item_pairs, grid_for(nme / kItemsPerThread + 1, 4096), dim3(kBlock),
                   0, s, w.first, nm, w.ipair);
         StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w, w.first, w.ipair, nm, nme,
-                    g->d_mpb, w.tfirst, G, w.deltas, run_chunk};
+                    g->d_mpb, w.tfirst, G, w.deltas, run_chunk,
+                    (families & TM_STARS) ? 1 : 0};
         TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
                   dim3(kBlock), 0, s, sa, w.spart);
     }
-    TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
-              dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max, w.tpart);
+    if (do_tri) {
+        TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
+                  dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max,
+                  w.tpart);
+    }
     TM_LAUNCH("graph_sums", k_graph_sums, dim3((unsigned)std::min<uint64_t>((uint64_t)G * kSumSplit, 16384)),
               dim3(kBlock), 0, s, w.spart, w.tfirst, w.tpart, w.ctfirst, G, w.gpart);
     TM_LAUNCH("graph_sums_fin", k_graph_sums_fin, grid_for((uint64_t)G * 40, 4096), dim3(kBlock), 0, s,
@@ -960,7 +974,7 @@ size_t count_workspace_bytes(const tm_graph *g) {
 struct Plan {
     Scratch mem;
     Workspace w;
-    uint32_t run_chunk = 0, tri_lane_max = 0;
+    uint32_t run_chunk = 0, tri_lane_max = 0, families = 0;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -986,9 +1000,12 @@ void plan_release(tm_graph *g) {
     g->plan = nullptr;
 }
 
-static int plan_prepare(tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max) {
+static int plan_prepare(tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max,
+                        uint32_t families) {
     Plan *p = g->plan;
-    if (p && p->exec && p->run_chunk == run_chunk && p->tri_lane_max == tri_lane_max) return TM_OK;
+    if (p && p->exec && p->run_chunk == run_chunk && p->tri_lane_max == tri_lane_max &&
+        p->families == families)
+        return TM_OK;
     plan_release(g);
     p = new (std::nothrow) Plan();
     if (!p) return TM_ENOMEM;
@@ -1001,10 +1018,11 @@ static int plan_prepare(tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max) 
     workspace_carve(g, p->mem, &p->w);
     p->run_chunk = run_chunk;
     p->tri_lane_max = tri_lane_max;
+    p->families = families;
     TM_HIP_TRY(hipStreamSynchronize(p->stream));
     TM_HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
     set_capturing(true);
-    rc = enqueue_count(g, p->w, run_chunk, tri_lane_max, p->stream);
+    rc = enqueue_count(g, p->w, run_chunk, tri_lane_max, families, p->stream);
     set_capturing(false);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(p->stream, &graph);
@@ -1063,7 +1081,7 @@ int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinne
     }
     uint32_t run_chunk = 0, tri_lane_max = 0;
     resolve_params(g, &run_chunk, &tri_lane_max);
-    int rc = plan_prepare(g, run_chunk, tri_lane_max);
+    int rc = plan_prepare(g, run_chunk, tri_lane_max, TM_ALL_MOTIFS);
     if (rc) return rc;
     Plan *p = g->plan;
     TM_HIP_TRY(hipEventRecord(p->ev, g->stream));
@@ -1077,13 +1095,13 @@ int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinne
 }
 
 int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t *raw, bool use_graph) {
+                uint64_t *raw, bool use_graph, uint32_t families) {
     resolve_params(g, &run_chunk, &tri_lane_max);
     const uint32_t G = g->G;
     std::vector<uint64_t> host((size_t)G * 40, 0);
     if (g->m >= 3) {
         if (use_graph) {
-            int rc = plan_prepare(g, run_chunk, tri_lane_max);
+            int rc = plan_prepare(g, run_chunk, tri_lane_max, families);
             if (rc) return rc;
             Plan *p = g->plan;
             // order after earlier work on the graph's stream, run, copy back
@@ -1103,13 +1121,24 @@ int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32
             if (rc) return rc;
             workspace_carve(g, sc, &w);
             TM_HIP_TRY(hipMemcpyAsync(w.deltas, h_deltas, G * 8, hipMemcpyHostToDevice, s));
-            rc = enqueue_count(g, w, run_chunk, tri_lane_max, s);
+            rc = enqueue_count(g, w, run_chunk, tri_lane_max, families, s);
             if (rc) return rc;
             TM_HIP_TRY(hipMemcpyAsync(host.data(), w.res, (size_t)G * 40 * 8, hipMemcpyDeviceToHost, s));
             TM_HIP_TRY(hipStreamSynchronize(s));
         }
     }
     raw_from_counters(host.data(), G, raw);
+    // families not asked for are zero (their kernels did not run, or ran
+    // only in part: the pair sweep also yields some star cells)
+    for (uint32_t gi = 0; gi < G; gi++) {
+        uint64_t *rw = raw + (size_t)gi * 56;
+        if (!(families & TM_STARS))
+            for (int i = 0; i < 24; i++) rw[i] = 0;
+        if (!(families & TM_PAIRS))
+            for (int i = 24; i < 32; i++) rw[i] = 0;
+        if (!(families & TM_TRIANGLES))
+            for (int i = 32; i < 56; i++) rw[i] = 0;
+    }
     return TM_OK;
 }
 
@@ -1143,7 +1172,7 @@ int autotune(tm_graph *g, const int64_t *h_deltas, uint32_t *best_chunk, uint32_
                 float tbest = -1;
                 for (int rep = 0; rep < 2 && rc == TM_OK; rep++) {
                     (void)hipEventRecord(e0, s);
-                    rc = enqueue_count(g, w, c, l, s);
+                    rc = enqueue_count(g, w, c, l, TM_ALL_MOTIFS, s);
                     (void)hipEventRecord(e1, s);
                     (void)hipEventSynchronize(e1);
                     float ms = 0;

@@ -196,8 +196,10 @@ int graph_max_degree(tm_graph *g, uint64_t *out);
 // Counts every graph of the batch with its own delta (host array of G) into
 // raw[G * 56] (host).  use_graph: replay the count as a captured hipGraph
 // (captured on first use for these partition parameters, then reused).
+// families: TM_STARS | TM_PAIRS | TM_TRIANGLES; the raw counters of the
+// others are zero.
 int count_graph(tm_graph *g, const int64_t *deltas, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t *raw, bool use_graph);
+                uint64_t *raw, bool use_graph, uint32_t families = TM_ALL_MOTIFS);
 void plan_release(tm_graph *g);
 void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw);
 int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,

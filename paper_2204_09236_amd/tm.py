@@ -17,6 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtm.so")
 
 TM_OK, TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_EAGAIN, TM_ENOTFOUND, TM_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+# motif families (tm_count_masked)
+STARS, PAIRS, TRIANGLES, ALL_MOTIFS = 1, 2, 4, 7
 TM_HOST_PTRS, TM_DEVICE_PTRS = 0, 1
 
 
@@ -34,6 +36,7 @@ def _load():
     lib.tm_graph_free.argtypes = [vp]
     lib.tm_graph_free.restype = None
     lib.tm_count.argtypes = [vp, ctypes.c_int64, u64p]
+    lib.tm_count_masked.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, u64p]
     lib.tm_count.restype = ctypes.c_int
     lib.tm_count_raw.argtypes = [vp, ctypes.c_int64, u64p]
     lib.tm_count_raw.restype = ctypes.c_int
@@ -123,9 +126,14 @@ class Graph:
             raise ValueError("graph was freed")
         return self._h
 
-    def count(self, delta: int) -> np.ndarray:
+    def count(self, delta: int, families: int = 7) -> np.ndarray:
+        """36 motif counts (6 x 6).  families: OR of STARS, PAIRS, TRIANGLES
+        (tm_count_masked); cells of the other families are 0."""
         out = np.zeros(36, dtype=np.uint64)
-        _check(_lib.tm_count(self.handle, int(delta), _u64(out)))
+        if families == ALL_MOTIFS:
+            _check(_lib.tm_count(self.handle, int(delta), _u64(out)))
+        else:
+            _check(_lib.tm_count_masked(self.handle, int(delta), int(families), _u64(out)))
         return out.reshape(6, 6)
 
     def count_raw(self, delta: int, run_chunk: int = 0, tri_lane_max: int = 0) -> np.ndarray:

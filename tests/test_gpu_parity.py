@@ -371,3 +371,41 @@ def test_autotune_then_count(tm):
         assert best["tri_lane_max"] in (8, 32, 64, 256, 1024)
         assert best["ms"] > 0
         np.testing.assert_array_equal(G.count_raw(86400), oracle.alg(g.src, g.dst, g.t, 86400, n=g.n))
+
+
+# motif-family masks (tm_count_masked): the selected cells equal the full
+# count, the others are zero
+STAR_CELLS = [(r, c) for r in range(6) for c in range(4)]
+PAIR_CELLS = [(r, c) for r in (4, 5) for c in (4, 5)]
+TRI_CELLS = [(r, c) for r in range(4) for c in (4, 5)]
+
+
+@pytest.mark.parametrize("families", [1, 2, 3, 4, 5, 6, 7])
+def test_masked_counts(tm, families):
+    rng = np.random.default_rng(900 + families)
+    g = graphgen.small_random(rng, 40, 3000, t_values=300, multi=0.3)
+    big = graphgen.chung_lu_pareto(901, 20_000, 400_000)
+    for src, dst, t, n, deltas in [(g.src, g.dst, g.t, g.n, [0, 5, 40]),
+                                   (big.src, big.dst, big.t, big.n, [3600, 86400])]:
+        with tm.build_graph(src, dst, t, n=n) as G:
+            for d in deltas:
+                case(f"masked families={families} m={len(src)} delta={d}")
+                full = G.count(d)
+                got = G.count(d, families=families)
+                want = np.zeros_like(full)
+                for bit, cells in ((1, STAR_CELLS), (2, PAIR_CELLS), (4, TRI_CELLS)):
+                    if families & bit:
+                        for rc in cells:
+                            want[rc] = full[rc]
+                np.testing.assert_array_equal(got, want)
+                if d == deltas[0]:
+                    np.testing.assert_array_equal(full, oracle.count(src, dst, t, d, n=n))
+
+
+def test_masked_rejects_bad_families(tm):
+    g = graphgen.chung_lu_pareto(902, 100, 1000)
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        for bad in (0, 8, 9):
+            with pytest.raises(tm.TMError) as ei:
+                G.count(100, families=bad)
+            assert ei.value.code == -1
