@@ -27,7 +27,7 @@ constexpr int64_t kTLimit = (int64_t)1 << 62;
 constexpr uint32_t kGapFill = 64;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr uint32_t kMaxStatBlocks = 4096;
-constexpr uint64_t kEntryTile = 8192, kElemTile = 8192;
+constexpr uint64_t kEntryTile = 8192, kElemTile = 1024;
 
 struct Stat {
     uint32_t bad;        // bit 0: id out of range / negative, bit 1: self-loop, bit 2: |t| too big

@@ -605,7 +605,8 @@ __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint
 
 // One block per candidate tile (kCandTile candidates of one graph); waves
 // take 64 candidates at a time; one partial row of 8 counters per tile.
-constexpr uint32_t kCandTile = 1024;
+constexpr uint32_t kCandTile = 256;
+constexpr uint32_t kTriRowsPerTile = kBlock / kWave;  // one partial row per wave
 constexpr int kRegWin = 8;
 // Wide candidates whose smaller window exceeds kHashMin entries are joined
 // through an LDS hash table of at most 2 * kHashChunk slots per wave (load
@@ -761,22 +762,15 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
             }
         }
     }
-    __shared__ uint64_t red[kBlock / kWave][8];
+    // one row per wave (no block barrier: a wave with a wide hub window does
+    // not hold the others of its block at the end of each tile)
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         uint64_t v = T.c[i];
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if (lane == 0) red[wv][i] = v;
+        if (lane == 0) partial[((uint64_t)ti * kTriRowsPerTile + wv) * 8 + i] = v;
     }
-    __syncthreads();
-    if (threadIdx.x < 8) {
-        uint64_t s = 0;
-#pragma unroll
-        for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
-        partial[(uint64_t)ti * 8 + threadIdx.x] = s;
-    }
-    __syncthreads();
   }
 }
 
@@ -810,10 +804,12 @@ __global__ void __launch_bounds__(kBlock) k_graph_sums(const uint64_t *spart, co
             const uint32_t cols = pass == 0 ? 32u : 8u;
             const uint64_t *part = pass == 0 ? spart : tpart;
             const uint32_t *fr = pass == 0 ? tfirst : ctfirst;
+            const uint64_t rpt = pass == 0 ? 1u : kTriRowsPerTile;  // rows per tile
             const uint32_t c = threadIdx.x % cols, grp = threadIdx.x / cols, groups = kBlock / cols;
             uint64_t v = 0;
-            for (uint32_t r = fr[gi] + sp * groups + grp; r < fr[gi + 1]; r += groups * kSumSplit)
-                v += part[(uint64_t)r * cols + c];
+            for (uint64_t r = fr[gi] * rpt + sp * groups + grp; r < fr[gi + 1] * rpt;
+                 r += groups * kSumSplit)
+                v += part[r * cols + c];
             lds[threadIdx.x] = v;
             __syncthreads();
             if (threadIdx.x < cols) {
@@ -873,7 +869,7 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
     return up(G * 8) + up(len * 4) + up((len / kWave + 1) * 8) + up(2 * nme * sizeof(uint4)) +
            up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * kSumSplit * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
-           up(n_tmp * 4) + up(w->max_itiles * 32 * 8) + up(w->max_ctiles * 8 * 8) +
+           up(n_tmp * 4) + up(w->max_itiles * 32 * 8) + up(w->max_ctiles * kTriRowsPerTile * 8 * 8) +
            up((size_t)G * 40 * 8) + 4096;
 }
 
@@ -897,7 +893,7 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->ctfirst = sc.take<uint32_t>(G + 1);
     w->tmp = sc.take<uint32_t>(n_tmp);
     w->spart = sc.take<uint64_t>(w->max_itiles * 32);
-    w->tpart = sc.take<uint64_t>(w->max_ctiles * 8);
+    w->tpart = sc.take<uint64_t>(w->max_ctiles * kTriRowsPerTile * 8);
     w->gpart = sc.take<uint64_t>((size_t)G * kSumSplit * 40);
     w->res = sc.take<uint64_t>((size_t)G * 40);
 }
