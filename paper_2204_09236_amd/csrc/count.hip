@@ -274,11 +274,6 @@ struct Win {
     }
 };
 
-// Accumulators: [0,24) Star[T][d1][d2][d3], [24,32) Pair[d1][d2][d3]
-struct StarAcc {
-    uint64_t c[32];
-};
-
 __device__ inline void add_sel(uint64_t &lo_cell, uint64_t &hi_cell, uint64_t v, uint64_t m1) {
     lo_cell += v & ~m1;
     hi_cell += v & m1;
@@ -327,8 +322,8 @@ __device__ inline uint32_t last_le(const uint32_t *a, uint32_t n, uint32_t x) {
 // One block per item tile (kItemTile items of one graph, one per thread);
 // one partial row of 32 counters per tile.  The tile's items cover one
 // contiguous range of elements; that range and kStageHalo elements on each
-// side are first copied into LDS with coalesced loads, so the sequential
-// window sweeps read LDS.  Elements outside the staged range (long delta
+// side (time, orientation, prefix counts) are first copied into LDS with
+// coalesced loads, so the sequential window sweeps read LDS.  Elements outside the staged range (long delta
 // halos of hub pairs, or ranges beyond the stage capacity when chunks are
 // long) are read from global memory, so the result does not depend on the
 // staging.
@@ -345,7 +340,7 @@ struct ElemView {
     uint32_t lo, hi;  // staged element range
     const int64_t *st;
     const uint8_t *so;
-    const uint4 *sa, *sw;
+    const uint4 *sa;
     const int64_t *gt;
     const uint8_t *go;
     const uint4 *ga, *gw;
@@ -371,15 +366,40 @@ struct ElemView {
         e.a1 = side ? aa.w : aa.y;
         return e;
     }
-    __device__ inline uint4 w(uint32_t k, uint32_t side) const {
-        return staged(k) ? sw[2 * (k - lo) + side] : gw[2 * (uint64_t)k + side];
-    }
+    // the window prefix counts are read once per contribution, off the
+    // sweep's dependency chain: straight from global memory
+    __device__ inline uint4 w(uint32_t k, uint32_t side) const { return gw[2 * (uint64_t)k + side]; }
 };
 
-__global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *partial) {
+// Sum a wave's lanes for cells [c0, c0 + N) of the tile's partial row: each
+// wave adds into LDS rows, then the block writes them (one barrier).
+template <int N>
+__device__ inline void star_flush(const uint64_t (&acc)[N], int c0, uint64_t (*red)[32],
+                                  uint64_t *row) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        uint64_t v = acc[i];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if (lane == 0) red[wv][c0 + i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        uint64_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; q++) s += red[q][c0 + threadIdx.x];
+        row[c0 + threadIdx.x] = s;
+    }
+}
+
+// Two phases per tile, so that only one set of accumulators is live at a
+// time (more waves fit): the e1 sweeps (Pair, Star_II, Star_III: cells
+// [8, 32)), then the e3 sweeps (Star_I: cells [0, 8)).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_star_pair(StarArgs a, uint64_t *partial) {
   __shared__ int64_t s_t[kStageCap];
   __shared__ uint4 s_a[kStageCap];
-  __shared__ uint4 s_w[2 * kStageCap];
   __shared__ uint8_t s_o[kStageCap];
   __shared__ uint64_t red[kBlock / kWave][32];
   const uint32_t n_tiles = a.tfirst[a.G];
@@ -396,26 +416,30 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
     const uint32_t lo = eb - min(eb, kStageHalo);
     const uint32_t hi = (uint32_t)min<uint64_t>(min<uint64_t>(a.n_me, (uint64_t)ee + kStageHalo),
                                                 (uint64_t)lo + kStageCap);
-    __syncthreads();  // the previous tile's sweeps are done with the stage
+    __syncthreads();  // the previous tile is done with the stage and the rows
     for (uint32_t k = lo + threadIdx.x; k < hi; k += kBlock) {
         s_t[k - lo] = a.me_t[k];
         s_o[k - lo] = a.me_o[k];
         s_a[k - lo] = a.me_a[k];
-        s_w[2 * (k - lo)] = a.me_w[2 * (uint64_t)k];
-        s_w[2 * (k - lo) + 1] = a.me_w[2 * (uint64_t)k + 1];
     }
     __syncthreads();
-    const ElemView V{lo, hi, s_t, s_o, s_a, s_w, a.me_t, a.me_o, a.me_a, a.me_w};
-    StarAcc A;
-#pragma unroll
-    for (int i = 0; i < 32; i++) A.c[i] = 0;
-    for (uint32_t it = ib + threadIdx.x; it < ie; it += blockDim.x) {
+    const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a, a.me_w};
+    uint64_t *row = partial + (uint64_t)ti * 32;
+    const uint32_t it = ib + threadIdx.x;  // one item per thread (kItemTile == kBlock)
+    uint32_t rs = 0, re = 0, cb = 0, ce = 0;
+    if (it < ie) {
         const WorkItem w = item_at(a, it);
-        const uint32_t rs = a.mp_start[w.pair], re = a.mp_start[w.pair + 1];
-        const uint32_t cb = rs + w.chunk * a.chunk;
-        const uint32_t ce = min(re, cb + a.chunk);
-        for (uint32_t side = 0; side < 2; side++) {
-            // ---- e1 sweep: Pair, Star_II, Star_III
+        rs = a.mp_start[w.pair];
+        re = a.mp_start[w.pair + 1];
+        cb = rs + w.chunk * a.chunk;
+        ce = min(re, cb + a.chunk);
+    }
+    {
+        // ---- phase 1, e1 sweeps: Pair, Star_II, Star_III (cell c -> A[c - 8])
+        uint64_t A[24];
+#pragma unroll
+        for (int i = 0; i < 24; i++) A[i] = 0;
+        for (uint32_t side = 0; side < 2 && it < ie; side++) {
             Win W;
             W.clear();
             uint32_t j = cb + 1;  // next pair edge to enter the window
@@ -442,20 +466,27 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
                     for (int dp = 0; dp < 2; dp++) {
                         const uint64_t s2 = W.S2[d][dp];
                         // Pair[d_i][d][d']
-                        add_sel(A.c[24 + 0 + d * 2 + dp], A.c[24 + 4 + d * 2 + dp], s2, m1);
+                        add_sel(A[16 + 0 + d * 2 + dp], A[16 + 4 + d * 2 + dp], s2, m1);
                         // Star_II[d_i][d][d']
                         const uint64_t v2 = W.sPm[dp][d] - W.in[dp] * pin[d] - s2;
-                        add_sel(A.c[8 + 0 + d * 2 + dp], A.c[8 + 4 + d * 2 + dp], v2, m1);
+                        add_sel(A[0 + 0 + d * 2 + dp], A[0 + 4 + d * 2 + dp], v2, m1);
                         // Star_III[d_i][d][d']
                         const uint64_t sp = W.sPm[d][dp] + (d == dp ? W.in[d] : 0ull);
                         const uint64_t v3 = W.in[d] * rp[dp] - sp - s2;
-                        add_sel(A.c[16 + 0 + d * 2 + dp], A.c[16 + 4 + d * 2 + dp], v3, m1);
+                        add_sel(A[8 + 0 + d * 2 + dp], A[8 + 4 + d * 2 + dp], v3, m1);
                     }
                 }
             }
-
-            // ---- e3 sweep: Star_I
-            if (!a.star_i) continue;
+        }
+        star_flush<24>(A, 8, red, row);
+    }
+    {
+        // ---- phase 2, e3 sweeps: Star_I (cells [0, 8))
+        uint64_t A[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) A[i] = 0;
+        for (uint32_t side = 0; side < 2 && it < ie && a.star_i; side++) {
+            Win W;
             W.clear();
             uint32_t f;  // front of the window [f, q)
             {
@@ -486,31 +517,14 @@ __global__ void __launch_bounds__(kBlock) k_star_pair(StarArgs a, uint64_t *part
                         for (int d2 = 0; d2 < 2; d2++) {
                             const uint64_t v1 = W.sPm[d2][d1] - W.in[d2] * lp[d1] - W.S2[d1][d2];
                             // Star_I[d1][d2][d3 = dir of q]
-                            add_sel(A.c[0 + d1 * 4 + d2 * 2 + 0], A.c[0 + d1 * 4 + d2 * 2 + 1], v1,
-                                    m1);
+                            add_sel(A[d1 * 4 + d2 * 2 + 0], A[d1 * 4 + d2 * 2 + 1], v1, m1);
                         }
                     }
                 }
                 W.push(eq.dir, eq.a0, eq.a1);
             }
         }
-    }
-
-    // block reduction of the 32 accumulators into this tile's row
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-#pragma unroll
-    for (int i = 0; i < 32; i++) {
-        uint64_t v = A.c[i];
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if (lane == 0) red[wv][i] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 32) {
-        uint64_t s = 0;
-#pragma unroll
-        for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
-        partial[(uint64_t)ti * 32 + threadIdx.x] = s;
+        star_flush<8>(A, 0, red, row);
     }
   }
 }
