@@ -106,12 +106,15 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
     me, nm = info["multi_pair_edges"], info["multi_pairs"]
     pn = max(passes["node"], 1)
     node_scatter = (e2 * 40 * (pn - 1) + e2 * (20 + 24)) / pn
+    # the time sort's last pass writes the rank-ordered arrays (t, input
+    # index, two node-sort entries, pair key and value: 64 B per edge)
+    pt = max(passes["time"], 1)
+    time_scatter = (m * (tk + 12) * 2 * (pt - 1) + m * (tk + 12 + 64)) / pt
     table = {
         "validate": m * 16,
         "time_keys": m * (16 + tk + 12),
         "sort_time_hist": m * tk,
-        "sort_time_scatter": m * (tk + 12) * 2,
-        "rank": m * (tk + 12 + 8 + 4 + 8 + 32 + 8 + 4),
+        "sort_time_scatter": time_scatter,
         "sort_node_hist": e2 * 4,
         "sort_node_scatter": node_scatter,
         "offsets_fill": (n + 1) * 4,
@@ -491,7 +494,8 @@ def bench_single(args):
 
     tspan = int(g.t.max() - g.t.min()) if g.m else 0
     info["tbits"] = max(tspan.bit_length(), 1)
-    passes = {"node": (max(int(g.n - 1).bit_length(), 1) + 7) // 8}
+    passes = {"node": (max(int(g.n - 1).bit_length(), 1) + 7) // 8,
+              "time": (max(info["tbits"], 1) + 7) // 8}
     wstats = {str(d): window_stats(src, dst, tt, d) for d in deltas}
     torch.cuda.empty_cache()
     # count kernels run once per delta: the model averages their bytes over deltas

@@ -104,32 +104,6 @@ __global__ void k_time_keys(const int32_t *src, const int32_t *dst, const int64_
     }
 }
 
-// From the time-sorted edges (rank r): timestamps and ids by rank, the
-// incident entries to sort by node (slot 2r: at src, out; 2r+1: at dst, in;
-// value = r << 32 | other endpoint << 1 | dir), and the node-pair keys.
-template <typename K>
-__global__ void k_rank(const K *tkey, const EdgeVal *tval, uint64_t m, const int64_t *tmin,
-                       int tbits, uint64_t n, int64_t *t_r, uint32_t *perm, uint32_t *nkey,
-                       NodeVal *nval, uint64_t *pkey, uint32_t *pval) {
-    const uint64_t tmask = tbits >= 64 ? ~0ull : ((1ull << tbits) - 1);
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
-         r += (uint64_t)gridDim.x * blockDim.x) {
-        const EdgeVal ev = tval[r];
-        const uint64_t key = (uint64_t)tkey[r];
-        const uint32_t gi = tbits >= 64 ? 0u : (uint32_t)(key >> tbits);
-        const int64_t te = (int64_t)((key & tmask) + (uint64_t)tmin[gi]);
-        t_r[r] = te;
-        perm[r] = ev.id;
-        nkey[2 * r] = ev.src;
-        nkey[2 * r + 1] = ev.dst;
-        nval[2 * r] = NodeVal{te, (uint32_t)r, ev.dst << 1};
-        nval[2 * r + 1] = NodeVal{te, (uint32_t)r, (ev.src << 1) | 1u};
-        const uint32_t lo = min(ev.src, ev.dst), hi = max(ev.src, ev.dst);
-        pkey[r] = (uint64_t)lo * n + hi;
-        pval[r] = (uint32_t)r | (ev.src == lo ? kOrientBit : 0u);
-    }
-}
-
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
@@ -430,40 +404,30 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     uint32_t *sort_err = sc.take<uint32_t>(1);
     TM_LAUNCH("sort_err_clear", k_fill_u32, dim3(1), dim3(kBlock), 0, s, sort_err, 1, 0u);
 
-    // ---- 2. time sort carrying (src, dst, id); rank-ordered arrays
-    // The sorted time data ends in one of (KA, VA) / (KB, VB); the node keys
-    // and values go to the other buffers.
+    // ---- 2. time sort carrying (src, dst, id); its last pass writes the
+    // rank-ordered arrays.  Pass i writes the (KB, VB) set when i is even, so
+    // the last pass reads (KA, VA) when the pass count is odd and the node
+    // keys and values go to the set it does not read.
     uint32_t *nkey = nullptr;
     NodeVal *nval = nullptr;
     {
+        const int tpasses = (std::max(kbits, 1) + 7) / 8;
+        const bool to_b = (tpasses % 2) == 1;
+        nkey = reinterpret_cast<uint32_t *>(to_b ? KB : KA);
+        nval = reinterpret_cast<NodeVal *>(to_b ? VB : VA);
+        const RankOut ro{g->d_tmin, G > 1 ? tbits : 64, n, TR, g->perm, nkey, nval, PKA, PVA};
         EdgeVal *ev = reinterpret_cast<EdgeVal *>(VA), *ev_alt = reinterpret_cast<EdgeVal *>(VB);
-        auto other_k = [&](const void *p) {
-            return reinterpret_cast<uint32_t *>(static_cast<const char *>(p) == KA ? KB : KA);
-        };
-        auto other_v = [&](const void *p) {
-            return reinterpret_cast<NodeVal *>(static_cast<const char *>(p) == VA ? VB : VA);
-        };
         const dim3 tgrid((unsigned)std::min<uint32_t>(n_etiles, 4096));
         if (kbits <= 32) {
             uint32_t *k = reinterpret_cast<uint32_t *>(KA), *k_alt = reinterpret_cast<uint32_t *>(KB);
             TM_LAUNCH("time_keys", k_time_keys<uint32_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
                       d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
-            TRY(radix_sort_u32_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, sort_err, s, "sort_time_hist",
-                                    "sort_time_scatter"));
-            nkey = other_k(k);
-            nval = other_v(ev);
-            TM_LAUNCH("rank", k_rank<uint32_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, g->d_tmin,
-                      G > 1 ? tbits : 64, n, TR, g->perm, nkey, nval, PKA, PVA);
+            TRY(radix_sort_time_u32(k, k_alt, ev, ev_alt, m, kbits, tmp, sort_err, s, ro));
         } else {
             uint64_t *k = reinterpret_cast<uint64_t *>(KA), *k_alt = reinterpret_cast<uint64_t *>(KB);
             TM_LAUNCH("time_keys", k_time_keys<uint64_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
                       d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
-            TRY(radix_sort_u64_edge(&k, &k_alt, &ev, &ev_alt, m, kbits, tmp, sort_err, s, "sort_time_hist",
-                                    "sort_time_scatter"));
-            nkey = other_k(k);
-            nval = other_v(ev);
-            TM_LAUNCH("rank", k_rank<uint64_t>, grid_for(m), dim3(kBlock), 0, s, k, ev, m, g->d_tmin,
-                      G > 1 ? tbits : 64, n, TR, g->perm, nkey, nval, PKA, PVA);
+            TRY(radix_sort_time_u64(k, k_alt, ev, ev_alt, m, kbits, tmp, sort_err, s, ro));
         }
     }
 

@@ -282,6 +282,26 @@ struct SeqWrite {
     }
 };
 
+template <typename K>
+struct RankWrite {
+    RankOut o;
+    __device__ inline void operator()(uint32_t r, K key, const EdgeVal &ev) const {
+        const uint64_t k = (uint64_t)key;
+        const uint32_t gi = o.tbits >= 64 ? 0u : (uint32_t)(k >> o.tbits);
+        const uint64_t tmask = o.tbits >= 64 ? ~0ull : ((1ull << o.tbits) - 1);
+        const int64_t te = (int64_t)((k & tmask) + (uint64_t)o.tmin[gi]);
+        o.t_r[r] = te;
+        o.perm[r] = ev.id;
+        o.nkey[2 * (uint64_t)r] = ev.src;
+        o.nkey[2 * (uint64_t)r + 1] = ev.dst;
+        o.nval[2 * (uint64_t)r] = NodeVal{te, r, ev.dst << 1};
+        o.nval[2 * (uint64_t)r + 1] = NodeVal{te, r, (ev.src << 1) | 1u};
+        const uint32_t lo = min(ev.src, ev.dst), hi = max(ev.src, ev.dst);
+        o.pkey[r] = (uint64_t)lo * o.n + hi;
+        o.pval[r] = r | (ev.src == lo ? kOrientBit : 0u);
+    }
+};
+
 // One digit pass.  ghist: this pass's 256 digit counts over all keys;
 // status: this pass's look-back words (tile x 256, zero on entry);
 // status_next: the next pass's words, whose row for this tile is cleared
@@ -502,9 +522,25 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
                                                s, hist_name, scatter_name, nullptr);             \
     }
 TM_RADIX_INST(radix_sort_u64, uint64_t, uint32_t)
-TM_RADIX_INST(radix_sort_u32_edge, uint32_t, EdgeVal)
-TM_RADIX_INST(radix_sort_u64_edge, uint64_t, EdgeVal)
 #undef TM_RADIX_INST
+
+int radix_sort_time_u32(uint32_t *keys, uint32_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                        uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut ro) {
+    if (n == 0) return TM_OK;
+    const RankWrite<uint32_t> fin{ro};
+    return radix_impl<uint32_t, EdgeVal, RankWrite<uint32_t>>(
+        &keys, &keys_alt, &vals, &vals_alt, n, bits < 1 ? 1 : bits, tmp, err, s, "sort_time_hist",
+        "sort_time_scatter", &fin);
+}
+
+int radix_sort_time_u64(uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                        uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut ro) {
+    if (n == 0) return TM_OK;
+    const RankWrite<uint64_t> fin{ro};
+    return radix_impl<uint64_t, EdgeVal, RankWrite<uint64_t>>(
+        &keys, &keys_alt, &vals, &vals_alt, n, bits < 1 ? 1 : bits, tmp, err, s, "sort_time_hist",
+        "sort_time_scatter", &fin);
+}
 
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
                      uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut so) {

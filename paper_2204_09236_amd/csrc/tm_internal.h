@@ -116,14 +116,34 @@ struct SeqOut {
     uint32_t *epos;
 };
 
+// Where the time sort's last pass writes: the arrays by edge rank r (rank =
+// position in (graph, t, input index) order): t_r, perm (input index), the
+// two incident entries to sort by node (slot 2r: at src, out; 2r + 1: at
+// dst, in), and the node-pair key and value (r | orientation).
+struct RankOut {
+    const int64_t *tmin;  // per graph
+    int tbits;            // time bits of the key (>= 64: one graph, no graph bits)
+    uint64_t n;           // nodes (pair key = lo * n + hi)
+    int64_t *t_r;
+    uint32_t *perm;
+    uint32_t *nkey;
+    NodeVal *nval;
+    uint64_t *pkey;
+    uint32_t *pval;
+};
+
 // hist_name / scatter_name label the sort's kernels for the tracer.
 #define TM_RADIX_DECL(NAME, K, V)                                                                \
     int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,   \
              uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name);
 TM_RADIX_DECL(radix_sort_u64, uint64_t, uint32_t)
-TM_RADIX_DECL(radix_sort_u32_edge, uint32_t, EdgeVal)
-TM_RADIX_DECL(radix_sort_u64_edge, uint64_t, EdgeVal)
 #undef TM_RADIX_DECL
+// Time sort: (graph | t key, EdgeVal) pairs on bits [0, bits); the last pass
+// writes RankOut (at least one pass always runs).
+int radix_sort_time_u32(uint32_t *keys, uint32_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                        uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut out);
+int radix_sort_time_u64(uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                        uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut out);
 // Node sort: (node, NodeVal) pairs on bits [0, bits); the last pass writes
 // SeqOut instead of the ping-pong buffers (at least one pass always runs).
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
