@@ -62,17 +62,25 @@ def parse():
     return ap.parse_args()
 
 
-def window_stats(src, dst, t, delta: int) -> dict:
-    """Delta-window facts of a graph, for the triangle kernel's byte model
+HUB_MIN_DEFAULT, HUB_CAP, HUB_SLICE = 32, 2048, 512
+
+
+def window_stats(src, dst, t, delta: int, hub_min: int = HUB_MIN_DEFAULT) -> dict:
+    """Delta-window facts of a graph, for the triangle kernels' byte models
     (measurement only, outside the timed region).  Entries of S_u are ordered
     by (node, t, edge id): interleaving the two entries of each edge by edge id
     and sorting stably by (node, t) gives that order.  W(p) = later entries of
     the same S_u within delta; a triangle candidate is an edge with non-empty
-    windows after it at both endpoints."""
+    windows after it at both endpoints.  Candidates whose larger window is at
+    least hub_min and whose smaller one is below HUB_CAP go to the slice
+    kernel: they belong to the position with the larger window (the source
+    side on a tie), and each HUB_SLICE-position slice of S holding such
+    owners reads the union of their windows once."""
     import torch
     m = src.numel()
     if m == 0:
-        return {"sum_w": 0, "cand": 0, "sum_cand_w": 0}
+        return {k: 0 for k in ("sum_w", "max_w", "cand", "sum_cand_w", "sum_cand_prod", "reg_cand",
+                                "reg_sum_w", "hub_cand", "hub_probes", "hub_tiles", "hub_union")}
     t0 = t - t.min()
     tb = max(int(t0.max().item() + delta).bit_length(), 1)
     node = torch.stack([src, dst], 1).reshape(-1).long()
@@ -85,12 +93,31 @@ def window_stats(src, dst, t, delta: int) -> dict:
     del R, skey
     pos = torch.empty_like(perm)
     pos[perm] = torch.arange(2 * m, device=perm.device)
-    ws, wd = W[pos[0::2]], W[pos[1::2]]
+    ps, pd = pos[0::2], pos[1::2]
+    ws, wd = W[ps], W[pd]
     cand = (ws > 0) & (wd > 0)
+    big, small = torch.maximum(ws, wd), torch.minimum(ws, wd)
+    hub = cand & (big >= hub_min) & (small < HUB_CAP)
+    reg = cand & ~hub
+    own = torch.where(ws >= wd, ps, pd)[hub]
+    ow = big[hub]
+    tile = own // HUB_SLICE
+    n_tiles = (2 * m + HUB_SLICE - 1) // HUB_SLICE
+    lo = torch.full((n_tiles,), 2 * m, dtype=torch.long, device=own.device)
+    hi = torch.full((n_tiles,), -1, dtype=torch.long, device=own.device)
+    lo.scatter_reduce_(0, tile, own + 1, reduce="amin")
+    hi.scatter_reduce_(0, tile, own + ow, reduce="amax")
+    used = hi >= 0
     return {"sum_w": int(W.sum().item()), "max_w": int(W.max().item()),
             "cand": int(cand.sum().item()),
             "sum_cand_w": int((ws + wd)[cand].sum().item()),
-            "sum_cand_prod": int((ws * wd)[cand].sum().item())}
+            "sum_cand_prod": int((ws * wd)[cand].sum().item()),
+            "reg_cand": int(reg.sum().item()),
+            "reg_sum_w": int((ws + wd)[reg].sum().item()),
+            "hub_cand": int(hub.sum().item()),
+            "hub_probes": int(small[hub].sum().item()),
+            "hub_tiles": int(used.sum().item()),
+            "hub_union": int((hi - lo + 1)[used].sum().item())}
 
 
 def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dict:
@@ -126,12 +153,20 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
         "windows": e2 * 16 + (n + 1) * 4,
         "star_prep": me * 32 + 2 * me * 28,
         "star_pair": me * 25 + 2 * me * 16,
-        "wbits": e2 * 4 + e2 / 8,
+        "wlevels": e2 * 4 + e2 / 8 + e2 / 4,
         "tri_flags": m * (8 + 4) + e2 / 8,
+        "hub_tiles": e2 / 4 + e2 / HUB_SLICE * 64,
     }
     if ws is not None:
-        table["tri_compact"] = m * 8 + ws["cand"] * (8 + 8 + 16)
-        table["triangles"] = ws["cand"] * 16 + ws["sum_cand_w"] * 8
+        # per-candidate kernel: its candidates' record and both windows
+        # (neighbour | dir and rank, 8 B an entry)
+        table["tri_compact"] = m * 8 + ws["reg_cand"] * (8 + 8 + 16)
+        table["triangles"] = ws["reg_cand"] * 16 + ws["reg_sum_w"] * 8
+        # slice kernel: per owner its W, rank, edge positions and the other
+        # W (20 B); per probe one entry of the smaller window; per slice the
+        # union of its owners' windows once and a row of 8 counters
+        table["tri_hub"] = (ws["hub_cand"] * 20 + ws["hub_probes"] * 8 + ws["hub_union"] * 8 +
+                            ws["hub_tiles"] * 64)
     return table
 
 
@@ -150,9 +185,9 @@ def kernel_table(prof: dict, model: dict) -> tuple[dict, str | None]:
     return kernels, dominant
 
 
-COUNT_KERNELS = ("windows", "star_prep", "item_counts", "item_pairs", "star_pair", "wbits",
-                 "tri_flags", "tri_compact", "triangles", "graph_tiles", "graph_sums",
-                 "graph_sums_fin")
+COUNT_KERNELS = ("windows", "star_prep", "item_counts", "item_pairs", "star_pair", "wlevels",
+                 "tri_flags", "tri_compact", "triangles", "hub_tiles", "tri_hub", "graph_tiles",
+                 "graph_sums", "graph_sums_fin")
 
 
 def kernel_sources(kernel: str) -> list[str]:
@@ -500,7 +535,7 @@ def bench_single(args):
     torch.cuda.empty_cache()
     # count kernels run once per delta: the model averages their bytes over deltas
     model = byte_model(g.m, g.n, info, None, passes)
-    tri = {"tri_compact": 0.0, "triangles": 0.0}
+    tri = {"tri_compact": 0.0, "triangles": 0.0, "tri_hub": 0.0}
     for d in deltas:
         md = byte_model(g.m, g.n, info, wstats[str(d)], passes)
         for k in tri:

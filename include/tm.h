@@ -64,6 +64,10 @@ enum { TM_HOST_PTRS = 0, TM_DEVICE_PTRS = 1 };
  * triangles), for tm_count_masked. */
 enum { TM_STARS = 1, TM_PAIRS = 2, TM_TRIANGLES = 4, TM_ALL_MOTIFS = 7 };
 
+/* hub_min value (tm_count_raw_tuned, tm_count_batch_raw_ex) that keeps every
+ * triangle candidate in the per-candidate kernel. */
+#define TM_HUB_OFF 0xffffffffu
+
 /*
  * Build the device-resident graph used by every count (delta-independent).
  *
@@ -122,24 +126,26 @@ int tm_count_batch_raw(tm_graph *g, const int64_t *deltas, uint64_t (*raw)[56]);
 
 /*
  * tm_count_batch_raw with explicit execution choices; results never depend
- * on them.  run_chunk / tri_lane_max as in tm_count_raw_tuned (0 = the
- * graph's tuned values, else the autotuner table's, else defaults);
+ * on them.  run_chunk / tri_lane_max / hub_min as in tm_count_raw_tuned (0 =
+ * the graph's tuned values, else the autotuner table's, else defaults);
  * use_graph = 1 replays the count as one captured hipGraph (captured on the
  * first call for these parameters and kept with the graph), 0 launches the
  * kernels one by one.  tm_count_batch / tm_count_batch_raw use the graph.
  */
 int tm_count_batch_raw_ex(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
-                          uint32_t tri_lane_max, int use_graph, uint64_t (*raw)[56]);
+                          uint32_t tri_lane_max, uint32_t hub_min, int use_graph,
+                          uint64_t (*raw)[56]);
 
 /*
- * Autotuner: times the count of g (graph i with deltas[i]) over a grid of
- * partition parameters, keeps the fastest on g (used by later counts that
- * pass 0) and in a process-wide table keyed by the graph's shape (later
- * graphs of that shape default to it).  Outputs (any may be NULL): the chosen
- * run_chunk, tri_lane_max and its time in milliseconds.
+ * Autotuner: times the count of g (graph i with deltas[i]) over partition
+ * parameters (run_chunk with tri_lane_max on a grid, then hub_min with those
+ * fixed), keeps the fastest on g (used by later counts that pass 0) and in a
+ * process-wide table keyed by the graph's shape (later graphs of that shape
+ * default to it).  Outputs (any may be NULL): the chosen run_chunk,
+ * tri_lane_max, hub_min and the count's time in milliseconds.
  */
 int tm_autotune(tm_graph *g, const int64_t *deltas, uint32_t *run_chunk, uint32_t *tri_lane_max,
-                float *best_ms);
+                uint32_t *hub_min, float *best_ms);
 
 /* Release a graph and its device memory.  NULL is ignored. */
 void tm_graph_free(tm_graph *g);
@@ -173,14 +179,21 @@ int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]);
 
 /*
  * tm_count_raw with explicit work partitioning; the result never depends on
- * these, only the schedule does.
+ * these, only the schedule does.  0 = the graph's tuned value, else the
+ * autotuner table's, else the default.
  *   run_chunk  edges of one node-pair edge set handled by one work item of
- *              the star/pair kernel (hub splitting); 0 = default
+ *              the star/pair kernel (hub splitting)
  *   tri_lane_max  window products (|W_src| * |W_dst|) up to this are counted
- *              by one lane, larger ones by a whole wavefront; 0 = default
+ *              by one lane, larger ones by a whole wavefront
+ *   hub_min    triangle candidates (first edges, Algorithm 2's triangle
+ *              search) whose larger window W holds at least hub_min entries
+ *              and whose smaller one fewer than 2048 are matched by slices
+ *              of S_u: each slice loads the union of its windows into
+ *              on-chip memory once, instead of once per candidate.
+ *              TM_HUB_OFF: never.  Default 32.
  */
 int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
-                       uint64_t raw[56]);
+                       uint32_t hub_min, uint64_t raw[56]);
 
 /*
  * Merge raw counters into the 36 motif counts (pair cells: the view from the

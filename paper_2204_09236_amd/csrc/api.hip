@@ -34,7 +34,7 @@ int Scratch::reserve(size_t bytes, hipStream_t s) {
 // ------------------------------------------------------- autotuner table
 namespace {
 std::mutex g_tune_mu;
-std::map<uint64_t, std::pair<uint32_t, uint32_t>> g_tune;
+std::map<uint64_t, tmc::Params> g_tune;
 
 int ilog2(uint64_t x) {
     int b = 0;
@@ -51,18 +51,15 @@ uint64_t shape_key(const tm_graph *g) {
 }
 }  // namespace
 
-void tune_table_lookup(const tm_graph *g, uint32_t *run_chunk, uint32_t *tri_lane_max) {
+void tune_table_lookup(const tm_graph *g, Params *p) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(shape_key(g));
-    if (it != g_tune.end()) {
-        *run_chunk = it->second.first;
-        *tri_lane_max = it->second.second;
-    }
+    if (it != g_tune.end()) *p = it->second;
 }
 
-void tune_table_store(const tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max) {
+void tune_table_store(const tm_graph *g, const Params &p) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[shape_key(g)] = {run_chunk, tri_lane_max};
+    g_tune[shape_key(g)] = p;
 }
 
 // --------------------------------------------------------------- profiler
@@ -263,9 +260,8 @@ int tm_build_batch(const int32_t *src, const int32_t *dst, const int64_t *t,
     return build_common(src, dst, t, edge_off, node_count, G, flags, hip_stream, out);
 }
 
-static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
-                        uint32_t tri_lane_max, uint64_t *raw, bool use_graph,
-                        uint32_t families = TM_ALL_MOTIFS) {
+static int count_common(tm_graph *g, const int64_t *deltas, const tmc::Params &pr, uint64_t *raw,
+                        bool use_graph, uint32_t families = TM_ALL_MOTIFS) {
     if (!g || !raw || !deltas) {
         tmc::set_error("NULL graph, deltas or output");
         return TM_EINVAL;
@@ -282,7 +278,7 @@ static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
     int rc;
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        rc = tmc::count_graph(g, deltas, run_chunk, tri_lane_max, tmp.data(), use_graph, families);
+        rc = tmc::count_graph(g, deltas, pr, tmp.data(), use_graph, families);
     }
     if (cur != g->device) (void)hipSetDevice(cur);
     if (rc) return rc;
@@ -290,14 +286,23 @@ static int count_common(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
     return TM_OK;
 }
 
+static tmc::Params params(uint32_t run_chunk, uint32_t tri_lane_max, uint32_t hub_min) {
+    tmc::Params p;
+    p.run_chunk = run_chunk;
+    p.tri_lane_max = tri_lane_max;
+    p.hub_min = hub_min;
+    return p;
+}
+
 int tm_count_batch_raw_ex(tm_graph *g, const int64_t *deltas, uint32_t run_chunk,
-                          uint32_t tri_lane_max, int use_graph, uint64_t (*raw)[56]) {
-    return count_common(g, deltas, run_chunk, tri_lane_max, raw ? &raw[0][0] : nullptr,
-                        use_graph != 0);
+                          uint32_t tri_lane_max, uint32_t hub_min, int use_graph,
+                          uint64_t (*raw)[56]) {
+    return count_common(g, deltas, params(run_chunk, tri_lane_max, hub_min),
+                        raw ? &raw[0][0] : nullptr, use_graph != 0);
 }
 
 int tm_autotune(tm_graph *g, const int64_t *deltas, uint32_t *run_chunk, uint32_t *tri_lane_max,
-                float *best_ms) {
+                uint32_t *hub_min, float *best_ms) {
     if (!g || !deltas) {
         tmc::set_error("NULL graph or deltas");
         return TM_EINVAL;
@@ -313,14 +318,20 @@ int tm_autotune(tm_graph *g, const int64_t *deltas, uint32_t *run_chunk, uint32_
     int rc;
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        rc = tmc::autotune(g, deltas, run_chunk, tri_lane_max, best_ms);
+        tmc::Params best;
+        rc = tmc::autotune(g, deltas, &best, best_ms);
+        if (rc == TM_OK) {
+            if (run_chunk) *run_chunk = best.run_chunk;
+            if (tri_lane_max) *tri_lane_max = best.tri_lane_max;
+            if (hub_min) *hub_min = best.hub_min;
+        }
     }
     if (cur != g->device) (void)hipSetDevice(cur);
     return rc;
 }
 
 int tm_count_batch_raw(tm_graph *g, const int64_t *deltas, uint64_t (*raw)[56]) {
-    return count_common(g, deltas, 0, 0, raw ? &raw[0][0] : nullptr, true);
+    return count_common(g, deltas, tmc::Params(), raw ? &raw[0][0] : nullptr, true);
 }
 
 int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]) {
@@ -329,7 +340,7 @@ int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]) {
         return TM_EINVAL;
     }
     std::vector<uint64_t> raw((size_t)g->G * 56);
-    int rc = count_common(g, deltas, 0, 0, raw.data(), true);
+    int rc = count_common(g, deltas, tmc::Params(), raw.data(), true);
     if (rc) return rc;
     std::vector<uint64_t> res((size_t)g->G * 36);
     for (uint32_t i = 0; i < g->G; i++) {
@@ -342,16 +353,16 @@ int tm_count_batch(tm_graph *g, const int64_t *deltas, uint64_t (*out)[36]) {
 }
 
 int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t tri_lane_max,
-                       uint64_t raw[56]) {
+                       uint32_t hub_min, uint64_t raw[56]) {
     if (g && g->G != 1) {
         tmc::set_error("a batch of several graphs is counted with tm_count_batch");
         return TM_EINVAL;
     }
-    return count_common(g, &delta, run_chunk, tri_lane_max, raw, false);
+    return count_common(g, &delta, params(run_chunk, tri_lane_max, hub_min), raw, false);
 }
 
 int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]) {
-    return tm_count_raw_tuned(g, delta, 0, 0, raw);
+    return tm_count_raw_tuned(g, delta, 0, 0, 0, raw);
 }
 
 // 36-cell layout: out[6*(row-1) + (col-1)] = M_{row,col}
@@ -422,7 +433,7 @@ int tm_count_masked(tm_graph *g, int64_t delta, uint32_t families, uint64_t out[
         return TM_EINVAL;
     }
     uint64_t raw[56];
-    int rc = count_common(g, &delta, 0, 0, raw, false, families);
+    int rc = count_common(g, &delta, tmc::Params(), raw, false, families);
     if (rc) return rc;
     return tm_merge(raw, out);
 }

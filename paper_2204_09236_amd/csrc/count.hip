@@ -565,17 +565,41 @@ __global__ void k_item_counts(const uint32_t *mp_start, uint64_t n_multi, uint32
 }
 
 // ---------------------------------------------------------------- triangles
-// One bit per entry: is its window non-empty.  The bitmap (len / 8 bytes)
-// stays in cache, so the per-edge lookups at two unrelated positions below
-// do not each fetch a line of Wf from HBM.
-__global__ void k_wbits(const uint32_t *Wf, uint64_t len, uint64_t *bits) {
+// Candidates whose larger window holds at least hub_min entries, and whose
+// smaller one fewer than kHubCap, go to the slice kernel k_tri_hub below;
+// the rest to the per-candidate kernel k_triangles.
+constexpr uint32_t kHubSlice = 512;          // S positions per hub tile
+constexpr uint32_t kHubBlock = 512;          // threads of a k_tri_hub block
+constexpr uint32_t kHubPer = kHubSlice / kHubBlock;  // positions per thread
+static_assert(kHubSlice % kHubBlock == 0, "hub slice");
+constexpr uint32_t kHubCap = 2048;           // window entries per LDS segment
+constexpr uint32_t kHubSlots = 2 * kHubCap;  // hash slots (load factor <= 1/2)
+constexpr uint32_t kHubBits = 12;            // log2(kHubSlots)
+static_assert((1u << kHubBits) == kHubSlots, "hub table size");
+
+// Window bits of each entry: bits[g] holds W >= 1 for entries 64g .. 64g+63;
+// lev[2g], lev[2g + 1] hold W >= t2 and W >= t3, where (t2, t3) are hub_min
+// and kHubCap in increasing order, side by side so one 16-byte load answers
+// both.  Every edge needs the first bitmap at its two entries, only
+// candidates the second (len / 8 and len / 4 bytes, kept in cache), so the
+// per-edge lookups at two unrelated positions do not each fetch a line of Wf
+// from HBM.
+__global__ void k_wlevels(const uint32_t *Wf, uint64_t len, uint32_t hub_min, uint64_t *bits,
+                          uint64_t *lev) {
     const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t t2 = min(hub_min, kHubCap), t3 = max(hub_min, kHubCap);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // the loop bound is rounded up to whole waves so every lane takes part in the ballot
+    // the loop bound is rounded up to whole waves so every lane takes part in the ballots
     const uint64_t lim = (len + kWave - 1) / kWave * kWave;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < lim; p += stride) {
-        const uint64_t b = __ballot(p < len && Wf[p] != 0);
-        if (lane == 0) bits[p / kWave] = b;
+        const uint32_t w = p < len ? Wf[p] : 0u;
+        const uint64_t b = __ballot(w != 0);
+        const uint64_t b2 = __ballot(w >= t2);
+        const uint64_t b3 = __ballot(w >= t3);
+        if (lane == 0) {
+            bits[p / kWave] = b;
+            reinterpret_cast<ulonglong2 *>(lev)[p / kWave] = make_ulonglong2(b2, b3);
+        }
     }
 }
 
@@ -583,13 +607,36 @@ __device__ inline bool wbit(const uint64_t *bits, uint32_t p) {
     return (bits[p / kWave] >> (p % kWave)) & 1ull;
 }
 
-// Candidate first edges: both windows after the edge (at its source and at
-// its destination) hold at least one entry.
-__global__ void k_tri_flags(const uint2 *epos2, const uint64_t *bits, uint64_t m, uint32_t *flag) {
+// (W >= t2, W >= t3) of entry p as bits 0 and 1
+__device__ inline uint32_t wlevel(const uint64_t *lev, uint32_t p) {
+    const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(lev)[p / kWave];
+    const uint32_t sh = p % kWave;
+    return (uint32_t)((v.x >> sh) & 1ull) | ((uint32_t)((v.y >> sh) & 1ull) << 1);
+}
+
+// Bits of 64 entries (word g of the planes) with W >= hub_min.
+__device__ inline uint64_t hub_word(const uint64_t *lev, uint64_t g, bool hub_first) {
+    const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(lev)[g];
+    return hub_first ? v.x : v.y;
+}
+
+// Candidate first edges for k_triangles: both windows after the edge (at its
+// source and at its destination) hold at least one entry, and the edge is
+// not one of k_tri_hub's (larger window >= hub_min, smaller < kHubCap).
+__global__ void k_tri_flags(const uint2 *epos2, const uint64_t *bits, const uint64_t *lev,
+                            uint32_t hub_min, uint64_t m, uint32_t *flag) {
+    // bit of wlevel() that holds W >= hub_min, and the one with W >= kHubCap
+    const uint32_t bh = hub_min <= kHubCap ? 1u : 2u, bc = hub_min <= kHubCap ? 2u : 1u;
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (uint64_t)gridDim.x * blockDim.x) {
         const uint2 e = epos2[r];
-        flag[r] = (wbit(bits, e.x) && wbit(bits, e.y)) ? 1u : 0u;
+        uint32_t f = 0;
+        if (wbit(bits, e.x) && wbit(bits, e.y)) {
+            const uint32_t ls = wlevel(lev, e.x), ld = wlevel(lev, e.y);
+            const bool hub = ((ls | ld) & bh) && !(ls & ld & bc);
+            f = hub ? 0u : 1u;
+        }
+        flag[r] = f;
     }
 }
 
@@ -788,61 +835,382 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
   }
 }
 
-// Per graph: item tiles (star/pair) and candidate tiles (triangles).
-// A family that is not counted gets no tiles (its arrays are not read).
-__global__ void k_graph_tiles(const uint32_t *first, const uint32_t *mpb, const uint32_t *tidx,
-                              const uint32_t *eoff, uint32_t G, int star_pair, int tri,
-                              uint32_t *n_item_tiles, uint32_t *n_cand_tiles) {
-    for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G; gi += gridDim.x * blockDim.x) {
-        const uint32_t items = star_pair ? first[mpb[gi + 1]] - first[mpb[gi]] : 0u;
-        const uint32_t cands = tri ? tidx[eoff[gi + 1]] - tidx[eoff[gi]] : 0u;
-        n_item_tiles[gi] = (items + kItemTile - 1) / kItemTile;
-        n_cand_tiles[gi] = (cands + kCandTile - 1) / kCandTile;
+// ------------------------------------------------------------ hub triangles
+// A hub candidate (larger window >= hub_min, smaller < kHubCap) belongs to
+// its "owner" position p: the side with the larger window, the source side
+// on a tie.  Its triangles are the pairs (entry of W(p), entry of the other
+// window) with equal neighbours, exactly the pairs k_triangles would match.
+// Consecutive positions of one S_u have overlapping windows, so rather than
+// reading the large window once per candidate, each tile (kHubSlice
+// positions of S) loads the union of its owners' windows into an LDS hash
+// table keyed by neighbour, one kHubCap-entry segment at a time, and every
+// owner probes it with each entry of its smaller window, keeping the matches
+// that lie in its own window (p, p + W(p)].  Per candidate the work is its
+// smaller window times the segments its window meets; the larger windows
+// are read once per tile.
+
+// Hub tiles: per graph, slices of kHubSlice positions of its S.  A slice
+// holding a position with W >= hub_min goes on the work list (in no
+// particular order: each tile writes its own row); the row of every other
+// slice is zeroed here.  *count was zeroed by k_graph_tiles.
+__global__ void k_hub_tiles(const uint64_t *lev, uint32_t hub_min, const uint32_t *eoff,
+                            const uint32_t *htfirst, uint32_t G, uint32_t *count, uint32_t *list,
+                            uint64_t *hpart) {
+    const bool hub_first = hub_min <= kHubCap;
+    const uint32_t n_tiles = htfirst[G];
+    for (uint32_t ti = blockIdx.x * blockDim.x + threadIdx.x; ti < n_tiles;
+         ti += gridDim.x * blockDim.x) {
+        const uint32_t gi = last_le(htfirst, G + 1, ti);
+        const uint32_t s0 = 2 * eoff[gi] + (ti - htfirst[gi]) * kHubSlice;
+        const uint32_t s1 = min(2 * eoff[gi + 1], s0 + kHubSlice);
+        bool any = false;
+        for (uint32_t w = s0 / kWave; w <= (s1 - 1) / kWave && !any; w++) {
+            uint64_t b = hub_word(lev, w, hub_first);
+            const uint32_t wlo = w * kWave;
+            if (s0 > wlo) b &= ~0ull << (s0 - wlo);
+            if (s1 - wlo < kWave) b &= (1ull << (s1 - wlo)) - 1;
+            any = b != 0;
+        }
+        if (any) {
+            list[atomicAdd(count, 1u)] = ti;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; i++) hpart[(uint64_t)ti * 8 + i] = 0;
+        }
     }
 }
 
-// Per graph: sum its star/pair tile rows and its triangle tile rows.  Each
-// graph's rows are split over kSumSplit blocks (a single graph can have
-// hundreds of thousands of rows); block (graph, part) writes one partial row
-// of 40, and k_graph_sums_fin adds the parts.  Integer sums, no atomics.
-constexpr uint32_t kSumSplit = 16;
+// Exclusive prefix sum over the block (NT threads) of one value per thread;
+// every thread also gets the block total.  Two block barriers.
+template <uint32_t NT>
+__device__ inline uint64_t block_scan_u64(uint64_t v, uint64_t *wtot, uint64_t &total) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
+    uint64_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wtot[wv] = x;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < NT / kWave; i++) {
+        const uint64_t sw = wtot[i];
+        off += i < wv ? sw : 0;
+        tot += sw;
+    }
+    __syncthreads();
+    total = tot;
+    return off + x - v;
+}
+
+constexpr uint64_t kLow48 = (1ull << 48) - 1;
+
+struct HubArgs {
+    SeqView S;
+    const uint2 *epos2;
+    const uint32_t *Wf;
+    const uint64_t *lev;
+    const uint32_t *eoff, *htfirst, *count, *list;
+    uint32_t G, hub_min;
+};
+
+__global__ void __launch_bounds__(kHubBlock) __attribute__((amdgpu_waves_per_eu(6, 6)))
+k_tri_hub(HubArgs a, uint64_t *hpart) {
+    __shared__ uint32_t hk[kHubSlots];             // neighbour, or kEmptyKey
+    __shared__ uint16_t ho[kHubSlots];             // entry's offset in the segment
+    __shared__ uint32_t srd[kHubCap];              // rank << 1 | dir, by segment offset
+    // owners: (p, W(p) | source side << 31, first position of the other
+    // window, its size); W(p) < 2^31 as an S_u holds fewer than 2^31 entries
+    __shared__ uint4 own_l[kHubSlice];
+    __shared__ uint16_t sidx[kHubSlice];           // owners meeting the segment
+    __shared__ uint64_t spre[kHubSlice + 1];       // their probe offsets
+    __shared__ uint32_t wmark[kHubBlock / kWave][kWave];
+    __shared__ uint64_t wtot[kHubBlock / kWave];
+    __shared__ uint64_t red[kHubBlock / kWave][8];
+    __shared__ uint32_t s_lo, s_hi;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave, nw = kHubBlock / kWave;
+    const SeqView &S = a.S;
+    const bool hub_first = a.hub_min <= kHubCap;
+    const uint32_t n_list = *a.count;
+    for (uint32_t li = blockIdx.x; li < n_list; li += gridDim.x) {
+        const uint32_t ti = a.list[li];
+        const uint32_t gi = last_le(a.htfirst, a.G + 1, ti);
+        const uint32_t s0 = 2 * a.eoff[gi] + (ti - a.htfirst[gi]) * kHubSlice;
+        const uint32_t s1 = min(2 * a.eoff[gi + 1], s0 + kHubSlice);
+        if (threadIdx.x == 0) {
+            s_lo = 0xffffffffu;
+            s_hi = 0;
+        }
+        // A. owners among this thread's positions
+        uint32_t own = 0, rp[kHubPer], rw[kHubPer], rq[kHubPer], rwo[kHubPer];
+#pragma unroll
+        for (uint32_t k = 0; k < kHubPer; k++) {
+            const uint32_t p = s0 + kHubPer * threadIdx.x + k;
+            rp[k] = p;
+            rw[k] = rq[k] = rwo[k] = 0;
+            if (p < s1 && ((hub_word(a.lev, p / kWave, hub_first) >> (p % kWave)) & 1ull)) {
+                const uint32_t W = a.Wf[p];
+                const uint2 e = a.epos2[S.rk[p]];
+                const bool is_s = e.x == p;
+                const uint32_t q = is_s ? e.y : e.x;
+                const uint32_t Wo = a.Wf[q];
+                if (Wo != 0 && Wo < kHubCap && (is_s ? W >= Wo : W > Wo)) {
+                    own |= 1u << k;
+                    rw[k] = W | (is_s ? 0x80000000u : 0u);
+                    rq[k] = q + 1;
+                    rwo[k] = Wo;
+                }
+            }
+        }
+        uint64_t n_own64;
+        uint32_t at = (uint32_t)block_scan_u64<kHubBlock>(__popc(own), wtot, n_own64);
+        const uint32_t n_own = (uint32_t)n_own64;
+#pragma unroll
+        for (uint32_t k = 0; k < kHubPer; k++)
+            if ((own >> k) & 1u) {
+                own_l[at] = make_uint4(rp[k], rw[k], rq[k], rwo[k]);
+                atomicMin(&s_lo, rp[k] + 1);
+                atomicMax(&s_hi, rp[k] + (rw[k] & 0x7fffffffu));
+                at++;
+            }
+        __syncthreads();
+        // the previous tile's row was read before the barriers above
+        if (threadIdx.x < nw * 8) red[threadIdx.x / 8][threadIdx.x % 8] = 0;
+        __syncthreads();
+        const uint64_t lo = s_lo, hi = s_hi;
+        for (uint64_t sl64 = lo; n_own != 0 && sl64 <= hi; sl64 += kHubCap) {
+            const uint32_t sl = (uint32_t)sl64;
+            const uint32_t sh = (uint32_t)min(hi, sl64 + kHubCap - 1);
+            // B. owners whose window (p, p + W] meets [sl, sh], and where
+            // their probes start in the flattened probe index; the scanned
+            // value packs count << 48 | probes (< 2^42)
+            uint32_t meet = 0;
+            uint64_t mine = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kHubPer; k++) {
+                const uint32_t i = threadIdx.x + k * kHubBlock;
+                if (i < n_own) {
+                    const uint4 o = own_l[i];
+                    const uint32_t W = o.y & 0x7fffffffu;
+                    if ((uint64_t)o.x + W >= sl && o.x + 1 <= sh) {
+                        meet |= 1u << k;
+                        mine += (1ull << 48) | o.w;
+                    }
+                }
+            }
+            uint64_t tot;
+            const uint64_t pre = block_scan_u64<kHubBlock>(mine, wtot, tot);
+            const uint32_t n_seg = (uint32_t)(tot >> 48);
+            const uint64_t t_seg = tot & kLow48;
+            {
+                uint32_t idx = (uint32_t)(pre >> 48);
+                uint64_t run = pre & kLow48;
+#pragma unroll
+                for (uint32_t k = 0; k < kHubPer; k++)
+                    if ((meet >> k) & 1u) {
+                        const uint32_t i = threadIdx.x + k * kHubBlock;
+                        sidx[idx] = (uint16_t)i;
+                        spre[idx] = run;
+                        run += own_l[i].w;
+                        idx++;
+                    }
+                if (threadIdx.x == 0) spre[n_seg] = t_seg;
+            }
+            // C. the segment's entries into the table
+            for (uint32_t i = threadIdx.x; i < kHubSlots; i += kHubBlock) hk[i] = kEmptyKey;
+            __syncthreads();
+            for (uint32_t y = sl + threadIdx.x; y <= sh; y += kHubBlock) {
+                const uint32_t nd = S.nd[y];
+                const uint32_t key = nd >> 1;
+                srd[y - sl] = (S.rk[y] << 1) | (nd & 1u);
+                uint32_t h = (key * kHashMul) >> (32 - kHubBits);
+                while (atomicCAS(&hk[h], kEmptyKey, key) != kEmptyKey) h = (h + 1) & (kHubSlots - 1);
+                ho[h] = (uint16_t)(y - sl);
+            }
+            __syncthreads();
+            // D. probes: each wave walks an equal share of the flattened index
+            // space, lane j taking probe base + j.  Every owner has at least
+            // one probe, so the probe ends spre[c + 1] are strictly
+            // increasing and at most 64 of them fall in (base, base + 64]:
+            // marking them in a 64-slot array gives each lane its owner by
+            // a popcount.  Two 64-probe steps are mapped first and their
+            // loads issued together, then both walk the table.
+            // Per-lane counts of one segment fit 32 bits: a lane takes at
+            // most t_seg / nw / 64 + 1 <= 2049 probes (t_seg < kHubSlice *
+            // kHubCap), each matching at most kHubCap entries; the wave's
+            // sums (< 2^29) go to its LDS row after the segment.
+            uint32_t T[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) T[i] = 0;
+            const uint64_t jb = t_seg * wv / nw, je = t_seg * (wv + 1) / nw;
+            if (jb < je) {
+                uint32_t c0 = 0, chi = n_seg;  // last c with spre[c] <= jb
+                while (chi - c0 > 1) {
+                    const uint32_t mid = (c0 + chi) / 2;
+                    if (spre[mid] <= jb) c0 = mid;
+                    else chi = mid;
+                }
+                uint32_t *wm = wmark[wv];
+                for (uint64_t base = jb; base < je; base += 2 * kWave) {
+                    uint32_t cu[2];
+#pragma unroll
+                    for (int u = 0; u < 2; u++) {
+                        const uint64_t bu = base + (uint64_t)u * kWave;
+                        wm[lane] = 0;
+                        wave_lds_sync();
+                        const uint32_t k = c0 + (uint32_t)lane;
+                        const uint64_t end = k < n_seg ? spre[k + 1] : ~0ull;  // > bu for k >= c0
+                        if (end - bu < kWave) wm[end - bu] = 1;
+                        wave_lds_sync();
+                        const uint64_t M = __ballot(wm[lane] != 0);
+                        const uint64_t done = __ballot(end <= bu + kWave);
+                        const uint64_t below = lane == kWave - 1 ? M : (M & ((2ull << lane) - 1));
+                        cu[u] = c0 + (uint32_t)__popcll(below);
+                        c0 += (uint32_t)__popcll(done);
+                        wave_lds_sync();
+                    }
+                    uint32_t nd[2], rx[2], pp[2], wpk[2];
+#pragma unroll
+                    for (int u = 0; u < 2; u++) {
+                        const uint64_t j = base + (uint64_t)u * kWave + (uint64_t)lane;
+                        nd[u] = rx[u] = pp[u] = wpk[u] = 0;
+                        if (j < je) {  // then cu[u] < n_seg
+                            const uint4 o = own_l[sidx[cu[u]]];
+                            const uint32_t x = o.z + (uint32_t)(j - spre[cu[u]]);
+                            pp[u] = o.x;
+                            wpk[u] = o.y;
+                            nd[u] = S.nd[x];
+                            rx[u] = S.rk[x];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; u++) {
+                        if (base + (uint64_t)u * kWave + (uint64_t)lane >= je) continue;
+                        const uint32_t key = nd[u] >> 1, p = pp[u], W = wpk[u] & 0x7fffffffu;
+                        for (uint32_t h = (key * kHashMul) >> (32 - kHubBits);; h = (h + 1) & (kHubSlots - 1)) {
+                            const uint32_t kk = hk[h];
+                            if (kk == kEmptyKey) break;
+                            if (kk == key) {
+                                const uint32_t off = ho[h], y = sl + off;
+                                if (y > p && y - p <= W) {
+                                    const uint32_t v = srd[off];
+                                    const uint32_t cls = (wpk[u] >> 31) ? tri_class(v >> 1, v & 1u, rx[u], nd[u] & 1u)
+                                                                        : tri_class(rx[u], nd[u] & 1u, v >> 1, v & 1u);
+#pragma unroll
+                                    for (int i = 0; i < 8; i++) T[i] += cls == (uint32_t)i ? 1u : 0u;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                uint32_t v = T[i];
+#pragma unroll
+                for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+                if (lane == 0) red[wv][i] += v;
+            }
+            __syncthreads();  // the next segment rewrites the table and lists
+        }
+        // one row per tile (the segment loop ended on a barrier)
+        if (threadIdx.x < 8) {
+            uint64_t v = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < nw; q++) v += red[q][threadIdx.x];
+            hpart[(uint64_t)ti * 8 + threadIdx.x] = v;
+        }
+    }
+}
+
+// Per graph: item tiles (star/pair), candidate tiles (triangles) and hub
+// tiles (slices of its S, when the hub pass runs; the hub work-list counter
+// is zeroed here).  A family that is not counted gets no tiles (its arrays
+// are not read).
+__global__ void k_graph_tiles(const uint32_t *first, const uint32_t *mpb, const uint32_t *tidx,
+                              const uint32_t *eoff, uint32_t G, int star_pair, int tri, int hub,
+                              uint32_t *n_item_tiles, uint32_t *n_cand_tiles,
+                              uint32_t *n_hub_tiles, uint32_t *hub_count) {
+    if (hub && blockIdx.x == 0 && threadIdx.x == 0) *hub_count = 0;
+    for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G; gi += gridDim.x * blockDim.x) {
+        const uint32_t items = star_pair ? first[mpb[gi + 1]] - first[mpb[gi]] : 0u;
+        const uint32_t cands = tri ? tidx[eoff[gi + 1]] - tidx[eoff[gi]] : 0u;
+        const uint32_t ents = hub ? 2 * (eoff[gi + 1] - eoff[gi]) : 0u;
+        n_item_tiles[gi] = (items + kItemTile - 1) / kItemTile;
+        n_cand_tiles[gi] = (cands + kCandTile - 1) / kCandTile;
+        n_hub_tiles[gi] = (ents + kHubSlice - 1) / kHubSlice;
+    }
+}
+
+// Per graph: sum its star/pair tile rows, its triangle tile rows and its hub
+// tile rows.  Each graph's rows are split over `split` blocks (a single
+// graph can have millions of rows); block (graph, part) writes one partial
+// row of 40, and k_graph_sums_fin adds the parts.  Integer sums, no atomics.
+constexpr uint32_t kSumSplitMin = 16, kSumSplitMax = 256;
+
+// Blocks per graph: a few graphs get many each, large batches 16.
+static uint32_t sum_split(uint32_t G) {
+    return std::max(kSumSplitMin, std::min(kSumSplitMax, 4096u / std::max(G, 1u)));
+}
 
 __global__ void __launch_bounds__(kBlock) k_graph_sums(const uint64_t *spart, const uint32_t *tfirst,
                                                        const uint64_t *tpart,
-                                                       const uint32_t *ctfirst, uint32_t G,
-                                                       uint64_t *gpart) {
+                                                       const uint32_t *ctfirst,
+                                                       const uint64_t *hpart,
+                                                       const uint32_t *htfirst, uint32_t G,
+                                                       uint32_t split, uint64_t *gpart) {
     __shared__ uint64_t lds[kBlock];
-    for (uint64_t bi = blockIdx.x; bi < (uint64_t)G * kSumSplit; bi += gridDim.x) {
-        const uint32_t gi = (uint32_t)(bi / kSumSplit), sp = (uint32_t)(bi % kSumSplit);
-        for (int pass = 0; pass < 2; pass++) {
+    for (uint64_t bi = blockIdx.x; bi < (uint64_t)G * split; bi += gridDim.x) {
+        const uint32_t gi = (uint32_t)(bi / split), sp = (uint32_t)(bi % split);
+        for (int pass = 0; pass < 3; pass++) {
             const uint32_t cols = pass == 0 ? 32u : 8u;
-            const uint64_t *part = pass == 0 ? spart : tpart;
-            const uint32_t *fr = pass == 0 ? tfirst : ctfirst;
-            const uint64_t rpt = pass == 0 ? 1u : kTriRowsPerTile;  // rows per tile
+            const uint64_t *part = pass == 0 ? spart : pass == 1 ? tpart : hpart;
+            const uint32_t *fr = pass == 0 ? tfirst : pass == 1 ? ctfirst : htfirst;
+            const uint64_t rpt = pass == 1 ? kTriRowsPerTile : 1u;  // rows per tile
             const uint32_t c = threadIdx.x % cols, grp = threadIdx.x / cols, groups = kBlock / cols;
             uint64_t v = 0;
             for (uint64_t r = fr[gi] * rpt + sp * groups + grp; r < fr[gi + 1] * rpt;
-                 r += groups * kSumSplit)
+                 r += groups * split)
                 v += part[r * cols + c];
             lds[threadIdx.x] = v;
             __syncthreads();
             if (threadIdx.x < cols) {
                 uint64_t sum = 0;
                 for (uint32_t q = 0; q < groups; q++) sum += lds[q * cols + threadIdx.x];
-                gpart[bi * 40 + (pass == 0 ? 0 : 32) + threadIdx.x] = sum;
+                // the hub rows add to the triangle columns written by pass 1
+                uint64_t *dst = &gpart[bi * 40 + (pass == 0 ? 0 : 32) + threadIdx.x];
+                *dst = pass == 2 ? *dst + sum : sum;
             }
             __syncthreads();
         }
     }
 }
 
-__global__ void k_graph_sums_fin(const uint64_t *gpart, uint32_t G, uint64_t *out) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)G * 40;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t gi = i / 40, c = i % 40;
-        uint64_t sum = 0;
-        for (uint32_t sp = 0; sp < kSumSplit; sp++) sum += gpart[(gi * kSumSplit + sp) * 40 + c];
-        out[i] = sum;
+// One block per graph: 6 groups of 40 threads take every 6th part row, then
+// one thread per counter adds the groups.
+__global__ void __launch_bounds__(kBlock) k_graph_sums_fin(const uint64_t *gpart, uint32_t G,
+                                                           uint32_t split, uint64_t *out) {
+    constexpr uint32_t kGroups = kBlock / 40;
+    __shared__ uint64_t lds[kGroups * 40];
+    const uint32_t c = threadIdx.x % 40, grp = threadIdx.x / 40;
+    for (uint32_t gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        if (grp < kGroups) {
+            uint64_t sum = 0;
+            for (uint32_t sp = grp; sp < split; sp += kGroups)
+                sum += gpart[((uint64_t)gi * split + sp) * 40 + c];
+            lds[grp * 40 + c] = sum;
+        }
+        __syncthreads();
+        if (threadIdx.x < 40) {
+            uint64_t sum = 0;
+            for (uint32_t q = 0; q < kGroups; q++) sum += lds[q * 40 + threadIdx.x];
+            out[(uint64_t)gi * 40 + threadIdx.x] = sum;
+        }
+        __syncthreads();
     }
 }
 
@@ -857,6 +1225,7 @@ dim3 grid_for(uint64_t n, uint64_t cap) {
 
 constexpr uint32_t kDefaultRunChunk = 4;
 constexpr uint32_t kDefaultTriLaneMax = 16;
+constexpr uint32_t kDefaultHubMin = 32;
 
 // ---------------------------------------------------------------- driver
 // Device workspace of one count: carved from one block, either per call or
@@ -864,13 +1233,14 @@ constexpr uint32_t kDefaultTriLaneMax = 16;
 struct Workspace {
     int64_t *deltas;
     uint32_t *Wf;
-    uint64_t *wbits;
+    uint64_t *wbits, *lev;
     uint4 *me_w;
     uint32_t *cnt, *first, *ipair, *tflag, *tidx;
     uint4 *cand;
     uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
-    uint64_t *spart, *tpart, *gpart, *res;
-    uint64_t max_itiles, max_ctiles;
+    uint32_t *n_htiles, *htfirst, *hcount, *hlist;
+    uint64_t *spart, *tpart, *hpart, *gpart, *res;
+    uint64_t max_itiles, max_ctiles, max_htiles;
 };
 
 static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
@@ -878,10 +1248,12 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
     const uint64_t m = g->m, len = 2 * m, nm = g->n_multi, nme = g->n_me;
     w->max_itiles = nme / kItemTile + G + 1;
     w->max_ctiles = m / kCandTile + G + 1;
+    w->max_htiles = len / kHubSlice + G + 1;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return up(G * 8) + up(len * 4) + up((len / kWave + 1) * 8) + up(2 * nme * sizeof(uint4)) +
-           up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * kSumSplit * 40 * 8) +
+    return up(G * 8) + up(len * 4) + up((len / kWave + 1) * 8) + up((len / kWave + 1) * 16) + up(2 * nme * sizeof(uint4)) +
+           up((G + 1) * 4) * 2 + up(4) + up(w->max_htiles * 4) + up(w->max_htiles * 8 * 8) +
+           up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * sum_split(G) * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
            up(n_tmp * 4) + up(w->max_itiles * 32 * 8) + up(w->max_ctiles * kTriRowsPerTile * 8 * 8) +
            up((size_t)G * 40 * 8) + 4096;
@@ -894,6 +1266,12 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->deltas = sc.take<int64_t>(G);
     w->Wf = sc.take<uint32_t>(len);
     w->wbits = sc.take<uint64_t>(len / kWave + 1);
+    w->lev = sc.take<uint64_t>(2 * (len / kWave + 1));
+    w->n_htiles = sc.take<uint32_t>(G + 1);
+    w->htfirst = sc.take<uint32_t>(G + 1);
+    w->hcount = sc.take<uint32_t>(1);
+    w->hlist = sc.take<uint32_t>(w->max_htiles);
+    w->hpart = sc.take<uint64_t>(w->max_htiles * 8);
     w->me_w = sc.take<uint4>(2 * nme);
     w->cnt = sc.take<uint32_t>(nm + 1);
     w->first = sc.take<uint32_t>(nm + 1);
@@ -908,19 +1286,21 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->tmp = sc.take<uint32_t>(n_tmp);
     w->spart = sc.take<uint64_t>(w->max_itiles * 32);
     w->tpart = sc.take<uint64_t>(w->max_ctiles * kTriRowsPerTile * 8);
-    w->gpart = sc.take<uint64_t>((size_t)G * kSumSplit * 40);
+    w->gpart = sc.take<uint64_t>((size_t)G * sum_split(G) * 40);
     w->res = sc.take<uint64_t>((size_t)G * 40);
 }
 
 // Every kernel of one count, deltas already in w.deltas, counters to w.res
 // (G x 40).  No host synchronisation, memset or allocation: capturable.
-static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
-                         uint32_t tri_lane_max, uint32_t families, hipStream_t s) {
+static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint32_t families,
+                         hipStream_t s) {
+    const uint32_t run_chunk = pr.run_chunk, tri_lane_max = pr.tri_lane_max;
     const uint32_t G = g->G;
     SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos};
     const uint64_t m = g->m, nme = g->n_me;
     const bool do_sp = (families & (TM_STARS | TM_PAIRS)) != 0;
     const bool do_tri = (families & TM_TRIANGLES) != 0;
+    const bool do_hub = do_tri && pr.hub_min != TM_HUB_OFF;
     const uint64_t nm = do_sp ? g->n_multi : 0;
     int rc;
     TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
@@ -939,9 +1319,10 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
     }
     // ---- triangles: candidate first edges
     if (do_tri) {
-        TM_LAUNCH("wbits", k_wbits, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m, w.wbits);
+        TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m,
+                  pr.hub_min, w.wbits, w.lev);
         TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
-                  reinterpret_cast<const uint2 *>(g->epos), w.wbits, m, w.tflag);
+                  reinterpret_cast<const uint2 *>(g->epos), w.wbits, w.lev, pr.hub_min, m, w.tflag);
         rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
         if (rc) return rc;
         TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
@@ -949,10 +1330,13 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
     }
     // ---- per-graph work tiles
     TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, w.first, g->d_mpb,
-              w.tidx, g->d_eoff, G, (int)do_sp, (int)do_tri, w.n_itiles, w.n_ctiles);
+              w.tidx, g->d_eoff, G, (int)do_sp, (int)do_tri, (int)do_hub, w.n_itiles, w.n_ctiles,
+              w.n_htiles, w.hcount);
     rc = scan_u32_array(w.n_itiles, w.tfirst, G, w.tmp, s);
     if (rc) return rc;
     rc = scan_u32_array(w.n_ctiles, w.ctfirst, G, w.tmp, s);
+    if (rc) return rc;
+    rc = scan_u32_array(w.n_htiles, w.htfirst, G, w.tmp, s);
     if (rc) return rc;
     if (nm) {
         TM_LAUNCH("item_pairs", k_item_pairs, grid_for(nme / kItemsPerThread + 1, 4096), dim3(kBlock),
@@ -968,10 +1352,20 @@ static int enqueue_count(tm_graph *g, const Workspace &w, uint32_t run_chunk,
                   dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max,
                   w.tpart);
     }
-    TM_LAUNCH("graph_sums", k_graph_sums, dim3((unsigned)std::min<uint64_t>((uint64_t)G * kSumSplit, 16384)),
-              dim3(kBlock), 0, s, w.spart, w.tfirst, w.tpart, w.ctfirst, G, w.gpart);
-    TM_LAUNCH("graph_sums_fin", k_graph_sums_fin, grid_for((uint64_t)G * 40, 4096), dim3(kBlock), 0, s,
-              w.gpart, G, w.res);
+    if (do_hub) {
+        TM_LAUNCH("hub_tiles", k_hub_tiles, grid_for(w.max_htiles, 4096), dim3(kBlock), 0, s, w.lev,
+                  pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, w.hpart);
+        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.lev, g->d_eoff, w.htfirst,
+                   w.hcount, w.hlist, G, pr.hub_min};
+        TM_LAUNCH("tri_hub", k_tri_hub, dim3((unsigned)std::min<uint64_t>(w.max_htiles, 4096)),
+                  dim3(kHubBlock), 0, s, ha, w.hpart);
+    }
+    const uint32_t split = sum_split(G);
+    TM_LAUNCH("graph_sums", k_graph_sums, dim3((unsigned)std::min<uint64_t>((uint64_t)G * split, 16384)),
+              dim3(kBlock), 0, s, w.spart, w.tfirst, w.tpart, w.ctfirst, w.hpart, w.htfirst, G,
+              split, w.gpart);
+    TM_LAUNCH("graph_sums_fin", k_graph_sums_fin, dim3(std::min<uint32_t>(G, 4096)), dim3(kBlock), 0, s,
+              w.gpart, G, split, w.res);
     return TM_OK;
 }
 
@@ -984,7 +1378,8 @@ size_t count_workspace_bytes(const tm_graph *g) {
 struct Plan {
     Scratch mem;
     Workspace w;
-    uint32_t run_chunk = 0, tri_lane_max = 0, families = 0;
+    Params pr;
+    uint32_t families = 0;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1010,12 +1405,9 @@ void plan_release(tm_graph *g) {
     g->plan = nullptr;
 }
 
-static int plan_prepare(tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max,
-                        uint32_t families) {
+static int plan_prepare(tm_graph *g, const Params &pr, uint32_t families) {
     Plan *p = g->plan;
-    if (p && p->exec && p->run_chunk == run_chunk && p->tri_lane_max == tri_lane_max &&
-        p->families == families)
-        return TM_OK;
+    if (p && p->exec && p->pr == pr && p->families == families) return TM_OK;
     plan_release(g);
     p = new (std::nothrow) Plan();
     if (!p) return TM_ENOMEM;
@@ -1026,13 +1418,12 @@ static int plan_prepare(tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max,
     int rc = p->mem.reserve(bytes, p->stream);
     if (rc) return rc;
     workspace_carve(g, p->mem, &p->w);
-    p->run_chunk = run_chunk;
-    p->tri_lane_max = tri_lane_max;
+    p->pr = pr;
     p->families = families;
     TM_HIP_TRY(hipStreamSynchronize(p->stream));
     TM_HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
     set_capturing(true);
-    rc = enqueue_count(g, p->w, run_chunk, tri_lane_max, families, p->stream);
+    rc = enqueue_count(g, p->w, pr, families, p->stream);
     set_capturing(false);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(p->stream, &graph);
@@ -1049,13 +1440,14 @@ static int plan_prepare(tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max,
     return TM_OK;
 }
 
-// Partition parameters used when a call passes 0: the graph's tuned values,
+// Partition parameters used where a call passes 0: the graph's tuned values,
 // else the autotuner table's entry for graphs of this shape, else defaults.
-static void resolve_params(const tm_graph *g, uint32_t *run_chunk, uint32_t *tri_lane_max) {
-    uint32_t rc = g->tuned_run_chunk, tl = g->tuned_tri_lane_max;
-    if (!rc || !tl) tune_table_lookup(g, &rc, &tl);
-    if (*run_chunk == 0) *run_chunk = rc ? rc : kDefaultRunChunk;
-    if (*tri_lane_max == 0) *tri_lane_max = tl ? tl : kDefaultTriLaneMax;
+static void resolve_params(const tm_graph *g, Params *pr) {
+    Params t = g->tuned;
+    if (!t.run_chunk || !t.tri_lane_max || !t.hub_min) tune_table_lookup(g, &t);
+    if (pr->run_chunk == 0) pr->run_chunk = t.run_chunk ? t.run_chunk : kDefaultRunChunk;
+    if (pr->tri_lane_max == 0) pr->tri_lane_max = t.tri_lane_max ? t.tri_lane_max : kDefaultTriLaneMax;
+    if (pr->hub_min == 0) pr->hub_min = t.hub_min ? t.hub_min : kDefaultHubMin;
 }
 
 // Raw counters (G x 56) from the kernels' per-graph counters (G x 40):
@@ -1089,9 +1481,9 @@ int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinne
         TM_HIP_TRY(hipEventRecord(done, g->stream));
         return TM_OK;
     }
-    uint32_t run_chunk = 0, tri_lane_max = 0;
-    resolve_params(g, &run_chunk, &tri_lane_max);
-    int rc = plan_prepare(g, run_chunk, tri_lane_max, TM_ALL_MOTIFS);
+    Params pr;
+    resolve_params(g, &pr);
+    int rc = plan_prepare(g, pr, TM_ALL_MOTIFS);
     if (rc) return rc;
     Plan *p = g->plan;
     TM_HIP_TRY(hipEventRecord(p->ev, g->stream));
@@ -1104,14 +1496,14 @@ int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinne
     return TM_OK;
 }
 
-int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t *raw, bool use_graph, uint32_t families) {
-    resolve_params(g, &run_chunk, &tri_lane_max);
+int count_graph(tm_graph *g, const int64_t *h_deltas, Params pr, uint64_t *raw, bool use_graph,
+                uint32_t families) {
+    resolve_params(g, &pr);
     const uint32_t G = g->G;
     std::vector<uint64_t> host((size_t)G * 40, 0);
     if (g->m >= 3) {
         if (use_graph) {
-            int rc = plan_prepare(g, run_chunk, tri_lane_max, families);
+            int rc = plan_prepare(g, pr, families);
             if (rc) return rc;
             Plan *p = g->plan;
             // order after earlier work on the graph's stream, run, copy back
@@ -1131,7 +1523,7 @@ int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32
             if (rc) return rc;
             workspace_carve(g, sc, &w);
             TM_HIP_TRY(hipMemcpyAsync(w.deltas, h_deltas, G * 8, hipMemcpyHostToDevice, s));
-            rc = enqueue_count(g, w, run_chunk, tri_lane_max, families, s);
+            rc = enqueue_count(g, w, pr, families, s);
             if (rc) return rc;
             TM_HIP_TRY(hipMemcpyAsync(host.data(), w.res, (size_t)G * 40 * 8, hipMemcpyDeviceToHost, s));
             TM_HIP_TRY(hipStreamSynchronize(s));
@@ -1153,17 +1545,21 @@ int count_graph(tm_graph *g, const int64_t *h_deltas, uint32_t run_chunk, uint32
 }
 
 // ------------------------------------------------------------- autotuner
-// Times the eager count of this graph (its own deltas) for a grid of
-// partition parameters (work-item chunk of the star/pair sweeps, lane/wave
-// split of the triangle matching) and keeps the fastest.  The result is
-// stored on the graph and in a process-wide table keyed by the graph's shape
-// (log2 of edges, of multi-pair edges, and of the graph count), which later
-// graphs of that shape use by default.
-int autotune(tm_graph *g, const int64_t *h_deltas, uint32_t *best_chunk, uint32_t *best_lane,
-             float *best_ms) {
+// Times the eager count of this graph (its own deltas) over partition
+// parameters and keeps the fastest: first the work-item chunk of the
+// star/pair sweeps with the lane/wave split of the triangle matching, then,
+// with those fixed, the window size from which triangle candidates go to the
+// hub kernel.  The result is stored on the graph and in a process-wide table
+// keyed by the graph's shape (log2 of edges, of multi-pair edges, and of the
+// graph count), which later graphs of that shape use by default.
+int autotune(tm_graph *g, const int64_t *h_deltas, Params *best, float *best_ms) {
     static const uint32_t chunks[] = {2, 4, 8, 16, 32, 64};
     static const uint32_t lanes[] = {8, 32, 64, 256, 1024};
-    uint32_t bc = kDefaultRunChunk, bl = kDefaultTriLaneMax;
+    static const uint32_t hubs[] = {16, 32, 64, 128, 256, 1024, TM_HUB_OFF};
+    Params bp;
+    bp.run_chunk = kDefaultRunChunk;
+    bp.tri_lane_max = kDefaultTriLaneMax;
+    bp.hub_min = kDefaultHubMin;
     float bt = 0;
     if (g->m >= 3) {
         hipStream_t s = g->stream;
@@ -1177,34 +1573,50 @@ int autotune(tm_graph *g, const int64_t *h_deltas, uint32_t *best_chunk, uint32_
         TM_HIP_TRY(hipEventCreate(&e0));
         TM_HIP_TRY(hipEventCreate(&e1));
         bt = -1;
+        // best of two runs of one setting; -1 on error
+        auto time_one = [&](const Params &pr) -> float {
+            float tbest = -1;
+            for (int rep = 0; rep < 2 && rc == TM_OK; rep++) {
+                (void)hipEventRecord(e0, s);
+                rc = enqueue_count(g, w, pr, TM_ALL_MOTIFS, s);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (tbest < 0 || ms < tbest) tbest = ms;
+            }
+            return rc == TM_OK ? tbest : -1.0f;
+        };
         for (uint32_t c : chunks)
             for (uint32_t l : lanes) {
-                float tbest = -1;
-                for (int rep = 0; rep < 2 && rc == TM_OK; rep++) {
-                    (void)hipEventRecord(e0, s);
-                    rc = enqueue_count(g, w, c, l, TM_ALL_MOTIFS, s);
-                    (void)hipEventRecord(e1, s);
-                    (void)hipEventSynchronize(e1);
-                    float ms = 0;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    if (tbest < 0 || ms < tbest) tbest = ms;
-                }
+                Params pr = bp;
+                pr.run_chunk = c;
+                pr.tri_lane_max = l;
+                const float t = time_one(pr);
                 if (rc) break;
-                if (bt < 0 || tbest < bt) {
-                    bt = tbest;
-                    bc = c;
-                    bl = l;
+                if (bt < 0 || t < bt) {
+                    bt = t;
+                    bp = pr;
                 }
             }
+        for (uint32_t h : hubs) {
+            if (rc) break;
+            Params pr = bp;
+            pr.hub_min = h;
+            const float t = time_one(pr);
+            if (rc) break;
+            if (t < bt) {
+                bt = t;
+                bp = pr;
+            }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc) return rc;
     }
-    g->tuned_run_chunk = bc;
-    g->tuned_tri_lane_max = bl;
-    tune_table_store(g, bc, bl);
-    if (best_chunk) *best_chunk = bc;
-    if (best_lane) *best_lane = bl;
+    g->tuned = bp;
+    tune_table_store(g, bp);
+    if (best) *best = bp;
     if (best_ms) *best_ms = bt;
     return TM_OK;
 }

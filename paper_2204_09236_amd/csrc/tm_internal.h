@@ -155,6 +155,16 @@ int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal 
 // ------------------------------------------------------------------ graph
 namespace tmc {
 struct Plan;
+// Partition parameters of a count; the counts never depend on them.  0 in a
+// call means: the graph's tuned value, else the autotuner table's, else the
+// default.  hub_min = TM_HUB_OFF keeps every triangle candidate in the
+// per-candidate kernel.
+struct Params {
+    uint32_t run_chunk = 0, tri_lane_max = 0, hub_min = 0;
+    bool operator==(const Params &o) const {
+        return run_chunk == o.run_chunk && tri_lane_max == o.tri_lane_max && hub_min == o.hub_min;
+    }
+};
 }
 
 struct tm_graph {
@@ -177,7 +187,7 @@ struct tm_graph {
     // captured count sequence for repeated counts (see count.hip)
     tmc::Plan *plan = nullptr;
     // partition parameters picked by the autotuner (0 = not tuned)
-    uint32_t tuned_run_chunk = 0, tuned_tri_lane_max = 0;
+    tmc::Params tuned;
     uint32_t n = 0;
     uint64_t m = 0;
     uint64_t max_degree = 0;
@@ -218,8 +228,8 @@ int graph_max_degree(tm_graph *g, uint64_t *out);
 // (captured on first use for these partition parameters, then reused).
 // families: TM_STARS | TM_PAIRS | TM_TRIANGLES; the raw counters of the
 // others are zero.
-int count_graph(tm_graph *g, const int64_t *deltas, uint32_t run_chunk, uint32_t tri_lane_max,
-                uint64_t *raw, bool use_graph, uint32_t families = TM_ALL_MOTIFS);
+int count_graph(tm_graph *g, const int64_t *deltas, Params pr, uint64_t *raw, bool use_graph,
+                uint32_t families = TM_ALL_MOTIFS);
 void plan_release(tm_graph *g);
 void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw);
 int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,
@@ -231,8 +241,7 @@ size_t count_workspace_bytes(const tm_graph *g);
 // Upper bound of device bytes a build of m edges uses at its peak.
 size_t build_peak_bytes(uint64_t m, uint64_t n, uint32_t G);
 // Autotuner (count.hip) and its process-wide table (api.hip).
-int autotune(tm_graph *g, const int64_t *deltas, uint32_t *best_chunk, uint32_t *best_lane,
-             float *best_ms);
-void tune_table_lookup(const tm_graph *g, uint32_t *run_chunk, uint32_t *tri_lane_max);
-void tune_table_store(const tm_graph *g, uint32_t run_chunk, uint32_t tri_lane_max);
+int autotune(tm_graph *g, const int64_t *deltas, Params *best, float *best_ms);
+void tune_table_lookup(const tm_graph *g, Params *p);
+void tune_table_store(const tm_graph *g, const Params &p);
 }  // namespace tmc

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtm.so")
 TM_OK, TM_EINVAL, TM_ENOMEM, TM_EHIP, TM_EAGAIN, TM_ENOTFOUND, TM_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 # motif families (tm_count_masked)
 STARS, PAIRS, TRIANGLES, ALL_MOTIFS = 1, 2, 4, 7
+HUB_OFF = 0xFFFFFFFF   # hub_min value that keeps the hub triangle pass off
 TM_HOST_PTRS, TM_DEVICE_PTRS = 0, 1
 
 
@@ -40,7 +41,8 @@ def _load():
     lib.tm_count.restype = ctypes.c_int
     lib.tm_count_raw.argtypes = [vp, ctypes.c_int64, u64p]
     lib.tm_count_raw.restype = ctypes.c_int
-    lib.tm_count_raw_tuned.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, u64p]
+    lib.tm_count_raw_tuned.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_uint32, u64p]
     lib.tm_count_raw_tuned.restype = ctypes.c_int
     lib.tm_merge.argtypes = [u64p, u64p]
     lib.tm_merge.restype = ctypes.c_int
@@ -65,10 +67,11 @@ def _load():
     lib.tm_count_batch_raw.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), u64p]
     lib.tm_count_batch_raw.restype = ctypes.c_int
     lib.tm_count_batch_raw_ex.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32,
-                                          ctypes.c_uint32, ctypes.c_int, u64p]
+                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, u64p]
     lib.tm_count_batch_raw_ex.restype = ctypes.c_int
     lib.tm_autotune.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32),
-                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]
+                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.POINTER(ctypes.c_float)]
     lib.tm_autotune.restype = ctypes.c_int
     lib.tm_server_create.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                      ctypes.POINTER(vp)]
@@ -136,10 +139,13 @@ class Graph:
             _check(_lib.tm_count_masked(self.handle, int(delta), int(families), _u64(out)))
         return out.reshape(6, 6)
 
-    def count_raw(self, delta: int, run_chunk: int = 0, tri_lane_max: int = 0) -> np.ndarray:
+    def count_raw(self, delta: int, run_chunk: int = 0, tri_lane_max: int = 0,
+                  hub_min: int = 0) -> np.ndarray:
+        """Raw counters; the partition parameters (0 = tuned or default,
+        hub_min=HUB_OFF: no hub pass) change the schedule, never the result."""
         raw = np.zeros(56, dtype=np.uint64)
         _check(_lib.tm_count_raw_tuned(self.handle, int(delta), int(run_chunk), int(tri_lane_max),
-                                       _u64(raw)))
+                                       int(hub_min), _u64(raw)))
         return raw
 
     @property
@@ -168,21 +174,21 @@ class Graph:
         return out
 
     def count_batch_raw_ex(self, deltas, run_chunk: int = 0, tri_lane_max: int = 0,
-                           use_graph: bool = True) -> np.ndarray:
+                           use_graph: bool = True, hub_min: int = 0) -> np.ndarray:
         d = self._deltas(deltas)
         out = np.zeros((d.size, 56), dtype=np.uint64)
         _check(_lib.tm_count_batch_raw_ex(self.handle,
                                           d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                          int(run_chunk), int(tri_lane_max), 1 if use_graph else 0,
-                                          _u64(out)))
+                                          int(run_chunk), int(tri_lane_max), int(hub_min),
+                                          1 if use_graph else 0, _u64(out)))
         return out
 
     def autotune(self, deltas) -> dict:
         d = self._deltas(deltas)
-        c, l, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
+        c, l, h, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
         _check(_lib.tm_autotune(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                ctypes.byref(c), ctypes.byref(l), ctypes.byref(ms)))
-        return {"run_chunk": c.value, "tri_lane_max": l.value, "ms": ms.value}
+                                ctypes.byref(c), ctypes.byref(l), ctypes.byref(h), ctypes.byref(ms)))
+        return {"run_chunk": c.value, "tri_lane_max": l.value, "hub_min": h.value, "ms": ms.value}
 
     def info(self) -> dict:
         n = ctypes.c_uint32()

@@ -34,13 +34,20 @@ def gpu_raw(tm, src, dst, t, delta, n=None, **kw):
         return g.count_raw(delta, **kw)
 
 
+# hub_min settings every check runs: the default threshold, every triangle
+# candidate through the slice kernel (1: any non-empty larger window), and
+# the slice kernel off
+HUB_SETTINGS = (0, 1, 0xFFFFFFFF)
+
+
 def check(tm, src, dst, t, deltas, n=None, label=""):
     with tm.build_graph(src, dst, t, n=n) as g:
         for d in deltas:
             case(f"{label} m={len(src)} n={n} delta={d}")
             want = oracle.alg(src, dst, t, d, n=n)
-            got = g.count_raw(d)
-            np.testing.assert_array_equal(got, want, err_msg=f"{label} delta={d}")
+            for hub in HUB_SETTINGS:
+                got = g.count_raw(d, hub_min=hub)
+                np.testing.assert_array_equal(got, want, err_msg=f"{label} delta={d} hub_min={hub}")
             np.testing.assert_array_equal(g.count(d), oracle.merge(want))
 
 
@@ -108,6 +115,9 @@ def test_partitioning_invariance(tm):
             for lm in (1, 4, 64, 1 << 30):
                 case(f"partition run_chunk={rc} tri_lane_max={lm}")
                 np.testing.assert_array_equal(G.count_raw(800, run_chunk=rc, tri_lane_max=lm), want)
+        for hub in (1, 2, 3, 8, 50, 200, 0xFFFFFFFF):
+            case(f"partition hub_min={hub}")
+            np.testing.assert_array_equal(G.count_raw(800, hub_min=hub), want)
 
 
 def test_hub_pair_long_run(tm):
@@ -136,7 +146,9 @@ def test_star_hub(tm):
     bg = graphgen.small_random(rng, 151, 8000, tmax=50000)
     s = np.concatenate([src, bg.src]); d = np.concatenate([dst, bg.dst])
     tt = np.concatenate([t, bg.t])
-    check(tm, s, d, tt, [0, 300, 5000], n=151, label="star hub")
+    # at delta 50000 the center's window spans ~6,000 entries: the slice
+    # kernel's union windows take several LDS segments
+    check(tm, s, d, tt, [0, 300, 5000, 50000], n=151, label="star hub")
 
 
 def test_all_timestamps_equal(tm):
@@ -280,9 +292,12 @@ def test_batch_matches_oracle_per_graph(tm, seed, G):
         assert B.num_graphs == G
         raw = B.count_batch_raw(deltas)
         grids = B.count_batch(deltas)
+        # every candidate through the hub slices (tiles never cross graphs)
+        raw_hub = B.count_batch_raw_ex(deltas, use_graph=False, hub_min=1)
     for i, (s, d, t, n) in enumerate(graphs):
         want = oracle.alg(s, d, t, deltas[i], n=n or None)
         np.testing.assert_array_equal(raw[i], want, err_msg=f"graph {i}")
+        np.testing.assert_array_equal(raw_hub[i], want, err_msg=f"graph {i} hub_min=1")
         np.testing.assert_array_equal(grids[i], oracle.merge(want))
 
 
@@ -356,10 +371,10 @@ def test_batch_graph_replays_match_eager(tm):
             if rep == 0:
                 for i, (s, d, t, n) in enumerate(graphs):
                     np.testing.assert_array_equal(replay[i], oracle.alg(s, d, t, ds[i], n=n or None))
-        for rc, lm in ((3, 16), (1, 1)):
-            case(f"graph replay params {rc} {lm}")
-            np.testing.assert_array_equal(B.count_batch_raw_ex(deltas, rc, lm, True),
-                                          B.count_batch_raw_ex(deltas, rc, lm, False))
+        for rc, lm, hub in ((3, 16, 0), (1, 1, 0), (0, 0, 1), (0, 0, 0xFFFFFFFF)):
+            case(f"graph replay params {rc} {lm} {hub}")
+            np.testing.assert_array_equal(B.count_batch_raw_ex(deltas, rc, lm, True, hub_min=hub),
+                                          B.count_batch_raw_ex(deltas, rc, lm, False, hub_min=hub))
 
 
 def test_autotune_then_count(tm):
@@ -369,6 +384,7 @@ def test_autotune_then_count(tm):
         best = G.autotune([86400])
         assert best["run_chunk"] in (2, 4, 8, 16, 32, 64)
         assert best["tri_lane_max"] in (8, 32, 64, 256, 1024)
+        assert best["hub_min"] in (16, 32, 64, 128, 256, 1024, 0xFFFFFFFF)
         assert best["ms"] > 0
         np.testing.assert_array_equal(G.count_raw(86400), oracle.alg(g.src, g.dst, g.t, 86400, n=g.n))
 
