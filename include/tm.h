@@ -277,6 +277,41 @@ int tm_wait(tm_server *s, tm_ticket tk, uint64_t out[36], uint64_t times_ns[3],
 int tm_server_stats(tm_server *s, uint64_t stats[8]);
 void tm_server_destroy(tm_server *s);
 
+/*
+ * Incremental counts of an append-only edge stream (the frequently updated
+ * dynamic graphs of Section I).  Every batch's timestamps must be >= every
+ * earlier edge's (ties allowed; the batch's rows follow all earlier rows in
+ * id order).  An instance containing a new edge then has a new last edge,
+ * and its first edge is at most delta before it (Definition 2), so only the
+ * earlier edges with t >= (smallest new t) - delta can take part.  The
+ * stream keeps that tail on the device and, per append, builds and counts
+ * tail + batch and the tail alone; the difference of the raw counters is
+ * exactly the instances whose last edge is in the batch.  Summed over all
+ * appends it equals tm_count of the whole stream.  Older whole batches are
+ * dropped, so device memory follows the edge rate times delta.
+ *
+ * tm_stream_create: delta as in tm_count; n_nodes as in tm_build_graph (an
+ *   id bound for every batch, or 0 for none); hip_stream as in
+ *   tm_build_graph.  out receives the handle (owned until tm_stream_free).
+ * tm_stream_append: src/dst/t/m/flags as in tm_build_graph (m = 0 is a
+ *   no-op); the caller keeps the arrays, needed only during the call.
+ *   new_counts (36, may be NULL): the instances whose last edge is in this
+ *   batch.  TM_EINVAL if the batch's smallest t is below the largest t
+ *   appended before, or for tm_build_graph's edge errors (bad id, self-loop,
+ *   |t| >= 2^62); the stream is then unchanged.  Calls on one stream run one
+ *   after another.
+ * tm_stream_totals: counts of every edge appended so far (36, may be NULL),
+ *   the number of those edges and of the edges kept in the tail (either may
+ *   be NULL).
+ * tm_stream_free: releases the stream; NULL is ignored.
+ */
+typedef struct tm_stream tm_stream;
+int tm_stream_create(int64_t delta, uint32_t n_nodes, void *hip_stream, tm_stream **out);
+int tm_stream_append(tm_stream *s, const int32_t *src, const int32_t *dst, const int64_t *t,
+                     uint64_t m, int flags, uint64_t new_counts[36]);
+int tm_stream_totals(tm_stream *s, uint64_t total[36], uint64_t *edges, uint64_t *tail_edges);
+void tm_stream_free(tm_stream *s);
+
 const char *tm_strerror(int code);
 const char *tm_last_error(void);
 

@@ -4,6 +4,6 @@ The counting path runs in the HIP library ``libtm.so`` (C ABI in
 ``include/tm.h``); this package is its thin Python binding.  Importing it
 fails loudly if the library has not been built.
 """
-from .tm import (ALL_MOTIFS, HUB_OFF, PAIRS, STARS, TRIANGLES, Graph, Server, TMError,  # noqa: F401
+from .tm import (ALL_MOTIFS, HUB_OFF, PAIRS, STARS, TRIANGLES, Graph, Server, Stream, TMError,  # noqa: F401
                  build_batch, build_batch_arrays, build_graph, count, merge, prof_enable, prof_read,
                  prof_reset)

@@ -73,6 +73,14 @@ def _load():
                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_float)]
     lib.tm_autotune.restype = ctypes.c_int
+    lib.tm_stream_create.argtypes = [ctypes.c_int64, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+    lib.tm_stream_create.restype = ctypes.c_int
+    lib.tm_stream_append.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, ctypes.c_int, u64p]
+    lib.tm_stream_append.restype = ctypes.c_int
+    lib.tm_stream_totals.argtypes = [vp, u64p, u64p, u64p]
+    lib.tm_stream_totals.restype = ctypes.c_int
+    lib.tm_stream_free.argtypes = [vp]
+    lib.tm_stream_free.restype = None
     lib.tm_server_create.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                      ctypes.POINTER(vp)]
     lib.tm_server_create.restype = ctypes.c_int
@@ -315,6 +323,58 @@ def merge(raw) -> np.ndarray:
     out = np.zeros(36, dtype=np.uint64)
     _check(_lib.tm_merge(_u64(raw), _u64(out)))
     return out.reshape(6, 6)
+
+
+class Stream:
+    """Incremental counts of an append-only edge stream (tm.h: tm_stream_*).
+    ``append`` returns the 6 x 6 counts of the instances whose last edge is
+    in the batch; batches must not go back in time."""
+
+    def __init__(self, delta: int, n: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(0)
+        if stream is not None:
+            sp = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        self._sp = sp
+        _check(_lib.tm_stream_create(int(delta), int(n), sp, ctypes.byref(h)))
+        self._h = h
+
+    def append(self, src, dst, t) -> np.ndarray:
+        out = np.zeros(36, dtype=np.uint64)
+        if _is_torch_device(src):
+            import torch
+            if not (src.dtype == torch.int32 and dst.dtype == torch.int32 and t.dtype == torch.int64):
+                raise TypeError("device inputs must be int32, int32, int64 tensors")
+            src, dst, t = src.contiguous(), dst.contiguous(), t.contiguous()
+            _check(_lib.tm_stream_append(self._h, src.data_ptr(), dst.data_ptr(), t.data_ptr(),
+                                         src.numel(), TM_DEVICE_PTRS, _u64(out)))
+        else:
+            s = np.ascontiguousarray(src, dtype=np.int32)
+            d = np.ascontiguousarray(dst, dtype=np.int32)
+            tt = np.ascontiguousarray(t, dtype=np.int64)
+            if not (s.shape == d.shape == tt.shape and s.ndim == 1):
+                raise ValueError("src, dst, t must be 1-D arrays of one length")
+            _check(_lib.tm_stream_append(self._h, s.ctypes.data, d.ctypes.data, tt.ctypes.data,
+                                         s.size, TM_HOST_PTRS, _u64(out)))
+        return out.reshape(6, 6)
+
+    def totals(self) -> tuple[np.ndarray, int, int]:
+        """(6 x 6 counts of every edge so far, edges so far, edges kept in the tail)."""
+        out = np.zeros(36, dtype=np.uint64)
+        e, k = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.tm_stream_totals(self._h, _u64(out), ctypes.byref(e), ctypes.byref(k)))
+        return out.reshape(6, 6), e.value, k.value
+
+    def free(self):
+        if self._h:
+            _lib.tm_stream_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
 
 
 class Server:
