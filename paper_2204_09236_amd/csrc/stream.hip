@@ -12,9 +12,10 @@
 // are sums over instances, so the difference merges like any count, and the
 // running sum over all appends equals the count of the whole stream.
 //
-// Edges older than (largest t so far) - delta can never join a later
-// instance; whole earlier batches below the next cut are dropped, so device
-// memory follows the edge rate times delta, not the stream's length.
+// Before each append the tail is cut to the rows with t >= (smallest new t)
+// - delta (an order-preserving compaction), so it holds only the edges that
+// can meet the batch and device memory follows the edge rate times delta,
+// not the stream's length.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,10 +63,30 @@ __global__ void __launch_bounds__(kRangeBlock) k_range(const int64_t *t, uint64_
     }
 }
 
-struct Batch {
-    uint64_t end;  // one past its last row in the tail buffers
-    int64_t tmax;  // its largest t
-};
+// Rows of the tail that stay: t >= cut.
+__global__ void k_keep_flags(const int64_t *t, uint64_t len, int64_t cut, uint32_t *flag) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        flag[i] = t[i] >= cut ? 1u : 0u;
+}
+
+// Kept rows to their scanned slots (input order preserved).
+__global__ void k_keep_scatter(const int32_t *src, const int32_t *dst, const int64_t *t,
+                               const uint32_t *flag, const uint32_t *idx, uint64_t len,
+                               int32_t *nsrc, int32_t *ndst, int64_t *nt) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (!flag[i]) continue;
+        const uint32_t j = idx[i];
+        nsrc[j] = src[i];
+        ndst[j] = dst[i];
+        nt[j] = t[i];
+    }
+}
+
+dim3 grid_of(uint64_t n) {
+    return dim3((unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096)));
+}
 
 // Raw counters of the graph on rows [0, len) of the device arrays.
 int count_rows(const int32_t *src, const int32_t *dst, const int64_t *t, uint64_t len, uint32_t n,
@@ -85,15 +106,15 @@ struct tm_stream {
     uint32_t n = 0;
     int device = 0;
     hipStream_t stream = nullptr;
-    // the kept tail: rows [0, len) of these device arrays, batch by batch
+    // the kept tail: rows [0, len) of these device arrays, in id order
     int32_t *src = nullptr, *dst = nullptr;
     int64_t *t = nullptr;
     uint64_t len = 0;
-    std::vector<Batch> batches;
     bool any = false;    // an edge has been appended
     int64_t tmax = 0;    // largest t so far
     uint64_t edges = 0;  // edges appended so far
     uint64_t total[56] = {};
+    uint64_t last[56] = {};    // raw counters of the current tail (rows [0, len))
     int64_t *range = nullptr;  // device scratch: batch min and max t
     std::mutex mu;
 };
@@ -144,13 +165,44 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
         tmc::set_error("timestamps must satisfy |t| < 2^62");
         return TM_EINVAL;
     }
-    // earlier batches that end before lo - delta cannot meet the new edges
+    // tail rows with t < lo - delta cannot meet the new edges
     const int64_t cut = lo - s->delta;
-    size_t first = 0;
-    while (first < s->batches.size() && s->batches[first].tmax < cut) first++;
-    const uint64_t drop = first ? s->batches[first - 1].end : 0;
-    const uint64_t kept = s->len - drop, len = kept + m;
+    uint32_t *flag = nullptr, *idx = nullptr, *tmp = nullptr;
+    auto free_scan = [&]() {
+        tmc::dev_free(flag, s->stream);
+        tmc::dev_free(idx, s->stream);
+        tmc::dev_free(tmp, s->stream);
+    };
+    uint64_t kept = 0;
+    if (s->len) {
+        rc = tmc::dev_alloc(reinterpret_cast<void **>(&flag), s->len * 4, s->stream);
+        if (!rc) rc = tmc::dev_alloc(reinterpret_cast<void **>(&idx), (s->len + 1) * 4, s->stream);
+        if (!rc) rc = tmc::dev_alloc(reinterpret_cast<void **>(&tmp), tmc::scan_tmp_count(s->len) * 4, s->stream);
+        if (rc) {
+            free_scan();
+            return rc;
+        }
+        TM_LAUNCH("stream_keep_flags", k_keep_flags, grid_of(s->len), dim3(256), 0, s->stream, s->t,
+                  s->len, cut, flag);
+        rc = tmc::scan_u32_array(flag, idx, s->len, tmp, s->stream);
+        uint32_t h = 0;
+        if (!rc) {
+            const hipError_t e1 = hipMemcpyAsync(&h, idx + s->len, 4, hipMemcpyDeviceToHost, s->stream);
+            const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(s->stream) : e1;
+            if (e2 != hipSuccess) {
+                tmc::set_error(std::string("stream scan: ") + hipGetErrorString(e2));
+                rc = TM_EHIP;
+            }
+        }
+        if (rc) {
+            free_scan();
+            return rc;
+        }
+        kept = h;
+    }
+    const uint64_t len = kept + m;
     if (len >= (1ull << 31)) {
+        free_scan();
         tmc::set_error("tail plus batch must stay below 2^31 edges");
         return TM_EINVAL;
     }
@@ -161,20 +213,18 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
     if (!rc) rc = tmc::dev_alloc(reinterpret_cast<void **>(&ndst), len * 4, s->stream);
     if (!rc) rc = tmc::dev_alloc(reinterpret_cast<void **>(&nt), len * 8, s->stream);
     auto fail = [&](int code) {
+        free_scan();
         tmc::dev_free(nsrc, s->stream);
         tmc::dev_free(ndst, s->stream);
         tmc::dev_free(nt, s->stream);
         return code;
     };
     if (rc) return fail(rc);
+    if (kept)
+        TM_LAUNCH("stream_keep_scatter", k_keep_scatter, grid_of(s->len), dim3(256), 0, s->stream,
+                  s->src, s->dst, s->t, flag, idx, s->len, nsrc, ndst, nt);
     const hipMemcpyKind kind = flags == TM_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    hipError_t e = hipSuccess;
-    if (kept) {
-        if (e == hipSuccess) e = hipMemcpyAsync(nsrc, s->src + drop, kept * 4, hipMemcpyDeviceToDevice, s->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(ndst, s->dst + drop, kept * 4, hipMemcpyDeviceToDevice, s->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(nt, s->t + drop, kept * 8, hipMemcpyDeviceToDevice, s->stream);
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(nsrc + kept, src, m * 4, kind, s->stream);
+    hipError_t e = hipMemcpyAsync(nsrc + kept, src, m * 4, kind, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ndst + kept, dst, m * 4, kind, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(nt + kept, t, m * 8, kind, s->stream);
     if (e != hipSuccess) {
@@ -185,7 +235,10 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
     uint64_t with[56] = {}, without[56] = {};
     rc = count_rows(nsrc, ndst, nt, len, s->n, s->delta, s->stream, with);
     if (rc) return fail(rc);
-    if (kept) {
+    if (kept == s->len) {
+        // nothing was cut: the tail is the last append's tail + batch
+        for (int i = 0; i < 56; i++) without[i] = s->last[i];
+    } else if (kept) {
         rc = count_rows(nsrc, ndst, nt, kept, s->n, s->delta, s->stream, without);
         if (rc) return fail(rc);
     }
@@ -197,16 +250,13 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
         diff[i] = with[i] - without[i];
     }
     // commit
+    free_scan();
     free_tail(s);
     s->src = nsrc;
     s->dst = ndst;
     s->t = nt;
     s->len = len;
-    std::vector<Batch> nb;
-    for (size_t i = first; i < s->batches.size(); i++)
-        nb.push_back({s->batches[i].end - drop, s->batches[i].tmax});
-    nb.push_back({len, hi});
-    s->batches.swap(nb);
+    for (int i = 0; i < 56; i++) s->last[i] = with[i];
     s->any = true;
     s->tmax = std::max(s->tmax, hi);
     s->edges += m;
