@@ -605,6 +605,19 @@ def bench_single(args):
             G.count(deltas[0], families=fam)
         torch.cuda.synchronize()
         family_ms[name] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
+    # every delta of the workload in one call (tm_count_multi)
+    multi = None
+    if len(deltas) > 1:
+        mc = G.count_multi(deltas)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for _ in range(args.steps):
+            mc = G.count_multi(deltas)
+        torch.cuda.synchronize()
+        multi = {"deltas": deltas, "ms": round((time.perf_counter() - t_c) * 1e3 / args.steps, 4),
+                 "sum_of_single_counts_ms": round(sum(count_ms.values()), 4),
+                 "equals_step_counts": bool(all(np.array_equal(mc[i], counts[i])
+                                                for i in range(len(deltas))))}
     G.free()
 
     tspan = int(g.t.max() - g.t.min()) if g.m else 0
@@ -648,6 +661,7 @@ def bench_single(args):
         "roofline": roofline, "cpu_baseline": cpu, "golden": golden,
         "build_only_ms": round(build_ms, 4), "count_only_ms": count_ms,
         "count_only_family_ms": {"delta": deltas[0], **family_ms},
+        "count_multi": multi,
         "pcie_inclusive": {"ms_per_step": round(host_ms, 3),
                            "edges_per_s": round(g.m * len(deltas) / (host_ms / 1e3), 1),
                            "note": "inputs in host memory, copied in by tm_build_graph"},

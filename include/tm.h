@@ -174,6 +174,20 @@ int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]);
  */
 int tm_count_masked(tm_graph *g, int64_t delta, uint32_t families, uint64_t out[36]);
 
+/*
+ * Counts of one graph for k windows in one call (the paper's experiments
+ * sweep delta, Section V): out[i] (36 motif counts) or raw[i] (56 raw
+ * counters) for deltas[i] (host array, 0 <= delta < 2^62, any order,
+ * repeats allowed), 1 <= k <= TM_MAX_DELTAS.  The graph is built once; the
+ * count sequences of all windows run back to back on the graph's stream and
+ * their counters come back in one copy.  Each out[i] equals
+ * tm_count(g, deltas[i]).  TM_EINVAL for a batch of several graphs, k out of
+ * range or a bad delta; other errors as tm_count.
+ */
+#define TM_MAX_DELTAS 1024
+int tm_count_multi(tm_graph *g, const int64_t *deltas, uint32_t k, uint64_t (*out)[36]);
+int tm_count_multi_raw(tm_graph *g, const int64_t *deltas, uint32_t k, uint64_t (*raw)[56]);
+
 /* The paper's raw counters (layout above), 56 x uint64, for window delta. */
 int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]);
 

@@ -438,6 +438,62 @@ int tm_count_masked(tm_graph *g, int64_t delta, uint32_t families, uint64_t out[
     return tm_merge(raw, out);
 }
 
+int tm_count_multi_raw(tm_graph *g, const int64_t *deltas, uint32_t k, uint64_t (*raw)[56]) {
+    if (!g || !deltas || !raw) {
+        tmc::set_error("NULL graph, deltas or output");
+        return TM_EINVAL;
+    }
+    if (g->G != 1) {
+        tmc::set_error("a batch of several graphs is counted with tm_count_batch");
+        return TM_EINVAL;
+    }
+    if (k == 0 || k > TM_MAX_DELTAS) {
+        tmc::set_error("k must be in [1, TM_MAX_DELTAS]");
+        return TM_EINVAL;
+    }
+    for (uint32_t i = 0; i < k; i++)
+        if (deltas[i] < 0 || deltas[i] >= ((int64_t)1 << 62)) {
+            tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+            return TM_EINVAL;
+        }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    std::vector<uint64_t> tmp((size_t)k * 56);
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        rc = tmc::count_graph_multi(g, deltas, k, tmc::Params(), tmp.data());
+    }
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < k; i++)
+        for (int c = 0; c < 56; c++) raw[i][c] = tmp[(size_t)i * 56 + c];
+    return TM_OK;
+}
+
+int tm_count_multi(tm_graph *g, const int64_t *deltas, uint32_t k, uint64_t (*out)[36]) {
+    if (!out) {
+        tmc::set_error("NULL output");
+        return TM_EINVAL;
+    }
+    if (k == 0 || k > TM_MAX_DELTAS) {
+        tmc::set_error("k must be in [1, TM_MAX_DELTAS]");
+        return TM_EINVAL;
+    }
+    std::vector<uint64_t> raw((size_t)k * 56);
+    int rc = tm_count_multi_raw(g, deltas, k, reinterpret_cast<uint64_t(*)[56]>(raw.data()));
+    if (rc) return rc;
+    std::vector<uint64_t> res((size_t)k * 36);
+    for (uint32_t i = 0; i < k; i++) {
+        rc = tm_merge(raw.data() + (size_t)i * 56, res.data() + (size_t)i * 36);
+        if (rc) return rc;
+    }
+    for (uint32_t i = 0; i < k; i++)
+        for (int c = 0; c < 36; c++) out[i][c] = res[(size_t)i * 36 + c];
+    return TM_OK;
+}
+
 int tm_graph_info(const tm_graph *g, uint32_t *n, uint64_t *m, uint64_t *multi_pairs,
                   uint64_t *multi_pair_edges, uint64_t *max_degree) {
     if (!g) return TM_EINVAL;

@@ -1544,6 +1544,38 @@ int count_graph(tm_graph *g, const int64_t *h_deltas, Params pr, uint64_t *raw, 
     return TM_OK;
 }
 
+// Several windows over one built graph (G == 1) in one call: the count
+// sequence runs once per delta, back to back on the graph's stream, each
+// delta's counters copied to its own device slot, then one download and one
+// synchronisation for all of them.
+int count_graph_multi(tm_graph *g, const int64_t *h_deltas, uint32_t k, Params pr, uint64_t *raw) {
+    resolve_params(g, &pr);
+    std::vector<uint64_t> host((size_t)k * 40, 0);
+    if (g->m >= 3) {
+        hipStream_t s = g->stream;
+        Workspace w;
+        Scratch sc, sk;
+        int rc = sc.reserve(workspace_bytes(g, &w), s);
+        if (rc) return rc;
+        workspace_carve(g, sc, &w);
+        rc = sk.reserve((size_t)k * 8 + (size_t)k * 40 * 8 + 1024, s);
+        if (rc) return rc;
+        int64_t *dk = sk.take<int64_t>(k);
+        uint64_t *resk = sk.take<uint64_t>((size_t)k * 40);
+        TM_HIP_TRY(hipMemcpyAsync(dk, h_deltas, (size_t)k * 8, hipMemcpyHostToDevice, s));
+        for (uint32_t i = 0; i < k; i++) {
+            TM_HIP_TRY(hipMemcpyAsync(w.deltas, dk + i, 8, hipMemcpyDeviceToDevice, s));
+            rc = enqueue_count(g, w, pr, TM_ALL_MOTIFS, s);
+            if (rc) return rc;
+            TM_HIP_TRY(hipMemcpyAsync(resk + (size_t)i * 40, w.res, 40 * 8, hipMemcpyDeviceToDevice, s));
+        }
+        TM_HIP_TRY(hipMemcpyAsync(host.data(), resk, (size_t)k * 40 * 8, hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipStreamSynchronize(s));
+    }
+    for (uint32_t i = 0; i < k; i++) raw_from_counters(host.data() + (size_t)i * 40, 1, raw + (size_t)i * 56);
+    return TM_OK;
+}
+
 // ------------------------------------------------------------- autotuner
 // Times the eager count of this graph (its own deltas) over partition
 // parameters and keeps the fastest: first the work-item chunk of the

@@ -230,6 +230,8 @@ int graph_max_degree(tm_graph *g, uint64_t *out);
 // others are zero.
 int count_graph(tm_graph *g, const int64_t *deltas, Params pr, uint64_t *raw, bool use_graph,
                 uint32_t families = TM_ALL_MOTIFS);
+// Raw counters of one graph (G == 1) for k windows, raw[k * 56].
+int count_graph_multi(tm_graph *g, const int64_t *deltas, uint32_t k, Params pr, uint64_t *raw);
 void plan_release(tm_graph *g);
 void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw);
 int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,

@@ -73,6 +73,10 @@ def _load():
                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_float)]
     lib.tm_autotune.restype = ctypes.c_int
+    lib.tm_count_multi.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32, u64p]
+    lib.tm_count_multi.restype = ctypes.c_int
+    lib.tm_count_multi_raw.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32, u64p]
+    lib.tm_count_multi_raw.restype = ctypes.c_int
     lib.tm_stream_create.argtypes = [ctypes.c_int64, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
     lib.tm_stream_create.restype = ctypes.c_int
     lib.tm_stream_append.argtypes = [vp, vp, vp, vp, ctypes.c_uint64, ctypes.c_int, u64p]
@@ -155,6 +159,22 @@ class Graph:
         _check(_lib.tm_count_raw_tuned(self.handle, int(delta), int(run_chunk), int(tri_lane_max),
                                        int(hub_min), _u64(raw)))
         return raw
+
+    def count_multi(self, deltas) -> np.ndarray:
+        """Counts for several windows in one call: (k, 6, 6)."""
+        d = np.ascontiguousarray(deltas, dtype=np.int64).reshape(-1)
+        out = np.zeros((d.size, 36), dtype=np.uint64)
+        _check(_lib.tm_count_multi(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   d.size, _u64(out)))
+        return out.reshape(d.size, 6, 6)
+
+    def count_multi_raw(self, deltas) -> np.ndarray:
+        """Raw counters for several windows in one call: (k, 56)."""
+        d = np.ascontiguousarray(deltas, dtype=np.int64).reshape(-1)
+        out = np.zeros((d.size, 56), dtype=np.uint64)
+        _check(_lib.tm_count_multi_raw(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       d.size, _u64(out)))
+        return out
 
     @property
     def num_graphs(self) -> int:

@@ -425,3 +425,44 @@ def test_masked_rejects_bad_families(tm):
             with pytest.raises(tm.TMError) as ei:
                 G.count(100, families=bad)
             assert ei.value.code == -1
+
+
+# several windows in one call (tm_count_multi): each equals its own count
+def test_count_multi_matches_oracle_per_delta(tm):
+    rng = np.random.default_rng(71)
+    g = graphgen.small_random(rng, 30, 4000, t_values=500, tmax=20000, multi=0.4)
+    deltas = [0, 800, 50, 800, 20000, 3]           # any order, repeats allowed
+    case(f"count_multi k={len(deltas)}")
+    with tm.build_graph(g.src, g.dst, g.t, n=30) as G:
+        raw = G.count_multi_raw(deltas)
+        grids = G.count_multi(deltas)
+    for i, d in enumerate(deltas):
+        want = oracle.alg(g.src, g.dst, g.t, d, n=30)
+        np.testing.assert_array_equal(raw[i], want, err_msg=f"delta={d}")
+        np.testing.assert_array_equal(grids[i], oracle.merge(want))
+
+
+def test_count_multi_equals_single_counts_skewed(tm):
+    g = graphgen.skewed(seed=104, n=10_000, m=300_000, top_degree=1000)
+    deltas = [600, 3600, 86400]
+    case("count_multi skewed/1000")
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        multi = G.count_multi_raw(deltas)
+        for i, d in enumerate(deltas):
+            np.testing.assert_array_equal(multi[i], G.count_raw(d), err_msg=f"delta={d}")
+    np.testing.assert_array_equal(multi[1], oracle.alg(g.src, g.dst, g.t, 3600, n=g.n))
+
+
+def test_count_multi_rejects(tm):
+    rng = np.random.default_rng(72)
+    g = graphgen.small_random(rng, 8, 200)
+    case("count_multi errors")
+    with tm.build_graph(g.src, g.dst, g.t, n=8) as G:
+        with pytest.raises(tm.TMError):
+            G.count_multi([])
+        with pytest.raises(tm.TMError):
+            G.count_multi([10, -1])
+    graphs, deltas = _batch_graphs(5, 3)
+    with tm.build_batch(graphs) as B:
+        with pytest.raises(tm.TMError):
+            B.count_multi([10])
