@@ -243,6 +243,9 @@ int tm_graph_sequences(const tm_graph *g, uint32_t *off, int64_t *t, uint32_t *n
  * counting; meant for benchmarks.
  */
 void tm_prof_enable(int on);
+/* Trace only launches of this name (NULL or "": every launch), so that
+ * timing one kernel adds two events per launch of it and nothing else. */
+void tm_prof_only(const char *name);
 void tm_prof_reset(void);
 int tm_prof_read(int i, char *name, int name_cap, uint64_t *launches, double *total_ms);
 

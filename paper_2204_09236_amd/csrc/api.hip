@@ -76,6 +76,7 @@ struct ProfSum {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+std::string g_prof_only;  // trace only launches of this name (empty: all)
 std::vector<ProfRec> g_pending;
 std::vector<ProfSum> g_sums;
 std::vector<hipEvent_t> g_event_pool;  // recycled events (creation is slow)
@@ -120,6 +121,7 @@ void set_capturing(bool on) { g_capturing = on; }
 
 void prof_begin(const char *name, hipStream_t s) {
     if (!g_prof_on || g_capturing) return;
+    if (!g_prof_only.empty() && g_prof_only != name) return;
     g_cur_name = name;
     g_cur_start = take_event();
     if (g_cur_start) (void)hipEventRecord(g_cur_start, s);
@@ -540,6 +542,11 @@ int tm_graph_sequences(const tm_graph *g, uint32_t *off, int64_t *t, uint32_t *n
 void tm_prof_enable(int on) {
     std::lock_guard<std::mutex> lk(tmc::g_prof_mu);
     tmc::g_prof_on = on != 0;
+}
+
+void tm_prof_only(const char *name) {
+    std::lock_guard<std::mutex> lk(tmc::g_prof_mu);
+    tmc::g_prof_only = name ? name : "";
 }
 
 void tm_prof_reset(void) {

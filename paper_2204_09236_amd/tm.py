@@ -52,6 +52,8 @@ def _load():
     lib.tm_graph_sequences.restype = ctypes.c_int
     lib.tm_prof_enable.argtypes = [ctypes.c_int]
     lib.tm_prof_enable.restype = None
+    lib.tm_prof_only.argtypes = [ctypes.c_char_p]
+    lib.tm_prof_only.restype = None
     lib.tm_prof_reset.argtypes = []
     lib.tm_prof_reset.restype = None
     lib.tm_prof_read.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_int, u64p,
@@ -463,6 +465,11 @@ class Server:
 # ---- kernel timing
 def prof_enable(on: bool = True) -> None:
     _lib.tm_prof_enable(1 if on else 0)
+
+
+def prof_only(name: str | None) -> None:
+    """Trace only launches of ``name`` (None: all)."""
+    _lib.tm_prof_only(name.encode() if name else None)
 
 
 def prof_reset() -> None:
