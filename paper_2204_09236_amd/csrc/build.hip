@@ -491,11 +491,16 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         TM_LAUNCH("graph_ranges", k_graph_ranges, grid_for(G + 1), dim3(kBlock), 0, s, g->off, d_nb, G,
                   g->mp_lo, g->n_multi, g->mp_start, r3, g->d_mpb, r3 + 2 * (G + 1));
         std::vector<uint32_t> h(3 * (G + 1));
-        TM_HIP_TRY(hipMemcpyAsync(h.data(), r3, (G + 1) * 4, hipMemcpyDeviceToHost, s));
-        TM_HIP_TRY(hipMemcpyAsync(h.data() + (G + 1), g->d_mpb, (G + 1) * 4, hipMemcpyDeviceToHost, s));
-        TM_HIP_TRY(hipMemcpyAsync(h.data() + 2 * (G + 1), r3 + 2 * (G + 1), (G + 1) * 4,
-                                  hipMemcpyDeviceToHost, s));
-        TM_HIP_TRY(hipStreamSynchronize(s));
+        if (G == 1) {
+            // one graph: its ranges are the whole arrays, known here already
+            h = {0u, (uint32_t)len, 0u, (uint32_t)g->n_multi, 0u, (uint32_t)g->n_me};
+        } else {
+            TM_HIP_TRY(hipMemcpyAsync(h.data(), r3, (G + 1) * 4, hipMemcpyDeviceToHost, s));
+            TM_HIP_TRY(hipMemcpyAsync(h.data() + (G + 1), g->d_mpb, (G + 1) * 4, hipMemcpyDeviceToHost, s));
+            TM_HIP_TRY(hipMemcpyAsync(h.data() + 2 * (G + 1), r3 + 2 * (G + 1), (G + 1) * 4,
+                                      hipMemcpyDeviceToHost, s));
+            TM_HIP_TRY(hipStreamSynchronize(s));
+        }
         g->h_ent_off.assign(h.begin(), h.begin() + (G + 1));
         g->h_mpb.assign(h.begin() + (G + 1), h.begin() + 2 * (G + 1));
         g->h_me_off.assign(h.begin() + 2 * (G + 1), h.end());
