@@ -466,3 +466,25 @@ def test_count_multi_rejects(tm):
     with tm.build_batch(graphs) as B:
         with pytest.raises(tm.TMError):
             B.count_multi([10])
+
+
+def test_hub_threshold_at_and_above_segment_cap(tm):
+    """hub_min at and above the 2,048-entry LDS segment (the window levels
+    then test W >= 2048 before W >= hub_min): a 6,000-edge center whose
+    window at delta 50,000 spans several segments, leaves with small
+    windows."""
+    rng = np.random.default_rng(33)
+    k = 6000
+    leaf = rng.integers(1, 151, k).astype(np.int32)
+    out = rng.random(k) < 0.5
+    src = np.where(out, 0, leaf).astype(np.int32)
+    dst = np.where(out, leaf, 0).astype(np.int32)
+    t = rng.integers(0, 50000, k).astype(np.int64)
+    bg = graphgen.small_random(rng, 151, 8000, tmax=50000)
+    s = np.concatenate([src, bg.src]); d = np.concatenate([dst, bg.dst])
+    tt = np.concatenate([t, bg.t])
+    want = oracle.alg(s, d, tt, 50000, n=151)
+    with tm.build_graph(s, d, tt, n=151) as G:
+        for hub in (2047, 2048, 2049, 3000, 5000):
+            case(f"hub_min={hub} delta=50000")
+            np.testing.assert_array_equal(G.count_raw(50000, hub_min=hub), want)
