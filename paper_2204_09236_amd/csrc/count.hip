@@ -319,7 +319,8 @@ __device__ inline uint32_t last_le(const uint32_t *a, uint32_t n, uint32_t x) {
     return lo;
 }
 
-// One block per item tile (kItemTile items of one graph, one per thread);
+// One block per item tile (kItemTile items of one graph, kSPItems per thread,
+// taken kBlock apart so that neighbouring lanes sweep neighbouring items);
 // one partial row of 32 counters per tile.  The tile's items cover one
 // contiguous range of elements; that range and kStageHalo elements on each
 // side (time, orientation, prefix counts) are first copied into LDS with
@@ -327,7 +328,8 @@ __device__ inline uint32_t last_le(const uint32_t *a, uint32_t n, uint32_t x) {
 // halos of hub pairs, or ranges beyond the stage capacity when chunks are
 // long) are read from global memory, so the result does not depend on the
 // staging.
-constexpr uint32_t kItemTile = kBlock;
+constexpr uint32_t kSPItems = 2;
+constexpr uint32_t kItemTile = kSPItems * kBlock;
 
 __device__ inline WorkItem item_at(const StarArgs &a, uint32_t it) {
     const uint32_t p = a.ipair[it];
@@ -425,21 +427,28 @@ k_star_pair(StarArgs a, uint64_t *partial) {
     __syncthreads();
     const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a, a.me_w};
     uint64_t *row = partial + (uint64_t)ti * 32;
-    const uint32_t it = ib + threadIdx.x;  // one item per thread (kItemTile == kBlock)
-    uint32_t rs = 0, re = 0, cb = 0, ce = 0;
-    if (it < ie) {
-        const WorkItem w = item_at(a, it);
-        rs = a.mp_start[w.pair];
-        re = a.mp_start[w.pair + 1];
-        cb = rs + w.chunk * a.chunk;
-        ce = min(re, cb + a.chunk);
+    // element ranges of this thread's items: the pair [rs, re), the chunk [cb, ce)
+    uint32_t rs_[kSPItems], re_[kSPItems], cb_[kSPItems], ce_[kSPItems];
+#pragma unroll
+    for (uint32_t u = 0; u < kSPItems; u++) {
+        const uint32_t it = ib + threadIdx.x + u * kBlock;
+        rs_[u] = re_[u] = cb_[u] = ce_[u] = 0;
+        if (it < ie) {
+            const WorkItem w = item_at(a, it);
+            rs_[u] = a.mp_start[w.pair];
+            re_[u] = a.mp_start[w.pair + 1];
+            cb_[u] = rs_[u] + w.chunk * a.chunk;
+            ce_[u] = min(re_[u], cb_[u] + a.chunk);
+        }
     }
     {
         // ---- phase 1, e1 sweeps: Pair, Star_II, Star_III (cell c -> A[c - 8])
         uint64_t A[24];
 #pragma unroll
         for (int i = 0; i < 24; i++) A[i] = 0;
-        for (uint32_t side = 0; side < 2 && it < ie; side++) {
+        for (uint32_t u = 0; u < kSPItems; u++) {
+        const uint32_t re = re_[u], cb = cb_[u], ce = ce_[u];
+        for (uint32_t side = 0; side < 2 && cb < ce; side++) {
             Win W;
             W.clear();
             uint32_t j = cb + 1;  // next pair edge to enter the window
@@ -478,6 +487,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
                 }
             }
         }
+        }
         star_flush<24>(A, 8, red, row);
     }
     {
@@ -485,7 +495,9 @@ k_star_pair(StarArgs a, uint64_t *partial) {
         uint64_t A[8];
 #pragma unroll
         for (int i = 0; i < 8; i++) A[i] = 0;
-        for (uint32_t side = 0; side < 2 && it < ie && a.star_i; side++) {
+        for (uint32_t u = 0; u < kSPItems; u++) {
+        const uint32_t rs = rs_[u], cb = cb_[u], ce = ce_[u];
+        for (uint32_t side = 0; side < 2 && cb < ce && a.star_i; side++) {
             Win W;
             W.clear();
             uint32_t f;  // front of the window [f, q)
@@ -523,6 +535,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
                 }
                 W.push(eq.dir, eq.a0, eq.a1);
             }
+        }
         }
         star_flush<8>(A, 0, red, row);
     }
