@@ -268,6 +268,36 @@ def test_powerlaw_full_size(tm):
         np.testing.assert_array_equal(got, want)
 
 
+def test_skewed_full_size(tm):
+    """The large skewed workload at full size (10M nodes, 300M edges, 20 %
+    repeated pairs, a hub of ~1e6 edges; delta 600 / 3,600 / 86,400), built
+    from device pointers as bench.py does, against the oracle's counts stored
+    by tests/golden/make_golden.py; at delta 86,400 also with the hub slice
+    kernel off.  Skipped when this host regenerates a different edge list
+    (the oracle takes minutes on it)."""
+    import torch
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "skewed_counts.json")))
+    case("skewed full: generating 300M edges")
+    g = graphgen.skewed()
+    if graphgen.edge_hash(g) != rec["edge_sha256"]:
+        pytest.skip("the regenerated skewed edge list differs from the stored one")
+    dev = torch.device("cuda:0")
+    s, d, t = (torch.from_numpy(a).to(dev) for a in (g.src, g.dst, g.t))
+    n = g.n
+    del g
+    with tm.build_graph(s, d, t, n=n) as G:
+        for key, val in rec["counts"].items():
+            delta = int(key)
+            case(f"skewed full m=300000000 delta={delta}")
+            want = np.array(val["raw"], dtype=np.uint64)
+            np.testing.assert_array_equal(G.count_raw(delta), want, err_msg=f"delta={delta}")
+            if delta == 86400:
+                case("skewed full delta=86400 hub pass off")
+                np.testing.assert_array_equal(G.count_raw(delta, hub_min=tm.HUB_OFF), want)
+    del s, d, t
+    torch.cuda.empty_cache()
+
+
 # --------------------------------------------------------------------------
 # batches: many graphs, one build, one count, per-graph delta
 
