@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--stream-batch", type=int, default=1_000_000,
                     help="stream workload: edges per append")
     ap.add_argument("--serve-pool", type=int, default=128, help="graphs in the serving pool")
-    ap.add_argument("--serve-mhi", type=float, default=5e6,
+    ap.add_argument("--serve-mhi", type=float, default=5e7,
                     help="largest edge count of a pool graph (log-uniform from 1e3)")
     ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
