@@ -115,77 +115,77 @@ __device__ inline uint32_t window_start(const int64_t *T, uint32_t p, uint32_t l
     return a;
 }
 
-// ------------------------------------------------------------ window sizes
-constexpr int kWinUnroll = 4;
+// Order this wave's LDS writes before its later LDS reads (all lanes).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
+// ------------------------------------------------------------ window sizes
 // Wf[p] = R(p) - p: how many later entries of the same S_u lie within delta
 // (the delta of the graph the entry belongs to; tiles never straddle graphs).
-// A wave takes 64 consecutive entries and holds the (center, t) keys of
-// those and of the next 64 in registers.  Entries are sorted by (center, t),
-// so "key <= (c_p, t_p + delta)" holds on a prefix of the entries after p:
-// each lane finds the end of that prefix by binary search over the 128
-// register-held keys (lane shuffles, no memory round trips), and only a
-// window that runs past them continues with a gallop in global memory.
+// A wave takes 64 consecutive entries at a time and keeps the (center, t)
+// keys of those and of the next 64 in a 128-slot ring in its LDS, refilled
+// 64 keys per step from coalesced loads issued one step ahead.  Entries are
+// sorted by (center, t), so "key <= (c_p, t_p + delta)" holds on a prefix of
+// the entries after p: each lane finds the end of that prefix by binary
+// search over the ring (one 16-byte LDS read per step), and only a window
+// that runs past the 128 keys continues with a gallop in global memory.
+constexpr uint32_t kRing = 2 * kWave;
+
 __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
                                                     uint64_t len, const int64_t *deltas,
                                                     uint32_t *Wf) {
+    // key j of the ring: (center, unused, t low, t high)
+    __shared__ uint4 ring[kBlock / kWave][kRing];
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    uint4 *rg = ring[wv];
+    auto key_at = [&](uint64_t q) -> uint4 {
+        if (q >= len) return make_uint4(0xffffffffu, 0u, 0u, 0u);  // matches no center
+        const uint64_t t = (uint64_t)S.t[q];
+        return make_uint4(S.c[q], 0u, (uint32_t)t, (uint32_t)(t >> 32));
+    };
     for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const Tile tl = tiles[ti];
         const int64_t delta = deltas[tl.g];
-        // each wave walks its own contiguous span of the tile, kWinUnroll
-        // chunks of 64 per step (their loads issued together), carrying the
-        // last chunk's keys into the next step
+        // each wave walks its own contiguous span of the tile in steps of 64
         const uint32_t span = ((tl.e - tl.b + nw - 1) / nw + kWave - 1) / kWave * kWave;
         const uint32_t w_b = tl.b + wv * span, w_e = min(tl.e, w_b + span);
         if (w_b >= w_e) continue;
-        uint32_t cc[kWinUnroll + 1];
-        int64_t tt[kWinUnroll + 1];
-        uint64_t q0 = (uint64_t)w_b + lane;
-        cc[0] = q0 < len ? S.c[q0] : 0xffffffffu;
-        tt[0] = q0 < len ? S.t[q0] : 0;
-        for (uint32_t b0 = w_b; b0 < w_e; b0 += kWinUnroll * kWave) {
+        rg[lane] = key_at((uint64_t)w_b + lane);
+        uint4 next = key_at((uint64_t)w_b + kWave + lane);
+        uint32_t half = 0;  // ring half holding the current 64 keys
+        for (uint32_t base = w_b; base < w_e; base += kWave) {
+            rg[(half ^ 1) * kWave + lane] = next;
+            next = key_at((uint64_t)base + 2 * kWave + lane);  // in flight during the search
+            wave_lds_sync();
+            const uint4 me = rg[half * kWave + lane];
+            const uint32_t ca = me.x;
+            const int64_t lim = (int64_t)(((uint64_t)me.w << 32) | me.z) + delta;
+            // last k in [lane, 128) with key(base + k) <= (ca, lim)
+            uint32_t lo = (uint32_t)lane, hi = kRing;
 #pragma unroll
-            for (int u = 1; u <= kWinUnroll; u++) {
-                const uint64_t q = q0 + (uint64_t)u * kWave;
-                cc[u] = q < len ? S.c[q] : 0xffffffffu;
-                tt[u] = q < len ? S.t[q] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kWinUnroll; u++) {
-                const uint32_t base = b0 + (uint32_t)u * kWave;
-                if (base >= w_e) break;
-                const uint64_t qa = (uint64_t)base + lane;
-                const uint32_t ca = cc[u], cb = cc[u + 1];
-                const int64_t ta = tt[u], tb = tt[u + 1];
-                const int64_t lim = ta + delta;
-                // last k in [lane, 128) with key(base + k) <= (ca, lim)
-                uint32_t lo = (uint32_t)lane, hi = 2 * kWave;
-#pragma unroll
-                for (int step = 0; step < 7; step++) {
-                    const uint32_t mid = (lo + hi) / 2;
-                    const int src = (int)(mid & (kWave - 1));
-                    const uint32_t c1 = __shfl(ca, src, kWave), c2 = __shfl(cb, src, kWave);
-                    const int64_t t1 = __shfl(ta, src, kWave), t2 = __shfl(tb, src, kWave);
-                    const uint32_t cm = mid < kWave ? c1 : c2;
-                    const int64_t tm = mid < kWave ? t1 : t2;
-                    const bool ok = cm < ca || (cm == ca && tm <= lim);
-                    if (hi - lo > 1) {
-                        if (ok) lo = mid;
-                        else hi = mid;
-                    }
-                }
-                if (qa < w_e) {
-                    uint64_t R = (uint64_t)base + lo;
-                    if (lo == 2 * kWave - 1)  // the window may run past the registers
-                        R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
-                    Wf[qa] = (uint32_t)(R - qa);
+            for (int step = 0; step < 7; step++) {
+                const uint32_t mid = (lo + hi) / 2;
+                const uint4 km = rg[(half * kWave + mid) & (kRing - 1)];
+                const int64_t tm = (int64_t)(((uint64_t)km.w << 32) | km.z);
+                const bool ok = km.x < ca || (km.x == ca && tm <= lim);
+                if (hi - lo > 1) {
+                    if (ok) lo = mid;
+                    else hi = mid;
                 }
             }
-            cc[0] = cc[kWinUnroll];
-            tt[0] = tt[kWinUnroll];
-            q0 += (uint64_t)kWinUnroll * kWave;
+            const uint64_t qa = (uint64_t)base + lane;
+            if (qa < w_e) {
+                uint64_t R = (uint64_t)base + lo;
+                if (lo == kRing - 1)  // the window may run past the ring
+                    R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
+                Wf[qa] = (uint32_t)(R - qa);
+            }
+            wave_lds_sync();  // the next step overwrites this half
+            half ^= 1;
         }
     }
 }
@@ -690,12 +690,6 @@ constexpr uint32_t kHashChunk = 256;
 constexpr uint32_t kEmptyKey = 0xffffffffu;  // node ids are below 2^31
 constexpr uint32_t kHashMul = 2654435761u;   // Knuth's multiplicative constant
 
-// Order this wave's LDS writes before its later LDS reads (all lanes).
-__device__ inline void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
                                                       const uint32_t *tidx, const uint32_t *eoff,

@@ -152,6 +152,28 @@ int batch_range(tm_stream *s, const int64_t *t, uint64_t m, int flags, int64_t *
     return TM_OK;
 }
 
+// Number of tail rows with t >= cut (flags and their scan into flag / idx,
+// which the caller owns).
+int count_kept(tm_stream *s, int64_t cut, uint32_t *flag, uint32_t *idx, uint32_t *tmp,
+               uint64_t *kept) {
+    TM_LAUNCH("stream_keep_flags", k_keep_flags, grid_of(s->len), dim3(256), 0, s->stream, s->t,
+              s->len, cut, flag);
+    const int rc = tmc::scan_u32_array(flag, idx, s->len, tmp, s->stream);
+    if (rc) return rc;
+    uint32_t h = 0;
+    TM_HIP_TRY(hipMemcpyAsync(&h, idx + s->len, 4, hipMemcpyDeviceToHost, s->stream));
+    TM_HIP_TRY(hipStreamSynchronize(s->stream));
+    *kept = h;
+    return TM_OK;
+}
+
+int keep_scatter(tm_stream *s, const uint32_t *flag, const uint32_t *idx, int32_t *nsrc,
+                 int32_t *ndst, int64_t *nt) {
+    TM_LAUNCH("stream_keep_scatter", k_keep_scatter, grid_of(s->len), dim3(256), 0, s->stream,
+              s->src, s->dst, s->t, flag, idx, s->len, nsrc, ndst, nt);
+    return TM_OK;
+}
+
 int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const int64_t *t,
                   uint64_t m, int flags, uint64_t *diff) {
     int64_t lo = 0, hi = 0;
@@ -182,23 +204,11 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
             free_scan();
             return rc;
         }
-        TM_LAUNCH("stream_keep_flags", k_keep_flags, grid_of(s->len), dim3(256), 0, s->stream, s->t,
-                  s->len, cut, flag);
-        rc = tmc::scan_u32_array(flag, idx, s->len, tmp, s->stream);
-        uint32_t h = 0;
-        if (!rc) {
-            const hipError_t e1 = hipMemcpyAsync(&h, idx + s->len, 4, hipMemcpyDeviceToHost, s->stream);
-            const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(s->stream) : e1;
-            if (e2 != hipSuccess) {
-                tmc::set_error(std::string("stream scan: ") + hipGetErrorString(e2));
-                rc = TM_EHIP;
-            }
-        }
+        rc = count_kept(s, cut, flag, idx, tmp, &kept);
         if (rc) {
             free_scan();
             return rc;
         }
-        kept = h;
     }
     const uint64_t len = kept + m;
     if (len >= (1ull << 31)) {
@@ -220,9 +230,10 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
         return code;
     };
     if (rc) return fail(rc);
-    if (kept)
-        TM_LAUNCH("stream_keep_scatter", k_keep_scatter, grid_of(s->len), dim3(256), 0, s->stream,
-                  s->src, s->dst, s->t, flag, idx, s->len, nsrc, ndst, nt);
+    if (kept) {
+        rc = keep_scatter(s, flag, idx, nsrc, ndst, nt);
+        if (rc) return fail(rc);
+    }
     const hipMemcpyKind kind = flags == TM_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     hipError_t e = hipMemcpyAsync(nsrc + kept, src, m * 4, kind, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ndst + kept, dst, m * 4, kind, s->stream);
