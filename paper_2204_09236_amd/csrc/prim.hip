@@ -118,6 +118,22 @@ __global__ void __launch_bounds__(kBlock) k_tile_scan(L ld, uint64_t n, const ui
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[np];
 }
 
+// The whole scan when the input fits one tile: one launch instead of three.
+template <typename L>
+__global__ void __launch_bounds__(kBlock) k_scan_one(L ld, uint64_t n, uint32_t *out) {
+    __shared__ uint32_t lds[kBlock / kWave];
+    uint32_t carry = 0;
+    for (int i = 0; i < kItems; i++) {
+        const uint64_t idx = (uint64_t)i * kBlock + threadIdx.x;
+        const uint32_t v = idx < n ? ld(idx) : 0;
+        uint32_t tot;
+        const uint32_t inc = block_incl_scan(v, &tot, lds);
+        if (idx < n) out[idx] = carry + inc - v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 __global__ void k_set_zero(uint32_t *p) { *p = 0; }
 
 template <typename L>
@@ -126,6 +142,10 @@ int scan_impl(L ld, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
     if (nb == 0) {
         // a kernel, not a memset: this may run inside a captured graph
         TM_LAUNCH("scan_empty", k_set_zero, dim3(1), dim3(1), 0, s, out);
+        return TM_OK;
+    }
+    if (nb == 1) {
+        TM_LAUNCH("scan_one", (k_scan_one<L>), dim3(1), dim3(kBlock), 0, s, ld, n, out);
         return TM_OK;
     }
     TM_LAUNCH("scan_tile_sum", (k_tile_sum<L>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp);
