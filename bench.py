@@ -154,7 +154,8 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
         "sort_pair_scatter": m * (8 + 4) * 2,
         "multi_flags": m * (8 + 8),
         "multi_fill": m * 28 + me * (32 + 33) + nm * 12,
-        "windows": e2 * 16 + (n + 1) * 4,
+        # one graph: the window kernel also writes the three window bit planes
+        "windows": e2 * 16 + (n + 1) * 4 + e2 / 8 + e2 / 4,
         "star_prep": me * 32 + 2 * me * 28,
         "star_pair": me * 25 + 2 * me * 16,
         "wlevels": e2 * 4 + e2 / 8 + e2 / 4,

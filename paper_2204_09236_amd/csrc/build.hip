@@ -28,6 +28,9 @@ constexpr uint32_t kGapFill = 64;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr uint32_t kMaxStatBlocks = 4096;
 constexpr uint64_t kEntryTile = 8192, kElemTile = 1024;
+// a single graph's entry tiles start at multiples of 64: the count's window
+// kernel then writes whole 64-entry words of the window bit planes
+static_assert(kEntryTile % 64 == 0, "entry tiles must be 64-aligned");
 
 struct Stat {
     uint32_t bad;        // bit 0: id out of range / negative, bit 1: self-loop, bit 2: |t| too big

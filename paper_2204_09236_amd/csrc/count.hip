@@ -132,11 +132,16 @@ __device__ inline void wave_lds_sync() {
 // the entries after p: each lane finds the end of that prefix by binary
 // search over the ring (one 16-byte LDS read per step), and only a window
 // that runs past the 128 keys continues with a gallop in global memory.
+// With `bits` non-null (one graph: tiles and wave spans start at multiples
+// of 64, so each step covers one 64-entry word) the step also writes the
+// window bit planes that k_wlevels would write.
 constexpr uint32_t kRing = 2 * kWave;
+constexpr uint32_t kHubCap = 2048;  // window entries per LDS segment of the hub pass
 
 __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
                                                     uint64_t len, const int64_t *deltas,
-                                                    uint32_t *Wf) {
+                                                    uint32_t *Wf, uint32_t hub_min, uint64_t *bits,
+                                                    uint64_t *lev) {
     // key j of the ring: (center, unused, t low, t high)
     __shared__ uint4 ring[kBlock / kWave][kRing];
     const int lane = threadIdx.x & (kWave - 1);
@@ -178,11 +183,23 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                 }
             }
             const uint64_t qa = (uint64_t)base + lane;
+            uint32_t W = 0;
             if (qa < w_e) {
                 uint64_t R = (uint64_t)base + lo;
                 if (lo == kRing - 1)  // the window may run past the ring
                     R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
-                Wf[qa] = (uint32_t)(R - qa);
+                W = (uint32_t)(R - qa);
+                Wf[qa] = W;
+            }
+            if (bits) {
+                const uint32_t t2 = min(hub_min, kHubCap), t3 = max(hub_min, kHubCap);
+                const uint64_t b = __ballot(W != 0);
+                const uint64_t b2 = __ballot(W >= t2);
+                const uint64_t b3 = __ballot(W >= t3);
+                if (lane == 0) {
+                    bits[base / kWave] = b;
+                    reinterpret_cast<ulonglong2 *>(lev)[base / kWave] = make_ulonglong2(b2, b3);
+                }
             }
             wave_lds_sync();  // the next step overwrites this half
             half ^= 1;
@@ -585,7 +602,6 @@ constexpr uint32_t kHubSlice = 512;          // S positions per hub tile
 constexpr uint32_t kHubBlock = 512;          // threads of a k_tri_hub block
 constexpr uint32_t kHubPer = kHubSlice / kHubBlock;  // positions per thread
 static_assert(kHubSlice % kHubBlock == 0, "hub slice");
-constexpr uint32_t kHubCap = 2048;           // window entries per LDS segment
 constexpr uint32_t kHubSlots = 2 * kHubCap;  // hash slots (load factor <= 1/2)
 constexpr uint32_t kHubBits = 12;            // log2(kHubSlots)
 static_assert((1u << kHubBits) == kHubSlots, "hub table size");
@@ -1310,8 +1326,11 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     const bool do_hub = do_tri && pr.hub_min != TM_HUB_OFF;
     const uint64_t nm = do_sp ? g->n_multi : 0;
     int rc;
+    // one graph: the window kernel also writes the triangle bit planes
+    const bool fused_levels = do_tri && G == 1;
     TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
-              s, S, g->t_entries, g->n_t_entries, 2 * m, w.deltas, w.Wf);
+              s, S, g->t_entries, g->n_t_entries, 2 * m, w.deltas, w.Wf, pr.hub_min,
+              fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr);
     // ---- star / pair: work items (pair, chunk)
     if (nm) {
         TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
@@ -1326,8 +1345,9 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     }
     // ---- triangles: candidate first edges
     if (do_tri) {
-        TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m,
-                  pr.hub_min, w.wbits, w.lev);
+        if (!fused_levels)
+            TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m,
+                      pr.hub_min, w.wbits, w.lev);
         TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
                   reinterpret_cast<const uint2 *>(g->epos), w.wbits, w.lev, pr.hub_min, m, w.tflag);
         rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
