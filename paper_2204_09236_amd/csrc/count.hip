@@ -1247,7 +1247,7 @@ dim3 grid_for(uint64_t n, uint64_t cap) {
 }  // namespace
 
 constexpr uint32_t kDefaultRunChunk = 4;
-constexpr uint32_t kDefaultTriLaneMax = 16;
+constexpr uint32_t kDefaultTriLaneMax = 64;
 constexpr uint32_t kDefaultHubMin = 32;
 
 // ---------------------------------------------------------------- driver
