@@ -131,22 +131,26 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
     must read and write at least once (reads + writes).  m edges, 2m incident
     entries, n nodes, tk = time-sort key width, me = edges on node pairs with
     >= 2 edges, nm = such pairs.  Radix scatter passes read and write every
-    (key, value) pair once; histogram passes read every key once; the node
-    sort's last pass writes the sequence arrays (node, t, other end | dir,
-    rank) and each edge's two positions instead of the ping-pong buffers."""
+    (key, value) pair once; histogram passes read every key once.  The time
+    sort of one graph reads the input arrays (src, dst, t: 16 B per edge) in
+    its histogram and first pass, and its last pass writes the rank-ordered
+    arrays (t, input index, the two node-sort entries, pair key and value:
+    64 B per edge).  The node sort's last pass writes the sequence arrays
+    (node, t, other end | dir, rank) and each edge's two positions instead
+    of the ping-pong buffers."""
     e2 = 2 * m
     tk = 4 if info["tbits"] <= 32 else 8
     me, nm = info["multi_pair_edges"], info["multi_pairs"]
     pn = max(passes["node"], 1)
     node_scatter = (e2 * 40 * (pn - 1) + e2 * (20 + 24)) / pn
-    # the time sort's last pass writes the rank-ordered arrays (t, input
-    # index, two node-sort entries, pair key and value: 64 B per edge)
     pt = max(passes["time"], 1)
-    time_scatter = (m * (tk + 12) * 2 * (pt - 1) + m * (tk + 12 + 64)) / pt
+    time_first = 16 + ((tk + 12) if pt > 1 else 64)
+    time_scatter = (m * time_first + m * (tk + 12) * 2 * max(pt - 2, 0) +
+                    (m * (tk + 12 + 64) if pt > 1 else 0)) / pt
     table = {
         "validate": m * 16,
-        "time_keys": m * (16 + tk + 12),
-        "sort_time_hist": m * tk,
+        "time_keys": m * (16 + tk + 12),   # batches only
+        "sort_time_hist": m * 8,
         "sort_time_scatter": time_scatter,
         "sort_node_hist": e2 * 4,
         "sort_node_scatter": node_scatter,

@@ -410,7 +410,9 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     // ---- 2. time sort carrying (src, dst, id); its last pass writes the
     // rank-ordered arrays.  Pass i writes the (KB, VB) set when i is even, so
     // the last pass reads (KA, VA) when the pass count is odd and the node
-    // keys and values go to the set it does not read.
+    // keys and values go to the set it does not read.  One graph: the first
+    // pass reads the input arrays themselves; a batch adds the graph index
+    // and the node base in k_time_keys first.
     uint32_t *nkey = nullptr;
     NodeVal *nval = nullptr;
     {
@@ -423,14 +425,24 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         const dim3 tgrid((unsigned)std::min<uint32_t>(n_etiles, 4096));
         if (kbits <= 32) {
             uint32_t *k = reinterpret_cast<uint32_t *>(KA), *k_alt = reinterpret_cast<uint32_t *>(KB);
-            TM_LAUNCH("time_keys", k_time_keys<uint32_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
-                      d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
-            TRY(radix_sort_time_u32(k, k_alt, ev, ev_alt, m, kbits, tmp, sort_err, s, ro));
+            if (G == 1) {
+                TRY(radix_sort_time_direct_u32(src, dst, t, k, k_alt, ev, ev_alt, m, kbits, tmp,
+                                               sort_err, s, ro));
+            } else {
+                TM_LAUNCH("time_keys", k_time_keys<uint32_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
+                          d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
+                TRY(radix_sort_time_u32(k, k_alt, ev, ev_alt, m, kbits, tmp, sort_err, s, ro));
+            }
         } else {
             uint64_t *k = reinterpret_cast<uint64_t *>(KA), *k_alt = reinterpret_cast<uint64_t *>(KB);
-            TM_LAUNCH("time_keys", k_time_keys<uint64_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
-                      d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
-            TRY(radix_sort_time_u64(k, k_alt, ev, ev_alt, m, kbits, tmp, sort_err, s, ro));
+            if (G == 1) {
+                TRY(radix_sort_time_direct_u64(src, dst, t, k, k_alt, ev, ev_alt, m, kbits, tmp,
+                                               sort_err, s, ro));
+            } else {
+                TM_LAUNCH("time_keys", k_time_keys<uint64_t>, tgrid, dim3(kBlock), 0, s, src, dst, t,
+                          d_etiles, n_etiles, g->d_tmin, d_nb, tbits, k, ev);
+                TRY(radix_sort_time_u64(k, k_alt, ev, ev_alt, m, kbits, tmp, sort_err, s, ro));
+            }
         }
     }
 

@@ -237,6 +237,34 @@ __global__ void k_os_init(uint32_t *counts, uint32_t n_counts, uint64_t *status,
         status[i] = 0;
 }
 
+// Where a sort's first pass (and its histogram) reads its elements: plain
+// arrays, or elements built on the fly from arrays another kernel wrote, so
+// that no separate kernel has to write them out first.
+template <typename K, typename V>
+struct ArrayIn {
+    const K *k;
+    const V *v;
+    __device__ inline K key(uint64_t i) const { return k[i]; }
+    __device__ inline void load(uint64_t i, K &key, V &val) const {
+        key = k[i];
+        val = v[i];
+    }
+};
+
+// Time sort of one graph from the input arrays: key t - tmin, value
+// (src, dst, input index).
+template <typename K>
+struct TimeIn {
+    const int32_t *src, *dst;
+    const int64_t *t;
+    const int64_t *tmin;  // one value, on the device
+    __device__ inline K key(uint64_t i) const { return (K)(uint64_t)(t[i] - *tmin); }
+    __device__ inline void load(uint64_t i, K &key, EdgeVal &val) const {
+        key = (K)(uint64_t)(t[i] - *tmin);
+        val = EdgeVal{(uint32_t)src[i], (uint32_t)dst[i], (uint32_t)i};
+    }
+};
+
 // Digit counts of every pass over all keys: per-block LDS counters (plain
 // LDS atomics: counting needs no ranks), each block writing its own row
 // part[block][pass][digit]; no global atomics here, since thousands of blocks
@@ -244,8 +272,8 @@ __global__ void k_os_init(uint32_t *counts, uint32_t n_counts, uint64_t *status,
 constexpr uint32_t kHistBlocks = 512;
 constexpr uint32_t kHistSumSplit = 16;
 
-template <typename K>
-__global__ void __launch_bounds__(kOsThreads) k_os_hist(const K *keys, uint64_t n, int passes,
+template <typename K, typename In>
+__global__ void __launch_bounds__(kOsThreads) k_os_hist(In in, uint64_t n, int passes,
                                                         uint32_t *part) {
     __shared__ uint32_t h[kMaxPasses][256];
     for (int i = threadIdx.x; i < kMaxPasses * 256; i += kOsThreads) (&h[0][0])[i] = 0;
@@ -256,7 +284,7 @@ __global__ void __launch_bounds__(kOsThreads) k_os_hist(const K *keys, uint64_t 
 #pragma unroll
         for (int i = 0; i < kHistItems; i++) {
             const uint64_t idx = base + (uint64_t)i * kOsThreads + threadIdx.x;
-            key[i] = idx < n ? keys[idx] : K(0);
+            key[i] = idx < n ? in.key(idx) : K(0);
         }
 #pragma unroll
         for (int i = 0; i < kHistItems; i++) {
@@ -326,8 +354,8 @@ struct RankWrite {
 // status: this pass's look-back words (tile x 256, zero on entry);
 // status_next: the next pass's words, whose row for this tile is cleared
 // here (null on the last pass); ticket: tile counter (zero on entry).
-template <typename K, typename V, typename Out, int THREADS, int ITEMS>
-__global__ void __launch_bounds__(THREADS) k_os_scatter(const K *kin, const V *vin, Out out,
+template <typename K, typename V, typename In, typename Out, int THREADS, int ITEMS>
+__global__ void __launch_bounds__(THREADS) k_os_scatter(In in, Out out,
                                                            uint64_t n, int shift,
                                                            const uint32_t *ghist, uint64_t *status,
                                                            uint64_t *status_next, uint32_t *ticket,
@@ -365,8 +393,9 @@ __global__ void __launch_bounds__(THREADS) k_os_scatter(const K *kin, const V *v
 #pragma unroll
         for (int j = 0; j < kVW; j++) val[i][j] = 0;
         if (idx < n) {
-            key[i] = kin[idx];
-            __builtin_memcpy(&val[i][0], vin + idx, sizeof(V));
+            V v;
+            in.load(idx, key[i], v);
+            __builtin_memcpy(&val[i][0], &v, sizeof(V));
         }
     }
 #pragma unroll
@@ -475,10 +504,12 @@ inline OsTmp os_tmp(void *tmp, uint64_t ntiles) {
     return t;
 }
 
-template <typename K, typename V, typename Final>
+// In0: where the histogram and the first pass read the elements (the later
+// passes read the ping-pong buffers *keys / *vals).
+template <typename K, typename V, typename Final, typename In0>
 int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,
                uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name,
-               const Final *fin) {
+               const Final *fin, const In0 &in0) {
     constexpr int kItems_ = os_items<K, V>();
     constexpr int kThr = os_threads<K, V>();
     constexpr uint64_t kT = (uint64_t)kThr * kItems_;
@@ -494,22 +525,34 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
               dim3(kBlock), 0, s, t.ghist, (uint32_t)(kMaxPasses * 257), t.status[0], n_status);
     const uint64_t hchunk = (uint64_t)kOsThreads * kHistItems;
     const uint32_t hblocks = (uint32_t)std::min<uint64_t>((n + hchunk - 1) / hchunk, kHistBlocks);
-    TM_LAUNCH(hist_name, k_os_hist<K>, dim3(hblocks), dim3(kOsThreads), 0, s, *keys, n, passes,
+    TM_LAUNCH(hist_name, (k_os_hist<K, In0>), dim3(hblocks), dim3(kOsThreads), 0, s, in0, n, passes,
               t.part);
     TM_LAUNCH("sort_hist_sum", k_os_hist_sum, dim3((unsigned)passes, kHistSumSplit), dim3(256), 0, s,
               t.part, hblocks, passes, t.ghist);
     for (int p = 0; p < passes; p++) {
         uint64_t *st = t.status[p & 1];
         uint64_t *st_next = p + 1 < passes ? t.status[(p + 1) & 1] : nullptr;
-        if (fin && p + 1 == passes) {
-            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, Final, kThr, kItems_>), dim3((unsigned)ntiles),
-                      dim3(kThr), 0, s, *keys, *vals, *fin, n, 8 * p, t.ghist + 256 * p, st,
-                      st_next, t.tickets + p, err);
+        const ArrayIn<K, V> arr{*keys, *vals};
+        const bool last = fin && p + 1 == passes;
+        if (p == 0 && last) {
+            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, In0, Final, kThr, kItems_>),
+                      dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, *fin, n, 8 * p,
+                      t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+        } else if (last) {
+            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, ArrayIn<K, V>, Final, kThr, kItems_>),
+                      dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, *fin, n, 8 * p,
+                      t.ghist + 256 * p, st, st_next, t.tickets + p, err);
         } else {
-            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, PairOut<K, V>, kThr, kItems_>),
-                      dim3((unsigned)ntiles), dim3(kThr), 0, s, *keys, *vals,
-                      (PairOut<K, V>{*keys_alt, *vals_alt}), n,
-                      8 * p, t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+            const PairOut<K, V> po{*keys_alt, *vals_alt};
+            if (p == 0)
+                TM_LAUNCH(scatter_name, (k_os_scatter<K, V, In0, PairOut<K, V>, kThr, kItems_>),
+                          dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, po, n, 8 * p,
+                          t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+            else
+                TM_LAUNCH(scatter_name,
+                          (k_os_scatter<K, V, ArrayIn<K, V>, PairOut<K, V>, kThr, kItems_>),
+                          dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, po, n, 8 * p,
+                          t.ghist + 256 * p, st, st_next, t.tickets + p, err);
             std::swap(*keys, *keys_alt);
             std::swap(*vals, *vals_alt);
         }
@@ -534,41 +577,69 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
     return scan_impl(LoadDirBit{ent_nd}, out, n, tmp, s);
 }
 
-#define TM_RADIX_INST(NAME, K, V)                                                                \
-    int NAME(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,   \
-             uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name) {    \
-        if (n == 0 || bits <= 0) return TM_OK;                                                   \
-        return radix_impl<K, V, PairOut<K, V>>(keys, keys_alt, vals, vals_alt, n, bits, tmp, err, \
-                                               s, hist_name, scatter_name, nullptr);             \
-    }
-TM_RADIX_INST(radix_sort_u64, uint64_t, uint32_t)
-#undef TM_RADIX_INST
+int radix_sort_u64(uint64_t **keys, uint64_t **keys_alt, uint32_t **vals, uint32_t **vals_alt,
+                   uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
+                   const char *hist_name, const char *scatter_name) {
+    if (n == 0 || bits <= 0) return TM_OK;
+    const ArrayIn<uint64_t, uint32_t> in0{*keys, *vals};
+    return radix_impl<uint64_t, uint32_t, PairOut<uint64_t, uint32_t>>(
+        keys, keys_alt, vals, vals_alt, n, bits, tmp, err, s, hist_name, scatter_name, nullptr, in0);
+}
 
 int radix_sort_time_u32(uint32_t *keys, uint32_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
                         uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut ro) {
     if (n == 0) return TM_OK;
     const RankWrite<uint32_t> fin{ro};
+    const ArrayIn<uint32_t, EdgeVal> in0{keys, vals};
     return radix_impl<uint32_t, EdgeVal, RankWrite<uint32_t>>(
         &keys, &keys_alt, &vals, &vals_alt, n, bits < 1 ? 1 : bits, tmp, err, s, "sort_time_hist",
-        "sort_time_scatter", &fin);
+        "sort_time_scatter", &fin, in0);
 }
 
 int radix_sort_time_u64(uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
                         uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut ro) {
     if (n == 0) return TM_OK;
     const RankWrite<uint64_t> fin{ro};
+    const ArrayIn<uint64_t, EdgeVal> in0{keys, vals};
     return radix_impl<uint64_t, EdgeVal, RankWrite<uint64_t>>(
         &keys, &keys_alt, &vals, &vals_alt, n, bits < 1 ? 1 : bits, tmp, err, s, "sort_time_hist",
-        "sort_time_scatter", &fin);
+        "sort_time_scatter", &fin, in0);
+}
+
+template <typename K>
+static int time_direct(const int32_t *src, const int32_t *dst, const int64_t *t, K *keys,
+                       K *keys_alt, EdgeVal *vals, EdgeVal *vals_alt, uint64_t n, int bits,
+                       void *tmp, uint32_t *err, hipStream_t s, RankOut ro) {
+    if (n == 0) return TM_OK;
+    const RankWrite<K> fin{ro};
+    const TimeIn<K> in0{src, dst, t, ro.tmin};
+    return radix_impl<K, EdgeVal, RankWrite<K>>(&keys, &keys_alt, &vals, &vals_alt, n,
+                                                bits < 1 ? 1 : bits, tmp, err, s,
+                                                "sort_time_hist", "sort_time_scatter", &fin, in0);
+}
+
+int radix_sort_time_direct_u32(const int32_t *src, const int32_t *dst, const int64_t *t,
+                               uint32_t *keys, uint32_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                               uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
+                               RankOut ro) {
+    return time_direct<uint32_t>(src, dst, t, keys, keys_alt, vals, vals_alt, n, bits, tmp, err, s, ro);
+}
+
+int radix_sort_time_direct_u64(const int32_t *src, const int32_t *dst, const int64_t *t,
+                               uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                               uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
+                               RankOut ro) {
+    return time_direct<uint64_t>(src, dst, t, keys, keys_alt, vals, vals_alt, n, bits, tmp, err, s, ro);
 }
 
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
                      uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut so) {
     if (n == 0) return TM_OK;
     const SeqWrite fin{so};
+    const ArrayIn<uint32_t, NodeVal> in0{keys, vals};
     return radix_impl<uint32_t, NodeVal, SeqWrite>(&keys, &keys_alt, &vals, &vals_alt, n,
                                                    bits < 1 ? 1 : bits, tmp, err, s,
-                                                   "sort_node_hist", "sort_node_scatter", &fin);
+                                                   "sort_node_hist", "sort_node_scatter", &fin, in0);
 }
 
 }  // namespace tmc

@@ -144,6 +144,17 @@ int radix_sort_time_u32(uint32_t *keys, uint32_t *keys_alt, EdgeVal *vals, EdgeV
                         uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut out);
 int radix_sort_time_u64(uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
                         uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, RankOut out);
+// The time sort of one graph read straight from the input arrays (key
+// t - tmin[0], value (src, dst, input index)); keys / vals are only the
+// ping-pong buffers.
+int radix_sort_time_direct_u32(const int32_t *src, const int32_t *dst, const int64_t *t,
+                               uint32_t *keys, uint32_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                               uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
+                               RankOut out);
+int radix_sort_time_direct_u64(const int32_t *src, const int32_t *dst, const int64_t *t,
+                               uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
+                               uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
+                               RankOut out);
 // Node sort: (node, NodeVal) pairs on bits [0, bits); the last pass writes
 // SeqOut instead of the ping-pong buffers (at least one pass always runs).
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
