@@ -450,7 +450,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     {
         uint32_t *k_alt = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(nkey) == KA ? KB : KA);
         NodeVal *v_alt = reinterpret_cast<NodeVal *>(reinterpret_cast<char *>(nval) == VA ? VB : VA);
-        const SeqOut so{g->ent_c, g->ent_t, g->ent_nd, g->ent_r, g->epos};
+        const SeqOut so{g->ent_c, g->ent_t, g->ent_nd, g->ent_r, g->epos, (uint64_t)len};
         TRY(radix_sort_nodes(nkey, k_alt, nval, v_alt, len, bits_for(n - 1), tmp, sort_err, s, so));
         TM_LAUNCH("offsets_fill", k_fill_u32, grid_for(n + 1), dim3(kBlock), 0, s, g->off, n + 1,
                   kUnset);

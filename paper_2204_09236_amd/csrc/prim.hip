@@ -326,7 +326,9 @@ struct SeqWrite {
         o.ent_t[pos] = v.t;
         o.ent_nd[pos] = v.nd;
         o.ent_r[pos] = v.r;
-        o.epos[2 * (uint64_t)v.r + (v.nd & 1u)] = pos;
+        const uint64_t slot = 2 * (uint64_t)v.r + (v.nd & 1u);
+        // a slot outside [0, n) only after an abandoned look-back (flagged)
+        if (slot < o.n) o.epos[slot] = pos;
     }
 };
 

@@ -114,6 +114,7 @@ struct SeqOut {
     uint32_t *ent_nd;
     uint32_t *ent_r;
     uint32_t *epos;
+    uint64_t n;  // entries (epos slots)
 };
 
 // Where the time sort's last pass writes: the arrays by edge rank r (rank =
