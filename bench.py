@@ -160,9 +160,11 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
         "sort_pair_scatter": m * (8 + 4) * 2,
         "multi_flags": m * (8 + 8),
         "multi_fill": m * 28 + me * (32 + 33) + nm * 12,
-        # one graph: the window kernel also writes the three window bit planes
-        "windows": e2 * 16 + (n + 1) * 4 + e2 / 8 + e2 / 4,
-        "star_prep": me * 32 + 2 * me * 28,
+        # keys read, window ends and starts written; one graph: the three
+        # window bit planes too
+        "windows": e2 * 20 + (n + 1) * 4 + e2 / 8 + e2 / 4,
+        # per element its record, per side X at p, R + 1 and L, Wf, Lf, result
+        "star_prep": me * 32 + 2 * me * 36,
         "star_pair": me * 25 + 2 * me * 16,
         "wlevels": e2 * 4 + e2 / 8 + e2 / 4,
         "tri_flags": m * (8 + 4) + e2 / 8,

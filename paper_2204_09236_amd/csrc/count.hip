@@ -85,36 +85,6 @@ __device__ inline uint32_t window_end(const int64_t *T, uint32_t p, uint32_t hi,
     return lo;
 }
 
-// Smallest x in [lo_bound, p] with t[x] >= lim, given t[p] >= lim.
-__device__ inline uint32_t window_start(const int64_t *T, uint32_t p, uint32_t lo_bound,
-                                        int64_t lim) {
-    uint32_t hi = p, bot = lo_bound;
-    uint64_t step = 1;
-    bool found_low = false;
-    while (true) {
-        if ((uint64_t)hi < (uint64_t)lo_bound + step) {
-            break;
-        }
-        const uint32_t probe = (uint32_t)(hi - step);
-        if (T[probe] >= lim) {
-            hi = probe;
-            step <<= 1;
-        } else {
-            bot = probe;
-            found_low = true;
-            break;
-        }
-    }
-    // T[hi] >= lim; answer in (bot, hi] if found_low, else [lo_bound, hi]
-    uint32_t a = found_low ? bot + 1 : lo_bound, b = hi;
-    while (a < b) {
-        const uint32_t mid = a + (b - a) / 2;
-        if (T[mid] >= lim) b = mid;
-        else a = mid + 1;
-    }
-    return a;
-}
-
 // Order this wave's LDS writes before its later LDS reads (all lanes).
 __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -135,15 +105,25 @@ __device__ inline void wave_lds_sync() {
 // With `bits` non-null (one graph: tiles and wave spans start at multiples
 // of 64, so each step covers one 64-entry word) the step also writes the
 // window bit planes that k_wlevels would write.
+//
+// With `Lf` non-null it also writes each entry's window start,
+// Lf[p] = L(p) = the first entry of S_u with t >= t_p - delta.  R(q) = q +
+// Wf[q] never decreases along the whole array and never leaves q's S_u, so
+// L(p) = min{q : R(q) >= p}: the entries p in (R(q - 1), R(q)] start their
+// windows at q.  A step owns the entries in (R(base - 1), R(base + 63)]; its
+// lanes write them in coalesced rounds of 64, each finding its q by
+// bisection over the step's 64 window ends kept in LDS.  A wave span finds
+// R of the entry before it with one gallop.
 constexpr uint32_t kRing = 2 * kWave;
 constexpr uint32_t kHubCap = 2048;  // window entries per LDS segment of the hub pass
 
 __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
                                                     uint64_t len, const int64_t *deltas,
                                                     uint32_t *Wf, uint32_t hub_min, uint64_t *bits,
-                                                    uint64_t *lev) {
+                                                    uint64_t *lev, uint32_t *Lf) {
     // key j of the ring: (center, unused, t low, t high)
     __shared__ uint4 ring[kBlock / kWave][kRing];
+    __shared__ uint32_t rend[kBlock / kWave][kWave];  // the step's window ends R
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     uint4 *rg = ring[wv];
@@ -159,6 +139,12 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
         const uint32_t span = ((tl.e - tl.b + nw - 1) / nw + kWave - 1) / kWave * kWave;
         const uint32_t w_b = tl.b + wv * span, w_e = min(tl.e, w_b + span);
         if (w_b >= w_e) continue;
+        // first entry whose window start this wave writes: R(w_b - 1) + 1
+        uint32_t p_next = w_b;
+        if (Lf && w_b > 0) {
+            const uint32_t q0 = w_b - 1, c0 = S.c[q0];
+            if (c0 == S.c[w_b]) p_next = window_end(S.t, q0, S.off[c0 + 1], S.t[q0] + delta) + 1;
+        }
         rg[lane] = key_at((uint64_t)w_b + lane);
         uint4 next = key_at((uint64_t)w_b + kWave + lane);
         uint32_t half = 0;  // ring half holding the current 64 keys
@@ -183,13 +169,35 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                 }
             }
             const uint64_t qa = (uint64_t)base + lane;
-            uint32_t W = 0;
+            uint32_t W = 0, Rq = 0;
             if (qa < w_e) {
                 uint64_t R = (uint64_t)base + lo;
                 if (lo == kRing - 1)  // the window may run past the ring
                     R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
                 W = (uint32_t)(R - qa);
                 Wf[qa] = W;
+                Rq = (uint32_t)R;
+            }
+            if (Lf) {
+                const uint32_t nvalid = min<uint32_t>(kWave, w_e - base);
+                const uint32_t r_last = __shfl(Rq, (int)nvalid - 1, kWave);
+                // lanes past the span own no entries
+                rend[wv][lane] = qa < w_e ? Rq : r_last;
+                wave_lds_sync();
+                for (uint32_t p0 = p_next; p0 <= r_last; p0 += kWave) {
+                    const uint32_t p = p0 + (uint32_t)lane;
+                    if (p <= r_last) {
+                        // first step entry j with R >= p (R of entry nvalid - 1 is r_last >= p)
+                        uint32_t a = 0, b = nvalid - 1;
+                        while (a < b) {
+                            const uint32_t mid = (a + b) / 2;
+                            if (rend[wv][mid] >= p) b = mid;
+                            else a = mid + 1;
+                        }
+                        Lf[p] = base + a;
+                    }
+                }
+                p_next = r_last + 1;
             }
             if (bits) {
                 const uint32_t t2 = min(hub_min, kHubCap), t3 = max(hub_min, kHubCap);
@@ -213,9 +221,10 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
 // window start L:  w = (P_0(R), P_1(R), P_0(L-1), P_1(L-1)).
 __global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me_p,
                                                       const uint4 *me_a, const int64_t *me_t,
-                                                      const uint32_t *Wf, uint64_t n_me,
-                                                      const Tile *tiles, uint32_t n_tiles,
-                                                      const int64_t *deltas, uint4 *me_w) {
+                                                      const uint32_t *Wf, const uint32_t *Lf,
+                                                      uint64_t n_me, const Tile *tiles,
+                                                      uint32_t n_tiles, const int64_t *deltas,
+                                                      uint4 *me_w) {
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const Tile tl = tiles[ti];
     const int64_t delta = deltas[tl.g];
@@ -226,7 +235,6 @@ __global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me
         const uint4 aa = me_a[k];
         const uint32_t p = side ? pp.y : pp.x;
         const uint32_t a0 = side ? aa.z : aa.x, a1 = side ? aa.w : aa.y;
-        const uint32_t seg_lo = p - (a0 + a1);
         const int64_t tp = me_t[k];
         // The sweeps read these only for an element whose pair has another
         // edge within delta after it (window end) or before it (window start);
@@ -242,7 +250,8 @@ __global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me
             rp0 = (a0 + a1) + (R - p) + 1 - rp1;
         }
         if (need_l) {
-            const uint32_t L = window_start(S.t, p, seg_lo, tp - delta);
+            const uint32_t seg_lo = p - (a0 + a1);
+            const uint32_t L = Lf[p];  // first entry of S_c with t >= tp - delta
             lp1 = a1 - (xp - S.X[L]);
             lp0 = (L - seg_lo) - lp1;
         }
@@ -1255,7 +1264,7 @@ constexpr uint32_t kDefaultHubMin = 32;
 // kept in the graph's plan for captured replays.
 struct Workspace {
     int64_t *deltas;
-    uint32_t *Wf;
+    uint32_t *Wf, *Lf;
     uint64_t *wbits, *lev;
     uint4 *me_w;
     uint32_t *cnt, *first, *ipair, *tflag, *tidx;
@@ -1274,7 +1283,7 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
     w->max_htiles = len / kHubSlice + G + 1;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return up(G * 8) + up(len * 4) + up((len / kWave + 1) * 8) + up((len / kWave + 1) * 16) + up(2 * nme * sizeof(uint4)) +
+    return up(G * 8) + up(len * 4) * 2 + up((len / kWave + 1) * 8) + up((len / kWave + 1) * 16) + up(2 * nme * sizeof(uint4)) +
            up((G + 1) * 4) * 2 + up(4) + up(w->max_htiles * 4) + up(w->max_htiles * 8 * 8) +
            up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * sum_split(G) * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
@@ -1288,6 +1297,7 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     w->deltas = sc.take<int64_t>(G);
     w->Wf = sc.take<uint32_t>(len);
+    w->Lf = sc.take<uint32_t>(len);
     w->wbits = sc.take<uint64_t>(len / kWave + 1);
     w->lev = sc.take<uint64_t>(2 * (len / kWave + 1));
     w->n_htiles = sc.take<uint32_t>(G + 1);
@@ -1330,11 +1340,12 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     const bool fused_levels = do_tri && G == 1;
     TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
               s, S, g->t_entries, g->n_t_entries, 2 * m, w.deltas, w.Wf, pr.hub_min,
-              fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr);
+              fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr,
+              nm ? w.Lf : nullptr);
     // ---- star / pair: work items (pair, chunk)
     if (nm) {
         TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
-                  dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, w.Wf, nme, g->t_elems,
+                  dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, w.Wf, w.Lf, nme, g->t_elems,
                   g->n_t_elems, w.deltas, w.me_w);
         TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
                   nm, run_chunk, w.cnt);
