@@ -1259,7 +1259,7 @@ constexpr uint32_t kDefaultRunChunk = 4;
 constexpr uint32_t kDefaultTriLaneMax = 64;
 constexpr uint32_t kDefaultHubMin = 32;
 
-// ---------------------------------------------------------------- driver
+// ------------------------------------------------------------- host side
 // Device workspace of one count: carved from one block, either per call or
 // kept in the graph's plan for captured replays.
 struct Workspace {

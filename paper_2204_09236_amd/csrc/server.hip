@@ -340,7 +340,7 @@ void admit(tm_server *S) {
             }
             continue;
         }
-        // anonymous: join the union batch of this round
+        // anonymous: join the union batch of this admission cycle
         if (!make_room(S, anon_need + need)) break;
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -351,7 +351,7 @@ void admit(tm_server *S) {
         anon_need += need;
     }
     if (anon.empty()) return;
-    // one union build for the anonymous requests of this round
+    // one union build for the anonymous requests of this admission cycle
     const uint32_t G = (uint32_t)anon.size();
     std::vector<uint64_t> eoff(G + 1, 0);
     std::vector<uint32_t> ncount(G);
