@@ -1,32 +1,52 @@
 """Throughput benchmark: exact 36-motif counting.
 
-Default workload: the power-law graph (1M nodes, 20M edges, delta 3600).  One
-step = the whole counting path on one synthetic graph already resident in
-HBM: build the device graph (validate, time sort, per-node sequences S_u,
-node-pair edge sets) from device pointers, count every motif for each delta
-of the workload (star/pair sweeps, triangle kernel, reduction), copy the 36
-counts back.
+Default workload: the large skewed graph (10M nodes, 300M edges, 20 %
+repeated node pairs, a hub of ~1.25M incident edges), counted at delta 600,
+3,600 and 86,400.  One step = the whole counting path on the graph already
+resident in HBM: build the device graph (validate, time sort, per-node
+sequences S_u, node-pair edge sets) from device pointers, count every motif
+for each delta of the workload (star/pair sweeps, triangle kernels,
+reduction), copy the counts back.  The power-law graph (1M nodes, 20M edges,
+delta 3,600) runs after it and is reported under ``extra_workloads``.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload powerlaw|tiny|skewed|batch|serve|stream]
+                    [--workload skewed|powerlaw|tiny|batch|serve|stream]
 
 Prints one JSON line.  ``value`` = edges counted per second over the K timed
 steps (m x number of deltas per step, wall clock bracketed by device
-synchronisation).  ``roofline`` is measured for the kernel with the largest
-share of GPU time: K traced steps first record HIP events around every launch
-on its stream (the per-kernel table), then the K timed steps trace only that
-kernel, whose launch durations inside the timed region give ``achieved``;
-algorithmic bytes per launch come from ``byte_model``; ``traffic`` is the HBM bytes per launch from
-rocprofv3 counters, read from the committed summary under profiles/ when it
-was taken from the current kernel sources.  ``cpu_baseline`` is the CPU
-oracle (test infrastructure: the paper's Algorithms 1 and 2, OpenMP over
-centers) timed on this host.
+synchronisation).
+
+Rooflines use the algorithmic bytes of each step of the path (the per-unit
+figures below; m edges, n nodes, P distinct node pairs, per delta):
+  a1 ingest + validate   16 B per edge read
+  a2 S_u build           16 B per edge read, 40 B per edge written, 8 B per node
+  a3 node-pair lists     16 B per edge written, 8 B per pair (index)
+  a4 star/pair           40 B per edge (every entry read once)
+  a5 triangles           16 B per edge (both window sizes of every edge, the
+                         candidate test) + 8 B per entry of the union of the
+                         candidates' larger windows (read once) + 8 B per entry
+                         of each candidate's smaller window
+``rows`` gives, per step of the path, the GPU time per step (HIP events
+around every launch, traced in a separate pass of K steps), these bytes and
+the fraction of the 8 TB/s HBM peak; ``whole_step`` the same for the whole
+step over the timed wall clock.  ``roofline`` is for the kernel with the
+largest share of GPU time: its row's algorithmic bytes are split over the
+row's kernels in proportion to the bytes each one's access pattern moves
+(``byte_model``), and the kernel's launch durations come from the timed
+steps themselves (it alone is traced there).  ``traffic`` is the HBM bytes
+per launch from rocprofv3 counters, read from the committed summary under
+profiles/ when it was taken from the current kernel sources.
+``cpu_baseline`` is the CPU oracle (test infrastructure: the paper's
+Algorithms 1 and 2, OpenMP over centers) timed on this host on a bounded
+time slice of the workload, on one thread and on all usable cores, median of
+3 runs each, with its counts compared with the GPU's on the same slice.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -35,6 +55,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "temporal edges/s counted (exact 36 motifs), %HBM peak; p50/p99 request latency"
 HBM_PEAK_GBS = 8000.0
+ROWS = {"a1": "ingest + validate", "a2": "S_u build (time sort, node sort, offsets)",
+        "a3": "node-pair lists", "a4": "star/pair (window kernel, sweeps)", "a5": "triangles",
+        "a6": "work items (chunks, tiles, hub slices)", "a7": "reduction"}
 
 
 def parse():
@@ -42,27 +65,30 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="powerlaw",
-                    choices=["powerlaw", "tiny", "skewed", "batch", "serve", "stream"])
+    ap.add_argument("--workload", default="skewed",
+                    choices=["skewed", "powerlaw", "tiny", "batch", "serve", "stream"])
+    ap.add_argument("--extra-workloads", default="powerlaw",
+                    help="single-graph workloads timed after the main one (comma list, '' for none)")
     ap.add_argument("--stream-batch", type=int, default=1_000_000,
                     help="stream workload: edges per append")
     ap.add_argument("--serve-pool", type=int, default=128, help="graphs in the serving pool")
     ap.add_argument("--serve-mhi", type=float, default=5e7,
                     help="largest edge count of a pool graph (log-uniform from 1e3)")
     ap.add_argument("--serve-rates", default="50,100,200,500,1000,2000")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="arrival window per rate (at most --serve-max requests)")
-    ap.add_argument("--serve-max", type=int, default=1000)
+    ap.add_argument("--serve-max", type=int, default=2000)
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--batch-mhi", type=float, default=2e6,
                     help="largest per-graph edge count of the batch workload (log-uniform from 1e3)")
-    ap.add_argument("--procs", type=int, default=16, help="generator processes (batch workload)")
+    ap.add_argument("--procs", type=int, default=16, help="generator processes (batch and serve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=float, default=0.05,
-                    help="skewed workload: fraction of the time span the CPU baseline counts")
+    ap.add_argument("--cpu-sample", type=float, default=0.0,
+                    help="fraction of the time span the CPU baseline counts (0: the workload's default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner pass before warm-up (library defaults)")
+    ap.add_argument("--separate-counts", action="store_true",
+                    help="count each delta with its own tm_count call instead of one tm_count_multi")
     ap.add_argument("--untraced", action="store_true",
                     help="time the steps without the per-launch event tracer (no roofline)")
     return ap.parse_args()
@@ -72,21 +98,25 @@ HUB_MIN_DEFAULT, HUB_CAP, HUB_SLICE = 32, 2048, 512
 
 
 def window_stats(src, dst, t, delta: int, hub_min: int = HUB_MIN_DEFAULT) -> dict:
-    """Delta-window facts of a graph, for the triangle kernels' byte models
-    (measurement only, outside the timed region).  Entries of S_u are ordered
-    by (node, t, edge id): interleaving the two entries of each edge by edge id
-    and sorting stably by (node, t) gives that order.  W(p) = later entries of
-    the same S_u within delta; a triangle candidate is an edge with non-empty
-    windows after it at both endpoints.  Candidates whose larger window is at
+    """Delta-window facts of a graph, for the byte models of the triangle
+    kernels and the algorithmic bytes of the triangle step (measurement
+    only, outside the timed region).  Entries of S_u are ordered by (node, t,
+    edge id): interleaving the two entries of each edge by edge id and sorting
+    stably by (node, t) gives that order.  W(p) = later entries of the same
+    S_u within delta; a triangle candidate is an edge with non-empty windows
+    after it at both endpoints.  ``union`` counts the entries that lie in the
+    larger window of at least one candidate, ``sum_cand_min`` the entries of
+    the candidates' smaller windows.  Candidates whose larger window is at
     least hub_min and whose smaller one is below HUB_CAP go to the slice
     kernel: they belong to the position with the larger window (the source
     side on a tie), and each HUB_SLICE-position slice of S holding such
     owners reads the union of their windows once."""
     import torch
     m = src.numel()
+    keys = ("sum_w", "max_w", "cand", "sum_cand_w", "sum_cand_min", "union", "sum_cand_prod",
+            "reg_cand", "reg_sum_w", "hub_cand", "hub_probes", "hub_tiles", "hub_union")
     if m == 0:
-        return {k: 0 for k in ("sum_w", "max_w", "cand", "sum_cand_w", "sum_cand_prod", "reg_cand",
-                                "reg_sum_w", "hub_cand", "hub_probes", "hub_tiles", "hub_union")}
+        return {k: 0 for k in keys}
     t0 = t - t.min()
     tb = max(int(t0.max().item() + delta).bit_length(), 1)
     node = torch.stack([src, dst], 1).reshape(-1).long()
@@ -103,9 +133,17 @@ def window_stats(src, dst, t, delta: int, hub_min: int = HUB_MIN_DEFAULT) -> dic
     ws, wd = W[ps], W[pd]
     cand = (ws > 0) & (wd > 0)
     big, small = torch.maximum(ws, wd), torch.minimum(ws, wd)
+    own_all = torch.where(ws >= wd, ps, pd)
+    # union of the candidates' larger windows (own, own + big]
+    diff = torch.zeros(2 * m + 2, dtype=torch.int32, device=W.device)
+    oc, bc = own_all[cand], big[cand]
+    diff.index_add_(0, oc + 1, torch.ones_like(oc, dtype=torch.int32))
+    diff.index_add_(0, oc + bc + 1, torch.full_like(oc, -1, dtype=torch.int32))
+    union = int((torch.cumsum(diff, 0) > 0).sum().item())
+    del diff, oc, bc
     hub = cand & (big >= hub_min) & (small < HUB_CAP)
     reg = cand & ~hub
-    own = torch.where(ws >= wd, ps, pd)[hub]
+    own = own_all[hub]
     ow = big[hub]
     tile = own // HUB_SLICE
     n_tiles = (2 * m + HUB_SLICE - 1) // HUB_SLICE
@@ -117,6 +155,8 @@ def window_stats(src, dst, t, delta: int, hub_min: int = HUB_MIN_DEFAULT) -> dic
     return {"sum_w": int(W.sum().item()), "max_w": int(W.max().item()),
             "cand": int(cand.sum().item()),
             "sum_cand_w": int((ws + wd)[cand].sum().item()),
+            "sum_cand_min": int(small[cand].sum().item()),
+            "union": union,
             "sum_cand_prod": int((ws * wd)[cand].sum().item()),
             "reg_cand": int(reg.sum().item()),
             "reg_sum_w": int((ws + wd)[reg].sum().item()),
@@ -126,14 +166,35 @@ def window_stats(src, dst, t, delta: int, hub_min: int = HUB_MIN_DEFAULT) -> dic
             "hub_union": int((hi - lo + 1)[used].sum().item())}
 
 
+def distinct_pairs(src, dst) -> int:
+    """Number of distinct unordered node pairs (the index of the pair lists)."""
+    import torch
+    lo = torch.minimum(src, dst).long()
+    hi = torch.maximum(src, dst).long()
+    return int(torch.unique(lo * (int(hi.max().item()) + 1) + hi).numel())
+
+
+def row_bytes(m: int, n: int, pairs: int, wstats: dict, deltas: list[int]) -> dict:
+    """Algorithmic bytes of each step of the path for one step of the
+    benchmark (every delta of the workload counted once); see the module
+    docstring for the per-unit figures."""
+    a5 = 0
+    for d in deltas:
+        ws = wstats[str(d)]
+        a5 += 16 * m + 8 * (ws["union"] + ws["sum_cand_min"])
+    return {"a1": 16 * m, "a2": 56 * m + 8 * n, "a3": 16 * m + 8 * (pairs + 1),
+            "a4": 40 * m * len(deltas), "a5": a5}
+
+
 def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dict:
-    """Algorithmic bytes per launch of each kernel: what its access pattern
-    must read and write at least once (reads + writes).  m edges, 2m incident
-    entries, n nodes, tk = time-sort key width, me = edges on node pairs with
-    >= 2 edges, nm = such pairs.  Radix scatter passes read and write every
-    (key, value) pair once; histogram passes read every key once.  The time
-    sort of one graph reads the input arrays (src, dst, t: 16 B per edge) in
-    its histogram and first pass, and its last pass writes the rank-ordered
+    """Bytes each kernel's access pattern moves per launch (reads + writes of
+    the data it touches, each byte once): the weights that split a row's
+    algorithmic bytes over its kernels.  m edges, 2m incident entries, n
+    nodes, tk = time-sort key width, me = edges on node pairs with >= 2
+    edges, nm = such pairs.  Radix scatter passes read and write every (key,
+    value) pair once; histogram passes read every key once.  The time sort
+    of one graph reads the input arrays (src, dst, t: 16 B per edge) in its
+    histogram and first pass, and its last pass writes the rank-ordered
     arrays (t, input index, the two node-sort entries, pair key and value:
     64 B per edge).  The node sort's last pass writes the sequence arrays
     (node, t, other end | dir, rank) and each edge's two positions instead
@@ -141,19 +202,20 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
     e2 = 2 * m
     tk = 4 if info["tbits"] <= 32 else 8
     me, nm = info["multi_pair_edges"], info["multi_pairs"]
-    pn = max(passes["node"], 1)
-    node_scatter = (e2 * 40 * (pn - 1) + e2 * (20 + 24)) / pn
     pt = max(passes["time"], 1)
     time_first = 16 + ((tk + 12) if pt > 1 else 64)
-    time_scatter = (m * time_first + m * (tk + 12) * 2 * max(pt - 2, 0) +
-                    (m * (tk + 12 + 64) if pt > 1 else 0)) / pt
+    # "sort_time_scatter": every pass but the last (the first reads the inputs)
+    time_scatter = ((m * time_first + m * (tk + 12) * 2 * max(pt - 2, 0)) / (pt - 1)
+                    if pt > 1 else 0)
     table = {
         "validate": m * 16,
         "time_keys": m * (16 + tk + 12),   # batches only
         "sort_time_hist": m * 8,
         "sort_time_scatter": time_scatter,
+        "sort_time_scatter_last": m * (tk + 12 + 64) if pt > 1 else m * (16 + 64),
         "sort_node_hist": e2 * 4,
-        "sort_node_scatter": node_scatter,
+        "sort_node_scatter": e2 * 40,
+        "sort_node_scatter_last": e2 * (20 + 24),
         "offsets_fill": (n + 1) * 4,
         "offsets": e2 * 4 + (n + 1) * 4,
         "sort_pair_hist": m * 8,
@@ -183,19 +245,50 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
     return table
 
 
-def kernel_table(prof: dict, model: dict) -> tuple[dict, str | None]:
-    kernels = {}
-    for k, (launches, total_ms) in prof.items():
+def split_name(full: str) -> tuple[str, str]:
+    """'a2:sort_node_scatter' -> ('a2', 'sort_node_scatter')."""
+    if ":" in full:
+        r, k = full.split(":", 1)
+        return r, k
+    return "other", full
+
+
+def kernel_table(prof: dict, model: dict, rows_alg: dict, steps: int) -> tuple[dict, dict]:
+    """Per traced kernel: launches, time, modelled bytes, and its share of its
+    row's algorithmic bytes (the row's bytes split over the row's kernels in
+    proportion to their modelled bytes per step) with the fraction of peak
+    that share reaches.  Also the per-row summary."""
+    kernels, per_row_model = {}, {}
+    for full, (launches, total_ms) in prof.items():
+        r, k = split_name(full)
+        b = model.get(k)
+        if b is not None:
+            per_row_model[r] = per_row_model.get(r, 0.0) + b * launches / steps
+    rows = {}
+    for full, (launches, total_ms) in prof.items():
+        r, k = split_name(full)
         row = {"launches": launches, "total_ms": round(total_ms, 4),
                "avg_ms": round(total_ms / max(launches, 1), 5)}
         b = model.get(k)
         if b is not None and total_ms > 0:
-            gbs = b / (total_ms / launches / 1e3) / 1e9
-            row.update({"bytes_per_launch": int(b), "achieved_GBs": round(gbs, 1),
-                        "frac": round(gbs / HBM_PEAK_GBS, 4)})
-        kernels[k] = row
-    dominant = max(prof.items(), key=lambda kv: kv[1][1])[0] if prof else None
-    return kernels, dominant
+            row["model_bytes_per_launch"] = int(b)
+            row["model_GBs"] = round(b / (total_ms / launches / 1e3) / 1e9, 1)
+            if r in rows_alg and per_row_model.get(r):
+                alg = rows_alg[r] * (b * launches / steps) / per_row_model[r] / (launches / steps)
+                gbs = alg / (total_ms / launches / 1e3) / 1e9
+                row.update({"alg_bytes_per_launch": int(alg), "achieved_GBs": round(gbs, 1),
+                            "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[full] = row
+        rr = rows.setdefault(r, {"ms_per_step": 0.0})
+        rr["ms_per_step"] += total_ms / steps
+    for r, rr in rows.items():
+        rr["ms_per_step"] = round(rr["ms_per_step"], 4)
+        rr["step"] = ROWS.get(r, "untagged launches")
+        if r in rows_alg and rr["ms_per_step"] > 0:
+            gbs = rows_alg[r] / (rr["ms_per_step"] / 1e3) / 1e9
+            rr.update({"alg_bytes_per_step": int(rows_alg[r]), "achieved_GBs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return kernels, rows
 
 
 COUNT_KERNELS = ("windows", "star_prep", "item_counts", "item_pairs", "star_pair", "wlevels",
@@ -205,9 +298,10 @@ COUNT_KERNELS = ("windows", "star_prep", "item_counts", "item_pairs", "star_pair
 
 def kernel_sources(kernel: str) -> list[str]:
     """The HIP source files that define a traced kernel."""
-    if kernel.startswith("sort_") or kernel.startswith("scan_"):
+    k = split_name(kernel)[1]
+    if k.startswith("sort_") or k.startswith("scan_"):
         return ["prim.hip", "tm_internal.h"]
-    if kernel in COUNT_KERNELS:
+    if k in COUNT_KERNELS:
         return ["count.hip", "tm_internal.h"]
     return ["build.hip", "tm_internal.h"]
 
@@ -228,7 +322,8 @@ def stored_traffic(kernel: str, workload: str) -> dict | None:
     """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by
     a copy kernel of known size, read from the committed counter summary of
     (kernel, workload) if it was taken from the current sources."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    fname = kernel.replace(":", ".")
+    path = os.path.join(ROOT, "profiles", f"pmc_{fname}_{workload}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -248,6 +343,318 @@ def stored_traffic(kernel: str, workload: str) -> dict | None:
         return None
 
 
+COPY_CALIB_BYTES = 256 << 20
+
+
+def run_single(args, workload: str, full: bool = True) -> dict:
+    """One graph: a step builds the device graph from device pointers and
+    counts every delta of the workload (one for power-law and tiny, three for
+    skewed) on it.  ``full`` adds the CPU baseline, the PCIe-inclusive rate
+    and the per-family and per-delta timings."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2204_09236_amd as tm
+
+    dev = torch.device("cuda:0")
+    spec = graphgen.CONFIGS[workload]
+    deltas = list(spec["deltas"])
+    t0 = time.time()
+    g = spec["fn"]()
+    print(f"[bench] generated {workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    src = torch.from_numpy(g.src).to(dev)
+    dst = torch.from_numpy(g.dst).to(dev)
+    tt = torch.from_numpy(g.t).to(dev)
+    stream = torch.cuda.current_stream()
+    # a plain device copy of known size: the reference reading for the
+    # FETCH_SIZE / WRITE_SIZE counters of a profiled run of this script
+    ca = torch.ones(COPY_CALIB_BYTES // 4, dtype=torch.int32, device=dev)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    del ca, cb
+    torch.cuda.synchronize()
+    multi = len(deltas) > 1 and not args.separate_counts
+
+    def step():
+        G = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
+        outs = list(G.count_multi(deltas)) if multi else [G.count(d) for d in deltas]
+        G.free()
+        return outs
+
+    # the library's autotuner, once, before warm-up and outside the timed
+    # region, at the workload's largest delta (the most work): its choice is
+    # kept in the process-wide table keyed by graph shape, so the timed
+    # steps' freshly built graphs of this shape count with it
+    tuned = None
+    if not args.no_autotune:
+        G0 = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
+        tuned = G0.autotune([max(deltas)])
+        G0.free()
+        print(f"[bench] autotuned at delta {max(deltas)}: {tuned}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        counts = step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    # every launch traced (events around each kernel): the per-kernel table
+    # and the kernel with the largest share of GPU time
+    tm.prof_reset()
+    tm.prof_enable(not args.untraced)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        counts = step()
+    torch.cuda.synchronize()
+    tm.prof_enable(False)
+    prof = tm.prof_read()
+    dominant_name = max(prof.items(), key=lambda kv: kv[1][1])[0] if prof else None
+    print("[bench] traced steps done", file=sys.stderr, flush=True)
+
+    # the timed steps trace only that kernel (two events per launch of it),
+    # so its launch durations come from the timed region itself
+    tm.prof_reset()
+    tm.prof_only(dominant_name)
+    tm.prof_enable(dominant_name is not None)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        counts = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    tm.prof_enable(False)
+    tm.prof_only(None)
+    prof_timed = tm.prof_read()
+    print("[bench] timed steps done", file=sys.stderr, flush=True)
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = g.m * len(deltas) * args.steps / elapsed
+
+    # build alone and count alone (outside the timed region above)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    for _ in range(args.steps):
+        tm.build_graph(src, dst, tt, n=g.n, stream=stream).free()
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t_b) * 1e3 / args.steps
+    G = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
+    info = G.info()
+    count_ms = {}
+    for d in deltas:
+        G.count(d)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for _ in range(args.steps):
+            G.count(d)
+        torch.cuda.synchronize()
+        count_ms[str(d)] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
+    extra = {}
+    if len(deltas) > 1:
+        # every delta in one call (tm_count_multi) against the single counts
+        mc = G.count_multi(deltas)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for _ in range(args.steps):
+            mc = G.count_multi(deltas)
+        torch.cuda.synchronize()
+        extra["count_multi"] = {
+            "deltas": deltas, "ms": round((time.perf_counter() - t_c) * 1e3 / args.steps, 4),
+            "sum_of_single_counts_ms": round(sum(count_ms.values()), 4),
+            "equals_single_counts": bool(all(np.array_equal(mc[i], G.count(d))
+                                              for i, d in enumerate(deltas)))}
+    if full:
+        # one family at a time (tm_count_masked), as the paper times its
+        # pair-only and triangle-only variants
+        family_ms = {}
+        for name, fam in (("stars+pairs", tm.STARS | tm.PAIRS), ("pairs", tm.PAIRS),
+                          ("triangles", tm.TRIANGLES)):
+            G.count(deltas[0], families=fam)
+            torch.cuda.synchronize()
+            t_c = time.perf_counter()
+            for _ in range(args.steps):
+                G.count(deltas[0], families=fam)
+            torch.cuda.synchronize()
+            family_ms[name] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
+        extra["count_only_family_ms"] = {"delta": deltas[0], **family_ms}
+    G.free()
+    if full:
+        # PCIe-inclusive: the same step from host arrays (the boundary copies them in)
+        host_reps = max(1, min(args.steps, 3))
+        torch.cuda.synchronize()
+        t_h = time.perf_counter()
+        for _ in range(host_reps):
+            Gh = tm.build_graph(g.src, g.dst, g.t, n=g.n)
+            if multi:
+                Gh.count_multi(deltas)
+            else:
+                for d in deltas:
+                    Gh.count(d)
+            Gh.free()
+        torch.cuda.synchronize()
+        host_ms = (time.perf_counter() - t_h) * 1e3 / host_reps
+        extra["pcie_inclusive"] = {"ms_per_step": round(host_ms, 3),
+                                   "edges_per_s": round(g.m * len(deltas) / (host_ms / 1e3), 1),
+                                   "note": "inputs in host memory, copied in by tm_build_graph"}
+
+    tspan = int(g.t.max() - g.t.min()) if g.m else 0
+    info["tbits"] = max(tspan.bit_length(), 1)
+    passes = {"node": (max(int(g.n - 1).bit_length(), 1) + 7) // 8,
+              "time": (max(info["tbits"], 1) + 7) // 8}
+    wstats = {str(d): window_stats(src, dst, tt, d) for d in deltas}
+    pairs = distinct_pairs(src, dst)
+    torch.cuda.empty_cache()
+    rows_alg = row_bytes(g.m, g.n, pairs, wstats, deltas)
+    # count kernels run once per delta: the model averages their bytes over deltas
+    model = byte_model(g.m, g.n, info, None, passes)
+    tri = {"tri_compact": 0.0, "triangles": 0.0, "tri_hub": 0.0}
+    for d in deltas:
+        md = byte_model(g.m, g.n, info, wstats[str(d)], passes)
+        for k in tri:
+            tri[k] += md[k] / len(deltas)
+    model.update(tri)
+    kernels, rows = kernel_table(prof, model, rows_alg, args.steps)
+    alg_step = sum(rows_alg.values())
+    whole = {"alg_bytes_per_step": int(alg_step), "ms_per_step": round(ms_per_step, 4),
+             "achieved_GBs": round(alg_step / (ms_per_step / 1e3) / 1e9, 1),
+             "frac": round(alg_step / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    roofline = None
+    if dominant_name is not None and dominant_name in prof_timed:
+        # the dominant kernel as measured inside the timed steps, with its
+        # per-launch algorithmic bytes from the traced pass
+        launches, tot = prof_timed[dominant_name]
+        kd = kernels.get(dominant_name, {})
+        if "alg_bytes_per_launch" in kd and tot > 0:
+            avg_ms = tot / launches
+            gbs = kd["alg_bytes_per_launch"] / (avg_ms / 1e3) / 1e9
+            tr = stored_traffic(dominant_name, workload)
+            roofline = {"kernel": dominant_name, "bound": "hbm", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "traffic": None if tr is None else tr["bytes"],
+                        "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
+                        "avg_launch_ms": round(avg_ms, 5), "launches_per_step": launches / args.steps,
+                        "model_bytes_per_launch": kd.get("model_bytes_per_launch")}
+            if tr is not None:
+                roofline["traffic_over_alg"] = round(tr["bytes"] / kd["alg_bytes_per_launch"], 3)
+                roofline["traffic_GBs"] = round(tr["bytes"] / (avg_ms / 1e3) / 1e9, 1)
+
+    cpu = None
+    if full and not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, workload, g, deltas)
+    golden = golden_check(workload, g, deltas, counts)
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": g.n, "m": g.m, "deltas": deltas,
+                   "counts_per_step": "tm_count_multi" if multi else "tm_count per delta",
+                   "parallelism": "single-gpu"},
+        "roofline": roofline, "cpu_baseline": cpu, "golden": golden,
+        "rows": rows, "whole_step": whole,
+        "build_only_ms": round(build_ms, 4), "count_only_ms": count_ms,
+        "count_only_edges_per_s": {d: round(g.m / (v / 1e3), 1) for d, v in count_ms.items()},
+        **extra,
+        "autotuned": tuned,
+        "gpu_kernel_ms_per_step": round(sum(v[1] for v in prof.values()) / args.steps, 4),
+        "graph": {**{k: info[k] for k in ("multi_pairs", "multi_pair_edges", "max_degree")},
+                  "distinct_pairs": pairs},
+        "window_stats": wstats,
+        "kernels": kernels,
+        "motif_total": [int(c.sum()) for c in counts],
+    }
+    del src, dst, tt
+    torch.cuda.empty_cache()
+    return line
+
+
+def golden_check(workload, g, deltas, counts):
+    """Compare with the oracle's stored counts for this workload
+    (tests/golden/<workload>_counts.json, written by make_golden.py from the
+    oracle alone) when the regenerated input has the stored sha256."""
+    import numpy as np
+
+    import graphgen
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_counts.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("edge_sha256") != graphgen.edge_hash(g):
+        return {"match": None, "note": "input differs from the stored one; not compared"}
+    ok = True
+    for d, c in zip(deltas, counts):
+        want = rec["counts"].get(str(d))
+        if want is None or not np.array_equal(np.array(want["grid"], dtype=np.uint64), c):
+            ok = False
+    return {"match": ok, "deltas": deltas, "source": os.path.relpath(path, ROOT)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores() -> int:
+    """Cores this process may run on, at most 16 (the host share that goes
+    with one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+CPU_SAMPLE = {"skewed": 0.005, "powerlaw": 0.1, "tiny": 1.0}
+
+
+def cpu_baseline(args, workload, g, deltas):
+    """The CPU oracle (the paper's Algorithms 1 and 2, OpenMP over centers,
+    building S_u and E_(v,w) itself) timed on this host on a bounded sample:
+    the edges of the first fraction of the time span (a temporal slice keeps
+    every window inside it intact), every delta of the workload, three runs
+    on one thread and three on all usable cores, median of each.  The GPU
+    counts the same slice, and the two are compared."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2204_09236_amd as tm
+    frac = args.cpu_sample or CPU_SAMPLE.get(workload, 0.05)
+    lim = int(g.t.min()) + int((int(g.t.max()) - int(g.t.min())) * frac)
+    sel = g.t <= lim
+    s, d, t = g.src[sel], g.dst[sel], g.t[sel]
+    m = int(s.size)
+    cores = usable_cores()
+    res = {}
+    want = None
+    for threads in (1, cores):
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            want = [oracle.alg(s, d, t, dl, n=g.n, threads=threads) for dl in deltas]
+            runs.append(time.perf_counter() - t0)
+        res[threads] = statistics.median(runs)
+    with tm.build_graph(torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(),
+                        torch.from_numpy(t).cuda(), n=g.n) as G:
+        got = [G.count_raw(dl) for dl in deltas]
+    match = all(np.array_equal(a, b) for a, b in zip(want, got))
+    sample = (f"edges with t in the first {frac:.1%} of the span (m={m} of {g.m}), "
+              f"deltas={deltas}, incl. building S_u and E_(v,w); median of 3 runs")
+    return {"value": round(m * len(deltas) / res[cores], 1), "unit": "edges/s", "cores": cores,
+            "kind": "oracle", "sample": sample,
+            "single_thread": {"value": round(m * len(deltas) / res[1], 1), "unit": "edges/s",
+                              "cores": 1, "seconds": round(res[1], 3)},
+            "all_cores_seconds": round(res[cores], 3),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "matches_gpu": bool(match)}
+
+
 def _gen_batch_member(item):
     import graphgen
     g = graphgen.batch_graph(item)
@@ -257,9 +664,11 @@ def _gen_batch_member(item):
 def bench_batch(args):
     """Batched vs per-graph counting of many uneven graphs, each with its own
     delta.  Batched step = one build of all graphs (tm_build_batch from
-    device pointers) + one count (tm_count_batch, a captured hipGraph) + free.
-    Per-graph = tm_build_graph + tm_count + free for every graph in turn.
-    Both must give identical counts."""
+    device pointers) + one count (tm_count_batch, a captured hipGraph) + free;
+    the build and the count are also timed alone.  Per-graph = tm_build_graph
+    + tm_count + free for every graph in turn.  Both must give identical
+    counts, and the graphs of the stored oracle sample
+    (tests/golden/batch_counts.json) must match it."""
     import multiprocessing as mp
 
     import numpy as np
@@ -269,7 +678,6 @@ def bench_batch(args):
     import paper_2204_09236_amd as tm
 
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     spec = graphgen.batch_spec(seed=3, graphs=args.batch_graphs, m_hi=args.batch_mhi)
     t0 = time.time()
     with mp.get_context("fork").Pool(args.procs) as pool:
@@ -291,26 +699,41 @@ def bench_batch(args):
 
     def batched():
         B = tm.build_batch_arrays(src, dst, tt, off, ncount, stream=stream)
-        out = B.count_batch(deltas)
+        out = B.count_batch_raw(deltas)
         B.free()
         return out
 
     for _ in range(args.warmup):
-        res_b = batched()
+        raw_b = batched()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        res_b = batched()
+        raw_b = batched()
     torch.cuda.synchronize()
     el_b = (time.perf_counter() - t_start) / args.steps
     print(f"[bench] batched: {el_b * 1e3:.1f} ms per batch", file=sys.stderr, flush=True)
+    # build alone, count alone
+    t_s = time.perf_counter()
+    for _ in range(args.steps):
+        tm.build_batch_arrays(src, dst, tt, off, ncount, stream=stream).free()
+    torch.cuda.synchronize()
+    el_build = (time.perf_counter() - t_s) / args.steps
+    B = tm.build_batch_arrays(src, dst, tt, off, ncount, stream=stream)
+    B.count_batch_raw(deltas)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter()
+    for _ in range(args.steps):
+        B.count_batch_raw(deltas)
+    torch.cuda.synchronize()
+    el_count = (time.perf_counter() - t_s) / args.steps
+    B.free()
 
     def per_graph():
         outs = []
         for i in range(G):
             a, b = int(off[i]), int(off[i + 1])
             Gi = tm.build_graph(src[a:b], dst[a:b], tt[a:b], n=int(ncount[i]), stream=stream)
-            outs.append(Gi.count(int(deltas[i])))
+            outs.append(Gi.count_raw(int(deltas[i])))
             Gi.free()
         return np.stack(outs)
 
@@ -320,7 +743,16 @@ def bench_batch(args):
     res_p = per_graph()
     torch.cuda.synchronize()
     el_p = time.perf_counter() - t_start
-    same = bool(np.array_equal(res_b, res_p))
+    same = bool(np.array_equal(raw_b, res_p))
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch_counts.json")
+    if args.batch_graphs == 4096 and args.batch_mhi == 2e6 and os.path.exists(gpath):
+        with open(gpath) as f:
+            rec = json.load(f)
+        bad = [r["index"] for r in rec["members"]
+               if not np.array_equal(raw_b[r["index"]], np.array(r["raw"], dtype=np.uint64))]
+        golden = {"match": not bad, "graphs_compared": len(rec["members"]), "mismatched": bad[:10],
+                  "source": os.path.relpath(gpath, ROOT)}
     line = {
         "metric": METRIC, "value": round(m_total / el_b, 1), "unit": "edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el_b * 1e3, 3),
@@ -329,14 +761,15 @@ def bench_batch(args):
         "config": {"workload": "batch", "graphs": G, "edges": m_total,
                    "m_range": [1000, args.batch_mhi], "delta_range": [60, 86400],
                    "parallelism": "single-gpu"},
+        "build_only_ms": round(el_build * 1e3, 3), "count_only_ms": round(el_count * 1e3, 3),
         "per_graph": {"value": round(m_total / el_p, 1), "unit": "edges/s",
                       "seconds": round(el_p, 3)},
         "batched_over_per_graph": round(el_p / el_b, 2),
-        "identical_counts": same,
-        "motif_total": int(res_b.sum()),
+        "identical_counts": same, "golden": golden,
+        "motif_total": int(res_p.sum()),
     }
     print(json.dumps(line))
-    if not same:
+    if not same or (golden is not None and not golden["match"]):
         sys.exit(1)
 
 
@@ -418,11 +851,15 @@ def bench_stream(args):
 
 
 def bench_serve(args):
-    """Serving: Poisson arrivals of (pool graph, delta) requests at each rate;
-    keyed graphs stay resident after their first request.  Latency = done -
-    submit on the server's clock; edges/s = edges of the completed requests /
-    (last done - first submit).  Every result is compared with the same
-    request counted alone."""
+    """Serving.  Open loop: Poisson arrivals of (pool graph, delta) requests
+    at each rate; keyed graphs stay resident after their first request.
+    Latency = done - submit on the server's clock; edges/s = edges of the
+    completed requests / (last done - first submit), the offered load when
+    the server keeps up.  Closed loop (saturation): one list of requests, all
+    submitted at once to the server, against the same list run as a plain
+    sequential loop of tm_count calls on resident graphs and as a plain loop
+    of tm_build_graph + tm_count per request; capacity = edges / wall time.
+    Every result is compared with the same request counted alone."""
     import math
     import multiprocessing as mp
 
@@ -432,11 +869,9 @@ def bench_serve(args):
     import graphgen
     import paper_2204_09236_amd as tm
 
-    torch.cuda.set_device(0)
     rng = np.random.default_rng(4)
-    ms = np.rint(np.exp(rng.uniform(math.log(1e3), math.log(args.serve_mhi), args.serve_pool)))
-    kids = np.random.SeedSequence(4).spawn(args.serve_pool)
-    spec = [graphgen.BatchItem(int(m), max(3, int(m) // 20), 0, kids[i]) for i, m in enumerate(ms)]
+    spec = graphgen.serve_spec(seed=4, pool=args.serve_pool, m_hi=args.serve_mhi)
+    ms = np.array([it.m for it in spec])
     t0 = time.time()
     with mp.get_context("fork").Pool(args.procs) as pool_:
         pool = pool_.map(_gen_batch_member, spec, chunksize=2)
@@ -444,16 +879,30 @@ def bench_serve(args):
           f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     rates = [float(r) for r in args.serve_rates.split(",")]
     budget = int(0.7 * torch.cuda.get_device_properties(0).total_memory)
-    S = tm.Server(budget, max_inflight=16)
+    max_inflight = 16
+    S = tm.Server(budget, max_inflight=max_inflight)
     alone_graphs = {}
+    alone_counts = {}
+
+    def alone(gi, delta):
+        if (gi, delta) not in alone_counts:
+            if gi not in alone_graphs:
+                src, dst, t, n = pool[gi]
+                alone_graphs[gi] = tm.build_graph(src, dst, t, n=n)
+            alone_counts[(gi, delta)] = alone_graphs[gi].count(delta)
+        return alone_counts[(gi, delta)]
+
+    def draw(k):
+        return [(int(rng.integers(0, len(pool))),
+                 int(round(math.exp(rng.uniform(math.log(60), math.log(86400))))))
+                for _ in range(k)]
+
     rows = []
     sent = set()
     for rate in rates:
         n_req = int(min(args.serve_max, max(20, rate * args.serve_seconds)))
         gaps = rng.exponential(1.0 / rate, n_req)
-        reqs = [(int(rng.integers(0, len(pool))),
-                 int(round(math.exp(rng.uniform(math.log(60), math.log(86400))))))
-                for _ in range(n_req)]
+        reqs = draw(n_req)
         outstanding, done = {}, {}
         start = time.perf_counter()
         t_next = start
@@ -481,298 +930,80 @@ def bench_serve(args):
         last_done = max(done[i][2][2] for i in range(n_req))
         edges = sum(pool[gi][0].size for gi, _ in reqs)
         ok = all(done[i][0] == 0 for i in range(n_req))
-        same = ok
-        if ok:
-            for i, (gi, delta) in enumerate(reqs):
-                if gi not in alone_graphs:
-                    src, dst, t, n = pool[gi]
-                    alone_graphs[gi] = tm.build_graph(src, dst, t, n=n)
-                if not np.array_equal(done[i][1], alone_graphs[gi].count(delta)):
-                    same = False
-                    break
+        same = ok and all(np.array_equal(done[i][1], alone(gi, d)) for i, (gi, d) in enumerate(reqs))
         row = {"rate": rate, "requests": n_req, "p50_ms": round(float(np.percentile(lat, 50)), 3),
                "p99_ms": round(float(np.percentile(lat, 99)), 3),
                "edges_per_s": round(edges / ((last_done - first_submit) / 1e9), 1),
                "all_ok": ok, "identical_to_alone": same}
         rows.append(row)
         print(f"[bench] serve rate {rate}: {row}", file=sys.stderr, flush=True)
+
+    # closed loop: every pool graph is resident by now (or rebuilt on demand)
+    sat_reqs = draw(args.serve_max)
+    sat_edges = sum(pool[gi][0].size for gi, _ in sat_reqs)
+    for gi, d in sat_reqs:          # the alone results first (not timed)
+        alone(gi, d)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter()
+    tks = [S.submit(d, key=gi + 1) if gi in sent else
+           S.submit(d, *pool[gi][:3], n=pool[gi][3], key=gi + 1) for gi, d in sat_reqs]
+    for gi, _ in sat_reqs:
+        sent.add(gi)
+    res = [S.wait(tk) for tk in tks]
+    el_srv = time.perf_counter() - t_s
+    srv_same = all(r[0] == 0 and np.array_equal(r[1], alone(gi, d))
+                   for r, (gi, d) in zip(res, sat_reqs))
+    torch.cuda.synchronize()
+    t_s = time.perf_counter()
+    plain = [alone_graphs[gi].count(d) for gi, d in sat_reqs]
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t_s
+    plain_same = all(np.array_equal(a, alone(gi, d)) for a, (gi, d) in zip(plain, sat_reqs))
+    n_build = min(len(sat_reqs), 200)
+    t_s = time.perf_counter()
+    for gi, d in sat_reqs[:n_build]:
+        src, dst, t, n = pool[gi]
+        with tm.build_graph(src, dst, t, n=n) as Gb:
+            Gb.count(d)
+    torch.cuda.synchronize()
+    el_build = time.perf_counter() - t_s
+    build_edges = sum(pool[gi][0].size for gi, _ in sat_reqs[:n_build])
+    saturation = {
+        "requests": len(sat_reqs), "edges": int(sat_edges),
+        "served": {"seconds": round(el_srv, 4), "edges_per_s": round(sat_edges / el_srv, 1),
+                   "identical_to_alone": bool(srv_same)},
+        "plain_resident": {"seconds": round(el_plain, 4),
+                           "edges_per_s": round(sat_edges / el_plain, 1),
+                           "identical_to_alone": bool(plain_same),
+                           "note": "sequential tm_count calls on graphs built beforehand"},
+        "plain_build_and_count": {"requests": n_build, "seconds": round(el_build, 4),
+                                  "edges_per_s": round(build_edges / el_build, 1),
+                                  "note": "sequential tm_build_graph (host arrays) + tm_count "
+                                          "per request"},
+        "served_over_plain_resident": round(el_plain / el_srv, 3),
+        "served_over_plain_build": round((sat_edges / el_srv) / (build_edges / el_build), 3),
+    }
+    print(f"[bench] saturation: {saturation}", file=sys.stderr, flush=True)
     st = S.stats()
     S.close()
     for G in alone_graphs.values():
         G.free()
     line = {
         "metric": METRIC,
-        "value": rows[-1]["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": len(rows),
-        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int64", "data": "synthetic",
+        "value": saturation["served"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 0, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": "serve", "pool_graphs": len(pool), "pool_edges": int(ms.sum()),
                    "m_range": [1000, args.serve_mhi], "delta_range": [60, 86400],
-                   "budget_bytes": budget, "max_inflight": 16, "parallelism": "single-gpu"},
-        "rates": rows, "server_stats": st,
-    }
-    print(json.dumps(line))
-    if not all(r["identical_to_alone"] for r in rows):
-        sys.exit(1)
-
-
-COPY_CALIB_BYTES = 256 << 20
-
-
-def bench_single(args):
-    """One graph: a step builds the device graph from device pointers and
-    counts every delta of the workload (one for power-law and tiny, three for
-    skewed) on it."""
-    import numpy as np
-    import torch
-
-    import graphgen
-    import paper_2204_09236_amd as tm
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    spec = graphgen.CONFIGS[args.workload]
-    deltas = list(spec["deltas"])
-    t0 = time.time()
-    g = spec["fn"]()
-    print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
-    src = torch.from_numpy(g.src).to(dev)
-    dst = torch.from_numpy(g.dst).to(dev)
-    tt = torch.from_numpy(g.t).to(dev)
-    stream = torch.cuda.current_stream()
-    # a plain device copy of known size: the reference reading for the
-    # FETCH_SIZE / WRITE_SIZE counters of a profiled run of this script
-    ca = torch.ones(COPY_CALIB_BYTES // 4, dtype=torch.int32, device=dev)
-    cb = torch.empty_like(ca)
-    cb.copy_(ca)
-    del ca, cb
-    torch.cuda.synchronize()
-
-    def step():
-        G = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
-        outs = [G.count(d) for d in deltas]
-        G.free()
-        return outs
-
-    # the library's autotuner, once, before warm-up and outside the timed
-    # region, at the workload's largest delta (the most work): its choice is
-    # kept in the process-wide table keyed by graph shape, so the timed
-    # steps' freshly built graphs of this shape count with it
-    tuned = None
-    if not args.no_autotune:
-        G0 = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
-        tuned = G0.autotune([max(deltas)])
-        G0.free()
-        print(f"[bench] autotuned at delta {max(deltas)}: {tuned}", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        counts = step()
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    # every launch traced (events around each kernel): the per-kernel table
-    # and the kernel with the largest share of GPU time
-    tm.prof_reset()
-    tm.prof_enable(not args.untraced)
-    torch.cuda.synchronize()
-    for _ in range(args.steps):
-        counts = step()
-    torch.cuda.synchronize()
-    tm.prof_enable(False)
-    prof = tm.prof_read()
-    dominant_name = max(prof.items(), key=lambda kv: kv[1][1])[0] if prof else None
-    print("[bench] traced steps done", file=sys.stderr, flush=True)
-
-    # the timed steps trace only that kernel (two events per launch of it),
-    # so its launch durations come from the timed region itself
-    tm.prof_reset()
-    tm.prof_only(dominant_name)
-    tm.prof_enable(dominant_name is not None)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        counts = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    tm.prof_enable(False)
-    tm.prof_only(None)
-    prof_timed = tm.prof_read()
-    print("[bench] timed steps done", file=sys.stderr, flush=True)
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = g.m * len(deltas) * args.steps / elapsed
-
-    # build alone and count alone (outside the timed region above)
-    torch.cuda.synchronize()
-    t_b = time.perf_counter()
-    for _ in range(args.steps):
-        tm.build_graph(src, dst, tt, n=g.n, stream=stream).free()
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - t_b) * 1e3 / args.steps
-    # PCIe-inclusive: the same step from host arrays (the boundary copies them in)
-    host_reps = max(1, min(args.steps, 3))
-    torch.cuda.synchronize()
-    t_h = time.perf_counter()
-    for _ in range(host_reps):
-        Gh = tm.build_graph(g.src, g.dst, g.t, n=g.n)
-        for d in deltas:
-            Gh.count(d)
-        Gh.free()
-    torch.cuda.synchronize()
-    host_ms = (time.perf_counter() - t_h) * 1e3 / host_reps
-    G = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
-    info = G.info()
-    count_ms = {}
-    for d in deltas:
-        G.count(d)
-        torch.cuda.synchronize()
-        t_c = time.perf_counter()
-        for _ in range(args.steps):
-            G.count(d)
-        torch.cuda.synchronize()
-        count_ms[str(d)] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
-    # one family at a time (tm_count_masked), as the paper times its
-    # pair-only and triangle-only variants
-    family_ms = {}
-    for name, fam in (("stars+pairs", tm.STARS | tm.PAIRS), ("pairs", tm.PAIRS),
-                      ("triangles", tm.TRIANGLES)):
-        G.count(deltas[0], families=fam)
-        torch.cuda.synchronize()
-        t_c = time.perf_counter()
-        for _ in range(args.steps):
-            G.count(deltas[0], families=fam)
-        torch.cuda.synchronize()
-        family_ms[name] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
-    # every delta of the workload in one call (tm_count_multi)
-    multi = None
-    if len(deltas) > 1:
-        mc = G.count_multi(deltas)
-        torch.cuda.synchronize()
-        t_c = time.perf_counter()
-        for _ in range(args.steps):
-            mc = G.count_multi(deltas)
-        torch.cuda.synchronize()
-        multi = {"deltas": deltas, "ms": round((time.perf_counter() - t_c) * 1e3 / args.steps, 4),
-                 "sum_of_single_counts_ms": round(sum(count_ms.values()), 4),
-                 "equals_step_counts": bool(all(np.array_equal(mc[i], counts[i])
-                                                for i in range(len(deltas))))}
-    G.free()
-
-    tspan = int(g.t.max() - g.t.min()) if g.m else 0
-    info["tbits"] = max(tspan.bit_length(), 1)
-    passes = {"node": (max(int(g.n - 1).bit_length(), 1) + 7) // 8,
-              "time": (max(info["tbits"], 1) + 7) // 8}
-    wstats = {str(d): window_stats(src, dst, tt, d) for d in deltas}
-    torch.cuda.empty_cache()
-    # count kernels run once per delta: the model averages their bytes over deltas
-    model = byte_model(g.m, g.n, info, None, passes)
-    tri = {"tri_compact": 0.0, "triangles": 0.0, "tri_hub": 0.0}
-    for d in deltas:
-        md = byte_model(g.m, g.n, info, wstats[str(d)], passes)
-        for k in tri:
-            tri[k] += md[k] / len(deltas)
-    model.update(tri)
-    kernels, dominant = kernel_table(prof, model)
-    roofline = None
-    if dominant is not None and dominant in prof_timed:
-        # the dominant kernel as measured inside the timed steps
-        kd = kernel_table({dominant: prof_timed[dominant]}, model)[0][dominant]
-    else:
-        kd = None
-    if kd is not None and "achieved_GBs" in kd:
-        tr = stored_traffic(dominant, args.workload)
-        roofline = {"kernel": dominant, "bound": "hbm", "achieved": kd["achieved_GBs"],
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["frac"],
-                    "traffic": None if tr is None else tr["bytes"],
-                    "bytes_per_launch": kd["bytes_per_launch"], "avg_launch_ms": kd["avg_ms"]}
-        if tr is not None:
-            roofline["traffic_over_algorithmic"] = round(tr["bytes"] / kd["bytes_per_launch"], 3)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, g, deltas, counts)
-    golden = golden_check(args.workload, g, deltas, counts)
-
-    line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "edges/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": g.n, "m": g.m, "deltas": deltas,
+                   "budget_bytes": budget, "max_inflight": max_inflight,
                    "parallelism": "single-gpu"},
-        "roofline": roofline, "cpu_baseline": cpu, "golden": golden,
-        "build_only_ms": round(build_ms, 4), "count_only_ms": count_ms,
-        "count_only_family_ms": {"delta": deltas[0], **family_ms},
-        "count_multi": multi,
-        "autotuned": tuned,
-        "pcie_inclusive": {"ms_per_step": round(host_ms, 3),
-                           "edges_per_s": round(g.m * len(deltas) / (host_ms / 1e3), 1),
-                           "note": "inputs in host memory, copied in by tm_build_graph"},
-        "count_only_edges_per_s": {d: round(g.m / (v / 1e3), 1) for d, v in count_ms.items()},
-        "gpu_kernel_ms_per_step": round(sum(v[1] for v in prof.values()) / args.steps, 4),
-        "graph": {k: info[k] for k in ("multi_pairs", "multi_pair_edges", "max_degree")},
-        "window_stats": wstats,
-        "kernels": kernels,
-        "motif_total": [int(c.sum()) for c in counts],
+        "value_is": "closed-loop served edges/s (capacity)",
+        "rates": rows, "requests_total": sum(r["requests"] for r in rows) + len(sat_reqs),
+        "saturation": saturation, "server_stats": st,
     }
     print(json.dumps(line))
-    if (cpu is not None and not cpu["matches_gpu"]) or (golden is not None and not golden["match"]):
+    if not all(r["identical_to_alone"] for r in rows) or not srv_same or not plain_same:
         sys.exit(1)
-
-
-def golden_check(workload, g, deltas, counts):
-    """Compare with the oracle's stored counts for this workload
-    (tests/golden/<workload>_counts.json, written by make_golden.py from the
-    oracle alone) when the regenerated input has the stored sha256."""
-    import numpy as np
-
-    import graphgen
-    path = os.path.join(ROOT, "tests", "golden", f"{workload}_counts.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    if rec.get("edge_sha256") != graphgen.edge_hash(g):
-        return {"match": None, "note": "input differs from the stored one; not compared"}
-    ok = True
-    for d, c in zip(deltas, counts):
-        want = rec["counts"].get(str(d))
-        if want is None or not np.array_equal(np.array(want["grid"], dtype=np.uint64), c):
-            ok = False
-    return {"match": ok, "deltas": deltas, "source": os.path.relpath(path, ROOT)}
-
-
-def cpu_baseline(args, g, deltas, counts):
-    """The CPU oracle (the paper's Algorithms 1 and 2, OpenMP over centers)
-    timed on this host.  Power-law and tiny: the whole workload.  Skewed: a
-    bounded sample, the edges of the first --cpu-sample fraction of the time
-    span (a temporal slice keeps every window of the slice intact), at the
-    smallest delta; counts of the sample are not compared."""
-    import numpy as np
-
-    import oracle
-    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-    if args.workload != "skewed":
-        t0 = time.perf_counter()
-        want = [oracle.count(g.src, g.dst, g.t, d, n=g.n, threads=threads) for d in deltas]
-        cpu_s = time.perf_counter() - t0
-        m = g.m * len(deltas)
-        sample = (f"whole {args.workload} workload (m={g.m}, deltas={deltas}), one run each, "
-                  f"{cpu_s:.1f} s incl. building S_u and E_(v,w)")
-        match = all(np.array_equal(a, b) for a, b in zip(want, counts))
-    else:
-        lim = int(g.t.min()) + int((int(g.t.max()) - int(g.t.min())) * args.cpu_sample)
-        sel = g.t <= lim
-        s, d, t = g.src[sel], g.dst[sel], g.t[sel]
-        t0 = time.perf_counter()
-        oracle.count(s, d, t, deltas[0], n=g.n, threads=threads)
-        cpu_s = time.perf_counter() - t0
-        m = int(s.size)
-        sample = (f"edges with t in the first {args.cpu_sample:.0%} of the span (m={m}), "
-                  f"delta={deltas[0]}, {cpu_s:.1f} s incl. building S_u and E_(v,w)")
-        match = True
-    return {"value": round(m / cpu_s, 1), "unit": "edges/s", "cores": threads, "kind": "oracle",
-            "sample": sample, "matches_gpu": bool(match)}
 
 
 def main():
@@ -782,13 +1013,30 @@ def main():
                           "not supported (the path would shard by center)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
     if args.workload == "stream":
         return bench_stream(args)
-    return bench_single(args)
+    line = run_single(args, args.workload, full=True)
+    extras = {}
+    for w in [x for x in args.extra_workloads.split(",") if x and x != args.workload]:
+        ex = run_single(args, w, full=False)
+        extras[w] = {k: ex[k] for k in ("value", "unit", "ms_per_step", "config", "roofline", "rows",
+                                        "whole_step", "build_only_ms", "count_only_ms", "golden",
+                                        "motif_total")}
+    if extras:
+        line["extra_workloads"] = extras
+    print(json.dumps(line))
+    bad = (line["cpu_baseline"] is not None and not line["cpu_baseline"]["matches_gpu"]) or \
+        (line["golden"] is not None and line["golden"]["match"] is False) or \
+        any(e["golden"] is not None and e["golden"]["match"] is False for e in extras.values())
+    if bad:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

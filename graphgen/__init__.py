@@ -25,6 +25,11 @@ available here, so these synthetic stand-ins take their place):
                Chung-Lu 2.1 + Pareto times over 6e7 s, per-graph delta
                log-uniform in [60, 86400], seed 3.  Each graph has its own
                spawned seed so any one of them can be rebuilt alone.
+* ``serve``    a pool of graphs with m log-uniform in [1e3, 5e7], n = m // 20,
+               generated like the batch members, seed 4; requests draw a pool
+               graph and a delta log-uniform in [60, 86400].  ``serve_max`` is
+               a request graph at the top of that range (5e7 edges, 2.5M
+               nodes, seed 40).
 """
 from __future__ import annotations
 
@@ -38,7 +43,8 @@ import numpy as np
 
 __all__ = [
     "EdgeList", "tiny", "powerlaw", "skewed", "batch_spec", "batch_graph",
-    "small_random", "chung_lu_pareto", "edge_hash", "CONFIGS",
+    "small_random", "chung_lu_pareto", "edge_hash", "CONFIGS", "batch_sample",
+    "serve_spec", "serve_max",
 ]
 
 
@@ -226,6 +232,37 @@ def batch_spec(seed: int = 3, graphs: int = 4096, m_lo: float = 1e3,
 
 def batch_graph(item: BatchItem) -> EdgeList:
     return chung_lu_pareto(item.seed, item.n, item.m, gamma=2.1, span=60_000_000, alpha=1.5)
+
+
+def batch_sample(spec: list[BatchItem], k: int = 256, seed: int = 30) -> list[int]:
+    """Indices of a seeded sample of a batch that spans its whole range: the
+    20 largest graphs, the 10 with the widest windows, the 10 smallest, and
+    the rest drawn uniformly from the others (sorted, no repeats)."""
+    ms = np.array([it.m for it in spec])
+    ds = np.array([it.delta for it in spec])
+    pick: list[int] = []
+    for idx in (np.argsort(-ms, kind="stable")[:20], np.argsort(-ds, kind="stable")[:10],
+                np.argsort(ms, kind="stable")[:10]):
+        pick += [int(i) for i in idx if int(i) not in pick]
+    rest = np.array([i for i in range(len(spec)) if i not in set(pick)])
+    rng = np.random.default_rng(seed)
+    extra = rng.choice(rest, size=max(0, min(k - len(pick), rest.size)), replace=False)
+    return sorted(pick + [int(i) for i in extra])
+
+
+def serve_spec(seed: int = 4, pool: int = 128, m_lo: float = 1e3,
+               m_hi: float = 5e7) -> list[BatchItem]:
+    """The serving pool: graphs with m log-uniform in [m_lo, m_hi], n = m // 20
+    (delta is drawn per request, not per graph)."""
+    rng = np.random.default_rng(seed)
+    ms = np.rint(np.exp(rng.uniform(math.log(m_lo), math.log(m_hi), pool)))
+    kids = np.random.SeedSequence(seed).spawn(pool)
+    return [BatchItem(int(m), max(3, int(m) // 20), 0, kids[i]) for i, m in enumerate(ms)]
+
+
+def serve_max(seed: int = 40, m: int = 50_000_000) -> EdgeList:
+    """A serving request graph at the top of the request-size range."""
+    return chung_lu_pareto(seed, m // 20, m, gamma=2.1, span=60_000_000, alpha=1.5)
 
 
 def small_random(rng: np.random.Generator, n: int, m: int, t_values: int | None = None,

@@ -214,6 +214,12 @@ int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t 
  * first edge's source; triangle cells: orbit sum / 3).  Returns TM_EINTERNAL,
  * leaving out untouched, if Pair[d] != Pair[not d] or the three triangle
  * views disagree.  Pure host function.
+ * For the library's own counts the pair check is a real one (each pair
+ * instance is counted once from each endpoint, by separate sweeps), but the
+ * triangle check always passes: the kernels count each triangle instance
+ * once, as its class, and all three views are derived from that class.  The
+ * triangle check guards raw counters that come from elsewhere (for example
+ * a per-center implementation of the paper's Algorithm 2).
  */
 int tm_merge(const uint64_t raw[56], uint64_t out[36]);
 
@@ -328,6 +334,17 @@ int tm_stream_append(tm_stream *s, const int32_t *src, const int32_t *dst, const
                      uint64_t m, int flags, uint64_t new_counts[36]);
 int tm_stream_totals(tm_stream *s, uint64_t total[36], uint64_t *edges, uint64_t *tail_edges);
 void tm_stream_free(tm_stream *s);
+
+/*
+ * Failure-path testing.  The radix sorts of tm_build_graph find each tile's
+ * place by waiting on the tiles before it (decoupled look-back), and every
+ * such wait is bounded: past the bound the build flags the sort as failed
+ * and returns TM_EINTERNAL, with every kernel still finishing in bounds.
+ * With on != 0, every wait of every later build gives up before it starts,
+ * so tests can drive that path from the host; 0 restores the normal bound.
+ * Process-wide; not for use while other threads build.
+ */
+void tm_debug_lookback_giveup(int on);
 
 const char *tm_strerror(int code);
 const char *tm_last_error(void);

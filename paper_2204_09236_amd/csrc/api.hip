@@ -93,7 +93,8 @@ hipEvent_t take_event() {
     return e;
 }
 thread_local hipEvent_t g_cur_start = nullptr;
-thread_local const char *g_cur_name = nullptr;
+thread_local std::string g_cur_name;
+thread_local const char *g_row = nullptr;  // step of the counting path the launches belong to
 thread_local bool g_capturing = false;
 
 void prof_drain_locked() {
@@ -119,10 +120,14 @@ void prof_drain_locked() {
 
 void set_capturing(bool on) { g_capturing = on; }
 
+ProfRow::ProfRow(const char *row) : prev(g_row) { g_row = row; }
+ProfRow::~ProfRow() { g_row = prev; }
+
 void prof_begin(const char *name, hipStream_t s) {
     if (!g_prof_on || g_capturing) return;
-    if (!g_prof_only.empty() && g_prof_only != name) return;
-    g_cur_name = name;
+    std::string full = g_row ? std::string(g_row) + ":" + name : std::string(name);
+    if (!g_prof_only.empty() && g_prof_only != full) return;
+    g_cur_name = std::move(full);
     g_cur_start = take_event();
     if (g_cur_start) (void)hipEventRecord(g_cur_start, s);
 }
@@ -156,6 +161,8 @@ const char *tm_strerror(int code) {
 }
 
 const char *tm_last_error(void) { return tmc::g_last_error.c_str(); }
+
+void tm_debug_lookback_giveup(int on) { tmc::set_lookback_giveup(on != 0); }
 
 uint32_t tm_graph_count(const tm_graph *g) { return g ? g->G : 0; }
 

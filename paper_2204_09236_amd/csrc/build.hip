@@ -116,13 +116,21 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
 // off[u] = first position of node u in the node-sorted keys, atomic-free:
 // each boundary between consecutive keys fills the offsets of the (absent)
 // nodes it skips over, up to kGapFill of them; longer runs of absent nodes are
-// left marked and resolved by k_offsets_gaps with a binary search.
-__global__ void k_offsets(const uint32_t *skey, uint64_t len, uint32_t n, uint32_t *off) {
+// left marked and resolved by k_offsets_gaps with a binary search.  Keys are
+// below n after a sound sort; a key >= n can only be left over where a sort's
+// look-back gave up (some positions then keep stale contents), so such a
+// boundary writes nothing and raises the sort's error flag instead.
+__global__ void k_offsets(const uint32_t *skey, uint64_t len, uint32_t n, uint32_t *off,
+                          uint32_t *err) {
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= len;
          p += (uint64_t)gridDim.x * blockDim.x) {
         const int64_t prev = p == 0 ? -1 : (int64_t)skey[p - 1];
         const int64_t cur = p == len ? (int64_t)n : (int64_t)skey[p];
         if (cur == prev) continue;
+        if (cur > (int64_t)n || prev >= (int64_t)n) {
+            atomicOr(err, 4u);
+            continue;
+        }
         off[cur] = (uint32_t)p;
         const int64_t stop = min(cur - 1, prev + (int64_t)kGapFill);
         for (int64_t u = prev + 1; u <= stop; u++) off[u] = (uint32_t)p;
@@ -296,6 +304,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     for (uint32_t i = 0; i < G; i++) h_lim[i] = ncount[i] ? ncount[i] : 0x7fffffffu;
     const std::vector<Tile> etiles = make_tiles(g->h_eoff, 1u << 13);
     {
+        ProfRow row_a1("a1");
         Scratch vs;
         TRY(vs.reserve(G * sizeof(Stat) + G * 4 + etiles.size() * sizeof(Tile) + 1024, s));
         Stat *d_st = vs.take<Stat>(G);
@@ -407,6 +416,9 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     uint32_t *sort_err = sc.take<uint32_t>(1);
     TM_LAUNCH("sort_err_clear", k_fill_u32, dim3(1), dim3(kBlock), 0, s, sort_err, 1, 0u);
 
+    // trace rows: a2 the sequences S_u (time sort, node sort, offsets,
+    // direction prefix), a3 the node-pair lists
+    ProfRow row_a2("a2");
     // ---- 2. time sort carrying (src, dst, id); its last pass writes the
     // rank-ordered arrays.  Pass i writes the (KB, VB) set when i is even, so
     // the last pass reads (KA, VA) when the pass count is odd and the node
@@ -455,7 +467,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         TM_LAUNCH("offsets_fill", k_fill_u32, grid_for(n + 1), dim3(kBlock), 0, s, g->off, n + 1,
                   kUnset);
         TM_LAUNCH("offsets", k_offsets, grid_for(len + 1), dim3(kBlock), 0, s, g->ent_c, len,
-                  (uint32_t)n, g->off);
+                  (uint32_t)n, g->off, sort_err);
         TM_LAUNCH("offsets_gaps", k_offsets_gaps, grid_for(n + 1), dim3(kBlock), 0, s, g->ent_c, len,
                   (uint32_t)n, g->off);
         TRY(scan_dirbits(g->ent_nd, g->X, len, tmp, s));
@@ -463,6 +475,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
 
     // ---- 4. node-pair edge sets; the edges of pairs with >= 2 edges
     {
+        ProfRow row_a3("a3");
         uint64_t *k = PKA, *k_alt = PKB;
         uint32_t *v = PVA, *v_alt = PVB;
         TRY(radix_sort_u64(&k, &k_alt, &v, &v_alt, m, bits_for(n * n - 1), tmp, sort_err, s,

@@ -1338,6 +1338,9 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     int rc;
     // one graph: the window kernel also writes the triangle bit planes
     const bool fused_levels = do_tri && G == 1;
+    // trace rows: a4 star/pair (with the shared window kernel), a5 triangles,
+    // a6 work items (chunks, tiles, hub slices), a7 reduction
+    ProfRow row_a4("a4");
     TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
               s, S, g->t_entries, g->n_t_entries, 2 * m, w.deltas, w.Wf, pr.hub_min,
               fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr,
@@ -1347,15 +1350,18 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
         TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
                   dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, w.Wf, w.Lf, nme, g->t_elems,
                   g->n_t_elems, w.deltas, w.me_w);
+        ProfRow row_a6("a6");
         TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
                   nm, run_chunk, w.cnt);
     }
     if (do_sp) {
+        ProfRow row_a6("a6");
         rc = scan_u32_array(w.cnt, w.first, nm, w.tmp, s);
         if (rc) return rc;
     }
     // ---- triangles: candidate first edges
     if (do_tri) {
+        ProfRow row_a5("a5");
         if (!fused_levels)
             TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m,
                       pr.hub_min, w.wbits, w.lev);
@@ -1367,6 +1373,8 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
                   reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.tflag, w.tidx, m, w.cand);
     }
     // ---- per-graph work tiles
+    {
+    ProfRow row_a6("a6");
     TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, w.first, g->d_mpb,
               w.tidx, g->d_eoff, G, (int)do_sp, (int)do_tri, (int)do_hub, w.n_itiles, w.n_ctiles,
               w.n_htiles, w.hcount);
@@ -1376,9 +1384,14 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     if (rc) return rc;
     rc = scan_u32_array(w.n_htiles, w.htfirst, G, w.tmp, s);
     if (rc) return rc;
-    if (nm) {
+    if (nm)
         TM_LAUNCH("item_pairs", k_item_pairs, grid_for(nme / kItemsPerThread + 1, 4096), dim3(kBlock),
                   0, s, w.first, nm, w.ipair);
+    if (do_hub)
+        TM_LAUNCH("hub_tiles", k_hub_tiles, grid_for(w.max_htiles, 4096), dim3(kBlock), 0, s, w.lev,
+                  pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, w.hpart);
+    }
+    if (nm) {
         StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w, w.first, w.ipair, nm, nme,
                     g->d_mpb, w.tfirst, G, w.deltas, run_chunk,
                     (families & TM_STARS) ? 1 : 0};
@@ -1386,19 +1399,20 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
                   dim3(kBlock), 0, s, sa, w.spart);
     }
     if (do_tri) {
+        ProfRow row_a5("a5");
         TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
                   dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max,
                   w.tpart);
     }
     if (do_hub) {
-        TM_LAUNCH("hub_tiles", k_hub_tiles, grid_for(w.max_htiles, 4096), dim3(kBlock), 0, s, w.lev,
-                  pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, w.hpart);
+        ProfRow row_a5("a5");
         HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.lev, g->d_eoff, w.htfirst,
                    w.hcount, w.hlist, G, pr.hub_min};
         TM_LAUNCH("tri_hub", k_tri_hub, dim3((unsigned)std::min<uint64_t>(w.max_htiles, 4096)),
                   dim3(kHubBlock), 0, s, ha, w.hpart);
     }
     const uint32_t split = sum_split(G);
+    ProfRow row_a7("a7");
     TM_LAUNCH("graph_sums", k_graph_sums, dim3((unsigned)std::min<uint64_t>((uint64_t)G * split, 16384)),
               dim3(kBlock), 0, s, w.spart, w.tfirst, w.tpart, w.ctfirst, w.hpart, w.htfirst, G,
               split, w.gpart);

@@ -2,6 +2,7 @@
 // 64-wide CDNA wavefronts (ballot-based digit matching, no block barriers in
 // the ranking loop).
 #include <algorithm>
+#include <atomic>
 #include <utility>
 
 #include "tm_internal.h"
@@ -180,6 +181,8 @@ constexpr uint64_t kStVal = (1ull << 62) - 1;
 // A look-back wait polls at most this many times (about a second) before it
 // gives up, flags the error and lets the kernel finish.
 constexpr uint32_t kSpinLimit = 1u << 20;
+std::atomic<uint32_t> g_spin_limit{kSpinLimit};
+uint32_t lookback_spin_limit() { return g_spin_limit.load(std::memory_order_relaxed); }
 constexpr uint64_t kMinTile = (uint64_t)kOsThreads * 6;
 
 // Block size and items per thread of a pass, by element type: the node
@@ -361,7 +364,7 @@ __global__ void __launch_bounds__(THREADS) k_os_scatter(In in, Out out,
                                                            uint64_t n, int shift,
                                                            const uint32_t *ghist, uint64_t *status,
                                                            uint64_t *status_next, uint32_t *ticket,
-                                                           uint32_t *err) {
+                                                           uint32_t *err, uint32_t spin_limit) {
     constexpr uint32_t kT = (uint32_t)THREADS * ITEMS;
     constexpr int kWv = THREADS / kWave;
     __shared__ V s_val[kT];
@@ -444,12 +447,15 @@ __global__ void __launch_bounds__(THREADS) k_os_scatter(In in, Out out,
             __hip_atomic_store(mine, kStAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t k = tile - 1;
             uint32_t spins = 0;
-            while (true) {
+            // a limit of 0 (set from the host by the failure-path tests)
+            // gives up before the first wait
+            if (spin_limit == 0) atomicOr(err, 1u);
+            while (spin_limit != 0) {
                 const uint64_t v = __hip_atomic_load(status + (uint64_t)k * 256 + d, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
                 const uint64_t st = v & ~kStVal;
                 if (st == 0) {
-                    if (++spins >= kSpinLimit) {
+                    if (++spins >= spin_limit) {
                         atomicOr(err, 1u);
                         break;
                     }
@@ -531,30 +537,33 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
               t.part);
     TM_LAUNCH("sort_hist_sum", k_os_hist_sum, dim3((unsigned)passes, kHistSumSplit), dim3(256), 0, s,
               t.part, hblocks, passes, t.ghist);
+    const uint32_t spin = lookback_spin_limit();
+    // the pass that writes the final arrays is traced under its own name
+    const std::string last_name = std::string(scatter_name) + "_last";
     for (int p = 0; p < passes; p++) {
         uint64_t *st = t.status[p & 1];
         uint64_t *st_next = p + 1 < passes ? t.status[(p + 1) & 1] : nullptr;
         const ArrayIn<K, V> arr{*keys, *vals};
         const bool last = fin && p + 1 == passes;
         if (p == 0 && last) {
-            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, In0, Final, kThr, kItems_>),
+            TM_LAUNCH(last_name.c_str(), (k_os_scatter<K, V, In0, Final, kThr, kItems_>),
                       dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, *fin, n, 8 * p,
-                      t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+                      t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
         } else if (last) {
-            TM_LAUNCH(scatter_name, (k_os_scatter<K, V, ArrayIn<K, V>, Final, kThr, kItems_>),
+            TM_LAUNCH(last_name.c_str(), (k_os_scatter<K, V, ArrayIn<K, V>, Final, kThr, kItems_>),
                       dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, *fin, n, 8 * p,
-                      t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+                      t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
         } else {
             const PairOut<K, V> po{*keys_alt, *vals_alt};
             if (p == 0)
                 TM_LAUNCH(scatter_name, (k_os_scatter<K, V, In0, PairOut<K, V>, kThr, kItems_>),
                           dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, po, n, 8 * p,
-                          t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+                          t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
             else
                 TM_LAUNCH(scatter_name,
                           (k_os_scatter<K, V, ArrayIn<K, V>, PairOut<K, V>, kThr, kItems_>),
                           dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, po, n, 8 * p,
-                          t.ghist + 256 * p, st, st_next, t.tickets + p, err);
+                          t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
             std::swap(*keys, *keys_alt);
             std::swap(*vals, *vals_alt);
         }
@@ -563,6 +572,8 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
 }
 
 }  // namespace
+
+void set_lookback_giveup(bool on) { g_spin_limit.store(on ? 0u : kSpinLimit); }
 
 size_t scan_tmp_count(uint64_t n) { return (n + kTile - 1) / kTile + 2; }
 

@@ -39,6 +39,14 @@ void prof_begin(const char *name, hipStream_t s);
 void prof_end(hipStream_t s);
 // While a stream is being captured into a hipGraph the tracer stays silent.
 void set_capturing(bool on);
+// Launches made while a ProfRow is alive are traced as "<row>:<name>", the
+// row naming the step of the counting path they belong to (validate, S_u
+// build, pair lists, star/pair, triangles, reduction).
+struct ProfRow {
+    const char *prev;
+    explicit ProfRow(const char *row);
+    ~ProfRow();
+};
 
 #define TM_LAUNCH(name, kernel, grid, block, shm, stream, ...)                       \
     do {                                                                              \
@@ -89,6 +97,8 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
 // err: a device flag the sort sets (and never clears) when a wait of its
 // look-back gave up; the sorted data are then invalid.
 size_t radix_tmp_bytes(uint64_t n);
+// Failure-path testing: make every later look-back wait give up at once.
+void set_lookback_giveup(bool on);
 // A range [b, e) of work items that all belong to graph g of a batch.
 struct Tile {
     uint32_t g, b, e;

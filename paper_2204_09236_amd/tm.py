@@ -105,6 +105,8 @@ def _load():
     lib.tm_strerror.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = []
     lib.tm_last_error.restype = ctypes.c_char_p
+    lib.tm_debug_lookback_giveup.argtypes = [ctypes.c_int]
+    lib.tm_debug_lookback_giveup.restype = None
     return lib
 
 
@@ -489,6 +491,12 @@ def prof_read() -> dict:
         out[buf.value.decode()] = (n.value, ms.value)
         i += 1
     return out
+
+
+def debug_lookback_giveup(on: bool) -> None:
+    """Failure-path testing: every look-back wait of later builds gives up
+    at once (the build then returns TM_EINTERNAL)."""
+    _lib.tm_debug_lookback_giveup(1 if on else 0)
 
 
 def library():

@@ -7,8 +7,15 @@ same edge list.
 
     python tests/golden/make_golden.py [workload] [threads]
 
-``workload`` is ``powerlaw`` (default) or ``skewed``; the file written is
-``tests/golden/<workload>_counts.json``.
+``workload``:
+  powerlaw, skewed  the named single-graph workloads at every delta of theirs
+  batch             a seeded sample of 256 graphs of the 4,096-graph batch
+                    (graphgen.batch_sample: the 20 largest, the 10 widest
+                    windows, the 10 smallest, the rest uniform), each at its
+                    own delta
+  serve             the largest serving request graph (graphgen.serve_max,
+                    5e7 edges) at delta 60, 3,600 and 86,400
+The file written is ``tests/golden/<workload>_counts.json``.
 """
 import json
 import os
@@ -21,27 +28,64 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import graphgen  # noqa: E402
 import oracle  # noqa: E402
 
+SERVE_DELTAS = [60, 3600, 86400]
+
+
+def counts_record(g, deltas, threads):
+    out = {}
+    for delta in deltas:
+        t0 = time.time()
+        raw = oracle.alg(g.src, g.dst, g.t, delta, n=g.n, threads=threads)
+        grid = oracle.merge(raw)
+        out[str(delta)] = {"raw": [int(x) for x in raw],
+                           "grid": [[int(x) for x in row] for row in grid],
+                           "oracle_seconds": round(time.time() - t0, 2)}
+        print(f"delta={delta}: {time.time() - t0:.1f}s", flush=True)
+    return out
+
+
+def single(workload, threads):
+    if workload == "serve":
+        gen, deltas = graphgen.serve_max, SERVE_DELTAS
+    else:
+        spec = graphgen.CONFIGS[workload]
+        gen, deltas = spec["fn"], spec["deltas"]
+    t0 = time.time()
+    g = gen()
+    print(f"generated {workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s", flush=True)
+    rec = {"workload": workload, "n": g.n, "m": g.m, "edge_sha256": graphgen.edge_hash(g),
+           "counts": counts_record(g, deltas, threads)}
+    return rec
+
+
+def batch(threads):
+    spec = graphgen.batch_spec()
+    idx = graphgen.batch_sample(spec)
+    rec = {"workload": "batch", "graphs_in_batch": len(spec), "sample": "graphgen.batch_sample",
+           "members": []}
+    t_all = time.time()
+    for k, i in enumerate(idx):
+        it = spec[i]
+        g = graphgen.batch_graph(it)
+        t0 = time.time()
+        raw = oracle.alg(g.src, g.dst, g.t, it.delta, n=g.n, threads=threads)
+        rec["members"].append({"index": i, "m": g.m, "n": g.n, "delta": it.delta,
+                               "edge_sha256": graphgen.edge_hash(g),
+                               "raw": [int(x) for x in raw],
+                               "oracle_seconds": round(time.time() - t0, 3)})
+        if k % 32 == 0:
+            print(f"member {k}/{len(idx)} (graph {i}, m={g.m}, delta={it.delta})", flush=True)
+    print(f"batch sample: {len(idx)} graphs in {time.time() - t_all:.1f}s", flush=True)
+    return rec
+
 
 def main():
     workload = sys.argv[1] if len(sys.argv) > 1 else "powerlaw"
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    spec = graphgen.CONFIGS[workload]
-    t0 = time.time()
-    g = spec["fn"]()
-    h = graphgen.edge_hash(g)
-    print(f"generated {workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s", flush=True)
-    rec = {"workload": workload, "n": g.n, "m": g.m, "edge_sha256": h, "counts": {}}
-    for delta in spec["deltas"]:
-        t0 = time.time()
-        raw = oracle.alg(g.src, g.dst, g.t, delta, n=g.n, threads=threads)
-        grid = oracle.merge(raw)
-        rec["counts"][str(delta)] = {"raw": [int(x) for x in raw],
-                                     "grid": [[int(x) for x in row] for row in grid],
-                                     "oracle_seconds": round(time.time() - t0, 2)}
-        print(f"delta={delta}: {time.time() - t0:.1f}s", flush=True)
+    rec = batch(threads) if workload == "batch" else single(workload, threads)
     with open(os.path.join(HERE, f"{workload}_counts.json"), "w") as f:
-        json.dump(rec, f, indent=1)
-    print(json.dumps({k: v for k, v in rec.items() if k != "counts"}))
+        json.dump(rec, f, indent=None if workload == "batch" else 1, separators=None)
+    print(json.dumps({k: v for k, v in rec.items() if k not in ("counts", "members")}))
 
 
 if __name__ == "__main__":

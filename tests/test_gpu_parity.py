@@ -214,6 +214,27 @@ def test_invalid_inputs(tm):
             G.count(-1)
 
 
+def test_lookback_giveup_fails_cleanly(tm):
+    """Every radix-sort tile gives up its look-back wait at once (forced from
+    the host): the sorts then leave some output positions unwritten, with
+    stale contents, and the build must stop with TM_EINTERNAL while every
+    kernel stays in bounds (node offsets are not written from keys >= n).
+    The next build with the normal bound is exact again."""
+    g = graphgen.chung_lu_pareto(31, 20_000, 200_000)
+    case("forced look-back give-up m=200000")
+    tm.debug_lookback_giveup(True)
+    try:
+        for _ in range(2):
+            with pytest.raises(tm.TMError) as ei:
+                tm.build_graph(g.src, g.dst, g.t, n=g.n)
+            assert ei.value.code == -6
+    finally:
+        tm.debug_lookback_giveup(False)
+    case("build after the forced give-up")
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        np.testing.assert_array_equal(G.count_raw(3600), oracle.alg(g.src, g.dst, g.t, 3600, n=g.n))
+
+
 def test_repeatable(tm):
     rng = np.random.default_rng(71)
     g = graphgen.small_random(rng, 300, 50000, t_values=5000, tmax=200000, multi=0.3)

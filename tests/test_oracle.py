@@ -109,6 +109,73 @@ def test_toy_full_brute_equals_alg():
         np.testing.assert_array_equal(oracle.merge(raw), grid_from_canon(canon))
 
 
+def _toy_instances():
+    """The hand enumeration of every instance of the toy graph at delta = 10
+    (tests/golden/toy_delta10_instances.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "toy_delta10_instances.txt")
+    out = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                w = line.split()
+                out.append(([int(x[1:]) - 1 for x in w[:3]], w[3], w[4:]))
+    return out
+
+
+def test_toy_graph_all_instances_at_delta_10():
+    """The toy graph of Figure 1 at delta = 10 s holds exactly 27 instances
+    (19 stars, 1 pair, 7 triangles), including every instance the paper
+    names in Sections III, IV-A and IV-B.  Each listed triple, counted on its
+    own, is exactly one instance of its listed class; the whole graph counts
+    exactly the listed instances, cell by cell."""
+    src, dst, t = load_toy()
+    inst = _toy_instances()
+    assert len(inst) == 27
+    assert [k for _, k, _ in inst].count("star") == 19
+    assert [k for _, k, _ in inst].count("pair") == 1
+    assert [k for _, k, _ in inst].count("tri") == 7
+    assert len({tuple(e) for e, _, _ in inst}) == 27
+    want = np.zeros(36, dtype=np.uint64)
+    for e3, kind, f in inst:
+        assert t[e3[2]] - t[e3[0]] <= 10
+        if kind == "star":
+            key = ("star", TYPES_[f[1]], D_[f[2]], D_[f[3]], D_[f[4]])
+        elif kind == "pair":
+            assert f[0] == "o"
+            key = ("pair", D_[f[1]], D_[f[2]])
+        else:
+            key = ("tri", D_[f[0]], D_[f[1]], D_[f[2]])
+        one = np.zeros(36, dtype=np.uint64)
+        one[GRID[key]] = 1
+        sel = np.array(e3)
+        np.testing.assert_array_equal(oracle.count(src[sel], dst[sel], t[sel], 10, n=5).reshape(-1),
+                                      one, err_msg=f"E{e3[0] + 1} E{e3[1] + 1} E{e3[2] + 1}")
+        if kind == "star":
+            center = "abcde".index(f[0])
+            raw = oracle.alg_centers(src[sel], dst[sel], t[sel], 10, [center], n=5)
+            assert raw[i_star(f[1], f[2], f[3], f[4])] == 1 and raw[:24].sum() == 1
+        want[GRID[key]] += 1
+    grid = oracle.count(src, dst, t, 10, n=5)
+    np.testing.assert_array_equal(grid.reshape(-1), want)
+    # the same 6 x 6, written out
+    np.testing.assert_array_equal(grid, np.array([[0, 2, 0, 0, 0, 2],
+                                                  [0, 1, 3, 0, 1, 1],
+                                                  [2, 1, 1, 0, 0, 0],
+                                                  [1, 2, 1, 0, 2, 1],
+                                                  [0, 1, 1, 0, 0, 0],
+                                                  [1, 1, 1, 0, 1, 0]], dtype=np.uint64))
+    assert int(grid.sum()) == 27
+    _, canon = oracle.brute(src, dst, t, 10, n=5)
+    np.testing.assert_array_equal(grid_from_canon(canon).reshape(-1), want)
+
+
+TYPES_ = {"I": 0, "II": 1, "III": 2}
+D_ = {"o": O, "in": IN}
+
+
 # --------------------------------------------------------------------------
 # brute force of the definition vs the paper's algorithms
 
