@@ -210,6 +210,26 @@ int tm_count_raw_tuned(tm_graph *g, int64_t delta, uint32_t run_chunk, uint32_t 
                        uint32_t hub_min, uint64_t raw[56]);
 
 /*
+ * tm_count without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as tm_count for a graph of
+ * one member (TM_EINVAL for a batch).  The count's workspace is carved from
+ * one fixed device array of 256 MiB that the library holds on every device
+ * it runs on until the process ends (enough for graphs of about 2-3 million
+ * edges); a graph whose workspace would not fit is refused with TM_ENOMEM
+ * and tm_last_error gives the bytes it would need.  Nothing is allocated on
+ * the device or pinned on the host.  Calls on one device share that array:
+ * the library runs them one at a time within a process (each returns only
+ * after its count is done), so overlapping calls from several threads wait
+ * for each other; the array keeps the last call's contents, and every count
+ * writes what it reads first.
+ */
+int tm_count_noalloc(tm_graph *g, int64_t delta, uint64_t out[36]);
+/* Device allocations the library has served so far, cached blocks included
+ * (a test aid: tm_count_noalloc leaves it unchanged). */
+uint64_t tm_debug_alloc_calls(void);
+
+/*
  * Merge raw counters into the 36 motif counts (pair cells: the view from the
  * first edge's source; triangle cells: orbit sum / 3).  Returns TM_EINTERNAL,
  * leaving out untouched, if Pair[d] != Pair[not d] or the three triangle

@@ -5,5 +5,6 @@ The counting path runs in the HIP library ``libtm.so`` (C ABI in
 fails loudly if the library has not been built.
 """
 from .tm import (ALL_MOTIFS, HUB_OFF, PAIRS, STARS, TRIANGLES, Graph, Server, Stream, TMError,  # noqa: F401
-                 build_batch, build_batch_arrays, build_graph, count, debug_lookback_giveup, merge,
+                 build_batch, build_batch_arrays, build_graph, count, debug_alloc_calls,
+                 debug_lookback_giveup, merge,
                  prof_enable, prof_only, prof_read, prof_reset)

@@ -16,7 +16,7 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 // ---------------------------------------------------------------- scratch
 Scratch::~Scratch() {
-    if (base) dev_free(base, stream);
+    if (base && owned) dev_free(base, stream);
 }
 
 int Scratch::reserve(size_t bytes, hipStream_t s) {
@@ -416,6 +416,35 @@ int tm_merge(const uint64_t raw[56], uint64_t out[36]) {
     for (int i = 0; i < 36; i++) out[i] = res[i];
     return TM_OK;
 }
+
+int tm_count_noalloc(tm_graph *g, int64_t delta, uint64_t out[36]) {
+    if (!g || !out) {
+        tmc::set_error("NULL graph or output");
+        return TM_EINVAL;
+    }
+    if (g->G != 1) {
+        tmc::set_error("a batch of several graphs is counted with tm_count_batch");
+        return TM_EINVAL;
+    }
+    if (delta < 0 || delta >= ((int64_t)1 << 62)) {
+        tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+        return TM_EINVAL;
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    uint64_t raw[56];
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        rc = tmc::count_graph_noalloc(g, delta, raw);
+    }
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc) return rc;
+    return tm_merge(raw, out);
+}
+
+uint64_t tm_debug_alloc_calls(void) { return tmc::dev_alloc_calls(); }
 
 int tm_count(tm_graph *g, int64_t delta, uint64_t out[36]) {
     if (!out) {

@@ -41,6 +41,8 @@
 // Per-lane uint64 accumulators are reduced per block, then all block partials
 // are summed by one deterministic tree reduction (no atomics on counts).
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "tm_internal.h"
@@ -1593,6 +1595,79 @@ int count_graph(tm_graph *g, const int64_t *h_deltas, Params pr, uint64_t *raw, 
         if (!(families & TM_TRIANGLES))
             for (int i = 32; i < 56; i++) rw[i] = 0;
     }
+    return TM_OK;
+}
+
+// ---------------------------------------------------- allocation-free count
+// The workspace of tm_count_noalloc: one fixed device array per device,
+// held from library load until the process ends.  Host code never passes
+// `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in, not a device address); it uses the address hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu[kMaxDevices];  // one call at a time per device (shared workspace)
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static int scratch_for_device(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index out of range for the allocation-free count");
+        return TM_EINVAL;
+    }
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return TM_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TM_OK;
+}
+
+int count_graph_noalloc(tm_graph *g, int64_t delta, uint64_t *raw) {
+    uint64_t host[40] = {0};
+    if (g->m >= 3) {
+        Params pr;
+        resolve_params(g, &pr);
+        const int dev = g->device;
+        if (dev < 0 || dev >= kMaxDevices) {
+            set_error("device index out of range for the allocation-free count");
+            return TM_EINVAL;
+        }
+        std::lock_guard<std::mutex> lk(g_noalloc_mu[dev]);
+        void *base = nullptr;
+        int rc = scratch_for_device(dev, &base);
+        if (rc) return rc;
+        Workspace w;
+        const size_t bytes = workspace_bytes(g, &w);
+        if (bytes > kNoAllocScratchBytes) {
+            set_error("the allocation-free count needs " + std::to_string(bytes) +
+                      " bytes of workspace for this graph; its fixed workspace holds " +
+                      std::to_string(kNoAllocScratchBytes));
+            return TM_ENOMEM;
+        }
+        hipStream_t s = g->stream;
+        Scratch sc;
+        sc.base = static_cast<char *>(base);
+        sc.cap = kNoAllocScratchBytes;
+        sc.stream = s;
+        sc.owned = false;
+        workspace_carve(g, sc, &w);
+        TM_HIP_TRY(hipMemcpyAsync(w.deltas, &delta, 8, hipMemcpyHostToDevice, s));
+        rc = enqueue_count(g, w, pr, TM_ALL_MOTIFS, s);
+        if (rc) return rc;
+        TM_HIP_TRY(hipMemcpyAsync(host, w.res, sizeof(host), hipMemcpyDeviceToHost, s));
+        // the next call may reuse the workspace only after this one is done
+        TM_HIP_TRY(hipStreamSynchronize(s));
+    }
+    raw_from_counters(host, 1, raw);
     return TM_OK;
 }
 

@@ -8,6 +8,7 @@
 // stream first makes that stream wait for the event.  Blocks stay cached
 // until the process ends or an allocation fails, in which case the cache is
 // released and the allocation retried once.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -34,6 +35,7 @@ struct DeviceCache {
 
 std::mutex g_mu;
 std::unordered_map<int, DeviceCache> g_cache;
+std::atomic<uint64_t> g_alloc_calls{0};
 
 size_t round_size(size_t bytes) {
     if (bytes == 0) bytes = 1;
@@ -67,8 +69,11 @@ void release_cached(DeviceCache &c) {
 
 }  // namespace
 
+uint64_t dev_alloc_calls() { return g_alloc_calls.load(); }
+
 int dev_alloc(void **out, size_t bytes, hipStream_t s) {
     *out = nullptr;
+    g_alloc_calls.fetch_add(1);
     int dev = 0;
     (void)hipGetDevice(&dev);
     const size_t size = round_size(bytes);

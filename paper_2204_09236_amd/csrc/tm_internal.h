@@ -72,6 +72,7 @@ struct Scratch {
     hipStream_t stream = nullptr;
     char *base = nullptr;
     size_t cap = 0, used = 0;
+    bool owned = true;  // false: base is fixed device memory, not from the cache
     ~Scratch();
     int reserve(size_t bytes, hipStream_t s);
     template <typename T>
@@ -252,6 +253,12 @@ int graph_max_degree(tm_graph *g, uint64_t *out);
 // others are zero.
 int count_graph(tm_graph *g, const int64_t *deltas, Params pr, uint64_t *raw, bool use_graph,
                 uint32_t families = TM_ALL_MOTIFS);
+// Raw counters of one graph (G == 1) with the count's workspace carved from
+// the library's fixed device array instead of the allocator (nothing is
+// allocated); TM_ENOMEM if the workspace would not fit that array.
+int count_graph_noalloc(tm_graph *g, int64_t delta, uint64_t *raw);
+// Device allocations served so far (cache hits included), for tests.
+uint64_t dev_alloc_calls();
 // Raw counters of one graph (G == 1) for k windows, raw[k * 56].
 int count_graph_multi(tm_graph *g, const int64_t *deltas, uint32_t k, Params pr, uint64_t *raw);
 void plan_release(tm_graph *g);

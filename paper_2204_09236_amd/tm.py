@@ -105,6 +105,10 @@ def _load():
     lib.tm_strerror.restype = ctypes.c_char_p
     lib.tm_last_error.argtypes = []
     lib.tm_last_error.restype = ctypes.c_char_p
+    lib.tm_count_noalloc.argtypes = [vp, ctypes.c_int64, u64p]
+    lib.tm_count_noalloc.restype = ctypes.c_int
+    lib.tm_debug_alloc_calls.argtypes = []
+    lib.tm_debug_alloc_calls.restype = ctypes.c_uint64
     lib.tm_debug_lookback_giveup.argtypes = [ctypes.c_int]
     lib.tm_debug_lookback_giveup.restype = None
     return lib
@@ -153,6 +157,13 @@ class Graph:
             _check(_lib.tm_count(self.handle, int(delta), _u64(out)))
         else:
             _check(_lib.tm_count_masked(self.handle, int(delta), int(families), _u64(out)))
+        return out.reshape(6, 6)
+
+    def count_noalloc(self, delta: int) -> np.ndarray:
+        """36 motif counts (6 x 6) by tm_count_noalloc: no device allocation,
+        workspace in the library's fixed device array."""
+        out = np.zeros(36, dtype=np.uint64)
+        _check(_lib.tm_count_noalloc(self.handle, int(delta), _u64(out)))
         return out.reshape(6, 6)
 
     def count_raw(self, delta: int, run_chunk: int = 0, tri_lane_max: int = 0,
@@ -491,6 +502,11 @@ def prof_read() -> dict:
         out[buf.value.decode()] = (n.value, ms.value)
         i += 1
     return out
+
+
+def debug_alloc_calls() -> int:
+    """Device allocations the library has served so far (cache hits included)."""
+    return int(_lib.tm_debug_alloc_calls())
 
 
 def debug_lookback_giveup(on: bool) -> None:
