@@ -116,9 +116,16 @@ __device__ inline void wave_lds_sync() {
 // lanes write them in coalesced rounds of 64, each finding its q by
 // bisection over the step's 64 window ends kept in LDS.  A wave span finds
 // R of the entry before it with one gallop.
+//
+// Several windows at once (K nested deltas, ascending; one graph): every step
+// searches the same ring once per window, each search starting where the
+// previous (smaller) window ended, and writes Wf and Lf of window i at
+// offset i * len.  The bit planes describe the largest window.
 constexpr uint32_t kRing = 2 * kWave;
 constexpr uint32_t kHubCap = 2048;  // window entries per LDS segment of the hub pass
+constexpr int kMaxLevels = 4;       // windows counted in one pass
 
+template <int K>
 __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
                                                     uint64_t len, const int64_t *deltas,
                                                     uint32_t *Wf, uint32_t hub_min, uint64_t *bits,
@@ -136,16 +143,23 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
     };
     for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const Tile tl = tiles[ti];
-        const int64_t delta = deltas[tl.g];
+        int64_t delta[K];
+#pragma unroll
+        for (int i = 0; i < K; i++) delta[i] = deltas[(uint64_t)tl.g * K + i];
         // each wave walks its own contiguous span of the tile in steps of 64
         const uint32_t span = ((tl.e - tl.b + nw - 1) / nw + kWave - 1) / kWave * kWave;
         const uint32_t w_b = tl.b + wv * span, w_e = min(tl.e, w_b + span);
         if (w_b >= w_e) continue;
         // first entry whose window start this wave writes: R(w_b - 1) + 1
-        uint32_t p_next = w_b;
-        if (Lf && w_b > 0) {
-            const uint32_t q0 = w_b - 1, c0 = S.c[q0];
-            if (c0 == S.c[w_b]) p_next = window_end(S.t, q0, S.off[c0 + 1], S.t[q0] + delta) + 1;
+        uint32_t p_next[K];
+#pragma unroll
+        for (int i = 0; i < K; i++) {
+            p_next[i] = w_b;
+            if (Lf && w_b > 0) {
+                const uint32_t q0 = w_b - 1, c0 = S.c[q0];
+                if (c0 == S.c[w_b])
+                    p_next[i] = window_end(S.t, q0, S.off[c0 + 1], S.t[q0] + delta[i]) + 1;
+            }
         }
         rg[lane] = key_at((uint64_t)w_b + lane);
         uint4 next = key_at((uint64_t)w_b + kWave + lane);
@@ -156,56 +170,65 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
             wave_lds_sync();
             const uint4 me = rg[half * kWave + lane];
             const uint32_t ca = me.x;
-            const int64_t lim = (int64_t)(((uint64_t)me.w << 32) | me.z) + delta;
-            // last k in [lane, 128) with key(base + k) <= (ca, lim)
-            uint32_t lo = (uint32_t)lane, hi = kRing;
-#pragma unroll
-            for (int step = 0; step < 7; step++) {
-                const uint32_t mid = (lo + hi) / 2;
-                const uint4 km = rg[(half * kWave + mid) & (kRing - 1)];
-                const int64_t tm = (int64_t)(((uint64_t)km.w << 32) | km.z);
-                const bool ok = km.x < ca || (km.x == ca && tm <= lim);
-                if (hi - lo > 1) {
-                    if (ok) lo = mid;
-                    else hi = mid;
-                }
-            }
+            const int64_t tme = (int64_t)(((uint64_t)me.w << 32) | me.z);
             const uint64_t qa = (uint64_t)base + lane;
-            uint32_t W = 0, Rq = 0;
-            if (qa < w_e) {
-                uint64_t R = (uint64_t)base + lo;
-                if (lo == kRing - 1)  // the window may run past the ring
-                    R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
-                W = (uint32_t)(R - qa);
-                Wf[qa] = W;
-                Rq = (uint32_t)R;
-            }
-            if (Lf) {
-                const uint32_t nvalid = min<uint32_t>(kWave, w_e - base);
-                const uint32_t r_last = __shfl(Rq, (int)nvalid - 1, kWave);
-                // lanes past the span own no entries
-                rend[wv][lane] = qa < w_e ? Rq : r_last;
-                wave_lds_sync();
-                for (uint32_t p0 = p_next; p0 <= r_last; p0 += kWave) {
-                    const uint32_t p = p0 + (uint32_t)lane;
-                    if (p <= r_last) {
-                        // first step entry j with R >= p (R of entry nvalid - 1 is r_last >= p)
-                        uint32_t a = 0, b = nvalid - 1;
-                        while (a < b) {
-                            const uint32_t mid = (a + b) / 2;
-                            if (rend[wv][mid] >= p) b = mid;
-                            else a = mid + 1;
-                        }
-                        Lf[p] = base + a;
+            uint32_t Wtop = 0;
+            uint32_t lo = (uint32_t)lane;  // a window contains the previous (smaller) one
+#pragma unroll
+            for (int i = 0; i < K; i++) {
+                const int64_t lim = tme + delta[i];
+                // last k in [lo, 128) with key(base + k) <= (ca, lim)
+                uint32_t hi = kRing;
+#pragma unroll
+                for (int step = 0; step < 7; step++) {
+                    const uint32_t mid = (lo + hi) / 2;
+                    const uint4 km = rg[(half * kWave + mid) & (kRing - 1)];
+                    const int64_t tm = (int64_t)(((uint64_t)km.w << 32) | km.z);
+                    const bool ok = km.x < ca || (km.x == ca && tm <= lim);
+                    if (hi - lo > 1) {
+                        if (ok) lo = mid;
+                        else hi = mid;
                     }
                 }
-                p_next = r_last + 1;
+                uint32_t W = 0, Rq = 0;
+                if (qa < w_e) {
+                    uint64_t R = (uint64_t)base + lo;
+                    if (lo == kRing - 1)  // the window may run past the ring
+                        R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
+                    W = (uint32_t)(R - qa);
+                    Wf[(uint64_t)i * len + qa] = W;
+                    Rq = (uint32_t)R;
+                }
+                if (i == K - 1) Wtop = W;
+                if (Lf) {
+                    uint32_t *Lfi = Lf + (uint64_t)i * len;
+                    const uint32_t nvalid = min<uint32_t>(kWave, w_e - base);
+                    const uint32_t r_last = __shfl(Rq, (int)nvalid - 1, kWave);
+                    wave_lds_sync();  // the previous window's reads of rend are done
+                    // lanes past the span own no entries
+                    rend[wv][lane] = qa < w_e ? Rq : r_last;
+                    wave_lds_sync();
+                    for (uint32_t p0 = p_next[i]; p0 <= r_last; p0 += kWave) {
+                        const uint32_t p = p0 + (uint32_t)lane;
+                        if (p <= r_last) {
+                            // first step entry j with R >= p (R of entry nvalid - 1 is r_last >= p)
+                            uint32_t a = 0, b = nvalid - 1;
+                            while (a < b) {
+                                const uint32_t mid = (a + b) / 2;
+                                if (rend[wv][mid] >= p) b = mid;
+                                else a = mid + 1;
+                            }
+                            Lfi[p] = base + a;
+                        }
+                    }
+                    p_next[i] = r_last + 1;
+                }
             }
             if (bits) {
                 const uint32_t t2 = min(hub_min, kHubCap), t3 = max(hub_min, kHubCap);
-                const uint64_t b = __ballot(W != 0);
-                const uint64_t b2 = __ballot(W >= t2);
-                const uint64_t b3 = __ballot(W >= t3);
+                const uint64_t b = __ballot(Wtop != 0);
+                const uint64_t b2 = __ballot(Wtop >= t2);
+                const uint64_t b3 = __ballot(Wtop >= t3);
                 if (lane == 0) {
                     bits[base / kWave] = b;
                     reinterpret_cast<ulonglong2 *>(lev)[base / kWave] = make_ulonglong2(b2, b3);
@@ -690,18 +713,33 @@ __global__ void k_tri_compact(const uint2 *epos2, const uint32_t *Wf, const uint
     }
 }
 
-struct TriAcc {
-    uint64_t c[8];  // class (a, b, c): Tri[I][a][b][c]
-};
-
-__device__ inline void tri_add(TriAcc &T, uint32_t idx) {
-#pragma unroll
-    for (int i = 0; i < 8; i++) T.c[i] += (idx == (uint32_t)i) ? 1ull : 0ull;
-}
+// Triangle counters of one wave, in LDS: class (a, b, c) = Tri[I][a][b][c]
+// of window level l at index 8 l + class.  Matches are rare next to the
+// neighbour comparisons, so each adds to its counter with an LDS atomic
+// instead of keeping 8 K accumulators live in every lane.
+__device__ inline void tri_add(unsigned long long *cnt, uint32_t idx) { atomicAdd(&cnt[idx], 1ull); }
 
 // class of a matched pair: a from W_s (dir relative to s), b from W_d
 __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint32_t db) {
     return ra < rb ? ((1u - da) * 4 + (1u - db) * 2 + 0u) : ((1u - db) * 4 + (1u - da) * 2 + 1u);
+}
+
+// Window level of a matched instance when K nested windows are counted in
+// one pass: the matching runs on the largest window, and the instance
+// belongs to every window that holds both of its later edges, i.e. to the
+// windows from index `level` up, where `level` = the number of smaller
+// windows that miss one of them.  oa, ob: the later edges' offsets after
+// the first edge's entries ps (at its source) and pd (at its destination);
+// Wf holds the window sizes of window i at offset i * len.  Matches are
+// rare next to the comparisons, so the sizes are read here, on a match.
+template <int K>
+__device__ inline uint32_t tri_level(const uint32_t *Wf, uint64_t len, uint32_t ps, uint32_t oa,
+                                     uint32_t pd, uint32_t ob) {
+    uint32_t l = 0;
+#pragma unroll
+    for (int i = 0; i + 1 < K; i++)
+        l += (oa > Wf[(uint64_t)i * len + ps] || ob > Wf[(uint64_t)i * len + pd]) ? 1u : 0u;
+    return l;
 }
 
 // One block per candidate tile (kCandTile candidates of one graph); waves
@@ -717,23 +755,30 @@ constexpr uint32_t kHashChunk = 256;
 constexpr uint32_t kEmptyKey = 0xffffffffu;  // node ids are below 2^31
 constexpr uint32_t kHashMul = 2654435761u;   // Knuth's multiplicative constant
 
-
+// K windows: the candidates and their windows are those of the largest one
+// (Wf at offset (K - 1) * len), each match is filed under its level, and
+// level l's rows go to partial + l * lvl_stride.
+template <int K>
 __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
                                                       const uint32_t *tidx, const uint32_t *eoff,
                                                       const uint32_t *ctfirst, uint32_t G,
-                                                      uint32_t lane_max, uint64_t *partial) {
+                                                      uint32_t lane_max, const uint32_t *Wf,
+                                                      uint64_t len, uint64_t lvl_stride,
+                                                      uint64_t *partial) {
   const uint32_t n_tiles = ctfirst[G];
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t wv = threadIdx.x / kWave;
   __shared__ uint32_t hkey[kBlock / kWave][2 * kHashChunk];
   __shared__ uint32_t hval[kBlock / kWave][2 * kHashChunk];
+  __shared__ uint32_t hpos[K > 1 ? kBlock / kWave : 1][K > 1 ? 2 * kHashChunk : 1];
+  __shared__ unsigned long long tcnt[kBlock / kWave][8 * K];
+  unsigned long long *T = tcnt[wv];
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const uint32_t gi = last_le(ctfirst, G + 1, ti);
     const uint32_t cb = tidx[eoff[gi]] + (ti - ctfirst[gi]) * kCandTile;
     const uint32_t ce = min(tidx[eoff[gi + 1]], cb + kCandTile);
-    TriAcc T;
-#pragma unroll
-    for (int i = 0; i < 8; i++) T.c[i] = 0;
+    if (lane < 8 * K) T[lane] = 0;
+    wave_lds_sync();
     for (uint32_t base = cb + wv * kWave; base < ce; base += kBlock) {
         const uint32_t ci = base + lane;
         uint32_t ps = 0, pd = 0, ws = 0, wd = 0;
@@ -765,9 +810,14 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                     const uint32_t rb = S.rk[b];
 #pragma unroll
                     for (int k = 0; k < kRegWin; k++) {
-                        if ((rn[k] >> 1) == (ndb >> 1))
-                            tri_add(T, s_reg ? tri_class(rr[k], rn[k] & 1u, rb, ndb & 1u)
-                                             : tri_class(rb, ndb & 1u, rr[k], rn[k] & 1u));
+                        if ((rn[k] >> 1) == (ndb >> 1)) {
+                            const uint32_t cls = s_reg ? tri_class(rr[k], rn[k] & 1u, rb, ndb & 1u)
+                                                       : tri_class(rb, ndb & 1u, rr[k], rn[k] & 1u);
+                            const uint32_t oreg = (uint32_t)k + 1, ostr = b - lp;
+                            const uint32_t l = s_reg ? tri_level<K>(Wf, len, ps, oreg, pd, ostr)
+                                                     : tri_level<K>(Wf, len, ps, ostr, pd, oreg);
+                            tri_add(T, l * 8 + cls);
+                        }
                     }
                 }
             } else {
@@ -776,8 +826,10 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                     const uint32_t ra = S.rk[a];
                     for (uint32_t b = pd + 1; b <= pd + wd; b++) {
                         const uint32_t ndb = S.nd[b];
-                        if ((ndb >> 1) == (nda >> 1))
-                            tri_add(T, tri_class(ra, nda & 1u, S.rk[b], ndb & 1u));
+                        if ((ndb >> 1) == (nda >> 1)) {
+                            const uint32_t cls = tri_class(ra, nda & 1u, S.rk[b], ndb & 1u);
+                            tri_add(T, tri_level<K>(Wf, len, ps, a - ps, pd, b - pd) * 8 + cls);
+                        }
                     }
                 }
             }
@@ -790,8 +842,9 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
             const uint32_t bps = __shfl(ps, L, kWave), bws = __shfl(ws, L, kWave);
             const uint32_t bpd = __shfl(pd, L, kWave), bwd = __shfl(wd, L, kWave);
             const bool s_outer = bws <= bwd;
-            const uint32_t o_lo = s_outer ? bps + 1 : bpd + 1, o_hi = s_outer ? bps + bws : bpd + bwd;
-            const uint32_t i_lo = s_outer ? bpd + 1 : bps + 1, i_hi = s_outer ? bpd + bwd : bps + bws;
+            const uint32_t o_base = s_outer ? bps : bpd, i_base = s_outer ? bpd : bps;
+            const uint32_t o_lo = o_base + 1, o_hi = s_outer ? bps + bws : bpd + bwd;
+            const uint32_t i_lo = i_base + 1, i_hi = s_outer ? bpd + bwd : bps + bws;
             if (o_hi - o_lo + 1 > kHashMin) {
                 // hash join: the smaller window, kHashChunk entries at a time,
                 // goes into an open-addressing table in this wave's LDS (one
@@ -812,6 +865,7 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                         uint32_t h = (key * kHashMul) >> hshift;
                         while (atomicCAS(&hk[h], kEmptyKey, key) != kEmptyKey) h = (h + 1) & hmask;
                         hv[h] = (S.rk[y] << 1) | (nd & 1u);
+                        if (K > 1) hpos[wv][h] = y;
                     }
                     wave_lds_sync();
                     for (uint32_t x = i_lo + lane; x <= i_hi; x += kWave) {
@@ -823,8 +877,15 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                             if (k == kEmptyKey) break;
                             if (k == key) {
                                 const uint32_t v = hv[h];
-                                tri_add(T, s_outer ? tri_class(v >> 1, v & 1u, rx, nd & 1u)
-                                                   : tri_class(rx, nd & 1u, v >> 1, v & 1u));
+                                const uint32_t cls = s_outer ? tri_class(v >> 1, v & 1u, rx, nd & 1u)
+                                                             : tri_class(rx, nd & 1u, v >> 1, v & 1u);
+                                uint32_t l = 0;
+                                if (K > 1) {
+                                    const uint32_t oo = hpos[wv][h] - o_base, oi = x - i_base;
+                                    l = s_outer ? tri_level<K>(Wf, len, bps, oo, bpd, oi)
+                                                : tri_level<K>(Wf, len, bps, oi, bpd, oo);
+                                }
+                                tri_add(T, l * 8 + cls);
                             }
                         }
                     }
@@ -850,22 +911,23 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                         if (valid && (ndx >> 1) == (ndo >> 1)) {
                             const uint32_t cls = s_outer ? tri_class(ro, ndo & 1u, rx, ndx & 1u)
                                                          : tri_class(rx, ndx & 1u, ro, ndo & 1u);
-                            tri_add(T, cls);
+                            const uint32_t oo = ob + k - o_base, oi = x - i_base;
+                            const uint32_t l = s_outer ? tri_level<K>(Wf, len, bps, oo, bpd, oi)
+                                                       : tri_level<K>(Wf, len, bps, oi, bpd, oo);
+                            tri_add(T, l * 8 + cls);
                         }
                     }
                 }
             }
         }
     }
-    // one row per wave (no block barrier: a wave with a wide hub window does
-    // not hold the others of its block at the end of each tile)
-#pragma unroll
-    for (int i = 0; i < 8; i++) {
-        uint64_t v = T.c[i];
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if (lane == 0) partial[((uint64_t)ti * kTriRowsPerTile + wv) * 8 + i] = v;
-    }
+    // one row per wave and level (no block barrier: a wave with a wide hub
+    // window does not hold the others of its block at the end of each tile)
+    wave_lds_sync();
+    if (lane < 8 * K)
+        partial[(uint64_t)(lane / 8) * lvl_stride + ((uint64_t)ti * kTriRowsPerTile + wv) * 8 + lane % 8] =
+            T[lane];
+    wave_lds_sync();  // the next tile clears the row
   }
 }
 
@@ -889,7 +951,7 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
 // slice is zeroed here.  *count was zeroed by k_graph_tiles.
 __global__ void k_hub_tiles(const uint64_t *lev, uint32_t hub_min, const uint32_t *eoff,
                             const uint32_t *htfirst, uint32_t G, uint32_t *count, uint32_t *list,
-                            uint64_t *hpart) {
+                            uint32_t levels, uint64_t lvl_stride, uint64_t *hpart) {
     const bool hub_first = hub_min <= kHubCap;
     const uint32_t n_tiles = htfirst[G];
     for (uint32_t ti = blockIdx.x * blockDim.x + threadIdx.x; ti < n_tiles;
@@ -908,8 +970,9 @@ __global__ void k_hub_tiles(const uint64_t *lev, uint32_t hub_min, const uint32_
         if (any) {
             list[atomicAdd(count, 1u)] = ti;
         } else {
+            for (uint32_t l = 0; l < levels; l++)
 #pragma unroll
-            for (int i = 0; i < 8; i++) hpart[(uint64_t)ti * 8 + i] = 0;
+                for (int i = 0; i < 8; i++) hpart[l * lvl_stride + (uint64_t)ti * 8 + i] = 0;
         }
     }
 }
@@ -945,12 +1008,17 @@ constexpr uint64_t kLow48 = (1ull << 48) - 1;
 struct HubArgs {
     SeqView S;
     const uint2 *epos2;
-    const uint32_t *Wf;
+    const uint32_t *Wf;  // window sizes; the largest window's at offset (K - 1) * len
+    uint64_t len;
     const uint64_t *lev;
     const uint32_t *eoff, *htfirst, *count, *list;
     uint32_t G, hub_min;
+    uint64_t lvl_stride;  // level l's rows go to hpart + l * lvl_stride
 };
 
+// K windows: owners, windows and segments are those of the largest one;
+// each match is filed under its window level.
+template <int K>
 __global__ void __launch_bounds__(kHubBlock) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_tri_hub(HubArgs a, uint64_t *hpart) {
     __shared__ uint32_t hk[kHubSlots];             // neighbour, or kEmptyKey
@@ -963,7 +1031,7 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
     __shared__ uint64_t spre[kHubSlice + 1];       // their probe offsets
     __shared__ uint32_t wmark[kHubBlock / kWave][kWave];
     __shared__ uint64_t wtot[kHubBlock / kWave];
-    __shared__ uint64_t red[kHubBlock / kWave][8];
+    __shared__ unsigned long long red[kHubBlock / kWave][8 * K];
     __shared__ uint32_t s_lo, s_hi;
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave, nw = kHubBlock / kWave;
@@ -980,6 +1048,7 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             s_hi = 0;
         }
         // A. owners among this thread's positions
+        const uint32_t *Wtop = a.Wf + (uint64_t)(K - 1) * a.len;
         uint32_t own = 0, rp[kHubPer], rw[kHubPer], rq[kHubPer], rwo[kHubPer];
 #pragma unroll
         for (uint32_t k = 0; k < kHubPer; k++) {
@@ -987,11 +1056,11 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             rp[k] = p;
             rw[k] = rq[k] = rwo[k] = 0;
             if (p < s1 && ((hub_word(a.lev, p / kWave, hub_first) >> (p % kWave)) & 1ull)) {
-                const uint32_t W = a.Wf[p];
+                const uint32_t W = Wtop[p];
                 const uint2 e = a.epos2[S.rk[p]];
                 const bool is_s = e.x == p;
                 const uint32_t q = is_s ? e.y : e.x;
-                const uint32_t Wo = a.Wf[q];
+                const uint32_t Wo = Wtop[q];
                 if (Wo != 0 && Wo < kHubCap && (is_s ? W >= Wo : W > Wo)) {
                     own |= 1u << k;
                     rw[k] = W | (is_s ? 0x80000000u : 0u);
@@ -1013,7 +1082,7 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             }
         __syncthreads();
         // the previous tile's row was read before the barriers above
-        if (threadIdx.x < nw * 8) red[threadIdx.x / 8][threadIdx.x % 8] = 0;
+        if (threadIdx.x < nw * 8 * K) red[threadIdx.x / (8 * K)][threadIdx.x % (8 * K)] = 0;
         __syncthreads();
         const uint64_t lo = s_lo, hi = s_hi;
         for (uint64_t sl64 = lo; n_own != 0 && sl64 <= hi; sl64 += kHubCap) {
@@ -1073,13 +1142,8 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             // marking them in a 64-slot array gives each lane its owner by
             // a popcount.  Two 64-probe steps are mapped first and their
             // loads issued together, then both walk the table.
-            // Per-lane counts of one segment fit 32 bits: a lane takes at
-            // most t_seg / nw / 64 + 1 <= 2049 probes (t_seg < kHubSlice *
-            // kHubCap), each matching at most kHubCap entries; the wave's
-            // sums (< 2^29) go to its LDS row after the segment.
-            uint32_t T[8];
-#pragma unroll
-            for (int i = 0; i < 8; i++) T[i] = 0;
+            // A match adds to its wave's LDS row of counters (u64) with an
+            // LDS atomic: matches are rare next to the probes.
             const uint64_t jb = t_seg * wv / nw, je = t_seg * (wv + 1) / nw;
             if (jb < je) {
                 uint32_t c0 = 0, chi = n_seg;  // last c with spre[c] <= jb
@@ -1107,16 +1171,18 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
                         c0 += (uint32_t)__popcll(done);
                         wave_lds_sync();
                     }
-                    uint32_t nd[2], rx[2], pp[2], wpk[2];
+                    uint32_t nd[2], rx[2], pp[2], wpk[2], qq[2], ox[2];
 #pragma unroll
                     for (int u = 0; u < 2; u++) {
                         const uint64_t j = base + (uint64_t)u * kWave + (uint64_t)lane;
-                        nd[u] = rx[u] = pp[u] = wpk[u] = 0;
+                        nd[u] = rx[u] = pp[u] = wpk[u] = qq[u] = ox[u] = 0;
                         if (j < je) {  // then cu[u] < n_seg
                             const uint4 o = own_l[sidx[cu[u]]];
                             const uint32_t x = o.z + (uint32_t)(j - spre[cu[u]]);
                             pp[u] = o.x;
                             wpk[u] = o.y;
+                            qq[u] = o.z - 1;  // the other window's first edge entry
+                            ox[u] = x - (o.z - 1);
                             nd[u] = S.nd[x];
                             rx[u] = S.rk[x];
                         }
@@ -1132,31 +1198,27 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
                                 const uint32_t off = ho[h], y = sl + off;
                                 if (y > p && y - p <= W) {
                                     const uint32_t v = srd[off];
-                                    const uint32_t cls = (wpk[u] >> 31) ? tri_class(v >> 1, v & 1u, rx[u], nd[u] & 1u)
-                                                                        : tri_class(rx[u], nd[u] & 1u, v >> 1, v & 1u);
-#pragma unroll
-                                    for (int i = 0; i < 8; i++) T[i] += cls == (uint32_t)i ? 1u : 0u;
+                                    const bool own_s = (wpk[u] >> 31) != 0;
+                                    const uint32_t cls = own_s ? tri_class(v >> 1, v & 1u, rx[u], nd[u] & 1u)
+                                                               : tri_class(rx[u], nd[u] & 1u, v >> 1, v & 1u);
+                                    const uint32_t l =
+                                        own_s ? tri_level<K>(a.Wf, a.len, p, y - p, qq[u], ox[u])
+                                              : tri_level<K>(a.Wf, a.len, qq[u], ox[u], p, y - p);
+                                    tri_add(red[wv], l * 8 + cls);
                                 }
                             }
                         }
                     }
                 }
             }
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                uint32_t v = T[i];
-#pragma unroll
-                for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-                if (lane == 0) red[wv][i] += v;
-            }
             __syncthreads();  // the next segment rewrites the table and lists
         }
-        // one row per tile (the segment loop ended on a barrier)
-        if (threadIdx.x < 8) {
+        // one row per tile and level (the segment loop ended on a barrier)
+        if (threadIdx.x < 8 * K) {
             uint64_t v = 0;
 #pragma unroll
             for (uint32_t q = 0; q < nw; q++) v += red[q][threadIdx.x];
-            hpart[(uint64_t)ti * 8 + threadIdx.x] = v;
+            hpart[(uint64_t)(threadIdx.x / 8) * a.lvl_stride + (uint64_t)ti * 8 + threadIdx.x % 8] = v;
         }
     }
 }
@@ -1265,49 +1327,52 @@ constexpr uint32_t kDefaultHubMin = 32;
 // Device workspace of one count: carved from one block, either per call or
 // kept in the graph's plan for captured replays.
 struct Workspace {
+    uint32_t K = 1;  // windows counted in one pass (one graph when K > 1)
     int64_t *deltas;
-    uint32_t *Wf, *Lf;
+    uint32_t *Wf, *Lf;  // window i at offset i * 2m
     uint64_t *wbits, *lev;
-    uint4 *me_w;
+    uint4 *me_w;        // window i at offset i * 2 * n_me
     uint32_t *cnt, *first, *ipair, *tflag, *tidx;
     uint4 *cand;
     uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
     uint32_t *n_htiles, *htfirst, *hcount, *hlist;
-    uint64_t *spart, *tpart, *hpart, *gpart, *res;
+    uint64_t *spart, *tpart, *hpart, *gpart, *res;  // per window (res: K x G x 40)
     uint64_t max_itiles, max_ctiles, max_htiles;
 };
 
-static size_t workspace_bytes(const tm_graph *g, Workspace *w) {
+static size_t workspace_bytes(const tm_graph *g, Workspace *w, uint32_t K = 1) {
     const uint32_t G = g->G;
     const uint64_t m = g->m, len = 2 * m, nm = g->n_multi, nme = g->n_me;
+    w->K = K;
     w->max_itiles = nme / kItemTile + G + 1;
     w->max_ctiles = m / kCandTile + G + 1;
     w->max_htiles = len / kHubSlice + G + 1;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return up(G * 8) + up(len * 4) * 2 + up((len / kWave + 1) * 8) + up((len / kWave + 1) * 16) + up(2 * nme * sizeof(uint4)) +
-           up((G + 1) * 4) * 2 + up(4) + up(w->max_htiles * 4) + up(w->max_htiles * 8 * 8) +
+    return up((size_t)G * K * 8) + up(len * 4 * K) * 2 + up((len / kWave + 1) * 8) +
+           up((len / kWave + 1) * 16) + up(2 * nme * sizeof(uint4) * K) +
+           up((G + 1) * 4) * 2 + up(4) + up(w->max_htiles * 4) + up(w->max_htiles * 8 * 8 * K) +
            up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * sum_split(G) * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
-           up(n_tmp * 4) + up(w->max_itiles * 32 * 8) + up(w->max_ctiles * kTriRowsPerTile * 8 * 8) +
-           up((size_t)G * 40 * 8) + 4096;
+           up(n_tmp * 4) + up(w->max_itiles * 32 * 8 * K) +
+           up(w->max_ctiles * kTriRowsPerTile * 8 * 8 * K) + up((size_t)G * 40 * 8 * K) + 4096;
 }
 
 static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
-    const uint32_t G = g->G;
+    const uint32_t G = g->G, K = w->K;
     const uint64_t m = g->m, len = 2 * m, nm = g->n_multi, nme = g->n_me;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
-    w->deltas = sc.take<int64_t>(G);
-    w->Wf = sc.take<uint32_t>(len);
-    w->Lf = sc.take<uint32_t>(len);
+    w->deltas = sc.take<int64_t>((size_t)G * K);
+    w->Wf = sc.take<uint32_t>(len * K);
+    w->Lf = sc.take<uint32_t>(len * K);
     w->wbits = sc.take<uint64_t>(len / kWave + 1);
     w->lev = sc.take<uint64_t>(2 * (len / kWave + 1));
     w->n_htiles = sc.take<uint32_t>(G + 1);
     w->htfirst = sc.take<uint32_t>(G + 1);
     w->hcount = sc.take<uint32_t>(1);
     w->hlist = sc.take<uint32_t>(w->max_htiles);
-    w->hpart = sc.take<uint64_t>(w->max_htiles * 8);
-    w->me_w = sc.take<uint4>(2 * nme);
+    w->hpart = sc.take<uint64_t>(w->max_htiles * 8 * K);
+    w->me_w = sc.take<uint4>(2 * nme * K);
     w->cnt = sc.take<uint32_t>(nm + 1);
     w->first = sc.take<uint32_t>(nm + 1);
     w->ipair = sc.take<uint32_t>(nme + 1);
@@ -1319,39 +1384,61 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->n_ctiles = sc.take<uint32_t>(G + 1);
     w->ctfirst = sc.take<uint32_t>(G + 1);
     w->tmp = sc.take<uint32_t>(n_tmp);
-    w->spart = sc.take<uint64_t>(w->max_itiles * 32);
-    w->tpart = sc.take<uint64_t>(w->max_ctiles * kTriRowsPerTile * 8);
+    w->spart = sc.take<uint64_t>(w->max_itiles * 32 * K);
+    w->tpart = sc.take<uint64_t>(w->max_ctiles * kTriRowsPerTile * 8 * K);
     w->gpart = sc.take<uint64_t>((size_t)G * sum_split(G) * 40);
-    w->res = sc.take<uint64_t>((size_t)G * 40);
+    w->res = sc.take<uint64_t>((size_t)G * 40 * K);
 }
 
-// Every kernel of one count, deltas already in w.deltas, counters to w.res
-// (G x 40).  No host synchronisation, memset or allocation: capturable.
+// Launch a kernel template instantiated for K windows (1 .. kMaxLevels).
+#define TM_LAUNCH_K(name, kern, K, grid, block, shm, stream, ...)                              \
+    do {                                                                                       \
+        switch (K) {                                                                           \
+            case 1: TM_LAUNCH(name, kern<1>, grid, block, shm, stream, __VA_ARGS__); break;    \
+            case 2: TM_LAUNCH(name, kern<2>, grid, block, shm, stream, __VA_ARGS__); break;    \
+            case 3: TM_LAUNCH(name, kern<3>, grid, block, shm, stream, __VA_ARGS__); break;    \
+            default: TM_LAUNCH(name, kern<4>, grid, block, shm, stream, __VA_ARGS__); break;   \
+        }                                                                                      \
+    } while (0)
+
+// Every kernel of one count, deltas already in w.deltas (G x K, each graph's
+// windows ascending), counters to w.res (K x G x 40; the triangle counters
+// of window i hold the instances whose smallest window is i).  No host
+// synchronisation, memset or allocation: capturable.
 static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint32_t families,
                          hipStream_t s) {
     const uint32_t run_chunk = pr.run_chunk, tri_lane_max = pr.tri_lane_max;
-    const uint32_t G = g->G;
+    const uint32_t G = g->G, K = w.K;
+    if (K < 1 || K > (uint32_t)kMaxLevels || (K > 1 && G != 1)) {
+        set_error("windows per pass out of range");
+        return TM_EINTERNAL;
+    }
     SeqView S{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos};
-    const uint64_t m = g->m, nme = g->n_me;
+    const uint64_t m = g->m, nme = g->n_me, len = 2 * m;
     const bool do_sp = (families & (TM_STARS | TM_PAIRS)) != 0;
     const bool do_tri = (families & TM_TRIANGLES) != 0;
     const bool do_hub = do_tri && pr.hub_min != TM_HUB_OFF;
     const uint64_t nm = do_sp ? g->n_multi : 0;
+    const uint32_t *Wtop = w.Wf + (uint64_t)(K - 1) * len;
+    const uint64_t t_stride = w.max_ctiles * kTriRowsPerTile * 8, h_stride = w.max_htiles * 8;
+    const uint64_t s_stride = w.max_itiles * 32;
     int rc;
     // one graph: the window kernel also writes the triangle bit planes
     const bool fused_levels = do_tri && G == 1;
     // trace rows: a4 star/pair (with the shared window kernel), a5 triangles,
     // a6 work items (chunks, tiles, hub slices), a7 reduction
     ProfRow row_a4("a4");
-    TM_LAUNCH("windows", k_windows, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock), 0,
-              s, S, g->t_entries, g->n_t_entries, 2 * m, w.deltas, w.Wf, pr.hub_min,
-              fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr,
-              nm ? w.Lf : nullptr);
-    // ---- star / pair: work items (pair, chunk)
+    TM_LAUNCH_K("windows", k_windows, K, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock),
+                0, s, S, g->t_entries, g->n_t_entries, len, w.deltas, w.Wf, pr.hub_min,
+                fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr,
+                nm ? w.Lf : nullptr);
+    // ---- star / pair: work items (pair, chunk); window i reads its own
+    // sizes and deltas (K > 1 only for one graph, whose delta i is deltas[i])
     if (nm) {
-        TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
-                  dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, w.Wf, w.Lf, nme, g->t_elems,
-                  g->n_t_elems, w.deltas, w.me_w);
+        for (uint32_t i = 0; i < K; i++)
+            TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
+                      dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, w.Wf + i * len, w.Lf + i * len,
+                      nme, g->t_elems, g->n_t_elems, w.deltas + i, w.me_w + i * 2 * nme);
         ProfRow row_a6("a6");
         TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
                   nm, run_chunk, w.cnt);
@@ -1361,18 +1448,18 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
         rc = scan_u32_array(w.cnt, w.first, nm, w.tmp, s);
         if (rc) return rc;
     }
-    // ---- triangles: candidate first edges
+    // ---- triangles: candidate first edges (of the largest window)
     if (do_tri) {
         ProfRow row_a5("a5");
         if (!fused_levels)
-            TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m,
+            TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, Wtop, 2 * m,
                       pr.hub_min, w.wbits, w.lev);
         TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
                   reinterpret_cast<const uint2 *>(g->epos), w.wbits, w.lev, pr.hub_min, m, w.tflag);
         rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
         if (rc) return rc;
         TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
-                  reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.tflag, w.tidx, m, w.cand);
+                  reinterpret_cast<const uint2 *>(g->epos), Wtop, w.tflag, w.tidx, m, w.cand);
     }
     // ---- per-graph work tiles
     {
@@ -1391,35 +1478,39 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
                   0, s, w.first, nm, w.ipair);
     if (do_hub)
         TM_LAUNCH("hub_tiles", k_hub_tiles, grid_for(w.max_htiles, 4096), dim3(kBlock), 0, s, w.lev,
-                  pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, w.hpart);
+                  pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, K, h_stride, w.hpart);
     }
     if (nm) {
-        StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w, w.first, w.ipair, nm, nme,
-                    g->d_mpb, w.tfirst, G, w.deltas, run_chunk,
-                    (families & TM_STARS) ? 1 : 0};
-        TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
-                  dim3(kBlock), 0, s, sa, w.spart);
+        for (uint32_t i = 0; i < K; i++) {
+            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w + i * 2 * nme, w.first, w.ipair,
+                        nm, nme, g->d_mpb, w.tfirst, G, w.deltas + i, run_chunk,
+                        (families & TM_STARS) ? 1 : 0};
+            TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
+                      dim3(kBlock), 0, s, sa, w.spart + i * s_stride);
+        }
     }
     if (do_tri) {
         ProfRow row_a5("a5");
-        TM_LAUNCH("triangles", k_triangles, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
-                  dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max,
-                  w.tpart);
+        TM_LAUNCH_K("triangles", k_triangles, K, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
+                    dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max,
+                    w.Wf, len, t_stride, w.tpart);
     }
     if (do_hub) {
         ProfRow row_a5("a5");
-        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.lev, g->d_eoff, w.htfirst,
-                   w.hcount, w.hlist, G, pr.hub_min};
-        TM_LAUNCH("tri_hub", k_tri_hub, dim3((unsigned)std::min<uint64_t>(w.max_htiles, 4096)),
-                  dim3(kHubBlock), 0, s, ha, w.hpart);
+        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, len, w.lev, g->d_eoff,
+                   w.htfirst, w.hcount, w.hlist, G, pr.hub_min, h_stride};
+        TM_LAUNCH_K("tri_hub", k_tri_hub, K, dim3((unsigned)std::min<uint64_t>(w.max_htiles, 4096)),
+                    dim3(kHubBlock), 0, s, ha, w.hpart);
     }
     const uint32_t split = sum_split(G);
     ProfRow row_a7("a7");
-    TM_LAUNCH("graph_sums", k_graph_sums, dim3((unsigned)std::min<uint64_t>((uint64_t)G * split, 16384)),
-              dim3(kBlock), 0, s, w.spart, w.tfirst, w.tpart, w.ctfirst, w.hpart, w.htfirst, G,
-              split, w.gpart);
-    TM_LAUNCH("graph_sums_fin", k_graph_sums_fin, dim3(std::min<uint32_t>(G, 4096)), dim3(kBlock), 0, s,
-              w.gpart, G, split, w.res);
+    for (uint32_t i = 0; i < K; i++) {
+        TM_LAUNCH("graph_sums", k_graph_sums, dim3((unsigned)std::min<uint64_t>((uint64_t)G * split, 16384)),
+                  dim3(kBlock), 0, s, w.spart + i * s_stride, w.tfirst, w.tpart + i * t_stride,
+                  w.ctfirst, w.hpart + i * h_stride, w.htfirst, G, split, w.gpart);
+        TM_LAUNCH("graph_sums_fin", k_graph_sums_fin, dim3(std::min<uint32_t>(G, 4096)), dim3(kBlock), 0,
+                  s, w.gpart, G, split, w.res + (size_t)i * G * 40);
+    }
     return TM_OK;
 }
 
@@ -1671,35 +1762,53 @@ int count_graph_noalloc(tm_graph *g, int64_t delta, uint64_t *raw) {
     return TM_OK;
 }
 
-// Several windows over one built graph (G == 1) in one call: the count
-// sequence runs once per delta, back to back on the graph's stream, each
-// delta's counters copied to its own device slot, then one download and one
-// synchronisation for all of them.
+// Several windows over one built graph (G == 1) in one call.  The windows
+// are taken in ascending order, up to kMaxLevels per pass: a pass builds the
+// window sizes of all its windows in one kernel, finds the triangle
+// candidates and matches them once, for its largest window, and files each
+// match under the smallest window holding it (so window i's triangles are
+// the sum of levels 0 .. i); the star/pair sweeps run per window.  Each
+// pass's counters go to their own device slot, then one download and one
+// synchronisation return all of them.
 int count_graph_multi(tm_graph *g, const int64_t *h_deltas, uint32_t k, Params pr, uint64_t *raw) {
     resolve_params(g, &pr);
-    std::vector<uint64_t> host((size_t)k * 40, 0);
-    if (g->m >= 3) {
+    std::vector<uint32_t> ord(k);
+    for (uint32_t i = 0; i < k; i++) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](uint32_t a, uint32_t b) { return h_deltas[a] < h_deltas[b]; });
+    std::vector<int64_t> sorted(k);
+    for (uint32_t i = 0; i < k; i++) sorted[i] = h_deltas[ord[i]];
+    std::vector<uint64_t> host((size_t)k * 40, 0);  // ascending window order
+    const uint32_t kmax = std::min<uint32_t>(k, (uint32_t)kMaxLevels);
+    if (g->m >= 3 && k > 0) {
         hipStream_t s = g->stream;
         Workspace w;
         Scratch sc, sk;
-        int rc = sc.reserve(workspace_bytes(g, &w), s);
+        int rc = sc.reserve(workspace_bytes(g, &w, kmax), s);
         if (rc) return rc;
         workspace_carve(g, sc, &w);
         rc = sk.reserve((size_t)k * 8 + (size_t)k * 40 * 8 + 1024, s);
         if (rc) return rc;
         int64_t *dk = sk.take<int64_t>(k);
         uint64_t *resk = sk.take<uint64_t>((size_t)k * 40);
-        TM_HIP_TRY(hipMemcpyAsync(dk, h_deltas, (size_t)k * 8, hipMemcpyHostToDevice, s));
-        for (uint32_t i = 0; i < k; i++) {
-            TM_HIP_TRY(hipMemcpyAsync(w.deltas, dk + i, 8, hipMemcpyDeviceToDevice, s));
+        TM_HIP_TRY(hipMemcpyAsync(dk, sorted.data(), (size_t)k * 8, hipMemcpyHostToDevice, s));
+        for (uint32_t g0 = 0; g0 < k; g0 += kmax) {
+            w.K = std::min(kmax, k - g0);
+            TM_HIP_TRY(hipMemcpyAsync(w.deltas, dk + g0, (size_t)w.K * 8, hipMemcpyDeviceToDevice, s));
             rc = enqueue_count(g, w, pr, TM_ALL_MOTIFS, s);
             if (rc) return rc;
-            TM_HIP_TRY(hipMemcpyAsync(resk + (size_t)i * 40, w.res, 40 * 8, hipMemcpyDeviceToDevice, s));
+            TM_HIP_TRY(hipMemcpyAsync(resk + (size_t)g0 * 40, w.res, (size_t)w.K * 40 * 8,
+                                      hipMemcpyDeviceToDevice, s));
         }
         TM_HIP_TRY(hipMemcpyAsync(host.data(), resk, (size_t)k * 40 * 8, hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
+        // a pass's window i holds the triangles of its levels 0 .. i
+        for (uint32_t g0 = 0; g0 < k; g0 += kmax)
+            for (uint32_t i = g0 + 1; i < std::min(k, g0 + kmax); i++)
+                for (int c = 32; c < 40; c++) host[(size_t)i * 40 + c] += host[(size_t)(i - 1) * 40 + c];
     }
-    for (uint32_t i = 0; i < k; i++) raw_from_counters(host.data() + (size_t)i * 40, 1, raw + (size_t)i * 56);
+    for (uint32_t i = 0; i < k; i++)
+        raw_from_counters(host.data() + (size_t)i * 40, 1, raw + (size_t)ord[i] * 56);
     return TM_OK;
 }
 

@@ -504,6 +504,33 @@ def test_count_multi_equals_single_counts_skewed(tm):
     np.testing.assert_array_equal(multi[1], oracle.alg(g.src, g.dst, g.t, 3600, n=g.n))
 
 
+def test_count_multi_hub_heavy(tm):
+    """Several windows in one pass on the hub-heavy skewed graph (1/100
+    scale): the hub slice kernel and the per-candidate kernel both file
+    their matches under window levels."""
+    g = graphgen.skewed(seed=103, n=100_000, m=3_000_000, top_degree=100_000)
+    deltas = [86400, 600, 3600]
+    case("count_multi skewed/100 hub-heavy")
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        multi = G.count_multi_raw(deltas)
+    for i, d in enumerate(deltas):
+        np.testing.assert_array_equal(multi[i], oracle.alg(g.src, g.dst, g.t, d, n=g.n),
+                                      err_msg=f"delta={d}")
+
+
+def test_count_multi_five_windows(tm):
+    """Five windows: a pass of four and a pass of one, with equal windows
+    inside a pass, against single counts and the oracle."""
+    g = graphgen.chung_lu_pareto(105, 20_000, 400_000)
+    deltas = [3600, 5, 86400, 600, 3600]
+    case("count_multi powerlaw/50 k=5")
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        multi = G.count_multi_raw(deltas)
+        for i, d in enumerate(deltas):
+            np.testing.assert_array_equal(multi[i], G.count_raw(d), err_msg=f"delta={d}")
+    np.testing.assert_array_equal(multi[2], oracle.alg(g.src, g.dst, g.t, 86400, n=g.n))
+
+
 def test_count_multi_rejects(tm):
     rng = np.random.default_rng(72)
     g = graphgen.small_random(rng, 8, 200)
