@@ -197,8 +197,9 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
     histogram and first pass, and its last pass writes the rank-ordered
     arrays (t, input index, the two node-sort entries, pair key and value:
     64 B per edge).  The node sort's last pass writes the sequence arrays
-    (node, t, other end | dir, rank) and each edge's two positions instead
-    of the ping-pong buffers."""
+    (node, t, other end | dir, rank) and each entry's slot instead of the
+    ping-pong buffers; each edge's two positions come from a two-pass
+    partition of (slot, position) pairs and a bucket fill."""
     e2 = 2 * m
     tk = 4 if info["tbits"] <= 32 else 8
     me, nm = info["multi_pair_edges"], info["multi_pairs"]
@@ -215,7 +216,14 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
         "sort_time_scatter_last": m * (tk + 12 + 64) if pt > 1 else m * (16 + 64),
         "sort_node_hist": e2 * 4,
         "sort_node_scatter": e2 * 40,
+        # the last pass also writes each entry's slot (2r + dir) in entry order
         "sort_node_scatter_last": e2 * (20 + 24),
+        # edge positions: (slot, position) pairs partitioned by the slot's
+        # high bits (the first pass reads the slots alone), then each bucket
+        # filled through LDS
+        "sort_slot_hist": e2 * 4,
+        "sort_slot_scatter": e2 * 14,
+        "epos_fill": e2 * (8 + 4),
         "offsets_fill": (n + 1) * 4,
         "offsets": e2 * 4 + (n + 1) * 4,
         "sort_pair_hist": m * 8,

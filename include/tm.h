@@ -365,6 +365,15 @@ void tm_stream_free(tm_stream *s);
  * Process-wide; not for use while other threads build.
  */
 void tm_debug_lookback_giveup(int on);
+/*
+ * Testing.  Each edge's two positions in the sequences S_u (an index of 2m
+ * words) are written straight from the node sort while the index fits the
+ * GPU's last-level cache, and built by a partition of (slot, position)
+ * pairs and a bucket fill above that.  With on != 0 every later build takes
+ * the second way, so that small tests cover it; 0 restores the size rule.
+ * Process-wide; not for use while other threads build.
+ */
+void tm_debug_force_edge_sort(int on);
 
 const char *tm_strerror(int code);
 const char *tm_last_error(void);

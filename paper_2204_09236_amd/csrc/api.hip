@@ -164,6 +164,8 @@ const char *tm_last_error(void) { return tmc::g_last_error.c_str(); }
 
 void tm_debug_lookback_giveup(int on) { tmc::set_lookback_giveup(on != 0); }
 
+void tm_debug_force_edge_sort(int on) { tmc::set_force_edge_sort(on != 0); }
+
 uint32_t tm_graph_count(const tm_graph *g) { return g ? g->G : 0; }
 
 void tm_graph_free(tm_graph *g) {

@@ -15,6 +15,7 @@
 //      arrays with, for each of the two nodes, the edge's position in S_u and
 //      the number of dir-o / dir-in entries before it.
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "tm_internal.h"
@@ -28,6 +29,11 @@ constexpr uint32_t kGapFill = 64;
 constexpr uint32_t kUnset = 0xffffffffu;
 constexpr uint32_t kMaxStatBlocks = 4096;
 constexpr uint64_t kEntryTile = 8192, kElemTile = 1024;
+// The edge-position index is scattered straight from the node sort while it
+// fits MI355X's 256 MiB last-level cache (random 4-byte writes merge there);
+// larger ones are built by edge_positions.
+constexpr uint64_t kDirectEposBytes = (uint64_t)256 << 20;
+std::atomic<bool> g_force_edge_sort{false};  // tests: build every index by edge_positions
 // a single graph's entry tiles start at multiples of 64: the count's window
 // kernel then writes whole 64-entry words of the window bit planes
 static_assert(kEntryTile % 64 == 0, "entry tiles must be 64-aligned");
@@ -239,6 +245,12 @@ __global__ void __launch_bounds__(kBlock) k_max_degree(const uint32_t *off, uint
         atomicMax(out, mx);
     }
 }
+
+}  // namespace
+
+void set_force_edge_sort(bool on) { g_force_edge_sort.store(on); }
+
+namespace {
 
 int bits_for(uint64_t maxval) {
     int b = 0;
@@ -462,8 +474,24 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     {
         uint32_t *k_alt = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(nkey) == KA ? KB : KA);
         NodeVal *v_alt = reinterpret_cast<NodeVal *>(reinterpret_cast<char *>(nval) == VA ? VB : VA);
-        const SeqOut so{g->ent_c, g->ent_t, g->ent_nd, g->ent_r, g->epos, (uint64_t)len};
+        // the last pass reads (nkey, nval) after an odd number of passes,
+        // else (k_alt, v_alt); the slots it writes go to the other value
+        // buffer, and the edge positions are then sorted through the two
+        // key buffers (8 bytes per entry each, both free by then)
+        const int node_passes = (std::max(bits_for(n - 1), 1) + 7) / 8;
+        char *k_read = reinterpret_cast<char *>(node_passes % 2 ? nkey : k_alt);
+        char *k_free = reinterpret_cast<char *>(node_passes % 2 ? k_alt : nkey);
+        uint32_t *slots = reinterpret_cast<uint32_t *>(node_passes % 2 ? (void *)v_alt : (void *)nval);
+        // an index that fits the last-level cache is scattered directly
+        const bool direct = len * sizeof(uint32_t) <= kDirectEposBytes && !g_force_edge_sort.load();
+        const SeqOut so{g->ent_c, g->ent_t, g->ent_nd, g->ent_r, direct ? g->epos : nullptr, slots,
+                        (uint64_t)len};
         TRY(radix_sort_nodes(nkey, k_alt, nval, v_alt, len, bits_for(n - 1), tmp, sort_err, s, so));
+        if (!direct) {
+            uint32_t *k0 = reinterpret_cast<uint32_t *>(k_read), *v0 = k0 + len;
+            uint32_t *k1 = reinterpret_cast<uint32_t *>(k_free), *v1 = k1 + len;
+            TRY(edge_positions(slots, len, k0, v0, k1, v1, tmp, sort_err, s, g->epos));
+        }
         TM_LAUNCH("offsets_fill", k_fill_u32, grid_for(n + 1), dim3(kBlock), 0, s, g->off, n + 1,
                   kUnset);
         TM_LAUNCH("offsets", k_offsets, grid_for(len + 1), dim3(kBlock), 0, s, g->ent_c, len,

@@ -120,7 +120,8 @@ __device__ inline void wave_lds_sync() {
 // Several windows at once (K nested deltas, ascending; one graph): every step
 // searches the same ring once per window, each search starting where the
 // previous (smaller) window ended, and writes Wf and Lf of window i at
-// offset i * len.  The bit planes describe the largest window.
+// p * K + i (an entry's K values side by side, so a reader of all of them
+// fetches one line).  The bit planes describe the largest window.
 constexpr uint32_t kRing = 2 * kWave;
 constexpr uint32_t kHubCap = 2048;  // window entries per LDS segment of the hub pass
 constexpr int kMaxLevels = 4;       // windows counted in one pass
@@ -196,12 +197,11 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                     if (lo == kRing - 1)  // the window may run past the ring
                         R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
                     W = (uint32_t)(R - qa);
-                    Wf[(uint64_t)i * len + qa] = W;
+                    Wf[qa * K + i] = W;
                     Rq = (uint32_t)R;
                 }
                 if (i == K - 1) Wtop = W;
                 if (Lf) {
-                    uint32_t *Lfi = Lf + (uint64_t)i * len;
                     const uint32_t nvalid = min<uint32_t>(kWave, w_e - base);
                     const uint32_t r_last = __shfl(Rq, (int)nvalid - 1, kWave);
                     wave_lds_sync();  // the previous window's reads of rend are done
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                                 if (rend[wv][mid] >= p) b = mid;
                                 else a = mid + 1;
                             }
-                            Lfi[p] = base + a;
+                            Lf[(uint64_t)p * K + i] = base + a;
                         }
                     }
                     p_next[i] = r_last + 1;
@@ -244,6 +244,11 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
 // Per element (edge of a multi-edge node pair) and side (center = smaller /
 // larger node): P_0, P_1 of S_c at the window end R and just before the
 // window start L:  w = (P_0(R), P_1(R), P_0(L-1), P_1(L-1)).
+// K windows in one pass (one graph when K > 1): window i's sizes and starts
+// are Wf[p * K + i] and Lf[p * K + i], and its rows of me_w start at
+// i * 2 * n_me.  An element's position, prefix counts and X at it are read
+// once for all windows.
+template <int K>
 __global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me_p,
                                                       const uint4 *me_a, const int64_t *me_t,
                                                       const uint32_t *Wf, const uint32_t *Lf,
@@ -252,35 +257,43 @@ __global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me
                                                       uint4 *me_w) {
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const Tile tl = tiles[ti];
-    const int64_t delta = deltas[tl.g];
+    int64_t delta[K];
+#pragma unroll
+    for (int lv = 0; lv < K; lv++) delta[lv] = deltas[(uint64_t)tl.g * K + lv];
     for (uint64_t i = tl.b + threadIdx.x; i < tl.e; i += blockDim.x) {
         const uint64_t k = i >> 1;
         const uint32_t side = (uint32_t)(i & 1);
-        const uint2 pp = me_p[k];
-        const uint4 aa = me_a[k];
-        const uint32_t p = side ? pp.y : pp.x;
-        const uint32_t a0 = side ? aa.z : aa.x, a1 = side ? aa.w : aa.y;
         const int64_t tp = me_t[k];
         // The sweeps read these only for an element whose pair has another
         // edge within delta after it (window end) or before it (window start);
         // that edge is then its neighbour in the element array.
-        const bool need_r = k + 1 < n_me && me_t[k + 1] - tp <= delta;
-        const bool need_l = k > 0 && tp - me_t[k - 1] <= delta;
-        if (!need_r && !need_l) continue;
+        const int64_t inf = (int64_t)1 << 62;
+        const int64_t dr = k + 1 < n_me ? me_t[k + 1] - tp : inf;
+        const int64_t dl = k > 0 ? tp - me_t[k - 1] : inf;
+        if (dr > delta[K - 1] && dl > delta[K - 1]) continue;
+        const uint2 pp = me_p[k];
+        const uint4 aa = me_a[k];
+        const uint32_t p = side ? pp.y : pp.x;
+        const uint32_t a0 = side ? aa.z : aa.x, a1 = side ? aa.w : aa.y;
         const uint32_t xp = S.X[p];
-        uint32_t rp0 = 0, rp1 = 0, lp0 = 0, lp1 = 0;
-        if (need_r) {
-            const uint32_t R = p + Wf[p];
-            rp1 = a1 + (S.X[R + 1] - xp);
-            rp0 = (a0 + a1) + (R - p) + 1 - rp1;
+        const uint32_t seg_lo = p - (a0 + a1);
+#pragma unroll
+        for (int lv = 0; lv < K; lv++) {
+            const bool need_r = dr <= delta[lv], need_l = dl <= delta[lv];
+            if (!need_r && !need_l) continue;
+            uint32_t rp0 = 0, rp1 = 0, lp0 = 0, lp1 = 0;
+            if (need_r) {
+                const uint32_t R = p + Wf[(uint64_t)p * K + lv];
+                rp1 = a1 + (S.X[R + 1] - xp);
+                rp0 = (a0 + a1) + (R - p) + 1 - rp1;
+            }
+            if (need_l) {
+                const uint32_t L = Lf[(uint64_t)p * K + lv];  // first entry of S_c with t >= tp - delta
+                lp1 = a1 - (xp - S.X[L]);
+                lp0 = (L - seg_lo) - lp1;
+            }
+            me_w[(uint64_t)lv * 2 * n_me + i] = make_uint4(rp0, rp1, lp0, lp1);
         }
-        if (need_l) {
-            const uint32_t seg_lo = p - (a0 + a1);
-            const uint32_t L = Lf[p];  // first entry of S_c with t >= tp - delta
-            lp1 = a1 - (xp - S.X[L]);
-            lp0 = (L - seg_lo) - lp1;
-        }
-        me_w[i] = make_uint4(rp0, rp1, lp0, lp1);
     }
   }
 }
@@ -703,13 +716,14 @@ __global__ void k_tri_flags(const uint2 *epos2, const uint64_t *bits, const uint
     }
 }
 
-__global__ void k_tri_compact(const uint2 *epos2, const uint32_t *Wf, const uint32_t *flag,
-                              const uint32_t *idx, uint64_t m, uint4 *cand) {
+// Wf: the window sizes to record, entry p's at Wf[p * stride].
+__global__ void k_tri_compact(const uint2 *epos2, const uint32_t *Wf, uint32_t stride,
+                              const uint32_t *flag, const uint32_t *idx, uint64_t m, uint4 *cand) {
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (uint64_t)gridDim.x * blockDim.x) {
         if (!flag[r]) continue;
         const uint2 e = epos2[r];
-        cand[idx[r]] = make_uint4(e.x, e.y, Wf[e.x], Wf[e.y]);
+        cand[idx[r]] = make_uint4(e.x, e.y, Wf[(uint64_t)e.x * stride], Wf[(uint64_t)e.y * stride]);
     }
 }
 
@@ -730,15 +744,15 @@ __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint
 // windows from index `level` up, where `level` = the number of smaller
 // windows that miss one of them.  oa, ob: the later edges' offsets after
 // the first edge's entries ps (at its source) and pd (at its destination);
-// Wf holds the window sizes of window i at offset i * len.  Matches are
-// rare next to the comparisons, so the sizes are read here, on a match.
+// Wf holds the size of window i at entry p at p * K + i.  Matches are rare
+// next to the comparisons, so the sizes are read here, on a match.
 template <int K>
-__device__ inline uint32_t tri_level(const uint32_t *Wf, uint64_t len, uint32_t ps, uint32_t oa,
-                                     uint32_t pd, uint32_t ob) {
+__device__ inline uint32_t tri_level(const uint32_t *Wf, uint32_t ps, uint32_t oa, uint32_t pd,
+                                     uint32_t ob) {
     uint32_t l = 0;
 #pragma unroll
     for (int i = 0; i + 1 < K; i++)
-        l += (oa > Wf[(uint64_t)i * len + ps] || ob > Wf[(uint64_t)i * len + pd]) ? 1u : 0u;
+        l += (oa > Wf[(uint64_t)ps * K + i] || ob > Wf[(uint64_t)pd * K + i]) ? 1u : 0u;
     return l;
 }
 
@@ -755,16 +769,15 @@ constexpr uint32_t kHashChunk = 256;
 constexpr uint32_t kEmptyKey = 0xffffffffu;  // node ids are below 2^31
 constexpr uint32_t kHashMul = 2654435761u;   // Knuth's multiplicative constant
 
-// K windows: the candidates and their windows are those of the largest one
-// (Wf at offset (K - 1) * len), each match is filed under its level, and
-// level l's rows go to partial + l * lvl_stride.
+// K windows: the candidates and their windows are those of the largest one,
+// each match is filed under its level (Wf: window i of entry p at p * K +
+// i), and level l's rows go to partial + l * lvl_stride.
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
                                                       const uint32_t *tidx, const uint32_t *eoff,
                                                       const uint32_t *ctfirst, uint32_t G,
                                                       uint32_t lane_max, const uint32_t *Wf,
-                                                      uint64_t len, uint64_t lvl_stride,
-                                                      uint64_t *partial) {
+                                                      uint64_t lvl_stride, uint64_t *partial) {
   const uint32_t n_tiles = ctfirst[G];
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t wv = threadIdx.x / kWave;
@@ -814,8 +827,8 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                             const uint32_t cls = s_reg ? tri_class(rr[k], rn[k] & 1u, rb, ndb & 1u)
                                                        : tri_class(rb, ndb & 1u, rr[k], rn[k] & 1u);
                             const uint32_t oreg = (uint32_t)k + 1, ostr = b - lp;
-                            const uint32_t l = s_reg ? tri_level<K>(Wf, len, ps, oreg, pd, ostr)
-                                                     : tri_level<K>(Wf, len, ps, ostr, pd, oreg);
+                            const uint32_t l = s_reg ? tri_level<K>(Wf, ps, oreg, pd, ostr)
+                                                     : tri_level<K>(Wf, ps, ostr, pd, oreg);
                             tri_add(T, l * 8 + cls);
                         }
                     }
@@ -828,7 +841,7 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                         const uint32_t ndb = S.nd[b];
                         if ((ndb >> 1) == (nda >> 1)) {
                             const uint32_t cls = tri_class(ra, nda & 1u, S.rk[b], ndb & 1u);
-                            tri_add(T, tri_level<K>(Wf, len, ps, a - ps, pd, b - pd) * 8 + cls);
+                            tri_add(T, tri_level<K>(Wf, ps, a - ps, pd, b - pd) * 8 + cls);
                         }
                     }
                 }
@@ -882,8 +895,8 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                                 uint32_t l = 0;
                                 if (K > 1) {
                                     const uint32_t oo = hpos[wv][h] - o_base, oi = x - i_base;
-                                    l = s_outer ? tri_level<K>(Wf, len, bps, oo, bpd, oi)
-                                                : tri_level<K>(Wf, len, bps, oi, bpd, oo);
+                                    l = s_outer ? tri_level<K>(Wf, bps, oo, bpd, oi)
+                                                : tri_level<K>(Wf, bps, oi, bpd, oo);
                                 }
                                 tri_add(T, l * 8 + cls);
                             }
@@ -912,8 +925,8 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                             const uint32_t cls = s_outer ? tri_class(ro, ndo & 1u, rx, ndx & 1u)
                                                          : tri_class(rx, ndx & 1u, ro, ndo & 1u);
                             const uint32_t oo = ob + k - o_base, oi = x - i_base;
-                            const uint32_t l = s_outer ? tri_level<K>(Wf, len, bps, oo, bpd, oi)
-                                                       : tri_level<K>(Wf, len, bps, oi, bpd, oo);
+                            const uint32_t l = s_outer ? tri_level<K>(Wf, bps, oo, bpd, oi)
+                                                       : tri_level<K>(Wf, bps, oi, bpd, oo);
                             tri_add(T, l * 8 + cls);
                         }
                     }
@@ -1008,8 +1021,7 @@ constexpr uint64_t kLow48 = (1ull << 48) - 1;
 struct HubArgs {
     SeqView S;
     const uint2 *epos2;
-    const uint32_t *Wf;  // window sizes; the largest window's at offset (K - 1) * len
-    uint64_t len;
+    const uint32_t *Wf;  // window sizes: window i of entry p at p * K + i
     const uint64_t *lev;
     const uint32_t *eoff, *htfirst, *count, *list;
     uint32_t G, hub_min;
@@ -1048,7 +1060,7 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             s_hi = 0;
         }
         // A. owners among this thread's positions
-        const uint32_t *Wtop = a.Wf + (uint64_t)(K - 1) * a.len;
+        const uint32_t *Wtop = a.Wf + (K - 1);  // window K - 1 of entry p at p * K
         uint32_t own = 0, rp[kHubPer], rw[kHubPer], rq[kHubPer], rwo[kHubPer];
 #pragma unroll
         for (uint32_t k = 0; k < kHubPer; k++) {
@@ -1056,11 +1068,11 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             rp[k] = p;
             rw[k] = rq[k] = rwo[k] = 0;
             if (p < s1 && ((hub_word(a.lev, p / kWave, hub_first) >> (p % kWave)) & 1ull)) {
-                const uint32_t W = Wtop[p];
+                const uint32_t W = Wtop[(uint64_t)p * K];
                 const uint2 e = a.epos2[S.rk[p]];
                 const bool is_s = e.x == p;
                 const uint32_t q = is_s ? e.y : e.x;
-                const uint32_t Wo = Wtop[q];
+                const uint32_t Wo = Wtop[(uint64_t)q * K];
                 if (Wo != 0 && Wo < kHubCap && (is_s ? W >= Wo : W > Wo)) {
                     own |= 1u << k;
                     rw[k] = W | (is_s ? 0x80000000u : 0u);
@@ -1202,8 +1214,8 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
                                     const uint32_t cls = own_s ? tri_class(v >> 1, v & 1u, rx[u], nd[u] & 1u)
                                                                : tri_class(rx[u], nd[u] & 1u, v >> 1, v & 1u);
                                     const uint32_t l =
-                                        own_s ? tri_level<K>(a.Wf, a.len, p, y - p, qq[u], ox[u])
-                                              : tri_level<K>(a.Wf, a.len, qq[u], ox[u], p, y - p);
+                                        own_s ? tri_level<K>(a.Wf, p, y - p, qq[u], ox[u])
+                                              : tri_level<K>(a.Wf, qq[u], ox[u], p, y - p);
                                     tri_add(red[wv], l * 8 + cls);
                                 }
                             }
@@ -1329,9 +1341,9 @@ constexpr uint32_t kDefaultHubMin = 32;
 struct Workspace {
     uint32_t K = 1;  // windows counted in one pass (one graph when K > 1)
     int64_t *deltas;
-    uint32_t *Wf, *Lf;  // window i at offset i * 2m
+    uint32_t *Wf, *Lf;  // window i of entry p at p * K + i
     uint64_t *wbits, *lev;
-    uint4 *me_w;        // window i at offset i * 2 * n_me
+    uint4 *me_w;        // window i's rows at offset i * 2 * n_me
     uint32_t *cnt, *first, *ipair, *tflag, *tidx;
     uint4 *cand;
     uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
@@ -1419,7 +1431,7 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     const bool do_tri = (families & TM_TRIANGLES) != 0;
     const bool do_hub = do_tri && pr.hub_min != TM_HUB_OFF;
     const uint64_t nm = do_sp ? g->n_multi : 0;
-    const uint32_t *Wtop = w.Wf + (uint64_t)(K - 1) * len;
+    const uint32_t *Wtop = w.Wf + (K - 1);  // entry p's largest window at Wtop[p * K]
     const uint64_t t_stride = w.max_ctiles * kTriRowsPerTile * 8, h_stride = w.max_htiles * 8;
     const uint64_t s_stride = w.max_itiles * 32;
     int rc;
@@ -1435,10 +1447,10 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     // ---- star / pair: work items (pair, chunk); window i reads its own
     // sizes and deltas (K > 1 only for one graph, whose delta i is deltas[i])
     if (nm) {
-        for (uint32_t i = 0; i < K; i++)
-            TM_LAUNCH("star_prep", k_star_prep, dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)),
-                      dim3(kBlock), 0, s, S, g->me_p, g->me_a, g->me_t, w.Wf + i * len, w.Lf + i * len,
-                      nme, g->t_elems, g->n_t_elems, w.deltas + i, w.me_w + i * 2 * nme);
+        TM_LAUNCH_K("star_prep", k_star_prep, K,
+                    dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)), dim3(kBlock), 0, s, S,
+                    g->me_p, g->me_a, g->me_t, w.Wf, w.Lf, nme, g->t_elems, g->n_t_elems, w.deltas,
+                    w.me_w);
         ProfRow row_a6("a6");
         TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
                   nm, run_chunk, w.cnt);
@@ -1451,15 +1463,15 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     // ---- triangles: candidate first edges (of the largest window)
     if (do_tri) {
         ProfRow row_a5("a5");
-        if (!fused_levels)
-            TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, Wtop, 2 * m,
+        if (!fused_levels)  // batches: K == 1
+            TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m,
                       pr.hub_min, w.wbits, w.lev);
         TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
                   reinterpret_cast<const uint2 *>(g->epos), w.wbits, w.lev, pr.hub_min, m, w.tflag);
         rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
         if (rc) return rc;
         TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
-                  reinterpret_cast<const uint2 *>(g->epos), Wtop, w.tflag, w.tidx, m, w.cand);
+                  reinterpret_cast<const uint2 *>(g->epos), Wtop, K, w.tflag, w.tidx, m, w.cand);
     }
     // ---- per-graph work tiles
     {
@@ -1493,11 +1505,11 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
         ProfRow row_a5("a5");
         TM_LAUNCH_K("triangles", k_triangles, K, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
                     dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max,
-                    w.Wf, len, t_stride, w.tpart);
+                    w.Wf, t_stride, w.tpart);
     }
     if (do_hub) {
         ProfRow row_a5("a5");
-        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, len, w.lev, g->d_eoff,
+        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.lev, g->d_eoff,
                    w.htfirst, w.hcount, w.hlist, G, pr.hub_min, h_stride};
         TM_LAUNCH_K("tri_hub", k_tri_hub, K, dim3((unsigned)std::min<uint64_t>(w.max_htiles, 4096)),
                     dim3(kHubBlock), 0, s, ha, w.hpart);

@@ -276,7 +276,7 @@ constexpr uint32_t kHistBlocks = 512;
 constexpr uint32_t kHistSumSplit = 16;
 
 template <typename K, typename In>
-__global__ void __launch_bounds__(kOsThreads) k_os_hist(In in, uint64_t n, int passes,
+__global__ void __launch_bounds__(kOsThreads) k_os_hist(In in, uint64_t n, int passes, int shift0,
                                                         uint32_t *part) {
     __shared__ uint32_t h[kMaxPasses][256];
     for (int i = threadIdx.x; i < kMaxPasses * 256; i += kOsThreads) (&h[0][0])[i] = 0;
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(kOsThreads) k_os_hist(In in, uint64_t n, int p
         for (int i = 0; i < kHistItems; i++) {
             if (base + (uint64_t)i * kOsThreads + threadIdx.x < n) {
                 for (int p = 0; p < passes; p++)
-                    atomicAdd(&h[p][(uint32_t)(key[i] >> (8 * p)) & 255u], 1u);
+                    atomicAdd(&h[p][(uint32_t)(key[i] >> (shift0 + 8 * p)) & 255u], 1u);
             }
         }
     }
@@ -329,9 +329,24 @@ struct SeqWrite {
         o.ent_t[pos] = v.t;
         o.ent_nd[pos] = v.nd;
         o.ent_r[pos] = v.r;
-        const uint64_t slot = 2 * (uint64_t)v.r + (v.nd & 1u);
-        // a slot outside [0, n) only after an abandoned look-back (flagged)
-        if (slot < o.n) o.epos[slot] = pos;
+        // the entry's slot: 2r at the source, 2r + 1 at the destination
+        const uint32_t slot = 2 * v.r + (v.nd & 1u);
+        if (o.epos) {
+            // a slot outside [0, n) only after an abandoned look-back (flagged)
+            if (slot < o.n) o.epos[slot] = pos;
+        } else {
+            o.slot[pos] = slot;  // in entry order, for edge_positions
+        }
+    }
+};
+
+// Slots in entry order as sort input: key = slot, value = its position.
+struct SlotIn {
+    const uint32_t *slot;
+    __device__ inline uint32_t key(uint64_t i) const { return slot[i]; }
+    __device__ inline void load(uint64_t i, uint32_t &key, uint32_t &val) const {
+        key = slot[i];
+        val = (uint32_t)i;
     }
 };
 
@@ -514,15 +529,16 @@ inline OsTmp os_tmp(void *tmp, uint64_t ntiles) {
 
 // In0: where the histogram and the first pass read the elements (the later
 // passes read the ping-pong buffers *keys / *vals).
+// Sorts on key bits [shift0, bits).
 template <typename K, typename V, typename Final, typename In0>
 int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,
                uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name,
-               const Final *fin, const In0 &in0) {
+               const Final *fin, const In0 &in0, int shift0 = 0) {
     constexpr int kItems_ = os_items<K, V>();
     constexpr int kThr = os_threads<K, V>();
     constexpr uint64_t kT = (uint64_t)kThr * kItems_;
-    const int passes = (bits + 7) / 8;
-    if (passes > kMaxPasses || (uint64_t)passes * 8 > sizeof(K) * 8) {
+    const int passes = (bits - shift0 + 7) / 8;
+    if (passes < 1 || passes > kMaxPasses || shift0 + 8 * (passes - 1) >= (int)sizeof(K) * 8) {
         set_error("radix sort: key bits out of range");
         return TM_EINTERNAL;
     }
@@ -534,7 +550,7 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
     const uint64_t hchunk = (uint64_t)kOsThreads * kHistItems;
     const uint32_t hblocks = (uint32_t)std::min<uint64_t>((n + hchunk - 1) / hchunk, kHistBlocks);
     TM_LAUNCH(hist_name, (k_os_hist<K, In0>), dim3(hblocks), dim3(kOsThreads), 0, s, in0, n, passes,
-              t.part);
+              shift0, t.part);
     TM_LAUNCH("sort_hist_sum", k_os_hist_sum, dim3((unsigned)passes, kHistSumSplit), dim3(256), 0, s,
               t.part, hblocks, passes, t.ghist);
     const uint32_t spin = lookback_spin_limit();
@@ -547,22 +563,22 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
         const bool last = fin && p + 1 == passes;
         if (p == 0 && last) {
             TM_LAUNCH(last_name.c_str(), (k_os_scatter<K, V, In0, Final, kThr, kItems_>),
-                      dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, *fin, n, 8 * p,
+                      dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, *fin, n, shift0 + 8 * p,
                       t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
         } else if (last) {
             TM_LAUNCH(last_name.c_str(), (k_os_scatter<K, V, ArrayIn<K, V>, Final, kThr, kItems_>),
-                      dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, *fin, n, 8 * p,
+                      dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, *fin, n, shift0 + 8 * p,
                       t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
         } else {
             const PairOut<K, V> po{*keys_alt, *vals_alt};
             if (p == 0)
                 TM_LAUNCH(scatter_name, (k_os_scatter<K, V, In0, PairOut<K, V>, kThr, kItems_>),
-                          dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, po, n, 8 * p,
+                          dim3((unsigned)ntiles), dim3(kThr), 0, s, in0, po, n, shift0 + 8 * p,
                           t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
             else
                 TM_LAUNCH(scatter_name,
                           (k_os_scatter<K, V, ArrayIn<K, V>, PairOut<K, V>, kThr, kItems_>),
-                          dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, po, n, 8 * p,
+                          dim3((unsigned)ntiles), dim3(kThr), 0, s, arr, po, n, shift0 + 8 * p,
                           t.ghist + 256 * p, st, st_next, t.tickets + p, err, spin);
             std::swap(*keys, *keys_alt);
             std::swap(*vals, *vals_alt);
@@ -643,6 +659,56 @@ int radix_sort_time_direct_u64(const int32_t *src, const int32_t *dst, const int
                                uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
                                RankOut ro) {
     return time_direct<uint64_t>(src, dst, t, keys, keys_alt, vals, vals_alt, n, bits, tmp, err, s, ro);
+}
+
+// ------------------------------------------------------- edge positions
+// epos[slot] = the entry position of slot (2r at the source of edge rank r,
+// 2r + 1 at its destination): the inverse of the node sort's permutation.
+// Written directly it is one random 4-byte write per entry, which costs a
+// partial-line write each once the index outgrows the last-level cache.
+// Instead, (slot, position) pairs in entry order are partitioned by the
+// slot's bits above kSlotBucketBits (stable radix passes, coalesced
+// writes), and then each block fills one bucket of 2^kSlotBucketBits
+// slots: slots are a permutation of [0, n), so bucket b is exactly sorted
+// positions [b * 2^kSlotBucketBits, ...); the block places them in LDS by
+// their low bits and writes the bucket out in order.
+constexpr int kSlotBucketBits = 14;
+constexpr uint32_t kSlotBucket = 1u << kSlotBucketBits;
+
+// key: slots; val: their positions (null: position = index, the unsorted case).
+__global__ void __launch_bounds__(1024) k_epos_fill(const uint32_t *key, const uint32_t *val,
+                                                    uint64_t n, uint32_t *epos) {
+    __shared__ uint32_t buf[kSlotBucket];
+    for (uint64_t b = blockIdx.x; b * kSlotBucket < n; b += gridDim.x) {
+        const uint64_t lo = b * kSlotBucket;
+        const uint32_t cnt = (uint32_t)min<uint64_t>(kSlotBucket, n - lo);
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x)
+            buf[key[lo + i] & (kSlotBucket - 1)] = val ? val[lo + i] : (uint32_t)(lo + i);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) epos[lo + i] = buf[i];
+        __syncthreads();
+    }
+}
+
+int edge_positions(const uint32_t *slot, uint64_t n, uint32_t *k0, uint32_t *v0, uint32_t *k1,
+                   uint32_t *v1, void *tmp, uint32_t *err, hipStream_t s, uint32_t *epos) {
+    if (n == 0) return TM_OK;
+    int bits = 0;
+    while (bits < 32 && ((n - 1) >> bits) != 0) bits++;
+    const uint32_t *key = slot, *val = nullptr;
+    if (bits > kSlotBucketBits) {
+        uint32_t *keys = k0, *keys_alt = k1, *vals = v0, *vals_alt = v1;
+        const SlotIn in0{slot};
+        const int rc = radix_impl<uint32_t, uint32_t, PairOut<uint32_t, uint32_t>>(
+            &keys, &keys_alt, &vals, &vals_alt, n, bits, tmp, err, s, "sort_slot_hist",
+            "sort_slot_scatter", nullptr, in0, kSlotBucketBits);
+        if (rc) return rc;
+        key = keys;
+        val = vals;
+    }
+    const uint64_t nb = std::min<uint64_t>((n + kSlotBucket - 1) / kSlotBucket, 8192);
+    TM_LAUNCH("epos_fill", k_epos_fill, dim3((unsigned)nb), dim3(1024), 0, s, key, val, n, epos);
+    return TM_OK;
 }
 
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,

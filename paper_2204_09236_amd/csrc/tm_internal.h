@@ -100,6 +100,8 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
 size_t radix_tmp_bytes(uint64_t n);
 // Failure-path testing: make every later look-back wait give up at once.
 void set_lookback_giveup(bool on);
+// Testing: build every edge-position index by edge_positions, whatever its size.
+void set_force_edge_sort(bool on);
 // A range [b, e) of work items that all belong to graph g of a batch.
 struct Tile {
     uint32_t g, b, e;
@@ -118,13 +120,17 @@ struct NodeVal {
 };
 
 // Where the node sort's last pass writes: the sequence arrays S_u directly,
-// plus each edge's two positions (epos[2r + dir]).
+// plus either each edge's two positions (epos[2r + dir], a random write per
+// entry: used while epos fits the last-level cache) or, with epos null,
+// each entry's slot 2r + dir in entry order, from which edge_positions
+// builds epos.
 struct SeqOut {
     uint32_t *ent_c;
     int64_t *ent_t;
     uint32_t *ent_nd;
     uint32_t *ent_r;
     uint32_t *epos;
+    uint32_t *slot;
     uint64_t n;  // entries (epos slots)
 };
 
@@ -167,6 +173,11 @@ int radix_sort_time_direct_u64(const int32_t *src, const int32_t *dst, const int
                                uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
                                uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
                                RankOut out);
+// epos[slot] = position of slot, from the slots in entry order (a
+// permutation of [0, n)); k0, v0, k1, v1: n words each of scratch, none of
+// them aliasing slot; tmp as for the radix sorts.
+int edge_positions(const uint32_t *slot, uint64_t n, uint32_t *k0, uint32_t *v0, uint32_t *k1,
+                   uint32_t *v1, void *tmp, uint32_t *err, hipStream_t s, uint32_t *epos);
 // Node sort: (node, NodeVal) pairs on bits [0, bits); the last pass writes
 // SeqOut instead of the ping-pong buffers (at least one pass always runs).
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,

@@ -109,6 +109,8 @@ def _load():
     lib.tm_count_noalloc.restype = ctypes.c_int
     lib.tm_debug_alloc_calls.argtypes = []
     lib.tm_debug_alloc_calls.restype = ctypes.c_uint64
+    lib.tm_debug_force_edge_sort.argtypes = [ctypes.c_int]
+    lib.tm_debug_force_edge_sort.restype = None
     lib.tm_debug_lookback_giveup.argtypes = [ctypes.c_int]
     lib.tm_debug_lookback_giveup.restype = None
     return lib
@@ -507,6 +509,12 @@ def prof_read() -> dict:
 def debug_alloc_calls() -> int:
     """Device allocations the library has served so far (cache hits included)."""
     return int(_lib.tm_debug_alloc_calls())
+
+
+def debug_force_edge_sort(on: bool) -> None:
+    """Testing: every later build makes its edge-position index by the
+    partition and bucket fill, whatever its size."""
+    _lib.tm_debug_force_edge_sort(1 if on else 0)
 
 
 def debug_lookback_giveup(on: bool) -> None:

@@ -235,6 +235,34 @@ def test_lookback_giveup_fails_cleanly(tm):
         np.testing.assert_array_equal(G.count_raw(3600), oracle.alg(g.src, g.dst, g.t, 3600, n=g.n))
 
 
+@pytest.mark.parametrize("m", [12, 9000, 200_000, 2_500_000])
+def test_edge_index_by_partition(tm, m):
+    """Each edge's two positions built by the partition of (slot, position)
+    pairs and the bucket fill (taken by graphs whose index outgrows the
+    last-level cache), forced at small sizes: no sort pass (under 2^14
+    slots), one pass, two passes; ragged last buckets."""
+    if m == 12:
+        src, dst, t = load_toy()
+        n = 5
+    else:
+        g = graphgen.chung_lu_pareto(40 + m % 97, max(3, m // 20), m)
+        src, dst, t, n = g.src, g.dst, g.t, g.n
+    tm.debug_force_edge_sort(True)
+    try:
+        check(tm, src, dst, t, [0, 3600, 86400] if m > 12 else [10], n=n, label=f"edge index m={m}")
+        if m == 200_000:
+            case("edge index with forced look-back give-up")
+            tm.debug_lookback_giveup(True)
+            try:
+                with pytest.raises(tm.TMError) as ei:
+                    tm.build_graph(src, dst, t, n=n)
+                assert ei.value.code == -6
+            finally:
+                tm.debug_lookback_giveup(False)
+    finally:
+        tm.debug_force_edge_sort(False)
+
+
 def test_repeatable(tm):
     rng = np.random.default_rng(71)
     g = graphgen.small_random(rng, 300, 50000, t_values=5000, tmax=200000, multi=0.3)
