@@ -300,7 +300,8 @@ int tm_prof_read(int i, char *name, int name_cap, uint64_t *launches, double *to
  *   the budget completes with TM_ENOMEM; an invalid edge list completes with
  *   TM_EINVAL without affecting other requests.
  * tm_poll: TM_EAGAIN while pending; otherwise the request's final status
- *   (TM_OK: out holds the 36 counts) and the ticket is released.
+ *   (TM_OK: out holds the 36 counts) and the ticket is released; for a
+ *   failed request, tm_last_error then gives its message.
  *   times_ns (optional): submit, start (admitted), done, steady-clock ns.
  * tm_wait: as tm_poll but blocks up to timeout_ms.
  * tm_server_stats: [queued, in flight, resident graphs, resident bytes,

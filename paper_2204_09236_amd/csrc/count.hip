@@ -1630,6 +1630,16 @@ void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw) {
 // Asynchronous count through the graph's captured plan: deltas are read from
 // pinned host memory, the G x 40 counters land in pinned host memory, and
 // `done` is recorded after the copy.  Returns without waiting.
+// Capture the count plan count_graph_async will replay (for all motifs,
+// with the graph's resolved partition parameters), so that the capture can
+// run on a thread of the caller's choosing.
+int count_plan_prepare(tm_graph *g) {
+    if (g->m < 3) return TM_OK;
+    Params pr;
+    resolve_params(g, &pr);
+    return plan_prepare(g, pr, TM_ALL_MOTIFS);
+}
+
 int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,
                       hipEvent_t done) {
     const uint32_t G = g->G;

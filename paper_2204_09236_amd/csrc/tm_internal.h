@@ -22,6 +22,8 @@ constexpr uint32_t kOrientBit = 0x80000000u;  // pair-list element: src is the s
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string &msg);
+// This thread's last error message.
+const std::string &last_error();
 
 #define TM_HIP_TRY(expr)                                                              \
     do {                                                                              \
@@ -276,6 +278,8 @@ void plan_release(tm_graph *g);
 void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw);
 int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,
                       hipEvent_t done);
+// Capture the plan count_graph_async replays (no-op when it is current).
+int count_plan_prepare(tm_graph *g);
 // Device bytes held by a graph (its buffers; not the per-count workspace).
 size_t graph_bytes(const tm_graph *g);
 // Device bytes one count of g needs for its workspace.

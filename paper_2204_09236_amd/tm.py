@@ -506,6 +506,12 @@ def prof_read() -> dict:
     return out
 
 
+def last_error() -> str:
+    """This thread's last error message from the library (for a failed
+    request: the message of the call that failed it)."""
+    return (_lib.tm_last_error() or b"").decode()
+
+
 def debug_alloc_calls() -> int:
     """Device allocations the library has served so far (cache hits included)."""
     return int(_lib.tm_debug_alloc_calls())

@@ -61,7 +61,7 @@ def test_server_mix_equals_alone(tm):
         results = []
         for tk in tickets:
             rc, out, times = S.wait(tk)
-            assert rc == 0, rc
+            assert rc == 0, (rc, tm.last_error())
             assert times[0] <= times[1] <= times[2]
             results.append(out)
         st = S.stats()
