@@ -186,7 +186,7 @@ def row_bytes(m: int, n: int, pairs: int, wstats: dict, deltas: list[int]) -> di
             "a4": 40 * m * len(deltas), "a5": a5}
 
 
-def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dict:
+def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels: int = 1) -> dict:
     """Bytes each kernel's access pattern moves per launch (reads + writes of
     the data it touches, each byte once): the weights that split a row's
     algorithmic bytes over its kernels.  m edges, 2m incident entries, n
@@ -230,12 +230,13 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict) -> dic
         "sort_pair_scatter": m * (8 + 4) * 2,
         "multi_flags": m * (8 + 8),
         "multi_fill": m * 28 + me * (32 + 33) + nm * 12,
-        # keys read, window ends and starts written; one graph: the three
-        # window bit planes too
-        "windows": e2 * 20 + (n + 1) * 4 + e2 / 8 + e2 / 4,
-        # per element its record, per side X at p, R + 1 and L, Wf, Lf, result
-        "star_prep": me * 32 + 2 * me * 36,
-        "star_pair": me * 25 + 2 * me * 16,
+        # keys read; per window the sizes (4 B) and, for non-empty windows,
+        # the two star/pair records (8 B each, with X read next to the entry;
+        # counted here as one); one graph: the three window bit planes too
+        "windows": e2 * (12 + 12 * levels) + (n + 1) * 4 + e2 / 8 + e2 / 4,
+        # per element its record; per side its position and the two window
+        # records of its entry
+        "star_pair": me * 25 + 2 * me * 24,
         "wlevels": e2 * 4 + e2 / 8 + e2 / 4,
         "tri_flags": m * (8 + 4) + e2 / 8,
         "hub_tiles": e2 / 4 + e2 / HUB_SLICE * 64,
@@ -513,10 +514,11 @@ def run_single(args, workload: str, full: bool = True) -> dict:
     torch.cuda.empty_cache()
     rows_alg = row_bytes(g.m, g.n, pairs, wstats, deltas)
     # count kernels run once per delta: the model averages their bytes over deltas
-    model = byte_model(g.m, g.n, info, None, passes)
+    levels = len(deltas) if multi else 1
+    model = byte_model(g.m, g.n, info, None, passes, levels)
     tri = {"tri_compact": 0.0, "triangles": 0.0, "tri_hub": 0.0}
     for d in deltas:
-        md = byte_model(g.m, g.n, info, wstats[str(d)], passes)
+        md = byte_model(g.m, g.n, info, wstats[str(d)], passes, levels)
         for k in tri:
             tri[k] += md[k] / len(deltas)
     model.update(tri)
@@ -735,6 +737,15 @@ def bench_batch(args):
     torch.cuda.synchronize()
     el_count = (time.perf_counter() - t_s) / args.steps
     B.free()
+    # one more batched step with every launch traced: the per-kernel table
+    tm.prof_reset()
+    tm.prof_enable(True)
+    batched()
+    torch.cuda.synchronize()
+    tm.prof_enable(False)
+    prof = tm.prof_read()
+    kernels = {k: {"launches": v[0], "total_ms": round(v[1], 4)}
+               for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:25]}
 
     def per_graph():
         outs = []
@@ -775,6 +786,7 @@ def bench_batch(args):
         "batched_over_per_graph": round(el_p / el_b, 2),
         "identical_counts": same, "golden": golden,
         "motif_total": int(res_p.sum()),
+        "kernels_one_step": kernels,
     }
     print(json.dumps(line))
     if not same or (golden is not None and not golden["match"]):

@@ -108,20 +108,27 @@ __device__ inline void wave_lds_sync() {
 // of 64, so each step covers one 64-entry word) the step also writes the
 // window bit planes that k_wlevels would write.
 //
-// With `Lf` non-null it also writes each entry's window start,
-// Lf[p] = L(p) = the first entry of S_u with t >= t_p - delta.  R(q) = q +
-// Wf[q] never decreases along the whole array and never leaves q's S_u, so
-// L(p) = min{q : R(q) >= p}: the entries p in (R(q - 1), R(q)] start their
-// windows at q.  A step owns the entries in (R(base - 1), R(base + 63)]; its
-// lanes write them in coalesced rounds of 64, each finding its q by
-// bisection over the step's 64 window ends kept in LDS.  A wave span finds
-// R of the entry before it with one gallop.
+// With `recR` / `recL` non-null (stars or pairs are counted) it also
+// writes, per entry p, what the star/pair sweeps need about p's window in
+// S_u: recR[p] = (W(p), number of dir-in entries in [p, R(p)]) and recL[p]
+// = (p - L(p), number of dir-in entries in [L(p), p)), where L(p) = the
+// first entry of S_u with t >= t_p - delta.  A record is written only when
+// its window is not empty: the sweeps read it only for an element with
+// another edge of its pair inside that window.  R(q) = q + Wf[q] never
+// decreases along the whole array and never leaves q's S_u, so L(p) =
+// min{q : R(q) >= p}: the entries p in (R(q - 1), R(q)] start their windows
+// at q.  A step owns the entries in (R(base - 1), R(base + 63)]; its lanes
+// write them in coalesced rounds of 64, each finding its q by bisection over
+// the step's 64 window ends kept in LDS.  A wave span finds R of the entry
+// before it with one gallop.  The direction prefix X is read next to p, R
+// and L, which the wave walks in order, so these reads stay in cache; the
+// sweeps then read one record per element instead of gathering X around
+// each element's position.
 //
 // Several windows at once (K nested deltas, ascending; one graph): every step
 // searches the same ring once per window, each search starting where the
-// previous (smaller) window ended, and writes Wf and Lf of window i at
-// p * K + i (an entry's K values side by side, so a reader of all of them
-// fetches one line).  The bit planes describe the largest window.
+// previous (smaller) window ended, and writes Wf, recR and recL of window i
+// at p * K + i.  The bit planes describe the largest window.
 constexpr uint32_t kRing = 2 * kWave;
 constexpr uint32_t kHubCap = 2048;  // window entries per LDS segment of the hub pass
 constexpr int kMaxLevels = 4;       // windows counted in one pass
@@ -130,7 +137,7 @@ template <int K>
 __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
                                                     uint64_t len, const int64_t *deltas,
                                                     uint32_t *Wf, uint32_t hub_min, uint64_t *bits,
-                                                    uint64_t *lev, uint32_t *Lf) {
+                                                    uint64_t *lev, uint2 *recR, uint2 *recL) {
     // key j of the ring: (center, unused, t low, t high)
     __shared__ uint4 ring[kBlock / kWave][kRing];
     __shared__ uint32_t rend[kBlock / kWave][kWave];  // the step's window ends R
@@ -156,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
 #pragma unroll
         for (int i = 0; i < K; i++) {
             p_next[i] = w_b;
-            if (Lf && w_b > 0) {
+            if (recL && w_b > 0) {
                 const uint32_t q0 = w_b - 1, c0 = S.c[q0];
                 if (c0 == S.c[w_b])
                     p_next[i] = window_end(S.t, q0, S.off[c0 + 1], S.t[q0] + delta[i]) + 1;
@@ -173,6 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
             const uint32_t ca = me.x;
             const int64_t tme = (int64_t)(((uint64_t)me.w << 32) | me.z);
             const uint64_t qa = (uint64_t)base + lane;
+            const uint32_t xq = recR && qa < w_e ? S.X[qa] : 0u;
             uint32_t Wtop = 0;
             uint32_t lo = (uint32_t)lane;  // a window contains the previous (smaller) one
 #pragma unroll
@@ -199,9 +207,11 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                     W = (uint32_t)(R - qa);
                     Wf[qa * K + i] = W;
                     Rq = (uint32_t)R;
+                    // only read for a non-empty window
+                    if (recR && W) recR[qa * K + i] = make_uint2(W, S.X[R + 1] - xq);
                 }
                 if (i == K - 1) Wtop = W;
-                if (Lf) {
+                if (recL) {
                     const uint32_t nvalid = min<uint32_t>(kWave, w_e - base);
                     const uint32_t r_last = __shfl(Rq, (int)nvalid - 1, kWave);
                     wave_lds_sync();  // the previous window's reads of rend are done
@@ -218,7 +228,9 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                                 if (rend[wv][mid] >= p) b = mid;
                                 else a = mid + 1;
                             }
-                            Lf[(uint64_t)p * K + i] = base + a;
+                            const uint32_t L = base + a;
+                            // only read for a non-empty window
+                            if (L < p) recL[(uint64_t)p * K + i] = make_uint2(p - L, S.X[p] - S.X[L]);
                         }
                     }
                     p_next[i] = r_last + 1;
@@ -244,60 +256,6 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
 // Per element (edge of a multi-edge node pair) and side (center = smaller /
 // larger node): P_0, P_1 of S_c at the window end R and just before the
 // window start L:  w = (P_0(R), P_1(R), P_0(L-1), P_1(L-1)).
-// K windows in one pass (one graph when K > 1): window i's sizes and starts
-// are Wf[p * K + i] and Lf[p * K + i], and its rows of me_w start at
-// i * 2 * n_me.  An element's position, prefix counts and X at it are read
-// once for all windows.
-template <int K>
-__global__ void __launch_bounds__(kBlock) k_star_prep(SeqView S, const uint2 *me_p,
-                                                      const uint4 *me_a, const int64_t *me_t,
-                                                      const uint32_t *Wf, const uint32_t *Lf,
-                                                      uint64_t n_me, const Tile *tiles,
-                                                      uint32_t n_tiles, const int64_t *deltas,
-                                                      uint4 *me_w) {
-  for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
-    const Tile tl = tiles[ti];
-    int64_t delta[K];
-#pragma unroll
-    for (int lv = 0; lv < K; lv++) delta[lv] = deltas[(uint64_t)tl.g * K + lv];
-    for (uint64_t i = tl.b + threadIdx.x; i < tl.e; i += blockDim.x) {
-        const uint64_t k = i >> 1;
-        const uint32_t side = (uint32_t)(i & 1);
-        const int64_t tp = me_t[k];
-        // The sweeps read these only for an element whose pair has another
-        // edge within delta after it (window end) or before it (window start);
-        // that edge is then its neighbour in the element array.
-        const int64_t inf = (int64_t)1 << 62;
-        const int64_t dr = k + 1 < n_me ? me_t[k + 1] - tp : inf;
-        const int64_t dl = k > 0 ? tp - me_t[k - 1] : inf;
-        if (dr > delta[K - 1] && dl > delta[K - 1]) continue;
-        const uint2 pp = me_p[k];
-        const uint4 aa = me_a[k];
-        const uint32_t p = side ? pp.y : pp.x;
-        const uint32_t a0 = side ? aa.z : aa.x, a1 = side ? aa.w : aa.y;
-        const uint32_t xp = S.X[p];
-        const uint32_t seg_lo = p - (a0 + a1);
-#pragma unroll
-        for (int lv = 0; lv < K; lv++) {
-            const bool need_r = dr <= delta[lv], need_l = dl <= delta[lv];
-            if (!need_r && !need_l) continue;
-            uint32_t rp0 = 0, rp1 = 0, lp0 = 0, lp1 = 0;
-            if (need_r) {
-                const uint32_t R = p + Wf[(uint64_t)p * K + lv];
-                rp1 = a1 + (S.X[R + 1] - xp);
-                rp0 = (a0 + a1) + (R - p) + 1 - rp1;
-            }
-            if (need_l) {
-                const uint32_t L = Lf[(uint64_t)p * K + lv];  // first entry of S_c with t >= tp - delta
-                lp1 = a1 - (xp - S.X[L]);
-                lp0 = (L - seg_lo) - lp1;
-            }
-            me_w[(uint64_t)lv * 2 * n_me + i] = make_uint4(rp0, rp1, lp0, lp1);
-        }
-    }
-  }
-}
-
 // Window state over the edges of one node pair inside a delta-window.
 struct Win {
     uint64_t in[2];
@@ -359,7 +317,9 @@ struct StarArgs {
     const int64_t *me_t;
     const uint8_t *me_o;
     const uint4 *me_a;
-    const uint4 *me_w;
+    const uint2 *me_p;       // element positions in S_lo, S_hi
+    const uint2 *recR, *recL;  // window records of entry p for this window: [p * K + level]
+    uint32_t K, level;
     const uint32_t *first;   // n_multi + 1: first work item of each pair (exclusive scan)
     const uint32_t *ipair;   // work item -> its pair
     uint64_t n_multi;
@@ -409,7 +369,10 @@ struct ElemView {
     const uint4 *sa;
     const int64_t *gt;
     const uint8_t *go;
-    const uint4 *ga, *gw;
+    const uint4 *ga;
+    const uint2 *gp;
+    const uint2 *recR, *recL;
+    uint32_t K, level;
     __device__ inline bool staged(uint32_t k) const { return k - lo < hi - lo; }
     __device__ inline int64_t t(uint32_t k) const { return staged(k) ? st[k - lo] : gt[k]; }
     __device__ inline El el(uint32_t k, uint32_t side) const {
@@ -432,9 +395,24 @@ struct ElemView {
         e.a1 = side ? aa.w : aa.y;
         return e;
     }
-    // the window prefix counts are read once per contribution, off the
-    // sweep's dependency chain: straight from global memory
-    __device__ inline uint4 w(uint32_t k, uint32_t side) const { return gw[2 * (uint64_t)k + side]; }
+    // P_0, P_1 of S_c at the window end R of element k (center on `side`),
+    // from its entry's record: with (a0, a1) the counts before the entry,
+    // P_1(R) = a1 + dir-in entries in [p, R], P_0(R) = entries up to R - P_1(R).
+    // Read once per contribution, off the sweep's dependency chain.
+    __device__ inline uint2 win_end(uint32_t k, uint32_t side, const El &e) const {
+        const uint2 pp = gp[k];
+        const uint2 r = recR[(uint64_t)(side ? pp.y : pp.x) * K + level];
+        const uint32_t p1 = e.a1 + r.y;
+        return make_uint2(e.a0 + e.a1 + r.x + 1 - p1, p1);
+    }
+    // P_0, P_1 of S_c just before the window start L of element k:
+    // P_1(L - 1) = a1 - dir-in entries in [L, p), P_0(L - 1) = L - start - P_1.
+    __device__ inline uint2 win_start(uint32_t k, uint32_t side, const El &e) const {
+        const uint2 pp = gp[k];
+        const uint2 r = recL[(uint64_t)(side ? pp.y : pp.x) * K + level];
+        const uint32_t p1 = e.a1 - r.y;
+        return make_uint2(e.a0 + e.a1 - r.x - p1, p1);
+    }
 };
 
 // Sum a wave's lanes for cells [c0, c0 + N) of the tile's partial row: each
@@ -489,7 +467,8 @@ k_star_pair(StarArgs a, uint64_t *partial) {
         s_a[k - lo] = a.me_a[k];
     }
     __syncthreads();
-    const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a, a.me_w};
+    const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a, a.me_p, a.recR, a.recL, a.K,
+                     a.level};
     uint64_t *row = partial + (uint64_t)ti * 32;
     // element ranges of this thread's items: the pair [rs, re), the chunk [cb, ce)
     uint32_t rs_[kSPItems], re_[kSPItems], cb_[kSPItems], ce_[kSPItems];
@@ -528,7 +507,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
                     j++;
                 }
                 if (W.in[0] + W.in[1] == 0) continue;
-                const uint4 ww = V.w(q, side);
+                const uint2 ww = V.win_end(q, side, eq);
                 const uint64_t rp[2] = {ww.x, ww.y};
                 const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0),
                                          (uint64_t)eq.a1 + (eq.dir == 1)};
@@ -584,8 +563,8 @@ k_star_pair(StarArgs a, uint64_t *partial) {
                     f++;
                 }
                 if (W.in[0] + W.in[1] != 0) {
-                    const uint4 ww = V.w(q, side);
-                    const uint64_t lp[2] = {ww.z, ww.w};
+                    const uint2 ww = V.win_start(q, side, eq);
+                    const uint64_t lp[2] = {ww.x, ww.y};
                     const uint64_t m1 = 0ull - (uint64_t)eq.dir;
 #pragma unroll
                     for (int d1 = 0; d1 < 2; d1++) {
@@ -783,7 +762,6 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
   const uint32_t wv = threadIdx.x / kWave;
   __shared__ uint32_t hkey[kBlock / kWave][2 * kHashChunk];
   __shared__ uint32_t hval[kBlock / kWave][2 * kHashChunk];
-  __shared__ uint32_t hpos[K > 1 ? kBlock / kWave : 1][K > 1 ? 2 * kHashChunk : 1];
   __shared__ unsigned long long tcnt[kBlock / kWave][8 * K];
   unsigned long long *T = tcnt[wv];
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
@@ -820,10 +798,10 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                 }
                 for (uint32_t b = lp + 1; b <= lp + lw; b++) {
                     const uint32_t ndb = S.nd[b];
-                    const uint32_t rb = S.rk[b];
 #pragma unroll
                     for (int k = 0; k < kRegWin; k++) {
                         if ((rn[k] >> 1) == (ndb >> 1)) {
+                            const uint32_t rb = S.rk[b];  // ranks only on a (rare) match
                             const uint32_t cls = s_reg ? tri_class(rr[k], rn[k] & 1u, rb, ndb & 1u)
                                                        : tri_class(rb, ndb & 1u, rr[k], rn[k] & 1u);
                             const uint32_t oreg = (uint32_t)k + 1, ostr = b - lp;
@@ -836,11 +814,10 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
             } else {
                 for (uint32_t a = ps + 1; a <= ps + ws; a++) {
                     const uint32_t nda = S.nd[a];
-                    const uint32_t ra = S.rk[a];
                     for (uint32_t b = pd + 1; b <= pd + wd; b++) {
                         const uint32_t ndb = S.nd[b];
                         if ((ndb >> 1) == (nda >> 1)) {
-                            const uint32_t cls = tri_class(ra, nda & 1u, S.rk[b], ndb & 1u);
+                            const uint32_t cls = tri_class(S.rk[a], nda & 1u, S.rk[b], ndb & 1u);
                             tri_add(T, tri_level<K>(Wf, ps, a - ps, pd, b - pd) * 8 + cls);
                         }
                     }
@@ -861,7 +838,7 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
             if (o_hi - o_lo + 1 > kHashMin) {
                 // hash join: the smaller window, kHashChunk entries at a time,
                 // goes into an open-addressing table in this wave's LDS (one
-                // slot per entry, key = neighbour, value = rank << 1 | dir);
+                // slot per entry, key = neighbour, value = its position);
                 // every entry of the larger window probes it.  Work is linear in
                 // the two windows plus the matches instead of their product.
                 uint32_t *hk = hkey[wv], *hv = hval[wv];
@@ -877,24 +854,23 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                         const uint32_t key = nd >> 1;
                         uint32_t h = (key * kHashMul) >> hshift;
                         while (atomicCAS(&hk[h], kEmptyKey, key) != kEmptyKey) h = (h + 1) & hmask;
-                        hv[h] = (S.rk[y] << 1) | (nd & 1u);
-                        if (K > 1) hpos[wv][h] = y;
+                        hv[h] = y;  // its rank and direction are read on a match
                     }
                     wave_lds_sync();
                     for (uint32_t x = i_lo + lane; x <= i_hi; x += kWave) {
                         const uint32_t nd = S.nd[x];
                         const uint32_t key = nd >> 1;
-                        const uint32_t rx = S.rk[x];
                         for (uint32_t h = (key * kHashMul) >> hshift;; h = (h + 1) & hmask) {
                             const uint32_t k = hk[h];
                             if (k == kEmptyKey) break;
                             if (k == key) {
-                                const uint32_t v = hv[h];
-                                const uint32_t cls = s_outer ? tri_class(v >> 1, v & 1u, rx, nd & 1u)
-                                                             : tri_class(rx, nd & 1u, v >> 1, v & 1u);
+                                const uint32_t y = hv[h], rx = S.rk[x], ry = S.rk[y];
+                                const uint32_t dy = S.nd[y] & 1u;
+                                const uint32_t cls = s_outer ? tri_class(ry, dy, rx, nd & 1u)
+                                                             : tri_class(rx, nd & 1u, ry, dy);
                                 uint32_t l = 0;
                                 if (K > 1) {
-                                    const uint32_t oo = hpos[wv][h] - o_base, oi = x - i_base;
+                                    const uint32_t oo = y - o_base, oi = x - i_base;
                                     l = s_outer ? tri_level<K>(Wf, bps, oo, bpd, oi)
                                                 : tri_level<K>(Wf, bps, oi, bpd, oo);
                                 }
@@ -912,16 +888,15 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                 const uint32_t x = ib + lane;
                 const bool valid = x <= i_hi;
                 const uint32_t ndx = valid ? S.nd[x] : 0xffffffffu;
-                const uint32_t rx = valid ? S.rk[x] : 0u;
                 for (uint32_t ob = o_lo; ob <= o_hi; ob += kWave) {
                     const uint32_t y = ob + lane;
                     const uint32_t ndy = y <= o_hi ? S.nd[y] : 0u;
-                    const uint32_t ry = y <= o_hi ? S.rk[y] : 0u;
                     const uint32_t cnt = min((uint32_t)kWave, o_hi - ob + 1);
                     for (uint32_t k = 0; k < cnt; k++) {
                         const uint32_t ndo = (uint32_t)__builtin_amdgcn_readlane((int)ndy, (int)k);
-                        const uint32_t ro = (uint32_t)__builtin_amdgcn_readlane((int)ry, (int)k);
                         if (valid && (ndx >> 1) == (ndo >> 1)) {
+                            // ranks are read on a (rare) match only
+                            const uint32_t ro = S.rk[ob + k], rx = S.rk[x];
                             const uint32_t cls = s_outer ? tri_class(ro, ndo & 1u, rx, ndx & 1u)
                                                          : tri_class(rx, ndx & 1u, ro, ndo & 1u);
                             const uint32_t oo = ob + k - o_base, oi = x - i_base;
@@ -1183,20 +1158,19 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
                         c0 += (uint32_t)__popcll(done);
                         wave_lds_sync();
                     }
-                    uint32_t nd[2], rx[2], pp[2], wpk[2], qq[2], ox[2];
+                    uint32_t nd[2], xs[2], pp[2], wpk[2], qq[2];
 #pragma unroll
                     for (int u = 0; u < 2; u++) {
                         const uint64_t j = base + (uint64_t)u * kWave + (uint64_t)lane;
-                        nd[u] = rx[u] = pp[u] = wpk[u] = qq[u] = ox[u] = 0;
+                        nd[u] = xs[u] = pp[u] = wpk[u] = qq[u] = 0;
                         if (j < je) {  // then cu[u] < n_seg
                             const uint4 o = own_l[sidx[cu[u]]];
                             const uint32_t x = o.z + (uint32_t)(j - spre[cu[u]]);
                             pp[u] = o.x;
                             wpk[u] = o.y;
                             qq[u] = o.z - 1;  // the other window's first edge entry
-                            ox[u] = x - (o.z - 1);
-                            nd[u] = S.nd[x];
-                            rx[u] = S.rk[x];
+                            xs[u] = x;
+                            nd[u] = S.nd[x];  // its rank is read on a (rare) match only
                         }
                     }
 #pragma unroll
@@ -1209,13 +1183,13 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
                             if (kk == key) {
                                 const uint32_t off = ho[h], y = sl + off;
                                 if (y > p && y - p <= W) {
-                                    const uint32_t v = srd[off];
+                                    const uint32_t v = srd[off], rx = S.rk[xs[u]], ox = xs[u] - qq[u];
                                     const bool own_s = (wpk[u] >> 31) != 0;
-                                    const uint32_t cls = own_s ? tri_class(v >> 1, v & 1u, rx[u], nd[u] & 1u)
-                                                               : tri_class(rx[u], nd[u] & 1u, v >> 1, v & 1u);
+                                    const uint32_t cls = own_s ? tri_class(v >> 1, v & 1u, rx, nd[u] & 1u)
+                                                               : tri_class(rx, nd[u] & 1u, v >> 1, v & 1u);
                                     const uint32_t l =
-                                        own_s ? tri_level<K>(a.Wf, p, y - p, qq[u], ox[u])
-                                              : tri_level<K>(a.Wf, qq[u], ox[u], p, y - p);
+                                        own_s ? tri_level<K>(a.Wf, p, y - p, qq[u], ox)
+                                              : tri_level<K>(a.Wf, qq[u], ox, p, y - p);
                                     tri_add(red[wv], l * 8 + cls);
                                 }
                             }
@@ -1341,9 +1315,9 @@ constexpr uint32_t kDefaultHubMin = 32;
 struct Workspace {
     uint32_t K = 1;  // windows counted in one pass (one graph when K > 1)
     int64_t *deltas;
-    uint32_t *Wf, *Lf;  // window i of entry p at p * K + i
+    uint32_t *Wf;       // window i of entry p at p * K + i
+    uint2 *recR, *recL; // window records for the star/pair sweeps, same layout
     uint64_t *wbits, *lev;
-    uint4 *me_w;        // window i's rows at offset i * 2 * n_me
     uint32_t *cnt, *first, *ipair, *tflag, *tidx;
     uint4 *cand;
     uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
@@ -1361,8 +1335,8 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w, uint32_t K = 1) {
     w->max_htiles = len / kHubSlice + G + 1;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return up((size_t)G * K * 8) + up(len * 4 * K) * 2 + up((len / kWave + 1) * 8) +
-           up((len / kWave + 1) * 16) + up(2 * nme * sizeof(uint4) * K) +
+    return up((size_t)G * K * 8) + up(len * 4 * K) + up(len * 8 * K) * 2 + up((len / kWave + 1) * 8) +
+           up((len / kWave + 1) * 16) +
            up((G + 1) * 4) * 2 + up(4) + up(w->max_htiles * 4) + up(w->max_htiles * 8 * 8 * K) +
            up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * sum_split(G) * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
@@ -1376,7 +1350,8 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     w->deltas = sc.take<int64_t>((size_t)G * K);
     w->Wf = sc.take<uint32_t>(len * K);
-    w->Lf = sc.take<uint32_t>(len * K);
+    w->recR = sc.take<uint2>(len * K);
+    w->recL = sc.take<uint2>(len * K);
     w->wbits = sc.take<uint64_t>(len / kWave + 1);
     w->lev = sc.take<uint64_t>(2 * (len / kWave + 1));
     w->n_htiles = sc.take<uint32_t>(G + 1);
@@ -1384,7 +1359,6 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->hcount = sc.take<uint32_t>(1);
     w->hlist = sc.take<uint32_t>(w->max_htiles);
     w->hpart = sc.take<uint64_t>(w->max_htiles * 8 * K);
-    w->me_w = sc.take<uint4>(2 * nme * K);
     w->cnt = sc.take<uint32_t>(nm + 1);
     w->first = sc.take<uint32_t>(nm + 1);
     w->ipair = sc.take<uint32_t>(nme + 1);
@@ -1443,14 +1417,10 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     TM_LAUNCH_K("windows", k_windows, K, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock),
                 0, s, S, g->t_entries, g->n_t_entries, len, w.deltas, w.Wf, pr.hub_min,
                 fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr,
-                nm ? w.Lf : nullptr);
+                nm ? w.recR : nullptr, nm ? w.recL : nullptr);
     // ---- star / pair: work items (pair, chunk); window i reads its own
-    // sizes and deltas (K > 1 only for one graph, whose delta i is deltas[i])
+    // records and delta (K > 1 only for one graph, whose delta i is deltas[i])
     if (nm) {
-        TM_LAUNCH_K("star_prep", k_star_prep, K,
-                    dim3(std::min<uint32_t>(std::max(g->n_t_elems, 1u), 16384)), dim3(kBlock), 0, s, S,
-                    g->me_p, g->me_a, g->me_t, w.Wf, w.Lf, nme, g->t_elems, g->n_t_elems, w.deltas,
-                    w.me_w);
         ProfRow row_a6("a6");
         TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
                   nm, run_chunk, w.cnt);
@@ -1494,8 +1464,8 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     }
     if (nm) {
         for (uint32_t i = 0; i < K; i++) {
-            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, w.me_w + i * 2 * nme, w.first, w.ipair,
-                        nm, nme, g->d_mpb, w.tfirst, G, w.deltas + i, run_chunk,
+            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, g->me_p, w.recR, w.recL, K, i,
+                        w.first, w.ipair, nm, nme, g->d_mpb, w.tfirst, G, w.deltas + i, run_chunk,
                         (families & TM_STARS) ? 1 : 0};
             TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
                       dim3(kBlock), 0, s, sa, w.spart + i * s_stride);

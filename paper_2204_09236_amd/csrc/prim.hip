@@ -667,12 +667,12 @@ int radix_sort_time_direct_u64(const int32_t *src, const int32_t *dst, const int
 // Written directly it is one random 4-byte write per entry, which costs a
 // partial-line write each once the index outgrows the last-level cache.
 // Instead, (slot, position) pairs in entry order are partitioned by the
-// slot's bits above kSlotBucketBits (stable radix passes, coalesced
-// writes), and then each block fills one bucket of 2^kSlotBucketBits
-// slots: slots are a permutation of [0, n), so bucket b is exactly sorted
-// positions [b * 2^kSlotBucketBits, ...); the block places them in LDS by
-// their low bits and writes the bucket out in order.
-constexpr int kSlotBucketBits = 14;
+// slot's bits above kSlotBucketBits (radix passes, coalesced writes), and
+// then each block fills one bucket of 2^kSlotBucketBits slots: slots are a
+// permutation of [0, n), so bucket b is exactly sorted positions
+// [b * 2^kSlotBucketBits, ...); the block places them in LDS by their low
+// bits and writes the bucket out in order.
+constexpr int kSlotBucketBits = 15;  // 128 KiB of LDS per bucket
 constexpr uint32_t kSlotBucket = 1u << kSlotBucketBits;
 
 // key: slots; val: their positions (null: position = index, the unsorted case).

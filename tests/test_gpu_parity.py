@@ -235,11 +235,11 @@ def test_lookback_giveup_fails_cleanly(tm):
         np.testing.assert_array_equal(G.count_raw(3600), oracle.alg(g.src, g.dst, g.t, 3600, n=g.n))
 
 
-@pytest.mark.parametrize("m", [12, 9000, 200_000, 2_500_000])
+@pytest.mark.parametrize("m", [12, 9000, 20_000, 200_000, 5_000_000])
 def test_edge_index_by_partition(tm, m):
     """Each edge's two positions built by the partition of (slot, position)
     pairs and the bucket fill (taken by graphs whose index outgrows the
-    last-level cache), forced at small sizes: no sort pass (under 2^14
+    last-level cache), forced at small sizes: no sort pass (under 2^15
     slots), one pass, two passes; ragged last buckets."""
     if m == 12:
         src, dst, t = load_toy()
