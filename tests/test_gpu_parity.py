@@ -343,6 +343,13 @@ def test_skewed_full_size(tm):
             if delta == 86400:
                 case("skewed full delta=86400 hub pass off")
                 np.testing.assert_array_equal(G.count_raw(delta, hub_min=tm.HUB_OFF), want)
+        # all windows in one pass, as the benchmark counts them
+        deltas = [int(k) for k in rec["counts"]]
+        case(f"skewed full, windows {deltas} in one pass")
+        multi = G.count_multi_raw(deltas)
+        for i, key in enumerate(rec["counts"]):
+            np.testing.assert_array_equal(multi[i], np.array(rec["counts"][key]["raw"], dtype=np.uint64),
+                                          err_msg=f"one pass, delta={key}")
     del s, d, t
     torch.cuda.empty_cache()
 
