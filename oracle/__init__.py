@@ -13,6 +13,10 @@ Two independent C implementations, compiled with gcc into ``liboracle.so``:
                definition (Definitions 2-3, Problem 1); returns raw counters
                built from each counter's definition and the class counts.
 
+``brute4`` and ``local4`` (tm_motif4.c) count the 32 classes of four-node
+three-edge motifs, the higher-order extension the paper leaves to future work,
+by two enumerations of the same definition.
+
 ``merge`` turns raw counters into the 36 motif counts (Sections IV-A/IV-B:
 isomorphic Pair cells, Tri orbit sum / 3) in the 6x6 layout.
 """
@@ -29,7 +33,8 @@ _DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
 # The mutation tests point this at a deliberately broken copy of the oracle
 # to show that the pins in tests/test_oracle.py reject it.
 _LIB_PATH = os.environ.get("TM_ORACLE_LIB") or _DEFAULT_LIB
-_SOURCES = [os.path.join(_HERE, "tm_oracle.c"), os.path.join(_HERE, "tm_brute.c")]
+_SOURCES = [os.path.join(_HERE, "tm_oracle.c"), os.path.join(_HERE, "tm_brute.c"),
+            os.path.join(_HERE, "tm_motif4.c")]
 _lib = None
 
 # status codes of the C functions
@@ -72,6 +77,12 @@ def _load():
         lib.oracle_brute.argtypes = [p32, p32, p64, ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.c_int64, pu64, pu64]
         lib.oracle_brute.restype = ctypes.c_int
+        lib.oracle4_brute.argtypes = [p32, p32, p64, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_int64, pu64]
+        lib.oracle4_brute.restype = ctypes.c_int
+        lib.oracle4_local.argtypes = [p32, p32, p64, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_int64, ctypes.c_int, pu64]
+        lib.oracle4_local.restype = ctypes.c_int
         lib.oracle_merge.argtypes = [pu64, pu64]
         lib.oracle_merge.restype = ctypes.c_int
         lib.oracle_validate.argtypes = [p32, p32, p64, ctypes.c_uint64, ctypes.c_uint32]
@@ -152,6 +163,34 @@ def brute(src, dst, t, delta: int, n: int | None = None) -> tuple[np.ndarray, np
     if rc:
         raise OracleError(rc)
     return raw, canon
+
+
+def brute4(src, dst, t, delta: int, n: int | None = None) -> np.ndarray:
+    """Four-node three-edge motif counts (32 x u64, layout in tm_motif4.c) by
+    classifying every chronological edge triple inside delta."""
+    lib = _load()
+    src, dst, t = _arrays(src, dst, t)
+    out = np.zeros(32, dtype=np.uint64)
+    rc = lib.oracle4_brute(_ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32),
+                           _ptr(t, ctypes.c_int64), src.size, _n_of(src, dst, n), int(delta),
+                           _ptr(out, ctypes.c_uint64))
+    if rc:
+        raise OracleError(rc)
+    return out
+
+
+def local4(src, dst, t, delta: int, n: int | None = None, threads: int = 0) -> np.ndarray:
+    """The same 32 counts, enumerated per center node (stars) and per middle
+    edge (paths)."""
+    lib = _load()
+    src, dst, t = _arrays(src, dst, t)
+    out = np.zeros(32, dtype=np.uint64)
+    rc = lib.oracle4_local(_ptr(src, ctypes.c_int32), _ptr(dst, ctypes.c_int32),
+                           _ptr(t, ctypes.c_int64), src.size, _n_of(src, dst, n), int(delta),
+                           int(threads), _ptr(out, ctypes.c_uint64))
+    if rc:
+        raise OracleError(rc)
+    return out
 
 
 def merge(raw) -> np.ndarray:

@@ -8,8 +8,9 @@ Each case applies one small edit to a copy of the oracle's C source:
 - swapped triangle types
 - a wrong slice in the merge
 
-It compiles the copy on the CPU and runs tests/test_oracle.py against it (the
-wrapper loads the library named by TM_ORACLE_LIB).  Every mutant must make
+It compiles the copy on the CPU and runs the pins of the part it edits
+against it: tests/test_oracle.py for the three-edge oracle, tests/test_oracle4.py
+for the four-node one (the wrapper loads the library named by TM_ORACLE_LIB).  Every mutant must make
 that suite fail; the unmodified source, built the same way, must pass it.
 """
 import os
@@ -71,9 +72,27 @@ MUTANTS = [
 ]
 
 
+MUTANTS4 = [
+    ("m4-local-reading-end", "tm_motif4.c", "if (rx < ry) { /* a - s - d - w */",
+     "if (rx > ry) { /* a - s - d - w */"),
+    ("m4-local-star-leaves", "tm_motif4.c", "if (nk == ni || nk == nj) continue;",
+     "if (nk == ni) continue;"),
+    ("m4-local-exclusive-delta", "tm_motif4.c", "if (hi - lo > delta) continue;",
+     "if (hi - lo >= delta) continue;"),
+    ("m4-local-triangle-not-excluded", "tm_motif4.c", "if (w == s || w == a) continue;",
+     "if (w == s) continue;"),
+    ("m4-brute-middle-bit", "tm_motif4.c", "f[mid] = (S[E[mid]] == v1);",
+     "f[mid] = (S[E[mid]] == v2);"),
+    ("m4-brute-star-direction", "tm_motif4.c", "idx = idx * 2 + (S[E[k]] == center ? 0 : 1);",
+     "idx = idx * 2 + (S[E[k]] == center ? 1 : 0);"),
+    ("m4-tie-order", "tm_motif4.c", "return x < y ? -1 : (x > y);",
+     "return x > y ? -1 : (x < y);"),
+]
+
+
 def _build(workdir, edit):
     srcs = []
-    for f in ("tm_oracle.c", "tm_brute.c"):
+    for f in ("tm_oracle.c", "tm_brute.c", "tm_motif4.c"):
         with open(os.path.join(ORACLE_DIR, f)) as fh:
             text = fh.read()
         if edit is not None and edit[0] == f:
@@ -86,22 +105,24 @@ def _build(workdir, edit):
     return oracle.compile_lib(srcs, os.path.join(workdir, "liboracle_variant.so"))
 
 
-def _run_pins(lib):
+def _run_pins(lib, pins="test_oracle.py"):
     env = dict(os.environ, TM_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
     env["PYTHONPATH"] = ROOT + os.pathsep + env.get("PYTHONPATH", "")
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle.py"),
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", pins),
                         "-x", "-q", "-p", "no:cacheprovider"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode, r.stdout[-2000:]
 
 
-def _case(edit):
+def _case(edit, pins="test_oracle.py"):
     with tempfile.TemporaryDirectory() as d:
-        return _run_pins(_build(d, edit))
+        return _run_pins(_build(d, edit), pins)
 
 
 def test_unmodified_copy_passes():
     rc, out = _case(None)
+    assert rc == 0, out
+    rc, out = _case(None, "test_oracle4.py")
     assert rc == 0, out
 
 
@@ -112,4 +133,13 @@ def test_every_mutant_is_caught():
     assert not survivors, f"mutants not caught by the pins: {survivors}"
     # each failure is a failed assertion, not a broken build or collection error
     for m, (rc, out) in zip(MUTANTS, results):
+        assert rc == 1, f"{m[0]}: pytest exit {rc}\n{out}"
+
+
+def test_every_four_node_mutant_is_caught():
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(lambda m: _case((m[1], m[2], m[3]), "test_oracle4.py"), MUTANTS4))
+    survivors = [m[0] for m, (rc, out) in zip(MUTANTS4, results) if rc == 0]
+    assert not survivors, f"mutants not caught by the pins: {survivors}"
+    for m, (rc, out) in zip(MUTANTS4, results):
         assert rc == 1, f"{m[0]}: pytest exit {rc}\n{out}"
