@@ -178,15 +178,40 @@ int tm_count_masked(tm_graph *g, int64_t delta, uint32_t families, uint64_t out[
  * Counts of one graph for k windows in one call (the paper's experiments
  * sweep delta, Section V): out[i] (36 motif counts) or raw[i] (56 raw
  * counters) for deltas[i] (host array, 0 <= delta < 2^62, any order,
- * repeats allowed), 1 <= k <= TM_MAX_DELTAS.  The graph is built once; the
- * count sequences of all windows run back to back on the graph's stream and
- * their counters come back in one copy.  Each out[i] equals
- * tm_count(g, deltas[i]).  TM_EINVAL for a batch of several graphs, k out of
- * range or a bad delta; other errors as tm_count.
+ * repeats allowed), 1 <= k <= TM_MAX_DELTAS.  The windows are taken in
+ * increasing order, up to four nested windows per pass: one window search per
+ * entry for all of them, one triangle matching at the largest, each match
+ * filed under the smallest window that holds it, and the star/pair sweeps once
+ * per window.  Each out[i] equals tm_count(g, deltas[i]).  TM_EINVAL for a
+ * batch of several graphs, k out of range or a bad delta; other errors as
+ * tm_count.
  */
 #define TM_MAX_DELTAS 1024
 int tm_count_multi(tm_graph *g, const int64_t *deltas, uint32_t k, uint64_t (*out)[36]);
 int tm_count_multi_raw(tm_graph *g, const int64_t *deltas, uint32_t k, uint64_t (*raw)[56]);
+
+/*
+ * Four-node three-edge motifs of one graph at window delta, the higher-order
+ * extension the paper leaves to future work (Section VI: more centers and
+ * bigger counters).  An instance is three distinct edges E1 < E2 < E3 in the
+ * (t, id) order with t(E3) - t(E1) <= delta whose static graph is connected
+ * on exactly four nodes (Definitions 2-3 and Problem 1 with four nodes): a
+ * star (one node c on all three edges) or a path v0 - v1 - v2 - v3.
+ *   out[0 .. 8)   star [d1][d2][d3]: d_k = 0 if E_k leaves c, 1 if it enters c
+ *   out[8 .. 32)  path 8 + r * 8 + f1 * 4 + f2 * 2 + f3: r = 0, 1, 2 the
+ *                 chronological position of the middle edge {v1, v2}; the
+ *                 path is read from the end edge that comes first ({v0, v1});
+ *                 f_k = 1 if E_k points from v_i to v_i+1, else 0
+ * raw (may be NULL) receives the 56 raw three-edge counters of the same
+ * delta, which the count needs anyway: stars are the ordered triples of one
+ * node's edges less the three-node stars and pairs at that node; paths are
+ * the choices (middle edge, one more edge at each end) less the triangles,
+ * three-node stars and pairs those choices also form.  Host outputs; the
+ * graph's stream; TM_EINVAL for a batch of several graphs or a bad delta;
+ * TM_EINTERNAL if a correction exceeds its sum (an internal inconsistency,
+ * never expected); other errors as tm_count.
+ */
+int tm_count4(tm_graph *g, int64_t delta, uint64_t raw[56], uint64_t out[32]);
 
 /* The paper's raw counters (layout above), 56 x uint64, for window delta. */
 int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]);

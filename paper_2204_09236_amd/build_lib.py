@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtm.so")
-SOURCES = ["prim.hip", "build.hip", "count.hip", "api.hip", "mem.hip", "server.hip", "stream.hip"]
+SOURCES = ["prim.hip", "build.hip", "count.hip", "count4.hip", "api.hip", "mem.hip", "server.hip", "stream.hip"]
 ARCH = os.environ.get("TM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep the compiler from emitting packed fp32 instructions

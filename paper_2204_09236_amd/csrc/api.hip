@@ -479,6 +479,36 @@ int tm_count_masked(tm_graph *g, int64_t delta, uint32_t families, uint64_t out[
     return tm_merge(raw, out);
 }
 
+int tm_count4(tm_graph *g, int64_t delta, uint64_t raw[56], uint64_t out[32]) {
+    if (!g || !out) {
+        tmc::set_error("NULL graph or output");
+        return TM_EINVAL;
+    }
+    if (g->G != 1) {
+        tmc::set_error("four-node motifs are counted on a single graph, not a batch");
+        return TM_EINVAL;
+    }
+    if (delta < 0 || delta >= ((int64_t)1 << 62)) {
+        tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+        return TM_EINVAL;
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    uint64_t r56[56], o32[32];
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        rc = tmc::count4_graph(g, delta, r56, o32);
+    }
+    if (cur != g->device) (void)hipSetDevice(cur);
+    if (rc) return rc;
+    if (raw)
+        for (int i = 0; i < 56; i++) raw[i] = r56[i];
+    for (int i = 0; i < 32; i++) out[i] = o32[i];
+    return TM_OK;
+}
+
 int tm_count_multi_raw(tm_graph *g, const int64_t *deltas, uint32_t k, uint64_t (*raw)[56]) {
     if (!g || !deltas || !raw) {
         tmc::set_error("NULL graph, deltas or output");

@@ -274,6 +274,9 @@ int count_graph_noalloc(tm_graph *g, int64_t delta, uint64_t *raw);
 uint64_t dev_alloc_calls();
 // Raw counters of one graph (G == 1) for k windows, raw[k * 56].
 int count_graph_multi(tm_graph *g, const int64_t *deltas, uint32_t k, Params pr, uint64_t *raw);
+// Four-node three-edge motif counts of one graph (G == 1) into out32 (host),
+// with the three-edge raw counters of the same delta into raw56 (host).
+int count4_graph(tm_graph *g, int64_t delta, uint64_t *raw56, uint64_t *out32);
 void plan_release(tm_graph *g);
 void raw_from_counters(const uint64_t *res40, uint32_t G, uint64_t *raw);
 int count_graph_async(tm_graph *g, const int64_t *pinned_deltas, uint64_t *pinned_res,

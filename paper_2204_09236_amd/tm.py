@@ -75,6 +75,8 @@ def _load():
                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_float)]
     lib.tm_autotune.restype = ctypes.c_int
+    lib.tm_count4.argtypes = [vp, ctypes.c_int64, u64p, u64p]
+    lib.tm_count4.restype = ctypes.c_int
     lib.tm_count_multi.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32, u64p]
     lib.tm_count_multi.restype = ctypes.c_int
     lib.tm_count_multi_raw.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32, u64p]
@@ -184,6 +186,14 @@ class Graph:
         _check(_lib.tm_count_multi(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    d.size, _u64(out)))
         return out.reshape(d.size, 6, 6)
+
+    def count4(self, delta: int, with_raw: bool = False):
+        """Four-node three-edge motif counts (32, layout of tm_count4); with
+        with_raw also the 56 raw three-edge counters of the same delta."""
+        out = np.zeros(32, dtype=np.uint64)
+        raw = np.zeros(56, dtype=np.uint64)
+        _check(_lib.tm_count4(self.handle, int(delta), _u64(raw), _u64(out)))
+        return (out, raw) if with_raw else out
 
     def count_multi_raw(self, deltas) -> np.ndarray:
         """Raw counters for several windows in one call: (k, 56)."""

@@ -15,6 +15,10 @@ same edge list.
                     own delta
   serve             the largest serving request graph (graphgen.serve_max,
                     5e7 edges) at delta 60, 3,600 and 86,400
+  motif4            four-node three-edge motif counts (oracle.local4) with the
+                    raw three-edge counters of the same delta (oracle.alg):
+                    the power-law workload at delta 600 and 3,600, the skewed
+                    one at delta 600
 The file written is ``tests/golden/<workload>_counts.json``.
 """
 import json
@@ -29,6 +33,7 @@ import graphgen  # noqa: E402
 import oracle  # noqa: E402
 
 SERVE_DELTAS = [60, 3600, 86400]
+MOTIF4 = {"powerlaw": [600, 3600], "skewed": [600]}
 
 
 def counts_record(g, deltas, threads):
@@ -79,13 +84,38 @@ def batch(threads):
     return rec
 
 
+def motif4(threads):
+    rec = {}
+    for workload, deltas in MOTIF4.items():
+        t0 = time.time()
+        g = graphgen.CONFIGS[workload]["fn"]()
+        print(f"generated {workload}: n={g.n} m={g.m} in {time.time() - t0:.1f}s", flush=True)
+        counts = {}
+        for delta in deltas:
+            t0 = time.time()
+            f4 = oracle.local4(g.src, g.dst, g.t, delta, n=g.n, threads=threads)
+            raw = oracle.alg(g.src, g.dst, g.t, delta, n=g.n, threads=threads)
+            counts[str(delta)] = {"f4": [int(x) for x in f4], "raw": [int(x) for x in raw],
+                                  "oracle_seconds": round(time.time() - t0, 2)}
+            print(f"{workload} delta={delta}: {time.time() - t0:.1f}s", flush=True)
+        rec[workload] = {"n": g.n, "m": g.m, "edge_sha256": graphgen.edge_hash(g), "counts": counts}
+        del g
+    return rec
+
+
 def main():
     workload = sys.argv[1] if len(sys.argv) > 1 else "powerlaw"
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    rec = batch(threads) if workload == "batch" else single(workload, threads)
+    if workload == "batch":
+        rec = batch(threads)
+    elif workload == "motif4":
+        rec = motif4(threads)
+    else:
+        rec = single(workload, threads)
     with open(os.path.join(HERE, f"{workload}_counts.json"), "w") as f:
         json.dump(rec, f, indent=None if workload == "batch" else 1, separators=None)
-    print(json.dumps({k: v for k, v in rec.items() if k not in ("counts", "members")}))
+    if workload != "motif4":
+        print(json.dumps({k: v for k, v in rec.items() if k not in ("counts", "members")}))
 
 
 if __name__ == "__main__":
