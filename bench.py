@@ -490,6 +490,8 @@ def run_single(args, workload: str, full: bool = True) -> dict:
             torch.cuda.synchronize()
             family_ms[name] = round((time.perf_counter() - t_c) * 1e3 / args.steps, 4)
         extra["count_only_family_ms"] = {"delta": deltas[0], **family_ms}
+    ehash = graphgen.edge_hash(g)
+    extra["four_node"] = four_node(tm, G, g, workload, deltas, args.steps, ehash)
     G.free()
     if full:
         # PCIe-inclusive: the same step from host arrays (the boundary copies them in)
@@ -555,7 +557,7 @@ def run_single(args, workload: str, full: bool = True) -> dict:
     cpu = None
     if full and not args.no_cpu_baseline:
         cpu = cpu_baseline(args, workload, g, deltas)
-    golden = golden_check(workload, g, deltas, counts)
+    golden = golden_check(workload, g, deltas, counts, ehash)
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "edges/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -582,19 +584,60 @@ def run_single(args, workload: str, full: bool = True) -> dict:
     return line
 
 
-def golden_check(workload, g, deltas, counts):
+def four_node(tm, G, g, workload, deltas, steps, ehash) -> dict:
+    """Four-node three-edge motifs (tm_count4) at each delta of the workload:
+    the time of one call (which runs the 36-class count its corrections need),
+    the time of its own kernels (traced "f4:" launches) and its dominant one,
+    and a comparison with the oracle's stored counts
+    (tests/golden/motif4_counts.json) where they exist for this input."""
+    import numpy as np
+    import torch
+    golden = {}
+    path = os.path.join(ROOT, "tests", "golden", "motif4_counts.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f).get(workload)
+        if rec and rec.get("edge_sha256") == ehash:
+            golden = rec["counts"]
+    out = {}
+    for d in deltas:
+        f4 = G.count4(d)
+        torch.cuda.synchronize()
+        reps = max(1, min(steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            G.count4(d)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        tm.prof_only(None)
+        tm.prof_reset()
+        tm.prof_enable(True)
+        G.count4(d)
+        tm.prof_enable(False)
+        pr = {k: v for k, v in tm.prof_read().items() if k.startswith("f4:")}
+        top = max(pr.items(), key=lambda kv: kv[1][1]) if pr else None
+        ent = {"ms": round(ms, 3), "edges_per_s": round(g.m / (ms / 1e3), 1),
+               "f4_kernels_ms": round(sum(v[1] for v in pr.values()), 3),
+               "dominant_kernel": None if top is None else {"name": top[0], "ms": round(top[1][1], 3)},
+               "instances": int(f4.sum())}
+        if str(d) in golden:
+            ent["golden_match"] = bool(np.array_equal(f4, np.array(golden[str(d)]["f4"], dtype=np.uint64)))
+        out[str(d)] = ent
+    return out
+
+
+def golden_check(workload, g, deltas, counts, ehash):
     """Compare with the oracle's stored counts for this workload
     (tests/golden/<workload>_counts.json, written by make_golden.py from the
     oracle alone) when the regenerated input has the stored sha256."""
     import numpy as np
 
-    import graphgen
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_counts.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("edge_sha256") != graphgen.edge_hash(g):
+    if rec.get("edge_sha256") != ehash:
         return {"match": None, "note": "input differs from the stored one; not compared"}
     ok = True
     for d, c in zip(deltas, counts):
@@ -852,7 +895,7 @@ def bench_stream(args):
             last = G.count(delta)
     torch.cuda.synchronize()
     el_re = time.perf_counter() - t0
-    golden = golden_check("powerlaw", g, [delta], [total])
+    golden = golden_check("powerlaw", g, [delta], [total], graphgen.edge_hash(g))
     same = bool(np.array_equal(total, last))
     lat_ms = np.array(lats) * 1e3
     line = {
@@ -1053,13 +1096,15 @@ def main():
         ex = run_single(args, w, full=False)
         extras[w] = {k: ex[k] for k in ("value", "unit", "ms_per_step", "config", "roofline", "rows",
                                         "whole_step", "build_only_ms", "count_only_ms", "golden",
-                                        "motif_total")}
+                                        "four_node", "motif_total")}
     if extras:
         line["extra_workloads"] = extras
     print(json.dumps(line))
+    f4_bad = any(v.get("golden_match") is False
+                 for ln in [line, *extras.values()] for v in ln.get("four_node", {}).values())
     bad = (line["cpu_baseline"] is not None and not line["cpu_baseline"]["matches_gpu"]) or \
         (line["golden"] is not None and line["golden"]["match"] is False) or \
-        any(e["golden"] is not None and e["golden"]["match"] is False for e in extras.values())
+        any(e["golden"] is not None and e["golden"]["match"] is False for e in extras.values()) or f4_bad
     if bad:
         sys.exit(1)
 

@@ -88,26 +88,31 @@ __device__ inline void block_rows(const uint64_t (&acc)[N], uint64_t (*red)[N], 
     }
 }
 
-// --------------------------------------------------------------- Q = prefix
+// ------------------------------------------------------- u64 prefix sums
+// Exclusive prefix sums of len values given by a loader, out[len] = total, in
+// three launches: tile sums, a one-block scan of them, the tiles.
 // value of entry y in Q: X[y] if the entry leaves its center, else 0
-__device__ inline uint64_t q_value(const uint32_t *nd, const uint32_t *X, uint64_t y) {
-    return (nd[y] & 1u) ? 0ull : (uint64_t)X[y];
-}
+struct QLoad {
+    const uint32_t *nd, *X;
+    __device__ inline uint64_t operator()(uint64_t y) const {
+        return (nd[y] & 1u) ? 0ull : (uint64_t)X[y];
+    }
+};
 
-__global__ void __launch_bounds__(kBlock) k_q_tile_sum(const uint32_t *nd, const uint32_t *X,
-                                                       uint64_t len, uint64_t *part) {
+template <class L>
+__global__ void __launch_bounds__(kBlock) k_u64_tile_sum(L ld, uint64_t len, uint64_t *part) {
     __shared__ uint64_t red[kBlock / kWave][1];
     const uint64_t base = (uint64_t)blockIdx.x * kQTile;
     uint64_t acc[1] = {0};
     for (uint32_t k = threadIdx.x; k < kQTile; k += kBlock) {
         const uint64_t y = base + k;
-        if (y < len) acc[0] += q_value(nd, X, y);
+        if (y < len) acc[0] += ld(y);
     }
     block_rows<1>(acc, red, part + blockIdx.x);
 }
 
 // Exclusive scan of part[0, np) in place, part[np] = total; one block.
-__global__ void __launch_bounds__(kPartsBlock) k_q_parts(uint64_t *part, uint32_t np) {
+__global__ void __launch_bounds__(kPartsBlock) k_u64_parts(uint64_t *part, uint32_t np) {
     __shared__ uint64_t lds[kPartsBlock / kWave];
     const uint32_t per = (np + kPartsBlock - 1) / kPartsBlock;
     const uint32_t b = min(np, threadIdx.x * per), e = min(np, b + per);
@@ -123,11 +128,11 @@ __global__ void __launch_bounds__(kPartsBlock) k_q_parts(uint64_t *part, uint32_
     if (threadIdx.x == 0) part[np] = total;
 }
 
-// Q[y] for y in the block's tile (each thread kQItems consecutive entries);
-// the block holding len also writes Q[len].
-__global__ void __launch_bounds__(kBlock) k_q_tile_scan(const uint32_t *nd, const uint32_t *X,
-                                                        uint64_t len, const uint64_t *part,
-                                                        uint64_t *Q) {
+// out[y] for y in the block's tile (each thread kQItems consecutive values);
+// the block holding len also writes out[len].
+template <class L>
+__global__ void __launch_bounds__(kBlock) k_u64_tile_scan(L ld, uint64_t len, const uint64_t *part,
+                                                          uint64_t *Q) {
     __shared__ uint64_t lds[kBlock / kWave];
     const uint64_t base = (uint64_t)blockIdx.x * kQTile + (uint64_t)threadIdx.x * kQItems;
     uint64_t v[kQItems];
@@ -135,7 +140,7 @@ __global__ void __launch_bounds__(kBlock) k_q_tile_scan(const uint32_t *nd, cons
 #pragma unroll
     for (uint32_t k = 0; k < kQItems; k++) {
         const uint64_t y = base + k;
-        v[k] = y < len ? q_value(nd, X, y) : 0;
+        v[k] = y < len ? ld(y) : 0;
         s += v[k];
     }
     uint64_t total;
@@ -233,10 +238,13 @@ __device__ inline uint32_t lower_time(const int64_t *T, uint32_t lo, uint32_t hi
 //   (in, out) = sum over out-entries l in [a, b) of (X[l] - X[a])
 //             = Q[b] - Q[a] - n0 X[a],  (out, in) = n0 n1 - (in, out).
 // Counter [d1][d2][d3], d = 0 for out (the paper's o), 1 for in.
+// The same pass writes each entry's window sizes for the paths: w[p] = (later
+// entries of S_c inside delta, earlier ones).
 __global__ void __launch_bounds__(kBlock) k_star4(const int64_t *T, const uint32_t *nd,
                                                   const uint32_t *C, const uint32_t *off,
                                                   const uint32_t *X, const uint64_t *Q,
-                                                  uint64_t len, int64_t delta, uint64_t *rows) {
+                                                  uint64_t len, int64_t delta, uint64_t *rows,
+                                                  uint2 *w) {
     __shared__ uint64_t red[kBlock / kWave][8];
     uint64_t acc[8];
 #pragma unroll
@@ -244,7 +252,10 @@ __global__ void __launch_bounds__(kBlock) k_star4(const int64_t *T, const uint32
     for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < len;
          p += (uint64_t)gridDim.x * kBlock) {
         const uint32_t c = C[p];
-        const uint32_t R = last_le_from(T, (uint32_t)p, off[c + 1], T[p] + delta);
+        const int64_t tp = T[p];
+        const uint32_t R = last_le_from(T, (uint32_t)p, off[c + 1], tp + delta);
+        const uint32_t L = first_ge_back(T, off[c], (uint32_t)p, tp - delta);
+        w[p] = make_uint2(R - (uint32_t)p, (uint32_t)p - L);
         if (R <= p + 1) continue;  // fewer than two later entries
         const uint32_t a = (uint32_t)p + 1, b = R + 1;
         const uint64_t xa = X[a];
@@ -298,95 +309,161 @@ struct PathArgs {
 // in-entries of [a, b) (a <= b)
 __device__ inline uint64_t ins(const uint32_t *X, uint32_t a, uint32_t b) { return X[b] - X[a]; }
 
-// One walk of window W against window V by rank: for each w in W, the entries
-// of V before w (lo) and after w (hi); an entry of the same edge (a parallel
-// edge seen from both ends) falls in neither.  V_IS_D: V is the window at d.
-// The counters per (walked side, order) are passed as template indices.
+// Window sizes of edge r as the middle edge e = s -> d, e at ps in S_s and
+// pd in S_d: (|As|, |Ad|, |Bs|, |Bd|) with As = (ps, R_s], Ad = (pd, R_d] the
+// later entries inside delta and Bs = [L_s, ps), Bd = [L_d, pd) the earlier
+// ones, gathered from the per-entry sizes.
+__global__ void __launch_bounds__(kBlock) k_path_prep(const uint32_t *epos, const uint2 *w,
+                                                      uint64_t m, uint4 *sz) {
+    for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < m;
+         r += (uint64_t)gridDim.x * kBlock) {
+        const uint2 pp = reinterpret_cast<const uint2 *>(epos)[r];
+        const uint2 a = w[pp.x], b = w[pp.y];
+        sz[r] = make_uint4(a.x, b.x, a.y, b.y);
+    }
+}
+
+// The four pairings walk the smaller window: e first (As, Ad), e last (Bs,
+// Bd), e second with x first (Bs, Ad) and with y first (Bd, As).
+__device__ inline void path_costs(uint4 z, uint32_t (&c)[4]) {
+    c[0] = min(z.x, z.y);
+    c[1] = min(z.z, z.w);
+    c[2] = min(z.z, z.y);
+    c[3] = min(z.w, z.x);
+}
+
+struct CostLoad {
+    const uint4 *sz;
+    __device__ inline uint64_t operator()(uint64_t r) const {
+        uint32_t c[4];
+        path_costs(sz[r], c);
+        return (uint64_t)c[0] + c[1] + c[2] + c[3];
+    }
+};
+
+// Items are numbered edge by edge (io = exclusive prefix of the costs); a
+// wave takes 64 consecutive items.  ce[c] = the edge of item 64c (the last
+// edge for the chunk past the end).
+__global__ void __launch_bounds__(kBlock) k_chunk_edges(const uint64_t *io, uint64_t m,
+                                                        uint64_t n_items, uint64_t n_chunks,
+                                                        uint32_t *ce) {
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c <= n_chunks;
+         c += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t item = min(c * kWave, n_items - 1);
+        uint64_t lo = 0, hi = m;  // largest r with io[r] <= item
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (io[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        ce[c] = (uint32_t)lo;
+    }
+}
+
+// Per walked set (which window is walked against which), the counters of the
+// searched window's entries, indexed [slot * 2 + b] for the walked entry's
+// direction bit b; rank walks have four slots (in / out before it, in / out
+// after it), time walks two (in / out inside delta).
 template <int A0, int A1, int B0, int B1, int C0, int C1, int D0, int D1>
-__device__ inline void walk_rank(const PathArgs &g, Range W, Range V, uint64_t (&acc)[24]) {
-    for (uint32_t w = W.lo; w < W.hi; w++) {
-        const uint32_t r = g.rk[w], b = g.nd[w] & 1u;
-        const uint32_t lb = lower_rank(g.rk, V.lo, V.hi, r);
-        const uint32_t ub = lb + ((lb < V.hi && g.rk[lb] == r) ? 1u : 0u);
-        const uint64_t in_lo = ins(g.X, V.lo, lb), out_lo = (lb - V.lo) - in_lo;
-        const uint64_t in_hi = ins(g.X, ub, V.hi), out_hi = (V.hi - ub) - in_hi;
-        sel_add<A0, A1>(acc, b, in_lo);
-        sel_add<B0, B1>(acc, b, out_lo);
-        sel_add<C0, C1>(acc, b, in_hi);
-        sel_add<D0, D1>(acc, b, out_hi);
-    }
+__device__ inline void add_rank(uint64_t (&acc)[24], uint32_t b, uint64_t il, uint64_t ol,
+                                uint64_t ih, uint64_t oh) {
+    sel_add<A0, A1>(acc, b, il);
+    sel_add<B0, B1>(acc, b, ol);
+    sel_add<C0, C1>(acc, b, ih);
+    sel_add<D0, D1>(acc, b, oh);
 }
 
-// For each w in W (earlier window), the entries of V (later window) with
-// t <= t_w + delta: V's prefix [V.lo, upper).
-template <int A0, int A1, int B0, int B1>
-__device__ inline void walk_fwd(const PathArgs &g, Range W, Range V, uint64_t (&acc)[24]) {
-    for (uint32_t w = W.lo; w < W.hi; w++) {
-        const uint32_t b = g.nd[w] & 1u;
+// One item: the j-th walked entry of one pairing of edge r's windows.
+__device__ inline void path_item(const PathArgs &g, const uint4 *sz, uint64_t r, uint64_t j,
+                                 uint64_t (&acc)[24]) {
+    const uint4 z = sz[r];
+    uint32_t c[4];
+    path_costs(z, c);
+    const uint32_t ps = g.epos[2 * r], pd = g.epos[2 * r + 1];
+    const Range As{ps + 1, ps + 1 + z.x}, Ad{pd + 1, pd + 1 + z.y};
+    const Range Bs{ps - z.z, ps}, Bd{pd - z.w, pd};
+    int set;
+    Range W, V;
+    if (j < c[0]) {
+        const bool wx = z.x <= z.y;
+        set = wx ? 0 : 1;
+        W = wx ? As : Ad;
+        V = wx ? Ad : As;
+    } else if ((j -= c[0]) < c[1]) {
+        const bool wx = z.z <= z.w;
+        set = wx ? 2 : 3;
+        W = wx ? Bs : Bd;
+        V = wx ? Bd : Bs;
+    } else if ((j -= c[1]) < c[2]) {
+        const bool wx = z.z <= z.y;
+        set = wx ? 4 : 5;
+        W = wx ? Bs : Ad;
+        V = wx ? Ad : Bs;
+    } else {
+        j -= c[2];
+        const bool wy = z.w <= z.x;
+        set = wy ? 6 : 7;
+        W = wy ? Bd : As;
+        V = wy ? As : Bd;
+    }
+    const uint32_t w = W.lo + (uint32_t)j;
+    const uint32_t b = g.nd[w] & 1u;
+    uint64_t il, ol, ih = 0, oh = 0;
+    if (set < 4) {
+        // by rank: entries of V before w and after w (an entry of the same
+        // edge, a parallel edge seen from both ends, is in neither)
+        const uint32_t rw = g.rk[w];
+        const uint32_t lb = lower_rank(g.rk, V.lo, V.hi, rw);
+        const uint32_t ub = lb + ((lb < V.hi && g.rk[lb] == rw) ? 1u : 0u);
+        il = ins(g.X, V.lo, lb);
+        ol = (lb - V.lo) - il;
+        ih = ins(g.X, ub, V.hi);
+        oh = (V.hi - ub) - ih;
+    } else if (set == 4 || set == 6) {
+        // W earlier than V: V's entries with t <= t_w + delta
         const uint32_t u = upper_time(g.T, V.lo, V.hi, g.T[w] + g.delta);
-        const uint64_t in = ins(g.X, V.lo, u), out = (u - V.lo) - in;
-        sel_add<A0, A1>(acc, b, in);
-        sel_add<B0, B1>(acc, b, out);
-    }
-}
-
-// For each w in W (later window), the entries of V (earlier window) with
-// t >= t_w - delta: V's suffix [lower, V.hi).
-template <int A0, int A1, int B0, int B1>
-__device__ inline void walk_back(const PathArgs &g, Range W, Range V, uint64_t (&acc)[24]) {
-    for (uint32_t w = W.lo; w < W.hi; w++) {
-        const uint32_t b = g.nd[w] & 1u;
+        il = ins(g.X, V.lo, u);
+        ol = (u - V.lo) - il;
+    } else {
+        // W later than V: V's entries with t >= t_w - delta
         const uint32_t l = lower_time(g.T, V.lo, V.hi, g.T[w] - g.delta);
-        const uint64_t in = ins(g.X, l, V.hi), out = (V.hi - l) - in;
-        sel_add<A0, A1>(acc, b, in);
-        sel_add<B0, B1>(acc, b, out);
+        il = ins(g.X, l, V.hi);
+        ol = (V.hi - l) - il;
+    }
+    switch (set) {
+        case 0: add_rank<3, 2, 1, 0, 4, 6, 5, 7>(acc, b, il, ol, ih, oh); break;          // x in As
+        case 1: add_rank<7, 6, 5, 4, 0, 2, 1, 3>(acc, b, il, ol, ih, oh); break;          // y in Ad
+        case 2: add_rank<22, 20, 18, 16, 17, 21, 19, 23>(acc, b, il, ol, ih, oh); break;  // x in Bs
+        case 3: add_rank<23, 21, 19, 17, 16, 20, 18, 22>(acc, b, il, ol, ih, oh); break;  // y in Bd
+        case 4: sel_add<10, 14>(acc, b, il); sel_add<11, 15>(acc, b, ol); break;          // x in Bs
+        case 5: sel_add<15, 14>(acc, b, il); sel_add<11, 10>(acc, b, ol); break;          // y in Ad
+        case 6: sel_add<8, 12>(acc, b, il); sel_add<9, 13>(acc, b, ol); break;            // y in Bd
+        default: sel_add<13, 12>(acc, b, il); sel_add<9, 8>(acc, b, ol); break;           // x in As
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_path4(PathArgs g, uint64_t *rows) {
+__global__ void __launch_bounds__(kBlock) k_path_items(PathArgs g, const uint4 *sz,
+                                                       const uint64_t *io, const uint32_t *ce,
+                                                       uint64_t n_items, uint64_t n_chunks,
+                                                       uint64_t *rows) {
     __shared__ uint64_t red[kBlock / kWave][24];
     uint64_t acc[24];
 #pragma unroll
     for (int i = 0; i < 24; i++) acc[i] = 0;
-    for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < g.m;
-         r += (uint64_t)gridDim.x * kBlock) {
-        const uint32_t ps = g.epos[2 * r], pd = g.epos[2 * r + 1];
-        const uint32_t s = g.C[ps], d = g.C[pd];
-        const int64_t te = g.T[ps];
-        const uint32_t s0 = g.off[s], s1 = g.off[s + 1], d0 = g.off[d], d1 = g.off[d + 1];
-        // windows of entries after / before e at s and at d
-        const Range As{ps + 1, last_le_from(g.T, ps, s1, te + g.delta) + 1};
-        const Range Ad{pd + 1, last_le_from(g.T, pd, d1, te + g.delta) + 1};
-        const Range Bs{first_ge_back(g.T, s0, ps, te - g.delta), ps};
-        const Range Bd{first_ge_back(g.T, d0, pd, te - g.delta), pd};
-        // e first: x in As, y in Ad
-        if (As.size() && Ad.size()) {
-            if (As.size() <= Ad.size())
-                walk_rank<3, 2, 1, 0, 4, 6, 5, 7>(g, As, Ad, acc);   // walk x
-            else
-                walk_rank<7, 6, 5, 4, 0, 2, 1, 3>(g, Ad, As, acc);   // walk y
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (uint64_t)gridDim.x * (kBlock / kWave);
+    for (uint64_t c = (uint64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; c < n_chunks;
+         c += waves) {
+        const uint64_t item = c * kWave + lane;
+        if (item >= n_items) continue;
+        // the item's edge: the largest r in [ce[c], ce[c + 1]] with io[r] <= item
+        uint64_t lo = ce[c], hi = (uint64_t)ce[c + 1] + 1;
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (io[mid] <= item) lo = mid;
+            else hi = mid;
         }
-        // e last: x in Bs, y in Bd
-        if (Bs.size() && Bd.size()) {
-            if (Bs.size() <= Bd.size())
-                walk_rank<22, 20, 18, 16, 17, 21, 19, 23>(g, Bs, Bd, acc);
-            else
-                walk_rank<23, 21, 19, 17, 16, 20, 18, 22>(g, Bd, Bs, acc);
-        }
-        // e second, x first: x in Bs, y in Ad with t_y <= t_x + delta
-        if (Bs.size() && Ad.size()) {
-            if (Bs.size() <= Ad.size())
-                walk_fwd<10, 14, 11, 15>(g, Bs, Ad, acc);
-            else
-                walk_back<15, 14, 11, 10>(g, Ad, Bs, acc);
-        }
-        // e second, y first: y in Bd, x in As with t_x <= t_y + delta
-        if (Bd.size() && As.size()) {
-            if (Bd.size() <= As.size())
-                walk_fwd<8, 12, 9, 13>(g, Bd, As, acc);
-            else
-                walk_back<13, 12, 9, 8>(g, As, Bd, acc);
-        }
+        path_item(g, sz, lo, item - io[lo], acc);
     }
     block_rows<24>(acc, red, rows + (uint64_t)blockIdx.x * 24);
 }
@@ -409,7 +486,7 @@ struct E3 {
 
 // The path counters the kernel's enumeration adds for one three-edge
 // instance: every middle edge e, x != e at src(e), y != e, x at dst(e),
-// classified with the rules of k_path4.
+// classified with the rules of path_item.
 void path_choices(const E3 (&ed)[3], uint64_t (&h)[24]) {
     for (int e = 0; e < 3; e++) {
         const int s = ed[e].s, d = ed[e].d;
@@ -487,35 +564,71 @@ int count4_graph(tm_graph *g, int64_t delta, uint64_t *raw56, uint64_t *out32) {
     const uint64_t len = 2 * g->m;
     if (g->m >= 3) {
         hipStream_t s = g->stream;
-        const uint32_t np = (uint32_t)(len / kQTile + 1);  // tiles covering [0, len]
+        const uint64_t m = g->m;
+        const uint32_t npq = (uint32_t)(len / kQTile + 1);  // tiles covering [0, len]
+        const uint32_t npc = (uint32_t)(m / kQTile + 1);    // tiles covering [0, m]
         const uint32_t gs = (uint32_t)std::min<uint64_t>(kStarGrid, (len + kBlock - 1) / kBlock);
-        const uint32_t gp = (uint32_t)std::min<uint64_t>(kPathGrid, (g->m + kBlock - 1) / kBlock);
+        const uint32_t gp = (uint32_t)std::min<uint64_t>(kPathGrid, (m + kBlock - 1) / kBlock);
         auto rnd = [](size_t b) { return (b + 255) & ~size_t(255); };
-        const size_t bytes = rnd((len + 1) * 8) + rnd((size_t)(np + 1) * 8) + rnd((size_t)gs * 64) +
-                             rnd((size_t)gp * 192) + rnd(32 * 8);
+        const size_t bytes = rnd((len + 1) * 8) + rnd((size_t)(std::max(npq, npc) + 1) * 8) +
+                             rnd((size_t)gs * 64) + rnd((size_t)kPathGrid * 192) + rnd(32 * 8) +
+                             rnd(m * 16) + rnd((m + 1) * 8) + rnd(len * 8);
         Scratch sc;
         rc = sc.reserve(bytes, s);
         if (rc) return rc;
         uint64_t *Q = sc.take<uint64_t>(len + 1);
-        uint64_t *part = sc.take<uint64_t>(np + 1);
+        uint64_t *part = sc.take<uint64_t>(std::max(npq, npc) + 1);
         uint64_t *srows = sc.take<uint64_t>((size_t)gs * 8);
-        uint64_t *prows = sc.take<uint64_t>((size_t)gp * 24);
+        uint64_t *prows = sc.take<uint64_t>((size_t)kPathGrid * 24);
         uint64_t *dsum = sc.take<uint64_t>(32);
-        if (!Q || !part || !srows || !prows || !dsum) {
+        uint4 *sz = sc.take<uint4>(m);
+        uint64_t *io = sc.take<uint64_t>(m + 1);
+        uint2 *wfb = sc.take<uint2>(len);
+        if (!Q || !part || !srows || !prows || !dsum || !sz || !io || !wfb) {
             set_error("four-node workspace carve");
             return TM_EINTERNAL;
         }
         ProfRow row("f4");
-        TM_LAUNCH("q_tile_sum", k_q_tile_sum, dim3(np), dim3(kBlock), 0, s, g->ent_nd, g->X, len, part);
-        TM_LAUNCH("q_parts", k_q_parts, dim3(1), dim3(kPartsBlock), 0, s, part, np);
-        TM_LAUNCH("q_tile_scan", k_q_tile_scan, dim3(np), dim3(kBlock), 0, s, g->ent_nd, g->X, len,
-                  part, Q);
+        // stars
+        const QLoad ql{g->ent_nd, g->X};
+        TM_LAUNCH("q_tile_sum", k_u64_tile_sum<QLoad>, dim3(npq), dim3(kBlock), 0, s, ql, len, part);
+        TM_LAUNCH("q_parts", k_u64_parts, dim3(1), dim3(kPartsBlock), 0, s, part, npq);
+        TM_LAUNCH("q_tile_scan", k_u64_tile_scan<QLoad>, dim3(npq), dim3(kBlock), 0, s, ql, len, part, Q);
         TM_LAUNCH("star4", k_star4, dim3(gs), dim3(kBlock), 0, s, g->ent_t, g->ent_nd, g->ent_c,
-                  g->off, g->X, Q, len, delta, srows);
-        PathArgs pa{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos, g->m, delta};
-        TM_LAUNCH("path4", k_path4, dim3(gp), dim3(kBlock), 0, s, pa, prows);
+                  g->off, g->X, Q, len, delta, srows, wfb);
         TM_LAUNCH("sum_rows", k_sum_rows, dim3(8), dim3(kBlock), 0, s, srows, gs, 8u, dsum);
-        TM_LAUNCH("sum_rows", k_sum_rows, dim3(24), dim3(kBlock), 0, s, prows, gp, 24u, dsum + 8);
+        // paths: window sizes, item numbering, items
+        const PathArgs pa{g->ent_t, g->ent_nd, g->ent_r, g->ent_c, g->X, g->off, g->epos, m, delta};
+        TM_LAUNCH("path_prep", k_path_prep, dim3(gp), dim3(kBlock), 0, s, g->epos, wfb, m, sz);
+        const CostLoad cl{sz};
+        TM_LAUNCH("cost_tile_sum", k_u64_tile_sum<CostLoad>, dim3(npc), dim3(kBlock), 0, s, cl, m, part);
+        TM_LAUNCH("cost_parts", k_u64_parts, dim3(1), dim3(kPartsBlock), 0, s, part, npc);
+        TM_LAUNCH("cost_tile_scan", k_u64_tile_scan<CostLoad>, dim3(npc), dim3(kBlock), 0, s, cl, m,
+                  part, io);
+        uint64_t n_items = 0;
+        TM_HIP_TRY(hipMemcpyAsync(&n_items, io + m, 8, hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipStreamSynchronize(s));
+        uint32_t gi = 1;
+        if (n_items) {
+            const uint64_t n_chunks = (n_items + kWave - 1) / kWave;
+            Scratch sc2;
+            rc = sc2.reserve(rnd((n_chunks + 1) * 4), s);
+            if (rc) return rc;
+            uint32_t *ce = sc2.take<uint32_t>(n_chunks + 1);
+            if (!ce) {
+                set_error("four-node workspace carve");
+                return TM_EINTERNAL;
+            }
+            TM_LAUNCH("chunk_edges", k_chunk_edges,
+                      dim3((unsigned)std::min<uint64_t>(16384, n_chunks / kBlock + 1)), dim3(kBlock), 0,
+                      s, io, m, n_items, n_chunks, ce);
+            gi = (uint32_t)std::min<uint64_t>(kPathGrid, n_chunks / (kBlock / kWave) + 1);
+            TM_LAUNCH("path_items", k_path_items, dim3(gi), dim3(kBlock), 0, s, pa, sz, io, ce, n_items,
+                      n_chunks, prows);
+            TM_LAUNCH("sum_rows", k_sum_rows, dim3(24), dim3(kBlock), 0, s, prows, gi, 24u, dsum + 8);
+        } else {
+            TM_HIP_TRY(hipMemsetAsync(dsum + 8, 0, 24 * 8, s));
+        }
         TM_HIP_TRY(hipMemcpyAsync(sums, dsum, sizeof(sums), hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
     }

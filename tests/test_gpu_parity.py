@@ -322,7 +322,7 @@ def test_skewed_full_size(tm):
     repeated pairs, a hub of ~1e6 edges; delta 600 / 3,600 / 86,400), built
     from device pointers as bench.py does, against the oracle's counts stored
     by tests/golden/make_golden.py; at delta 86,400 also with the hub slice
-    kernel off.  Skipped when this host regenerates a different edge list
+    kernel off; the four-node motif counts at delta 600.  Skipped when this host regenerates a different edge list
     (the oracle takes minutes on it)."""
     import torch
     rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "skewed_counts.json")))
@@ -350,6 +350,15 @@ def test_skewed_full_size(tm):
         for i, key in enumerate(rec["counts"]):
             np.testing.assert_array_equal(multi[i], np.array(rec["counts"][key]["raw"], dtype=np.uint64),
                                           err_msg=f"one pass, delta={key}")
+        # four-node motifs (tm_count4) against the oracle's stored counts
+        rec4 = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                           "motif4_counts.json")))["skewed"]
+        assert rec4["edge_sha256"] == rec["edge_sha256"]
+        for key, val in rec4["counts"].items():
+            case(f"skewed full four-node motifs delta={key}")
+            got, raw = G.count4(int(key), with_raw=True)
+            np.testing.assert_array_equal(got, np.array(val["f4"], dtype=np.uint64))
+            np.testing.assert_array_equal(raw, np.array(val["raw"], dtype=np.uint64))
     del s, d, t
     torch.cuda.empty_cache()
 
