@@ -234,9 +234,9 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
         # the two star/pair records (8 B each, with X read next to the entry;
         # counted here as one); one graph: the three window bit planes too
         "windows": e2 * (12 + 12 * levels) + (n + 1) * 4 + e2 / 8 + e2 / 4,
-        # per element its record; per side its position and the two window
-        # records of its entry
-        "star_pair": me * 25 + 2 * me * 24,
+        # per element its record, once for all windows of the pass; per side
+        # and window its position and the two window records of its entry
+        "star_pair": me * 25 + levels * 2 * me * 24,
         "wlevels": e2 * 4 + e2 / 8 + e2 / 4,
         "tri_flags": m * (8 + 4) + e2 / 8,
         "hub_tiles": e2 / 4 + e2 / HUB_SLICE * 64,

@@ -318,8 +318,9 @@ struct StarArgs {
     const uint8_t *me_o;
     const uint4 *me_a;
     const uint2 *me_p;       // element positions in S_lo, S_hi
-    const uint2 *recR, *recL;  // window records of entry p for this window: [p * K + level]
-    uint32_t K, level;
+    const uint2 *recR, *recL;  // window records of entry p: [p * K + level]
+    uint32_t K;              // windows of the pass; each tile runs all of them
+    uint64_t part_stride;    // partial rows of window i start at partial + i * part_stride
     const uint32_t *first;   // n_multi + 1: first work item of each pair (exclusive scan)
     const uint32_t *ipair;   // work item -> its pair
     uint64_t n_multi;
@@ -327,7 +328,7 @@ struct StarArgs {
     const uint32_t *mpb;     // G + 1: multi-edge pair bounds per graph
     const uint32_t *tfirst;  // G + 1: first item tile of each graph
     uint32_t G;
-    const int64_t *deltas;
+    const int64_t *deltas;   // K == 1: per graph; K > 1 (one graph): per window
     uint32_t chunk;
     int star_i;              // run the Star_I sweep (stars requested)
 };
@@ -449,7 +450,6 @@ k_star_pair(StarArgs a, uint64_t *partial) {
   const uint32_t n_tiles = a.tfirst[a.G];
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const uint32_t gi = last_le(a.tfirst, a.G + 1, ti);
-    const int64_t delta = a.deltas[gi];
     const uint32_t ib = a.first[a.mpb[gi]] + (ti - a.tfirst[gi]) * kItemTile;
     const uint32_t ie = min(a.first[a.mpb[gi + 1]], ib + kItemTile);
     // element range of the tile's items, plus halos, clipped to the capacity
@@ -467,9 +467,6 @@ k_star_pair(StarArgs a, uint64_t *partial) {
         s_a[k - lo] = a.me_a[k];
     }
     __syncthreads();
-    const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a, a.me_p, a.recR, a.recL, a.K,
-                     a.level};
-    uint64_t *row = partial + (uint64_t)ti * 32;
     // element ranges of this thread's items: the pair [rs, re), the chunk [cb, ce)
     uint32_t rs_[kSPItems], re_[kSPItems], cb_[kSPItems], ce_[kSPItems];
 #pragma unroll
@@ -484,6 +481,14 @@ k_star_pair(StarArgs a, uint64_t *partial) {
             ce_[u] = min(re_[u], cb_[u] + a.chunk);
         }
     }
+    // every window of the pass on the staged tile, one after another, so that
+    // the records of one entry (side by side for all windows) are read while
+    // their line is still cached
+    for (uint32_t level = 0; level < a.K; level++) {
+    const int64_t delta = a.deltas[gi + level];
+    const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a, a.me_p, a.recR, a.recL, a.K,
+                     level};
+    uint64_t *row = partial + level * a.part_stride + (uint64_t)ti * 32;
     {
         // ---- phase 1, e1 sweeps: Pair, Star_II, Star_III (cell c -> A[c - 8])
         uint64_t A[24];
@@ -581,6 +586,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
         }
         }
         star_flush<8>(A, 0, red, row);
+    }
     }
   }
 }
@@ -1463,13 +1469,11 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
                   pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, K, h_stride, w.hpart);
     }
     if (nm) {
-        for (uint32_t i = 0; i < K; i++) {
-            StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, g->me_p, w.recR, w.recL, K, i,
-                        w.first, w.ipair, nm, nme, g->d_mpb, w.tfirst, G, w.deltas + i, run_chunk,
-                        (families & TM_STARS) ? 1 : 0};
-            TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
-                      dim3(kBlock), 0, s, sa, w.spart + i * s_stride);
-        }
+        StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, g->me_p, w.recR, w.recL, K, s_stride,
+                    w.first, w.ipair, nm, nme, g->d_mpb, w.tfirst, G, w.deltas, run_chunk,
+                    (families & TM_STARS) ? 1 : 0};
+        TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
+                  dim3(kBlock), 0, s, sa, w.spart);
     }
     if (do_tri) {
         ProfRow row_a5("a5");
