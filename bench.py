@@ -195,8 +195,9 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
     value) pair once; histogram passes read every key once.  The time sort
     of one graph reads the input arrays (src, dst, t: 16 B per edge) in its
     histogram and first pass, and its last pass writes the rank-ordered
-    arrays (t, input index, the two node-sort entries, pair key and value:
-    64 B per edge).  The node sort's last pass writes the sequence arrays
+    arrays (t, input index, the two node-sort entries: 52 B per edge).  The
+    pair sort reads each edge once from its entry at the smaller node and
+    sorts (larger node, (smaller node, rank)) pairs on the node bits.  The node sort's last pass writes the sequence arrays
     (node, t, other end | dir, rank) and each entry's slot instead of the
     ping-pong buffers; each edge's two positions come from a two-pass
     partition of (slot, position) pairs and a bucket fill."""
@@ -204,7 +205,7 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
     tk = 4 if info["tbits"] <= 32 else 8
     me, nm = info["multi_pair_edges"], info["multi_pairs"]
     pt = max(passes["time"], 1)
-    time_first = 16 + ((tk + 12) if pt > 1 else 64)
+    time_first = 16 + ((tk + 12) if pt > 1 else 52)
     # "sort_time_scatter": every pass but the last (the first reads the inputs)
     time_scatter = ((m * time_first + m * (tk + 12) * 2 * max(pt - 2, 0)) / (pt - 1)
                     if pt > 1 else 0)
@@ -213,7 +214,7 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
         "time_keys": m * (16 + tk + 12),   # batches only
         "sort_time_hist": m * 8,
         "sort_time_scatter": time_scatter,
-        "sort_time_scatter_last": m * (tk + 12 + 64) if pt > 1 else m * (16 + 64),
+        "sort_time_scatter_last": m * (tk + 12 + 52) if pt > 1 else m * (16 + 52),
         "sort_node_hist": e2 * 4,
         "sort_node_scatter": e2 * 40,
         # the last pass also writes each entry's slot (2r + dir) in entry order
@@ -226,7 +227,7 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
         "epos_fill": e2 * (8 + 4),
         "offsets_fill": (n + 1) * 4,
         "offsets": e2 * 4 + (n + 1) * 4,
-        "sort_pair_hist": m * 8,
+        "sort_pair_hist": m * 4,
         "sort_pair_scatter": m * (8 + 4) * 2,
         "multi_flags": m * (8 + 8),
         "multi_fill": m * 28 + me * (32 + 33) + nm * 12,

@@ -158,13 +158,13 @@ __global__ void k_offsets_gaps(const uint32_t *skey, uint64_t len, uint32_t n, u
 }
 
 // Element g of the pair-sorted edges lies in a pair with >= 2 edges; head = first of its pair.
-__global__ void k_multi_flags(const uint64_t *pkey, uint64_t m, uint32_t *in_multi,
-                              uint32_t *multi_head) {
+__global__ void k_multi_flags(const uint32_t *pkey, const uint2 *pval, uint64_t m,
+                              uint32_t *in_multi, uint32_t *multi_head) {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m;
          g += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = pkey[g];
-        const bool same_prev = g > 0 && pkey[g - 1] == k;
-        const bool same_next = g + 1 < m && pkey[g + 1] == k;
+        const uint32_t k = pkey[g], lo = pval[g].x;
+        const bool same_prev = g > 0 && pkey[g - 1] == k && pval[g - 1].x == lo;
+        const bool same_next = g + 1 < m && pkey[g + 1] == k && pval[g + 1].x == lo;
         in_multi[g] = (same_prev || same_next) ? 1u : 0u;
         multi_head[g] = (!same_prev && same_next) ? 1u : 0u;
     }
@@ -178,7 +178,7 @@ struct MultiOut {
     uint8_t *me_o;
 };
 
-__global__ void k_multi_fill(const uint64_t *pkey, const uint32_t *pval, uint64_t m, uint64_t n,
+__global__ void k_multi_fill(const uint32_t *pkey, const uint2 *pval, uint64_t m,
                              const uint32_t *in_multi, const uint32_t *eidx,
                              const uint32_t *multi_head, const uint32_t *pidx,
                              const int64_t *t_r, const uint32_t *epos, const uint32_t *X,
@@ -188,15 +188,15 @@ __global__ void k_multi_fill(const uint64_t *pkey, const uint32_t *pval, uint64_
         if (g == 0) o.mp_start[n_multi] = (uint32_t)n_me;
         if (!in_multi[g]) continue;
         const uint32_t k = eidx[g];
-        const uint64_t key = pkey[g];
-        const uint32_t lo = (uint32_t)(key / n), hi = (uint32_t)(key % n);
+        const uint2 pv = pval[g];
+        const uint32_t lo = pv.x, hi = pkey[g];
         if (multi_head[g]) {
             const uint32_t q = pidx[g];
             o.mp_start[q] = k;
             o.mp_lo[q] = lo;
             o.mp_hi[q] = hi;
         }
-        const uint32_t el = pval[g];
+        const uint32_t el = pv.y;
         const uint32_t r = el & ~kOrientBit;
         const uint32_t src_is_lo = el >> 31;
         // entry of this edge at lo / at hi: the src entry sits at 2r, the dst entry at 2r+1
@@ -211,18 +211,19 @@ __global__ void k_multi_fill(const uint64_t *pkey, const uint32_t *pval, uint64_
     }
 }
 
-// Per graph: first S_u position, first multi-edge pair and its first element.
+// Per graph: first S_u position, first multi-edge pair and its first element
+// (pairs are ordered by their larger node, which lies in their graph).
 __global__ void k_graph_ranges(const uint32_t *off, const uint32_t *node_base, uint32_t G,
-                               const uint32_t *mp_lo, uint64_t n_multi, const uint32_t *mp_start,
+                               const uint32_t *mp_hi, uint64_t n_multi, const uint32_t *mp_start,
                                uint32_t *ent_off, uint32_t *mpb, uint32_t *me_off) {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= G;
          g += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t nb = node_base[g];
         ent_off[g] = off[nb];
-        uint64_t a = 0, b = n_multi;  // first pair whose smaller node is >= nb
+        uint64_t a = 0, b = n_multi;  // first pair whose larger node is >= nb
         while (a < b) {
             const uint64_t mid = a + (b - a) / 2;
-            if (mp_lo[mid] < nb) a = mid + 1;
+            if (mp_hi[mid] < nb) a = mid + 1;
             else b = mid;
         }
         mpb[g] = (uint32_t)a;
@@ -409,7 +410,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     // ---- scratch (stream-ordered, released when this function returns)
     // KA, KB: 8 bytes x 2m each   (time keys, node keys)
     // VA, VB: 16 bytes x 2m each  (EdgeVal of m, NodeVal of 2m)
-    // PKA, PKB: u64 x m; PVA, PVB: u32 x m   (pair sort)
+    // PKA, PKB: 8 bytes x m; PVA, PVB: u32 x m   (pair sort values, keys)
     // TR: i64 x m                 (timestamps by rank)
     // TMP: scan / histogram scratch
     const size_t ntmp =
@@ -444,7 +445,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         const bool to_b = (tpasses % 2) == 1;
         nkey = reinterpret_cast<uint32_t *>(to_b ? KB : KA);
         nval = reinterpret_cast<NodeVal *>(to_b ? VB : VA);
-        const RankOut ro{g->d_tmin, G > 1 ? tbits : 64, n, TR, g->perm, nkey, nval, PKA, PVA};
+        const RankOut ro{g->d_tmin, G > 1 ? tbits : 64, TR, g->perm, nkey, nval};
         EdgeVal *ev = reinterpret_cast<EdgeVal *>(VA), *ev_alt = reinterpret_cast<EdgeVal *>(VB);
         const dim3 tgrid((unsigned)std::min<uint32_t>(n_etiles, 4096));
         if (kbits <= 32) {
@@ -504,16 +505,17 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     // ---- 4. node-pair edge sets; the edges of pairs with >= 2 edges
     {
         ProfRow row_a3("a3");
-        uint64_t *k = PKA, *k_alt = PKB;
-        uint32_t *v = PVA, *v_alt = PVB;
-        TRY(radix_sort_u64(&k, &k_alt, &v, &v_alt, m, bits_for(n * n - 1), tmp, sort_err, s,
-                           "sort_pair_hist", "sort_pair_scatter"));
+        // each edge once, from its entry at the smaller node, in S order
+        uint32_t *k = PVA, *k_alt = PVB;
+        uint2 *v = reinterpret_cast<uint2 *>(PKA), *v_alt = reinterpret_cast<uint2 *>(PKB);
+        TRY(lower_side_pairs(g->ent_c, g->ent_nd, g->ent_r, len, k, v, tmp, s));
+        TRY(radix_sort_pairs(&k, &k_alt, &v, &v_alt, m, bits_for(n - 1), tmp, sort_err, s));
         // flags and their scans reuse the (now free) node-sort buffers
         uint32_t *in_multi = reinterpret_cast<uint32_t *>(KA);
         uint32_t *head = reinterpret_cast<uint32_t *>(KB);
         uint32_t *eidx = reinterpret_cast<uint32_t *>(VA);
         uint32_t *pidx = reinterpret_cast<uint32_t *>(VB);
-        TM_LAUNCH("multi_flags", k_multi_flags, grid_for(m), dim3(kBlock), 0, s, k, m, in_multi,
+        TM_LAUNCH("multi_flags", k_multi_flags, grid_for(m), dim3(kBlock), 0, s, k, v, m, in_multi,
                   head);
         TRY(scan_u32_array(in_multi, eidx, m, tmp, s));
         TRY(scan_u32_array(head, pidx, m, tmp, s));
@@ -536,7 +538,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         TRY(galloc(g, &g->me_a, g->n_me));
         TRY(galloc(g, &g->me_o, g->n_me));
         MultiOut o{g->mp_start, g->mp_lo, g->mp_hi, g->me_t, g->me_p, g->me_a, g->me_o};
-        TM_LAUNCH("multi_fill", k_multi_fill, grid_for(m), dim3(kBlock), 0, s, k, v, m, n, in_multi,
+        TM_LAUNCH("multi_fill", k_multi_fill, grid_for(m), dim3(kBlock), 0, s, k, v, m, in_multi,
                   eidx, head, pidx, TR, g->epos, g->X, g->off, g->n_multi, g->n_me, o);
     }
 
@@ -545,7 +547,7 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         uint32_t *r3 = tmp;  // 3 x (G + 1)
         TRY(galloc(g, &g->d_mpb, G + 1));
         TM_LAUNCH("graph_ranges", k_graph_ranges, grid_for(G + 1), dim3(kBlock), 0, s, g->off, d_nb, G,
-                  g->mp_lo, g->n_multi, g->mp_start, r3, g->d_mpb, r3 + 2 * (G + 1));
+                  g->mp_hi, g->n_multi, g->mp_start, r3, g->d_mpb, r3 + 2 * (G + 1));
         std::vector<uint32_t> h(3 * (G + 1));
         if (G == 1) {
             // one graph: its ranges are the whole arrays, known here already

@@ -72,6 +72,11 @@ struct LoadDirBit {
     const uint32_t *nd;
     __device__ uint32_t operator()(uint64_t i) const { return nd[i] & 1u; }
 };
+// 1 for an entry of S seen from the smaller node of its edge
+struct LoadLowerSide {
+    const uint32_t *c, *nd;
+    __device__ uint32_t operator()(uint64_t i) const { return (nd[i] >> 1) > c[i] ? 1u : 0u; }
+};
 
 template <typename L>
 __global__ void __launch_bounds__(kBlock) k_tile_sum(L ld, uint64_t n, uint32_t *part) {
@@ -102,9 +107,36 @@ __global__ void __launch_bounds__(kBlock) k_scan_parts(uint32_t *part, uint32_t 
     if (threadIdx.x == 0) part[np] = carry;
 }
 
-template <typename L>
+// Where a scan's results go: wr(i, exclusive prefix, value) per element and
+// wr.total(n, total) once.  ArrayWrite stores the prefixes (out[n] = total).
+struct ArrayWrite {
+    uint32_t *out;
+    __device__ void operator()(uint64_t i, uint32_t ex, uint32_t) const { out[i] = ex; }
+    __device__ void total(uint64_t n, uint32_t t) const { out[n] = t; }
+};
+
+// The pair sort's input: each edge once, from its entry at the smaller node
+// (S order: smaller node, then (t, id)), as key = the larger node, value =
+// (smaller node, rank | orientation), compacted by the scan of LoadLowerSide.
+// A stable sort by the key then groups every node pair, its edges in (t, id)
+// order, pairs by (larger, smaller).
+struct LowerSideWrite {
+    const uint32_t *c, *nd, *r;
+    uint32_t *key;
+    uint2 *val;
+    __device__ void operator()(uint64_t i, uint32_t ex, uint32_t v) const {
+        if (!v) return;
+        const uint32_t e = nd[i];
+        key[ex] = e >> 1;
+        // direction bit 0: the edge leaves the center, so its source is the smaller node
+        val[ex] = make_uint2(c[i], r[i] | ((e & 1u) ? 0u : kOrientBit));
+    }
+    __device__ void total(uint64_t, uint32_t) const {}
+};
+
+template <typename L, typename W>
 __global__ void __launch_bounds__(kBlock) k_tile_scan(L ld, uint64_t n, const uint32_t *part,
-                                                      uint32_t np, uint32_t *out) {
+                                                      uint32_t np, W wr) {
     __shared__ uint32_t lds[kBlock / kWave];
     const uint64_t base = (uint64_t)blockIdx.x * kTile;
     uint32_t carry = part[blockIdx.x];
@@ -113,15 +145,15 @@ __global__ void __launch_bounds__(kBlock) k_tile_scan(L ld, uint64_t n, const ui
         uint32_t v = idx < n ? ld(idx) : 0;
         uint32_t tot;
         uint32_t inc = block_incl_scan(v, &tot, lds);
-        if (idx < n) out[idx] = carry + inc - v;
+        if (idx < n) wr(idx, carry + inc - v, v);
         carry += tot;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[np];
+    if (blockIdx.x == 0 && threadIdx.x == 0) wr.total(n, part[np]);
 }
 
 // The whole scan when the input fits one tile: one launch instead of three.
-template <typename L>
-__global__ void __launch_bounds__(kBlock) k_scan_one(L ld, uint64_t n, uint32_t *out) {
+template <typename L, typename W>
+__global__ void __launch_bounds__(kBlock) k_scan_one(L ld, uint64_t n, W wr) {
     __shared__ uint32_t lds[kBlock / kWave];
     uint32_t carry = 0;
     for (int i = 0; i < kItems; i++) {
@@ -129,30 +161,31 @@ __global__ void __launch_bounds__(kBlock) k_scan_one(L ld, uint64_t n, uint32_t 
         const uint32_t v = idx < n ? ld(idx) : 0;
         uint32_t tot;
         const uint32_t inc = block_incl_scan(v, &tot, lds);
-        if (idx < n) out[idx] = carry + inc - v;
+        if (idx < n) wr(idx, carry + inc - v, v);
         carry += tot;
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (threadIdx.x == 0) wr.total(n, carry);
 }
 
-__global__ void k_set_zero(uint32_t *p) { *p = 0; }
+template <typename W>
+__global__ void k_scan_empty(W wr) { wr.total(0, 0); }
 
-template <typename L>
-int scan_impl(L ld, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
+template <typename L, typename W = ArrayWrite>
+int scan_impl(L ld, W wr, uint64_t n, uint32_t *tmp, hipStream_t s) {
     const uint64_t nb = (n + kTile - 1) / kTile;
     if (nb == 0) {
         // a kernel, not a memset: this may run inside a captured graph
-        TM_LAUNCH("scan_empty", k_set_zero, dim3(1), dim3(1), 0, s, out);
+        TM_LAUNCH("scan_empty", k_scan_empty<W>, dim3(1), dim3(1), 0, s, wr);
         return TM_OK;
     }
     if (nb == 1) {
-        TM_LAUNCH("scan_one", (k_scan_one<L>), dim3(1), dim3(kBlock), 0, s, ld, n, out);
+        TM_LAUNCH("scan_one", (k_scan_one<L, W>), dim3(1), dim3(kBlock), 0, s, ld, n, wr);
         return TM_OK;
     }
     TM_LAUNCH("scan_tile_sum", (k_tile_sum<L>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp);
     TM_LAUNCH("scan_parts", k_scan_parts, dim3(1), dim3(kBlock), 0, s, tmp, (uint32_t)nb);
-    TM_LAUNCH("scan_tile", (k_tile_scan<L>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp,
-              (uint32_t)nb, out);
+    TM_LAUNCH("scan_tile", (k_tile_scan<L, W>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp,
+              (uint32_t)nb, wr);
     return TM_OK;
 }
 
@@ -364,9 +397,6 @@ struct RankWrite {
         o.nkey[2 * (uint64_t)r + 1] = ev.dst;
         o.nval[2 * (uint64_t)r] = NodeVal{te, r, ev.dst << 1};
         o.nval[2 * (uint64_t)r + 1] = NodeVal{te, r, (ev.src << 1) | 1u};
-        const uint32_t lo = min(ev.src, ev.dst), hi = max(ev.src, ev.dst);
-        o.pkey[r] = (uint64_t)lo * o.n + hi;
-        o.pval[r] = r | (ev.src == lo ? kOrientBit : 0u);
     }
 };
 
@@ -599,11 +629,26 @@ size_t radix_tmp_bytes(uint64_t n) {
 }
 
 int scan_u32_array(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
-    return scan_impl(LoadArray{in}, out, n, tmp, s);
+    return scan_impl(LoadArray{in}, ArrayWrite{out}, n, tmp, s);
 }
 
 int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
-    return scan_impl(LoadDirBit{ent_nd}, out, n, tmp, s);
+    return scan_impl(LoadDirBit{ent_nd}, ArrayWrite{out}, n, tmp, s);
+}
+
+int lower_side_pairs(const uint32_t *ent_c, const uint32_t *ent_nd, const uint32_t *ent_r,
+                     uint64_t n, uint32_t *key, uint2 *val, uint32_t *tmp, hipStream_t s) {
+    return scan_impl(LoadLowerSide{ent_c, ent_nd}, LowerSideWrite{ent_c, ent_nd, ent_r, key, val},
+                     n, tmp, s);
+}
+
+int radix_sort_pairs(uint32_t **keys, uint32_t **keys_alt, uint2 **vals, uint2 **vals_alt,
+                     uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s) {
+    if (n == 0 || bits <= 0) return TM_OK;
+    const ArrayIn<uint32_t, uint2> in0{*keys, *vals};
+    return radix_impl<uint32_t, uint2, PairOut<uint32_t, uint2>>(
+        keys, keys_alt, vals, vals_alt, n, bits, tmp, err, s, "sort_pair_hist", "sort_pair_scatter",
+        nullptr, in0);
 }
 
 int radix_sort_u64(uint64_t **keys, uint64_t **keys_alt, uint32_t **vals, uint32_t **vals_alt,

@@ -93,6 +93,14 @@ struct Scratch {
 size_t scan_tmp_count(uint64_t n);
 int scan_u32_array(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s);
 int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s);
+// Each edge once, from its entry of S at the smaller node, in S order:
+// key[i] = the larger node, val[i] = (smaller node, rank | orientation).
+int lower_side_pairs(const uint32_t *ent_c, const uint32_t *ent_nd, const uint32_t *ent_r,
+                     uint64_t n, uint32_t *key, uint2 *val, uint32_t *tmp, hipStream_t s);
+// Stable sort of (larger node, (smaller node, rank | orientation)) pairs on
+// key bits [0, bits); *keys / *vals point at the sorted data on return.
+int radix_sort_pairs(uint32_t **keys, uint32_t **keys_alt, uint2 **vals, uint2 **vals_alt,
+                     uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8 bits per
 // pass, ping-ponging between the two buffers; *keys / *vals point at the
@@ -137,19 +145,16 @@ struct SeqOut {
 };
 
 // Where the time sort's last pass writes: the arrays by edge rank r (rank =
-// position in (graph, t, input index) order): t_r, perm (input index), the
-// two incident entries to sort by node (slot 2r: at src, out; 2r + 1: at
-// dst, in), and the node-pair key and value (r | orientation).
+// position in (graph, t, input index) order): t_r, perm (input index) and
+// the two incident entries to sort by node (slot 2r: at src, out; 2r + 1: at
+// dst, in).
 struct RankOut {
     const int64_t *tmin;  // per graph
     int tbits;            // time bits of the key (>= 64: one graph, no graph bits)
-    uint64_t n;           // nodes (pair key = lo * n + hi)
     int64_t *t_r;
     uint32_t *perm;
     uint32_t *nkey;
     NodeVal *nval;
-    uint64_t *pkey;
-    uint32_t *pval;
 };
 
 // hist_name / scatter_name label the sort's kernels for the tracer.
@@ -239,7 +244,8 @@ struct tm_graph {
     uint32_t *epos = nullptr;    // 2m: position of edge rank r's src entry (2r) and dst entry (2r+1)
     uint32_t *perm = nullptr;    // m: edge id of rank r
     // node pairs with at least two edges (the only ones that hold pair or star
-    // instances) and their edges ("elements"), pair by pair in (t, id) order
+    // instances), ordered by (larger node, smaller node), and their edges
+    // ("elements"), pair by pair in (t, id) order
     uint64_t n_multi = 0, n_me = 0;
     uint32_t *mp_start = nullptr;  // n_multi + 1: first element of each pair
     uint32_t *mp_lo = nullptr;     // n_multi: smaller node
