@@ -354,10 +354,14 @@ void tm_server_destroy(tm_server *s);
  * and its first edge is at most delta before it (Definition 2), so only the
  * earlier edges with t >= (smallest new t) - delta can take part.  The
  * stream keeps that tail on the device and, per append, builds and counts
- * tail + batch and the tail alone; the difference of the raw counters is
- * exactly the instances whose last edge is in the batch.  Summed over all
- * appends it equals tm_count of the whole stream.  Older whole batches are
- * dropped, so device memory follows the edge rate times delta.
+ * tail + batch; less the count of the tail alone, that is exactly the
+ * instances whose last edge is in the batch.  Summed over all appends it
+ * equals tm_count of the whole stream.  The tail is cut to the rows that can
+ * still meet a new edge only once at least half of it is stale; between cuts
+ * the tail's count is the previous append's, so an append costs one build
+ * and count, and a cutting append two.  Device memory follows the edge rate
+ * times delta (at most about twice the rows that can meet a new edge, plus a
+ * batch).
  *
  * tm_stream_create: delta as in tm_count; n_nodes as in tm_build_graph (an
  *   id bound for every batch, or 0 for none); hip_stream as in

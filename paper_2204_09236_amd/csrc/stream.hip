@@ -12,10 +12,15 @@
 // are sums over instances, so the difference merges like any count, and the
 // running sum over all appends equals the count of the whole stream.
 //
-// Before each append the tail is cut to the rows with t >= (smallest new t)
-// - delta (an order-preserving compaction), so it holds only the edges that
-// can meet the batch and device memory follows the edge rate times delta,
-// not the stream's length.
+// Rows older than (smallest new t) - delta can no longer meet a new edge.
+// Keeping a few of them costs nothing in exactness: the instances among the
+// tail's own rows cancel in the difference.  So the tail is cut (an
+// order-preserving compaction) only once at least half of it is certainly
+// stale, judged from each batch's largest t kept on the host.  Between cuts,
+// tail + batch of one append is the whole tail of the next, whose count is
+// then already known: one build and count per append instead of two.  Device
+// memory still follows the edge rate times delta (at most about twice the
+// rows that can meet a new edge, plus a batch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -115,6 +120,9 @@ struct tm_stream {
     uint64_t edges = 0;  // edges appended so far
     uint64_t total[56] = {};
     uint64_t last[56] = {};    // raw counters of the current tail (rows [0, len))
+    // (largest t, rows) of each batch in the tail, in order; after a cut the
+    // kept rows count as one batch with the largest t seen so far
+    std::vector<std::pair<int64_t, uint64_t>> spans;
     int64_t *range = nullptr;  // device scratch: batch min and max t
     std::mutex mu;
 };
@@ -189,14 +197,19 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
     }
     // tail rows with t < lo - delta cannot meet the new edges
     const int64_t cut = lo - s->delta;
+    // rows certainly below the cut: whole batches whose largest t is
+    uint64_t stale = 0;
+    for (const auto &b : s->spans)
+        if (b.first < cut) stale += b.second;
+    const bool trim = s->len && 2 * stale >= s->len;
     uint32_t *flag = nullptr, *idx = nullptr, *tmp = nullptr;
     auto free_scan = [&]() {
         tmc::dev_free(flag, s->stream);
         tmc::dev_free(idx, s->stream);
         tmc::dev_free(tmp, s->stream);
     };
-    uint64_t kept = 0;
-    if (s->len) {
+    uint64_t kept = s->len;
+    if (trim) {
         rc = tmc::dev_alloc(reinterpret_cast<void **>(&flag), s->len * 4, s->stream);
         if (!rc) rc = tmc::dev_alloc(reinterpret_cast<void **>(&idx), (s->len + 1) * 4, s->stream);
         if (!rc) rc = tmc::dev_alloc(reinterpret_cast<void **>(&tmp), tmc::scan_tmp_count(s->len) * 4, s->stream);
@@ -230,9 +243,17 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
         return code;
     };
     if (rc) return fail(rc);
-    if (kept) {
+    if (trim && kept) {
         rc = keep_scatter(s, flag, idx, nsrc, ndst, nt);
         if (rc) return fail(rc);
+    } else if (kept) {
+        hipError_t ce = hipMemcpyAsync(nsrc, s->src, kept * 4, hipMemcpyDeviceToDevice, s->stream);
+        if (ce == hipSuccess) ce = hipMemcpyAsync(ndst, s->dst, kept * 4, hipMemcpyDeviceToDevice, s->stream);
+        if (ce == hipSuccess) ce = hipMemcpyAsync(nt, s->t, kept * 8, hipMemcpyDeviceToDevice, s->stream);
+        if (ce != hipSuccess) {
+            tmc::set_error(std::string("stream tail copy: ") + hipGetErrorString(ce));
+            return fail(TM_EHIP);
+        }
     }
     const hipMemcpyKind kind = flags == TM_HOST_PTRS ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     hipError_t e = hipMemcpyAsync(nsrc + kept, src, m * 4, kind, s->stream);
@@ -267,6 +288,11 @@ int append_locked(tm_stream *s, const int32_t *src, const int32_t *dst, const in
     s->dst = ndst;
     s->t = nt;
     s->len = len;
+    if (trim) {
+        s->spans.clear();
+        if (kept) s->spans.emplace_back(s->tmax, kept);
+    }
+    s->spans.emplace_back(hi, m);
     for (int i = 0; i < 56; i++) s->last[i] = with[i];
     s->any = true;
     s->tmax = std::max(s->tmax, hi);
