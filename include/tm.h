@@ -220,8 +220,9 @@ int tm_count_raw(tm_graph *g, int64_t delta, uint64_t raw[56]);
  * tm_count_raw with explicit work partitioning; the result never depends on
  * these, only the schedule does.  0 = the graph's tuned value, else the
  * autotuner table's, else the default.
- *   run_chunk  edges of one node-pair edge set handled by one work item of
- *              the star/pair kernel (hub splitting)
+ *   run_chunk  node-pair edges (elements) per thread of the star/pair
+ *              kernel, which counts every element independently (1 .. 64;
+ *              larger values are taken as 64)
  *   tri_lane_max  window products (|W_src| * |W_dst|) up to this are counted
  *              by one lane, larger ones by a whole wavefront
  *   hub_min    triangle candidates (first edges, Algorithm 2's triangle

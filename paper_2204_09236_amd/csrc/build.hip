@@ -175,7 +175,7 @@ struct MultiOut {
     int64_t *me_t;
     uint2 *me_p;
     uint4 *me_a;
-    uint8_t *me_o;
+    uint8_t *me_o;  // bit 0: leaves the smaller node, bit 1: first of its pair
 };
 
 __global__ void k_multi_fill(const uint32_t *pkey, const uint2 *pval, uint64_t m,
@@ -207,7 +207,8 @@ __global__ void k_multi_fill(const uint32_t *pkey, const uint2 *pval, uint64_t m
         o.me_t[k] = t_r[r];
         o.me_p[k] = make_uint2(p_lo, p_hi);
         o.me_a[k] = make_uint4(p_lo - s_lo - a1_lo, a1_lo, p_hi - s_hi - a1_hi, a1_hi);
-        o.me_o[k] = (uint8_t)src_is_lo;
+        // bit 0: the edge leaves the smaller node; bit 1: first element of its pair
+        o.me_o[k] = (uint8_t)(src_is_lo | (multi_head[g] ? 2u : 0u));
     }
 }
 

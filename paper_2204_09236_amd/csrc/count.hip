@@ -253,10 +253,18 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
 }
 
 // --------------------------------------------------------------- star/pair
-// Per element (edge of a multi-edge node pair) and side (center = smaller /
-// larger node): P_0, P_1 of S_c at the window end R and just before the
-// window start L:  w = (P_0(R), P_1(R), P_0(L-1), P_1(L-1)).
-// Window state over the edges of one node pair inside a delta-window.
+// Alg. 1 counts, for every edge e of S_c, the ordered pairs of later edges
+// inside delta by their node pairs and directions.  Here the instances with
+// two or three edges on one node pair are counted from the pair's side: per
+// element q (an edge of a node pair with >= 2 edges) and side (center c =
+// smaller / larger node), the other edges of its pair inside q's forward
+// window (q, j) give the Pair, Star_II and Star_III instances whose first
+// edge is q, and those inside its backward window [f, q) give the Star_I
+// instances whose last edge is q.  Besides the window's own edges each needs
+// the prefix counts P_0, P_1 of S_c at q's window end R (forward) or just
+// before its window start L (backward), which k_windows records per entry.
+//
+// Window state over edges of one node pair.
 struct Win {
     uint64_t in[2];
     uint64_t S2[2][2];   // S2[d][d']: ordered pairs k < j, dir k = d, dir j = d'
@@ -280,19 +288,19 @@ struct Win {
         sPm[1][0] += a0 & m1;
         sPm[1][1] += a1 & m1;
     }
-    // remove the earliest edge (dir d)
-    __device__ inline void pop(uint32_t d, uint32_t a0, uint32_t a1) {
+    // prepend an earlier edge (dir d, prefix counts a0, a1)
+    __device__ inline void push_front(uint32_t d, uint32_t a0, uint32_t a1) {
         const uint64_t m1 = 0ull - (uint64_t)d, m0 = ~m1;
-        in[0] -= 1 & m0;
-        in[1] -= 1 & m1;
-        S2[0][0] -= in[0] & m0;
-        S2[0][1] -= in[1] & m0;
-        S2[1][0] -= in[0] & m1;
-        S2[1][1] -= in[1] & m1;
-        sPm[0][0] -= a0 & m0;
-        sPm[0][1] -= a1 & m0;
-        sPm[1][0] -= a0 & m1;
-        sPm[1][1] -= a1 & m1;
+        S2[0][0] += in[0] & m0;
+        S2[0][1] += in[1] & m0;
+        S2[1][0] += in[0] & m1;
+        S2[1][1] += in[1] & m1;
+        in[0] += 1 & m0;
+        in[1] += 1 & m1;
+        sPm[0][0] += a0 & m0;
+        sPm[0][1] += a1 & m0;
+        sPm[1][0] += a0 & m1;
+        sPm[1][1] += a1 & m1;
     }
 };
 
@@ -301,36 +309,34 @@ __device__ inline void add_sel(uint64_t &lo_cell, uint64_t &hi_cell, uint64_t v,
     hi_cell += v & m1;
 }
 
-struct WorkItem {
-    uint32_t pair;   // index of the multi-edge node pair
-    uint32_t chunk;  // chunk index inside it
-};
-
-// One element of a pair seen from one side.
+// One element of a pair seen from one side: direction relative to the
+// center and the prefix counts (#o, #in) of S_c before its entry.
 struct El {
-    int64_t t;
     uint32_t dir, a0, a1;
 };
+__device__ inline El elem(uint8_t o, uint4 a, uint32_t side) {
+    El e;
+    e.dir = 1u - ((o & 1u) ^ side);  // side 0: center = smaller node
+    e.a0 = side ? a.z : a.x;
+    e.a1 = side ? a.w : a.y;
+    return e;
+}
 
 struct StarArgs {
     const uint32_t *mp_start;
     const int64_t *me_t;
-    const uint8_t *me_o;
+    const uint8_t *me_o;     // bit 0: leaves the smaller node; bit 1: first of its pair
     const uint4 *me_a;
     const uint2 *me_p;       // element positions in S_lo, S_hi
     const uint2 *recR, *recL;  // window records of entry p: [p * K + level]
     uint32_t K;              // windows of the pass; each tile runs all of them
     uint64_t part_stride;    // partial rows of window i start at partial + i * part_stride
-    const uint32_t *first;   // n_multi + 1: first work item of each pair (exclusive scan)
-    const uint32_t *ipair;   // work item -> its pair
-    uint64_t n_multi;
-    uint64_t n_me;
     const uint32_t *mpb;     // G + 1: multi-edge pair bounds per graph
-    const uint32_t *tfirst;  // G + 1: first item tile of each graph
+    const uint32_t *tfirst;  // G + 1: first element tile of each graph
     uint32_t G;
     const int64_t *deltas;   // K == 1: per graph; K > 1 (one graph): per window
-    uint32_t chunk;
-    int star_i;              // run the Star_I sweep (stars requested)
+    uint32_t per;            // elements per thread; a tile holds per * kBlock elements
+    int star_i;              // count Star_I (stars requested)
 };
 
 // Largest i in [0, n) with a[i] <= x, for ascending a with a[0] <= x.
@@ -344,24 +350,42 @@ __device__ inline uint32_t last_le(const uint32_t *a, uint32_t n, uint32_t x) {
     return lo;
 }
 
-// One block per item tile (kItemTile items of one graph, kSPItems per thread,
-// taken kBlock apart so that neighbouring lanes sweep neighbouring items);
-// one partial row of 32 counters per tile.  The tile's items cover one
-// contiguous range of elements; that range and kStageHalo elements on each
-// side (time, orientation, prefix counts) are first copied into LDS with
-// coalesced loads, so the sequential window sweeps read LDS.  Elements outside the staged range (long delta
-// halos of hub pairs, or ranges beyond the stage capacity when chunks are
-// long) are read from global memory, so the result does not depend on the
-// staging.
-constexpr uint32_t kSPItems = 2;
-constexpr uint32_t kItemTile = kSPItems * kBlock;
-
-__device__ inline WorkItem item_at(const StarArgs &a, uint32_t it) {
-    const uint32_t p = a.ipair[it];
-    return WorkItem{p, it - a.first[p]};
+// Sum a block's N counters per thread into row[c0, c0 + N): wave sums, then
+// one thread per counter adds the waves.
+template <int N>
+__device__ inline void star_flush(const uint64_t (&acc)[N], int c0, uint64_t (*red)[32],
+                                  uint64_t *row) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    __syncthreads();  // the previous flush has read red
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        uint64_t v = acc[i];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if (lane == 0) red[wv][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        uint64_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; q++) s += red[q][threadIdx.x];
+        row[c0 + threadIdx.x] = s;
+    }
 }
+
+// One block per element tile (per * kBlock consecutive elements of one
+// graph, neighbouring lanes on neighbouring elements); one partial row of 32
+// counters per tile and window.  Every element is independent: its windows
+// hold only the few other edges of its pair inside delta, found by walking
+// its neighbours in element order up to the pair's ends (bit 1 of me_o).
+// The tile and kStageHalo elements on each side (time, flags, prefix counts)
+// are first copied into LDS with coalesced loads, so those walks read LDS;
+// elements outside the staged range are read from global memory, so the
+// result does not depend on the staging.  The windows of a pass are counted
+// one after another on the staged tile, so an entry's records (side by side
+// for all windows) are read again while their line is still cached.
 constexpr uint32_t kStageHalo = 64;
-constexpr uint32_t kStageCap = 1024 + 2 * kStageHalo;
+constexpr uint32_t kStageCap = 4 * kBlock + 2 * kStageHalo;
 
 struct ElemView {
     uint32_t lo, hi;  // staged element range
@@ -371,259 +395,135 @@ struct ElemView {
     const int64_t *gt;
     const uint8_t *go;
     const uint4 *ga;
-    const uint2 *gp;
-    const uint2 *recR, *recL;
-    uint32_t K, level;
     __device__ inline bool staged(uint32_t k) const { return k - lo < hi - lo; }
     __device__ inline int64_t t(uint32_t k) const { return staged(k) ? st[k - lo] : gt[k]; }
-    __device__ inline El el(uint32_t k, uint32_t side) const {
-        int64_t tt;
-        uint32_t o;
-        uint4 aa;
-        if (staged(k)) {
-            tt = st[k - lo];
-            o = so[k - lo];
-            aa = sa[k - lo];
-        } else {
-            tt = gt[k];
-            o = go[k];
-            aa = ga[k];
-        }
-        El e;
-        e.t = tt;
-        e.dir = 1u - (o ^ side);  // side 0: center = smaller node
-        e.a0 = side ? aa.z : aa.x;
-        e.a1 = side ? aa.w : aa.y;
-        return e;
-    }
-    // P_0, P_1 of S_c at the window end R of element k (center on `side`),
-    // from its entry's record: with (a0, a1) the counts before the entry,
-    // P_1(R) = a1 + dir-in entries in [p, R], P_0(R) = entries up to R - P_1(R).
-    // Read once per contribution, off the sweep's dependency chain.
-    __device__ inline uint2 win_end(uint32_t k, uint32_t side, const El &e) const {
-        const uint2 pp = gp[k];
-        const uint2 r = recR[(uint64_t)(side ? pp.y : pp.x) * K + level];
-        const uint32_t p1 = e.a1 + r.y;
-        return make_uint2(e.a0 + e.a1 + r.x + 1 - p1, p1);
-    }
-    // P_0, P_1 of S_c just before the window start L of element k:
-    // P_1(L - 1) = a1 - dir-in entries in [L, p), P_0(L - 1) = L - start - P_1.
-    __device__ inline uint2 win_start(uint32_t k, uint32_t side, const El &e) const {
-        const uint2 pp = gp[k];
-        const uint2 r = recL[(uint64_t)(side ? pp.y : pp.x) * K + level];
-        const uint32_t p1 = e.a1 - r.y;
-        return make_uint2(e.a0 + e.a1 - r.x - p1, p1);
-    }
+    __device__ inline uint8_t o(uint32_t k) const { return staged(k) ? so[k - lo] : go[k]; }
+    __device__ inline uint4 a(uint32_t k) const { return staged(k) ? sa[k - lo] : ga[k]; }
 };
 
-// Sum a wave's lanes for cells [c0, c0 + N) of the tile's partial row: each
-// wave adds into LDS rows, then the block writes them (one barrier).
-template <int N>
-__device__ inline void star_flush(const uint64_t (&acc)[N], int c0, uint64_t (*red)[32],
-                                  uint64_t *row) {
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-        uint64_t v = acc[i];
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if (lane == 0) red[wv][c0 + i] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < N) {
-        uint64_t s = 0;
-#pragma unroll
-        for (int q = 0; q < kBlock / kWave; q++) s += red[q][c0 + threadIdx.x];
-        row[c0 + threadIdx.x] = s;
-    }
-}
-
-// Two phases per tile, so that only one set of accumulators is live at a
-// time (more waves fit): the e1 sweeps (Pair, Star_II, Star_III: cells
-// [8, 32)), then the e3 sweeps (Star_I: cells [0, 8)).
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_star_pair(StarArgs a, uint64_t *partial) {
   __shared__ int64_t s_t[kStageCap];
   __shared__ uint4 s_a[kStageCap];
   __shared__ uint8_t s_o[kStageCap];
   __shared__ uint64_t red[kBlock / kWave][32];
   const uint32_t n_tiles = a.tfirst[a.G];
+  const uint32_t tile = a.per * kBlock;
   for (uint32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
     const uint32_t gi = last_le(a.tfirst, a.G + 1, ti);
-    const uint32_t ib = a.first[a.mpb[gi]] + (ti - a.tfirst[gi]) * kItemTile;
-    const uint32_t ie = min(a.first[a.mpb[gi + 1]], ib + kItemTile);
-    // element range of the tile's items, plus halos, clipped to the capacity
-    const WorkItem w0 = item_at(a, ib);
-    const WorkItem w1 = item_at(a, ie - 1);
-    const uint32_t eb = a.mp_start[w0.pair] + w0.chunk * a.chunk;
-    const uint32_t ee = min(a.mp_start[w1.pair + 1], a.mp_start[w1.pair] + (w1.chunk + 1) * a.chunk);
-    const uint32_t lo = eb - min(eb, kStageHalo);
-    const uint32_t hi = (uint32_t)min<uint64_t>(min<uint64_t>(a.n_me, (uint64_t)ee + kStageHalo),
-                                                (uint64_t)lo + kStageCap);
-    __syncthreads();  // the previous tile is done with the stage and the rows
+    const uint32_t gb = a.mp_start[a.mpb[gi]], ge = a.mp_start[a.mpb[gi + 1]];
+    const uint32_t eb = gb + (ti - a.tfirst[gi]) * tile;
+    const uint32_t ee = min(ge, eb + tile);
+    const uint32_t lo = eb - min(eb - gb, kStageHalo);
+    const uint32_t hi = min(min(ge, ee + kStageHalo), lo + kStageCap);
+    __syncthreads();  // the previous tile is done with the stage
     for (uint32_t k = lo + threadIdx.x; k < hi; k += kBlock) {
         s_t[k - lo] = a.me_t[k];
         s_o[k - lo] = a.me_o[k];
         s_a[k - lo] = a.me_a[k];
     }
     __syncthreads();
-    // element ranges of this thread's items: the pair [rs, re), the chunk [cb, ce)
-    uint32_t rs_[kSPItems], re_[kSPItems], cb_[kSPItems], ce_[kSPItems];
-#pragma unroll
-    for (uint32_t u = 0; u < kSPItems; u++) {
-        const uint32_t it = ib + threadIdx.x + u * kBlock;
-        rs_[u] = re_[u] = cb_[u] = ce_[u] = 0;
-        if (it < ie) {
-            const WorkItem w = item_at(a, it);
-            rs_[u] = a.mp_start[w.pair];
-            re_[u] = a.mp_start[w.pair + 1];
-            cb_[u] = rs_[u] + w.chunk * a.chunk;
-            ce_[u] = min(re_[u], cb_[u] + a.chunk);
-        }
-    }
-    // every window of the pass on the staged tile, one after another, so that
-    // the records of one entry (side by side for all windows) are read while
-    // their line is still cached
+    const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a};
     for (uint32_t level = 0; level < a.K; level++) {
-    const int64_t delta = a.deltas[gi + level];
-    const ElemView V{lo, hi, s_t, s_o, s_a, a.me_t, a.me_o, a.me_a, a.me_p, a.recR, a.recL, a.K,
-                     level};
-    uint64_t *row = partial + level * a.part_stride + (uint64_t)ti * 32;
-    {
-        // ---- phase 1, e1 sweeps: Pair, Star_II, Star_III (cell c -> A[c - 8])
+      const int64_t delta = a.deltas[gi + level];
+      uint64_t *row = partial + level * a.part_stride + (uint64_t)ti * 32;
+      {
+        // ---- phase 1: Pair, Star_II, Star_III with first edge q (cell c -> A[c - 8])
         uint64_t A[24];
 #pragma unroll
         for (int i = 0; i < 24; i++) A[i] = 0;
-        for (uint32_t u = 0; u < kSPItems; u++) {
-        const uint32_t re = re_[u], cb = cb_[u], ce = ce_[u];
-        for (uint32_t side = 0; side < 2 && cb < ce; side++) {
+        for (uint32_t u = 0; u < a.per; u++) {
+          const uint32_t q = eb + threadIdx.x + u * kBlock;
+          if (q >= ee) break;
+          const int64_t tq = V.t(q);
+          // the pair's other edges inside q's forward window (q, jf)
+          uint32_t jf = q + 1;
+          while (jf < ge && !(V.o(jf) & 2u) && V.t(jf) <= tq + delta) jf++;
+          if (jf == q + 1) continue;
+          const uint8_t oq = V.o(q);
+          const uint4 aq = V.a(q);
+          const uint2 pq = a.me_p[q];
+          for (uint32_t side = 0; side < 2; side++) {
+            const El eq = elem(oq, aq, side);
+            const uint64_t m1 = 0ull - (uint64_t)eq.dir;
             Win W;
             W.clear();
-            uint32_t j = cb + 1;  // next pair edge to enter the window
-            for (uint32_t q = cb; q < ce; q++) {
-                const El eq = V.el(q, side);
-                if (q > cb && j > q) W.pop(eq.dir, eq.a0, eq.a1);
-                if (j <= q) j = q + 1;
-                const int64_t lim = eq.t + delta;
-                while (j < re) {
-                    const El ej = V.el(j, side);
-                    if (ej.t > lim) break;
-                    W.push(ej.dir, ej.a0, ej.a1);
-                    j++;
-                }
-                if (W.in[0] + W.in[1] == 0) continue;
-                const uint2 ww = V.win_end(q, side, eq);
-                const uint64_t rp[2] = {ww.x, ww.y};
-                const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0),
-                                         (uint64_t)eq.a1 + (eq.dir == 1)};
-                const uint64_t m1 = 0ull - (uint64_t)eq.dir;
+            for (uint32_t j = q + 1; j < jf; j++) {
+                const El ej = elem(V.o(j), V.a(j), side);
+                W.push(ej.dir, ej.a0, ej.a1);
+            }
+            // P_0, P_1 of S_c at q's window end R from q's record: with
+            // (a0, a1) the counts before q, P_1(R) = a1 + dir-in entries in
+            // [q, R], P_0(R) = entries up to R - P_1(R)
+            const uint2 r = a.recR[(uint64_t)(side ? pq.y : pq.x) * a.K + level];
+            const uint32_t p1 = eq.a1 + r.y;
+            const uint64_t rp[2] = {(uint64_t)(eq.a0 + eq.a1 + r.x + 1 - p1), (uint64_t)p1};
+            const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0), (uint64_t)eq.a1 + (eq.dir == 1)};
 #pragma unroll
-                for (int d = 0; d < 2; d++) {
+            for (int d = 0; d < 2; d++) {
 #pragma unroll
-                    for (int dp = 0; dp < 2; dp++) {
-                        const uint64_t s2 = W.S2[d][dp];
-                        // Pair[d_i][d][d']
-                        add_sel(A[16 + 0 + d * 2 + dp], A[16 + 4 + d * 2 + dp], s2, m1);
-                        // Star_II[d_i][d][d']
-                        const uint64_t v2 = W.sPm[dp][d] - W.in[dp] * pin[d] - s2;
-                        add_sel(A[0 + 0 + d * 2 + dp], A[0 + 4 + d * 2 + dp], v2, m1);
-                        // Star_III[d_i][d][d']
-                        const uint64_t sp = W.sPm[d][dp] + (d == dp ? W.in[d] : 0ull);
-                        const uint64_t v3 = W.in[d] * rp[dp] - sp - s2;
-                        add_sel(A[8 + 0 + d * 2 + dp], A[8 + 4 + d * 2 + dp], v3, m1);
-                    }
+                for (int dp = 0; dp < 2; dp++) {
+                    const uint64_t s2 = W.S2[d][dp];
+                    // Pair[d_q][d][d']
+                    add_sel(A[16 + d * 2 + dp], A[20 + d * 2 + dp], s2, m1);
+                    // Star_II[d_q][d][d']
+                    const uint64_t v2 = W.sPm[dp][d] - W.in[dp] * pin[d] - s2;
+                    add_sel(A[0 + d * 2 + dp], A[4 + d * 2 + dp], v2, m1);
+                    // Star_III[d_q][d][d']
+                    const uint64_t sp = W.sPm[d][dp] + (d == dp ? W.in[d] : 0ull);
+                    const uint64_t v3 = W.in[d] * rp[dp] - sp - s2;
+                    add_sel(A[8 + d * 2 + dp], A[12 + d * 2 + dp], v3, m1);
                 }
             }
-        }
+          }
         }
         star_flush<24>(A, 8, red, row);
-    }
-    {
-        // ---- phase 2, e3 sweeps: Star_I (cells [0, 8))
+      }
+      {
+        // ---- phase 2: Star_I with last edge q (cells 0..7)
         uint64_t A[8];
 #pragma unroll
         for (int i = 0; i < 8; i++) A[i] = 0;
-        for (uint32_t u = 0; u < kSPItems; u++) {
-        const uint32_t rs = rs_[u], cb = cb_[u], ce = ce_[u];
-        for (uint32_t side = 0; side < 2 && cb < ce && a.star_i; side++) {
+        for (uint32_t u = 0; u < a.per && a.star_i; u++) {
+          const uint32_t q = eb + threadIdx.x + u * kBlock;
+          if (q >= ee) break;
+          const int64_t tq = V.t(q);
+          // the pair's other edges inside q's backward window [fb, q)
+          uint32_t fb = q;
+          while (fb > gb && !(V.o(fb) & 2u) && V.t(fb - 1) >= tq - delta) fb--;
+          if (fb == q) continue;
+          const uint8_t oq = V.o(q);
+          const uint4 aq = V.a(q);
+          const uint2 pq = a.me_p[q];
+          for (uint32_t side = 0; side < 2; side++) {
+            const El eq = elem(oq, aq, side);
+            const uint64_t m1 = 0ull - (uint64_t)eq.dir;
             Win W;
             W.clear();
-            uint32_t f;  // front of the window [f, q)
-            {
-                const int64_t lim = V.t(cb) - delta;
-                f = cb;
-                while (f > rs && V.t(f - 1) >= lim) f--;
-                for (uint32_t k = f; k < cb; k++) {
-                    const El ek = V.el(k, side);
-                    W.push(ek.dir, ek.a0, ek.a1);
+            for (uint32_t f = q; f > fb; f--) {
+                const El ef = elem(V.o(f - 1), V.a(f - 1), side);
+                W.push_front(ef.dir, ef.a0, ef.a1);
+            }
+            // P_0, P_1 of S_c just before q's window start L:
+            // P_1(L - 1) = a1 - dir-in entries in [L, q), P_0 = L - start - P_1
+            const uint2 r = a.recL[(uint64_t)(side ? pq.y : pq.x) * a.K + level];
+            const uint32_t p1 = eq.a1 - r.y;
+            const uint64_t lp[2] = {(uint64_t)(eq.a0 + eq.a1 - r.x - p1), (uint64_t)p1};
+#pragma unroll
+            for (int d1 = 0; d1 < 2; d1++) {
+#pragma unroll
+                for (int d2 = 0; d2 < 2; d2++) {
+                    const uint64_t v1 = W.sPm[d2][d1] - W.in[d2] * lp[d1] - W.S2[d1][d2];
+                    // Star_I[d1][d2][d3 = dir of q]
+                    add_sel(A[d1 * 4 + d2 * 2 + 0], A[d1 * 4 + d2 * 2 + 1], v1, m1);
                 }
             }
-            for (uint32_t q = cb; q < ce; q++) {
-                const El eq = V.el(q, side);
-                const int64_t lim = eq.t - delta;
-                while (f < q) {
-                    const El ef = V.el(f, side);
-                    if (ef.t >= lim) break;
-                    W.pop(ef.dir, ef.a0, ef.a1);
-                    f++;
-                }
-                if (W.in[0] + W.in[1] != 0) {
-                    const uint2 ww = V.win_start(q, side, eq);
-                    const uint64_t lp[2] = {ww.x, ww.y};
-                    const uint64_t m1 = 0ull - (uint64_t)eq.dir;
-#pragma unroll
-                    for (int d1 = 0; d1 < 2; d1++) {
-#pragma unroll
-                        for (int d2 = 0; d2 < 2; d2++) {
-                            const uint64_t v1 = W.sPm[d2][d1] - W.in[d2] * lp[d1] - W.S2[d1][d2];
-                            // Star_I[d1][d2][d3 = dir of q]
-                            add_sel(A[d1 * 4 + d2 * 2 + 0], A[d1 * 4 + d2 * 2 + 1], v1, m1);
-                        }
-                    }
-                }
-                W.push(eq.dir, eq.a0, eq.a1);
-            }
-        }
+          }
         }
         star_flush<8>(A, 0, red, row);
-    }
+      }
     }
   }
-}
-
-// item -> pair.  Every pair has at least one item, so first[] strictly
-// increases; a thread fills kItemsPerThread consecutive items, finding the
-// first one's pair by binary search and walking forward from there (long hub
-// pairs do not serialise one thread).
-constexpr uint32_t kItemsPerThread = 32;
-
-__global__ void k_item_pairs(const uint32_t *first, uint64_t n_multi, uint32_t *ipair) {
-    const uint64_t n_items = first[n_multi];
-    for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kItemsPerThread;
-         base < n_items; base += (uint64_t)gridDim.x * blockDim.x * kItemsPerThread) {
-        uint64_t lo = 0, hi = n_multi;  // first[lo] <= base < first[hi]
-        while (hi - lo > 1) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            if (first[mid] <= base) lo = mid;
-            else hi = mid;
-        }
-        uint64_t p = lo;
-        const uint64_t end = min(base + kItemsPerThread, n_items);
-        for (uint64_t it = base; it < end; it++) {
-            while (first[p + 1] <= it) p++;
-            ipair[it] = (uint32_t)p;
-        }
-    }
-}
-
-// Work items: node pair k is cut into ceil(len / chunk) items.
-__global__ void k_item_counts(const uint32_t *mp_start, uint64_t n_multi, uint32_t chunk,
-                              uint32_t *cnt) {
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_multi;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t len = mp_start[k + 1] - mp_start[k];
-        cnt[k] = (len + chunk - 1) / chunk;
-    }
 }
 
 // ---------------------------------------------------------------- triangles
@@ -1219,16 +1119,16 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
 // tiles (slices of its S, when the hub pass runs; the hub work-list counter
 // is zeroed here).  A family that is not counted gets no tiles (its arrays
 // are not read).
-__global__ void k_graph_tiles(const uint32_t *first, const uint32_t *mpb, const uint32_t *tidx,
+__global__ void k_graph_tiles(const uint32_t *mp_start, const uint32_t *mpb, const uint32_t *tidx,
                               const uint32_t *eoff, uint32_t G, int star_pair, int tri, int hub,
-                              uint32_t *n_item_tiles, uint32_t *n_cand_tiles,
+                              uint32_t elem_tile, uint32_t *n_item_tiles, uint32_t *n_cand_tiles,
                               uint32_t *n_hub_tiles, uint32_t *hub_count) {
     if (hub && blockIdx.x == 0 && threadIdx.x == 0) *hub_count = 0;
     for (uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x; gi < G; gi += gridDim.x * blockDim.x) {
-        const uint32_t items = star_pair ? first[mpb[gi + 1]] - first[mpb[gi]] : 0u;
+        const uint32_t elems = star_pair ? mp_start[mpb[gi + 1]] - mp_start[mpb[gi]] : 0u;
         const uint32_t cands = tri ? tidx[eoff[gi + 1]] - tidx[eoff[gi]] : 0u;
         const uint32_t ents = hub ? 2 * (eoff[gi + 1] - eoff[gi]) : 0u;
-        n_item_tiles[gi] = (items + kItemTile - 1) / kItemTile;
+        n_item_tiles[gi] = (elems + elem_tile - 1) / elem_tile;
         n_cand_tiles[gi] = (cands + kCandTile - 1) / kCandTile;
         n_hub_tiles[gi] = (ents + kHubSlice - 1) / kHubSlice;
     }
@@ -1311,7 +1211,8 @@ dim3 grid_for(uint64_t n, uint64_t cap) {
 
 }  // namespace
 
-constexpr uint32_t kDefaultRunChunk = 4;
+constexpr uint32_t kDefaultRunChunk = 2;  // star/pair elements per thread
+constexpr uint32_t kMaxRunChunk = 64;
 constexpr uint32_t kDefaultTriLaneMax = 64;
 constexpr uint32_t kDefaultHubMin = 32;
 
@@ -1324,7 +1225,7 @@ struct Workspace {
     uint32_t *Wf;       // window i of entry p at p * K + i
     uint2 *recR, *recL; // window records for the star/pair sweeps, same layout
     uint64_t *wbits, *lev;
-    uint32_t *cnt, *first, *ipair, *tflag, *tidx;
+    uint32_t *tflag, *tidx;
     uint4 *cand;
     uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
     uint32_t *n_htiles, *htfirst, *hcount, *hlist;
@@ -1336,7 +1237,7 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w, uint32_t K = 1) {
     const uint32_t G = g->G;
     const uint64_t m = g->m, len = 2 * m, nm = g->n_multi, nme = g->n_me;
     w->K = K;
-    w->max_itiles = nme / kItemTile + G + 1;
+    w->max_itiles = nme / kBlock + G + 1;  // element tiles of at least kBlock elements
     w->max_ctiles = m / kCandTile + G + 1;
     w->max_htiles = len / kHubSlice + G + 1;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
@@ -1344,7 +1245,7 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w, uint32_t K = 1) {
     return up((size_t)G * K * 8) + up(len * 4 * K) + up(len * 8 * K) * 2 + up((len / kWave + 1) * 8) +
            up((len / kWave + 1) * 16) +
            up((G + 1) * 4) * 2 + up(4) + up(w->max_htiles * 4) + up(w->max_htiles * 8 * 8 * K) +
-           up((nm + 1) * 4) * 2 + up((nme + 1) * 4) + up((size_t)G * sum_split(G) * 40 * 8) +
+           up((size_t)G * sum_split(G) * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
            up(n_tmp * 4) + up(w->max_itiles * 32 * 8 * K) +
            up(w->max_ctiles * kTriRowsPerTile * 8 * 8 * K) + up((size_t)G * 40 * 8 * K) + 4096;
@@ -1365,9 +1266,6 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->hcount = sc.take<uint32_t>(1);
     w->hlist = sc.take<uint32_t>(w->max_htiles);
     w->hpart = sc.take<uint64_t>(w->max_htiles * 8 * K);
-    w->cnt = sc.take<uint32_t>(nm + 1);
-    w->first = sc.take<uint32_t>(nm + 1);
-    w->ipair = sc.take<uint32_t>(nme + 1);
     w->tflag = sc.take<uint32_t>(m);
     w->tidx = sc.take<uint32_t>(m + 1);
     w->cand = sc.take<uint4>(m);
@@ -1399,7 +1297,9 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
 // synchronisation, memset or allocation: capturable.
 static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint32_t families,
                          hipStream_t s) {
-    const uint32_t run_chunk = pr.run_chunk, tri_lane_max = pr.tri_lane_max;
+    // star/pair elements per thread (the run_chunk parameter)
+    const uint32_t per = std::max(1u, std::min(pr.run_chunk, kMaxRunChunk));
+    const uint32_t tri_lane_max = pr.tri_lane_max;
     const uint32_t G = g->G, K = w.K;
     if (K < 1 || K > (uint32_t)kMaxLevels || (K > 1 && G != 1)) {
         set_error("windows per pass out of range");
@@ -1424,18 +1324,6 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
                 0, s, S, g->t_entries, g->n_t_entries, len, w.deltas, w.Wf, pr.hub_min,
                 fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr,
                 nm ? w.recR : nullptr, nm ? w.recL : nullptr);
-    // ---- star / pair: work items (pair, chunk); window i reads its own
-    // records and delta (K > 1 only for one graph, whose delta i is deltas[i])
-    if (nm) {
-        ProfRow row_a6("a6");
-        TM_LAUNCH("item_counts", k_item_counts, grid_for(nm, 4096), dim3(kBlock), 0, s, g->mp_start,
-                  nm, run_chunk, w.cnt);
-    }
-    if (do_sp) {
-        ProfRow row_a6("a6");
-        rc = scan_u32_array(w.cnt, w.first, nm, w.tmp, s);
-        if (rc) return rc;
-    }
     // ---- triangles: candidate first edges (of the largest window)
     if (do_tri) {
         ProfRow row_a5("a5");
@@ -1452,26 +1340,22 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     // ---- per-graph work tiles
     {
     ProfRow row_a6("a6");
-    TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, w.first, g->d_mpb,
-              w.tidx, g->d_eoff, G, (int)do_sp, (int)do_tri, (int)do_hub, w.n_itiles, w.n_ctiles,
-              w.n_htiles, w.hcount);
+    TM_LAUNCH("graph_tiles", k_graph_tiles, grid_for(G, 1024), dim3(kBlock), 0, s, g->mp_start,
+              g->d_mpb, w.tidx, g->d_eoff, G, (int)(nm != 0), (int)do_tri, (int)do_hub,
+              per * kBlock, w.n_itiles, w.n_ctiles, w.n_htiles, w.hcount);
     rc = scan_u32_array(w.n_itiles, w.tfirst, G, w.tmp, s);
     if (rc) return rc;
     rc = scan_u32_array(w.n_ctiles, w.ctfirst, G, w.tmp, s);
     if (rc) return rc;
     rc = scan_u32_array(w.n_htiles, w.htfirst, G, w.tmp, s);
     if (rc) return rc;
-    if (nm)
-        TM_LAUNCH("item_pairs", k_item_pairs, grid_for(nme / kItemsPerThread + 1, 4096), dim3(kBlock),
-                  0, s, w.first, nm, w.ipair);
     if (do_hub)
         TM_LAUNCH("hub_tiles", k_hub_tiles, grid_for(w.max_htiles, 4096), dim3(kBlock), 0, s, w.lev,
                   pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, K, h_stride, w.hpart);
     }
     if (nm) {
         StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, g->me_p, w.recR, w.recL, K, s_stride,
-                    w.first, w.ipair, nm, nme, g->d_mpb, w.tfirst, G, w.deltas, run_chunk,
-                    (families & TM_STARS) ? 1 : 0};
+                    g->d_mpb, w.tfirst, G, w.deltas, per, (families & TM_STARS) ? 1 : 0};
         TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
                   dim3(kBlock), 0, s, sa, w.spart);
     }
@@ -1817,7 +1701,7 @@ int count_graph_multi(tm_graph *g, const int64_t *h_deltas, uint32_t k, Params p
 // keyed by the graph's shape (log2 of edges, of multi-pair edges, and of the
 // graph count), which later graphs of that shape use by default.
 int autotune(tm_graph *g, const int64_t *h_deltas, Params *best, float *best_ms) {
-    static const uint32_t chunks[] = {2, 4, 8, 16, 32, 64};
+    static const uint32_t chunks[] = {1, 2, 4};  // tiles up to the staging capacity
     static const uint32_t lanes[] = {8, 32, 64, 256, 1024};
     static const uint32_t hubs[] = {16, 32, 64, 128, 256, 1024, TM_HUB_OFF};
     Params bp;

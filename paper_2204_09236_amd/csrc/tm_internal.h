@@ -253,7 +253,7 @@ struct tm_graph {
     int64_t *me_t = nullptr;       // n_me: timestamp
     uint2 *me_p = nullptr;         // n_me: position in S_lo, in S_hi
     uint4 *me_a = nullptr;         // n_me: (#o, #in) entries before it in S_lo, then in S_hi
-    uint8_t *me_o = nullptr;       // n_me: 1 if the edge leaves the smaller node
+    uint8_t *me_o = nullptr;       // n_me: bit 0 the edge leaves the smaller node, bit 1 first of its pair
 };
 
 namespace tmc {
