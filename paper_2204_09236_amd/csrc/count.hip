@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                     Wf[qa * K + i] = W;
                     Rq = (uint32_t)R;
                     // only read for a non-empty window
-                    if (recR && W) recR[qa * K + i] = make_uint2(W, S.X[R + 1] - xq);
+                    if (recR) recR[i * len + qa] = W ? make_uint2(W, S.X[R + 1] - xq) : make_uint2(0u, 0u);
                 }
                 if (i == K - 1) Wtop = W;
                 if (recL) {
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                             }
                             const uint32_t L = base + a;
                             // only read for a non-empty window
-                            if (L < p) recL[(uint64_t)p * K + i] = make_uint2(p - L, S.X[p] - S.X[L]);
+                            recL[i * len + p] = L < p ? make_uint2(p - L, S.X[p] - S.X[L]) : make_uint2(0u, 0u);
                         }
                     }
                     p_next[i] = r_last + 1;
@@ -328,7 +328,8 @@ struct StarArgs {
     const uint8_t *me_o;     // bit 0: leaves the smaller node; bit 1: first of its pair
     const uint4 *me_a;
     const uint2 *me_p;       // element positions in S_lo, S_hi
-    const uint2 *recR, *recL;  // window records of entry p: [p * K + level]
+    const uint2 *recR, *recL;  // window records of entry p: [level * n_ent + p]
+    uint64_t n_ent;          // entries of S (2m)
     uint32_t K;              // windows of the pass; each tile runs all of them
     uint64_t part_stride;    // partial rows of window i start at partial + i * part_stride
     const uint32_t *mpb;     // G + 1: multi-edge pair bounds per graph
@@ -455,7 +456,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
             // P_0, P_1 of S_c at q's window end R from q's record: with
             // (a0, a1) the counts before q, P_1(R) = a1 + dir-in entries in
             // [q, R], P_0(R) = entries up to R - P_1(R)
-            const uint2 r = a.recR[(uint64_t)(side ? pq.y : pq.x) * a.K + level];
+            const uint2 r = a.recR[level * a.n_ent + (side ? pq.y : pq.x)];
             const uint32_t p1 = eq.a1 + r.y;
             const uint64_t rp[2] = {(uint64_t)(eq.a0 + eq.a1 + r.x + 1 - p1), (uint64_t)p1};
             const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0), (uint64_t)eq.a1 + (eq.dir == 1)};
@@ -506,7 +507,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
             }
             // P_0, P_1 of S_c just before q's window start L:
             // P_1(L - 1) = a1 - dir-in entries in [L, q), P_0 = L - start - P_1
-            const uint2 r = a.recL[(uint64_t)(side ? pq.y : pq.x) * a.K + level];
+            const uint2 r = a.recL[level * a.n_ent + (side ? pq.y : pq.x)];
             const uint32_t p1 = eq.a1 - r.y;
             const uint64_t lp[2] = {(uint64_t)(eq.a0 + eq.a1 - r.x - p1), (uint64_t)p1};
 #pragma unroll
@@ -1354,7 +1355,7 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
                   pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, K, h_stride, w.hpart);
     }
     if (nm) {
-        StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, g->me_p, w.recR, w.recL, K, s_stride,
+        StarArgs sa{g->mp_start, g->me_t, g->me_o, g->me_a, g->me_p, w.recR, w.recL, len, K, s_stride,
                     g->d_mpb, w.tfirst, G, w.deltas, per, (families & TM_STARS) ? 1 : 0};
         TM_LAUNCH("star_pair", k_star_pair, dim3((unsigned)std::min<uint64_t>(w.max_itiles, 8192)),
                   dim3(kBlock), 0, s, sa, w.spart);
