@@ -128,7 +128,8 @@ __device__ inline void wave_lds_sync() {
 // Several windows at once (K nested deltas, ascending; one graph): every step
 // searches the same ring once per window, each search starting where the
 // previous (smaller) window ended, and writes Wf, recR and recL of window i
-// at p * K + i.  The bit planes describe the largest window.
+// at i * len + p (level-major: each store instruction of a window covers
+// whole lines).  The bit planes describe the largest window.
 constexpr uint32_t kRing = 2 * kWave;
 constexpr uint32_t kHubCap = 2048;  // window entries per LDS segment of the hub pass
 constexpr int kMaxLevels = 4;       // windows counted in one pass
@@ -205,7 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                     if (lo == kRing - 1)  // the window may run past the ring
                         R = window_end(S.t, (uint32_t)R, S.off[ca + 1], lim);
                     W = (uint32_t)(R - qa);
-                    Wf[qa * K + i] = W;
+                    Wf[i * len + qa] = W;
                     Rq = (uint32_t)R;
                     // only read for a non-empty window
                     if (recR) recR[i * len + qa] = W ? make_uint2(W, S.X[R + 1] - xq) : make_uint2(0u, 0u);
@@ -630,15 +631,15 @@ __device__ inline uint32_t tri_class(uint32_t ra, uint32_t da, uint32_t rb, uint
 // windows from index `level` up, where `level` = the number of smaller
 // windows that miss one of them.  oa, ob: the later edges' offsets after
 // the first edge's entries ps (at its source) and pd (at its destination);
-// Wf holds the size of window i at entry p at p * K + i.  Matches are rare
+// Wf holds the size of window i at entry p at i * len + p.  Matches are rare
 // next to the comparisons, so the sizes are read here, on a match.
 template <int K>
-__device__ inline uint32_t tri_level(const uint32_t *Wf, uint32_t ps, uint32_t oa, uint32_t pd,
-                                     uint32_t ob) {
+__device__ inline uint32_t tri_level(const uint32_t *Wf, uint64_t len, uint32_t ps, uint32_t oa,
+                                     uint32_t pd, uint32_t ob) {
     uint32_t l = 0;
 #pragma unroll
     for (int i = 0; i + 1 < K; i++)
-        l += (oa > Wf[(uint64_t)ps * K + i] || ob > Wf[(uint64_t)pd * K + i]) ? 1u : 0u;
+        l += (oa > Wf[i * len + ps] || ob > Wf[i * len + pd]) ? 1u : 0u;
     return l;
 }
 
@@ -656,14 +657,15 @@ constexpr uint32_t kEmptyKey = 0xffffffffu;  // node ids are below 2^31
 constexpr uint32_t kHashMul = 2654435761u;   // Knuth's multiplicative constant
 
 // K windows: the candidates and their windows are those of the largest one,
-// each match is filed under its level (Wf: window i of entry p at p * K +
-// i), and level l's rows go to partial + l * lvl_stride.
+// each match is filed under its level (Wf: window i of entry p at i * len +
+// p), and level l's rows go to partial + l * lvl_stride.
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *cand,
                                                       const uint32_t *tidx, const uint32_t *eoff,
                                                       const uint32_t *ctfirst, uint32_t G,
                                                       uint32_t lane_max, const uint32_t *Wf,
-                                                      uint64_t lvl_stride, uint64_t *partial) {
+                                                      uint64_t len, uint64_t lvl_stride,
+                                                      uint64_t *partial) {
   const uint32_t n_tiles = ctfirst[G];
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t wv = threadIdx.x / kWave;
@@ -712,8 +714,8 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                             const uint32_t cls = s_reg ? tri_class(rr[k], rn[k] & 1u, rb, ndb & 1u)
                                                        : tri_class(rb, ndb & 1u, rr[k], rn[k] & 1u);
                             const uint32_t oreg = (uint32_t)k + 1, ostr = b - lp;
-                            const uint32_t l = s_reg ? tri_level<K>(Wf, ps, oreg, pd, ostr)
-                                                     : tri_level<K>(Wf, ps, ostr, pd, oreg);
+                            const uint32_t l = s_reg ? tri_level<K>(Wf, len, ps, oreg, pd, ostr)
+                                                     : tri_level<K>(Wf, len, ps, ostr, pd, oreg);
                             tri_add(T, l * 8 + cls);
                         }
                     }
@@ -725,7 +727,7 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                         const uint32_t ndb = S.nd[b];
                         if ((ndb >> 1) == (nda >> 1)) {
                             const uint32_t cls = tri_class(S.rk[a], nda & 1u, S.rk[b], ndb & 1u);
-                            tri_add(T, tri_level<K>(Wf, ps, a - ps, pd, b - pd) * 8 + cls);
+                            tri_add(T, tri_level<K>(Wf, len, ps, a - ps, pd, b - pd) * 8 + cls);
                         }
                     }
                 }
@@ -778,8 +780,8 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                                 uint32_t l = 0;
                                 if (K > 1) {
                                     const uint32_t oo = y - o_base, oi = x - i_base;
-                                    l = s_outer ? tri_level<K>(Wf, bps, oo, bpd, oi)
-                                                : tri_level<K>(Wf, bps, oi, bpd, oo);
+                                    l = s_outer ? tri_level<K>(Wf, len, bps, oo, bpd, oi)
+                                                : tri_level<K>(Wf, len, bps, oi, bpd, oo);
                                 }
                                 tri_add(T, l * 8 + cls);
                             }
@@ -807,8 +809,8 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
                             const uint32_t cls = s_outer ? tri_class(ro, ndo & 1u, rx, ndx & 1u)
                                                          : tri_class(rx, ndx & 1u, ro, ndo & 1u);
                             const uint32_t oo = ob + k - o_base, oi = x - i_base;
-                            const uint32_t l = s_outer ? tri_level<K>(Wf, bps, oo, bpd, oi)
-                                                       : tri_level<K>(Wf, bps, oi, bpd, oo);
+                            const uint32_t l = s_outer ? tri_level<K>(Wf, len, bps, oo, bpd, oi)
+                                                       : tri_level<K>(Wf, len, bps, oi, bpd, oo);
                             tri_add(T, l * 8 + cls);
                         }
                     }
@@ -903,7 +905,8 @@ constexpr uint64_t kLow48 = (1ull << 48) - 1;
 struct HubArgs {
     SeqView S;
     const uint2 *epos2;
-    const uint32_t *Wf;  // window sizes: window i of entry p at p * K + i
+    const uint32_t *Wf;  // window sizes: window i of entry p at i * len + p
+    uint64_t len;        // entries of S
     const uint64_t *lev;
     const uint32_t *eoff, *htfirst, *count, *list;
     uint32_t G, hub_min;
@@ -942,7 +945,7 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             s_hi = 0;
         }
         // A. owners among this thread's positions
-        const uint32_t *Wtop = a.Wf + (K - 1);  // window K - 1 of entry p at p * K
+        const uint32_t *Wtop = a.Wf + (K - 1) * a.len;  // the largest window
         uint32_t own = 0, rp[kHubPer], rw[kHubPer], rq[kHubPer], rwo[kHubPer];
 #pragma unroll
         for (uint32_t k = 0; k < kHubPer; k++) {
@@ -950,11 +953,11 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             rp[k] = p;
             rw[k] = rq[k] = rwo[k] = 0;
             if (p < s1 && ((hub_word(a.lev, p / kWave, hub_first) >> (p % kWave)) & 1ull)) {
-                const uint32_t W = Wtop[(uint64_t)p * K];
+                const uint32_t W = Wtop[p];
                 const uint2 e = a.epos2[S.rk[p]];
                 const bool is_s = e.x == p;
                 const uint32_t q = is_s ? e.y : e.x;
-                const uint32_t Wo = Wtop[(uint64_t)q * K];
+                const uint32_t Wo = Wtop[q];
                 if (Wo != 0 && Wo < kHubCap && (is_s ? W >= Wo : W > Wo)) {
                     own |= 1u << k;
                     rw[k] = W | (is_s ? 0x80000000u : 0u);
@@ -1095,8 +1098,8 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
                                     const uint32_t cls = own_s ? tri_class(v >> 1, v & 1u, rx, nd[u] & 1u)
                                                                : tri_class(rx, nd[u] & 1u, v >> 1, v & 1u);
                                     const uint32_t l =
-                                        own_s ? tri_level<K>(a.Wf, p, y - p, qq[u], ox)
-                                              : tri_level<K>(a.Wf, qq[u], ox, p, y - p);
+                                        own_s ? tri_level<K>(a.Wf, a.len, p, y - p, qq[u], ox)
+                                              : tri_level<K>(a.Wf, a.len, qq[u], ox, p, y - p);
                                     tri_add(red[wv], l * 8 + cls);
                                 }
                             }
@@ -1223,7 +1226,7 @@ constexpr uint32_t kDefaultHubMin = 32;
 struct Workspace {
     uint32_t K = 1;  // windows counted in one pass (one graph when K > 1)
     int64_t *deltas;
-    uint32_t *Wf;       // window i of entry p at p * K + i
+    uint32_t *Wf;       // window i of entry p at i * len + p
     uint2 *recR, *recL; // window records for the star/pair sweeps, same layout
     uint64_t *wbits, *lev;
     uint32_t *tflag, *tidx;
@@ -1312,7 +1315,7 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     const bool do_tri = (families & TM_TRIANGLES) != 0;
     const bool do_hub = do_tri && pr.hub_min != TM_HUB_OFF;
     const uint64_t nm = do_sp ? g->n_multi : 0;
-    const uint32_t *Wtop = w.Wf + (K - 1);  // entry p's largest window at Wtop[p * K]
+    const uint32_t *Wtop = w.Wf + (uint64_t)(K - 1) * len;  // entries' largest windows
     const uint64_t t_stride = w.max_ctiles * kTriRowsPerTile * 8, h_stride = w.max_htiles * 8;
     const uint64_t s_stride = w.max_itiles * 32;
     int rc;
@@ -1336,7 +1339,7 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
         rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
         if (rc) return rc;
         TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
-                  reinterpret_cast<const uint2 *>(g->epos), Wtop, K, w.tflag, w.tidx, m, w.cand);
+                  reinterpret_cast<const uint2 *>(g->epos), Wtop, 1u, w.tflag, w.tidx, m, w.cand);
     }
     // ---- per-graph work tiles
     {
@@ -1364,11 +1367,11 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
         ProfRow row_a5("a5");
         TM_LAUNCH_K("triangles", k_triangles, K, dim3((unsigned)std::min<uint64_t>(w.max_ctiles, 8192)),
                     dim3(kBlock), 0, s, S, w.cand, w.tidx, g->d_eoff, w.ctfirst, G, tri_lane_max,
-                    w.Wf, t_stride, w.tpart);
+                    w.Wf, len, t_stride, w.tpart);
     }
     if (do_hub) {
         ProfRow row_a5("a5");
-        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, w.lev, g->d_eoff,
+        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, len, w.lev, g->d_eoff,
                    w.htfirst, w.hcount, w.hlist, G, pr.hub_min, h_stride};
         TM_LAUNCH_K("tri_hub", k_tri_hub, K, dim3((unsigned)std::min<uint64_t>(w.max_htiles, 4096)),
                     dim3(kHubBlock), 0, s, ha, w.hpart);
