@@ -137,8 +137,8 @@ constexpr int kMaxLevels = 4;       // windows counted in one pass
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles, uint32_t n_tiles,
                                                     uint64_t len, const int64_t *deltas,
-                                                    uint32_t *Wf, uint32_t hub_min, uint64_t *bits,
-                                                    uint64_t *lev, uint2 *recR, uint2 *recL) {
+                                                    uint32_t *Wf, uint32_t hub_min, uint64_t *planes,
+                                                    uint2 *recR, uint2 *recL) {
     // key j of the ring: (center, unused, t low, t high)
     __shared__ uint4 ring[kBlock / kWave][kRing];
     __shared__ uint32_t rend[kBlock / kWave][kWave];  // the step's window ends R
@@ -237,14 +237,16 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                     p_next[i] = r_last + 1;
                 }
             }
-            if (bits) {
+            if (planes) {
                 const uint32_t t2 = min(hub_min, kHubCap), t3 = max(hub_min, kHubCap);
                 const uint64_t b = __ballot(Wtop != 0);
                 const uint64_t b2 = __ballot(Wtop >= t2);
                 const uint64_t b3 = __ballot(Wtop >= t3);
                 if (lane == 0) {
-                    bits[base / kWave] = b;
-                    reinterpret_cast<ulonglong2 *>(lev)[base / kWave] = make_ulonglong2(b2, b3);
+                    uint64_t *pw = planes + 3 * (uint64_t)(base / kWave);
+                    pw[0] = b;
+                    pw[1] = b2;
+                    pw[2] = b3;
                 }
             }
             wave_lds_sync();  // the next step overwrites this half
@@ -540,15 +542,13 @@ constexpr uint32_t kHubSlots = 2 * kHubCap;  // hash slots (load factor <= 1/2)
 constexpr uint32_t kHubBits = 12;            // log2(kHubSlots)
 static_assert((1u << kHubBits) == kHubSlots, "hub table size");
 
-// Window bits of each entry: bits[g] holds W >= 1 for entries 64g .. 64g+63;
-// lev[2g], lev[2g + 1] hold W >= t2 and W >= t3, where (t2, t3) are hub_min
-// and kHubCap in increasing order, side by side so one 16-byte load answers
-// both.  Every edge needs the first bitmap at its two entries, only
-// candidates the second (len / 8 and len / 4 bytes, kept in cache), so the
-// per-edge lookups at two unrelated positions do not each fetch a line of Wf
-// from HBM.
-__global__ void k_wlevels(const uint32_t *Wf, uint64_t len, uint32_t hub_min, uint64_t *bits,
-                          uint64_t *lev) {
+// Window bit planes of the entries (largest window): for entries 64g ..
+// 64g+63, planes[3g] holds W >= 1, planes[3g + 1] and planes[3g + 2] hold
+// W >= t2 and W >= t3, where (t2, t3) are hub_min and kHubCap in increasing
+// order.  The three words of a group lie side by side (3 len / 64 words in
+// all, kept in cache), so an edge's candidate test at each of its two
+// unrelated entries fetches one line, not one of Wf from HBM.
+__global__ void k_wlevels(const uint32_t *Wf, uint64_t len, uint32_t hub_min, uint64_t *planes) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t t2 = min(hub_min, kHubCap), t3 = max(hub_min, kHubCap);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -560,42 +560,40 @@ __global__ void k_wlevels(const uint32_t *Wf, uint64_t len, uint32_t hub_min, ui
         const uint64_t b2 = __ballot(w >= t2);
         const uint64_t b3 = __ballot(w >= t3);
         if (lane == 0) {
-            bits[p / kWave] = b;
-            reinterpret_cast<ulonglong2 *>(lev)[p / kWave] = make_ulonglong2(b2, b3);
+            uint64_t *pw = planes + 3 * (p / kWave);
+            pw[0] = b;
+            pw[1] = b2;
+            pw[2] = b3;
         }
     }
 }
 
-__device__ inline bool wbit(const uint64_t *bits, uint32_t p) {
-    return (bits[p / kWave] >> (p % kWave)) & 1ull;
-}
-
-// (W >= t2, W >= t3) of entry p as bits 0 and 1
-__device__ inline uint32_t wlevel(const uint64_t *lev, uint32_t p) {
-    const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(lev)[p / kWave];
+// (W >= 1, W >= t2, W >= t3) of entry p as bits 0, 1 and 2
+__device__ inline uint32_t wplanes(const uint64_t *planes, uint32_t p) {
+    const uint64_t *pw = planes + 3 * (uint64_t)(p / kWave);
     const uint32_t sh = p % kWave;
-    return (uint32_t)((v.x >> sh) & 1ull) | ((uint32_t)((v.y >> sh) & 1ull) << 1);
+    return (uint32_t)((pw[0] >> sh) & 1ull) | ((uint32_t)((pw[1] >> sh) & 1ull) << 1) |
+           ((uint32_t)((pw[2] >> sh) & 1ull) << 2);
 }
 
-// Bits of 64 entries (word g of the planes) with W >= hub_min.
-__device__ inline uint64_t hub_word(const uint64_t *lev, uint64_t g, bool hub_first) {
-    const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(lev)[g];
-    return hub_first ? v.x : v.y;
+// Bits of 64 entries (group g of the planes) with W >= hub_min.
+__device__ inline uint64_t hub_word(const uint64_t *planes, uint64_t g, bool hub_first) {
+    return planes[3 * g + (hub_first ? 1 : 2)];
 }
 
 // Candidate first edges for k_triangles: both windows after the edge (at its
 // source and at its destination) hold at least one entry, and the edge is
 // not one of k_tri_hub's (larger window >= hub_min, smaller < kHubCap).
-__global__ void k_tri_flags(const uint2 *epos2, const uint64_t *bits, const uint64_t *lev,
-                            uint32_t hub_min, uint64_t m, uint32_t *flag) {
-    // bit of wlevel() that holds W >= hub_min, and the one with W >= kHubCap
-    const uint32_t bh = hub_min <= kHubCap ? 1u : 2u, bc = hub_min <= kHubCap ? 2u : 1u;
+__global__ void k_tri_flags(const uint2 *epos2, const uint64_t *planes, uint32_t hub_min,
+                            uint64_t m, uint32_t *flag) {
+    // bit of wplanes() that holds W >= hub_min, and the one with W >= kHubCap
+    const uint32_t bh = hub_min <= kHubCap ? 2u : 4u, bc = hub_min <= kHubCap ? 4u : 2u;
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (uint64_t)gridDim.x * blockDim.x) {
         const uint2 e = epos2[r];
+        const uint32_t ls = wplanes(planes, e.x), ld = wplanes(planes, e.y);
         uint32_t f = 0;
-        if (wbit(bits, e.x) && wbit(bits, e.y)) {
-            const uint32_t ls = wlevel(lev, e.x), ld = wlevel(lev, e.y);
+        if (ls & ld & 1u) {
             const bool hub = ((ls | ld) & bh) && !(ls & ld & bc);
             f = hub ? 0u : 1u;
         }
@@ -846,7 +844,7 @@ __global__ void __launch_bounds__(kBlock) k_triangles(SeqView S, const uint4 *ca
 // holding a position with W >= hub_min goes on the work list (in no
 // particular order: each tile writes its own row); the row of every other
 // slice is zeroed here.  *count was zeroed by k_graph_tiles.
-__global__ void k_hub_tiles(const uint64_t *lev, uint32_t hub_min, const uint32_t *eoff,
+__global__ void k_hub_tiles(const uint64_t *planes, uint32_t hub_min, const uint32_t *eoff,
                             const uint32_t *htfirst, uint32_t G, uint32_t *count, uint32_t *list,
                             uint32_t levels, uint64_t lvl_stride, uint64_t *hpart) {
     const bool hub_first = hub_min <= kHubCap;
@@ -858,7 +856,7 @@ __global__ void k_hub_tiles(const uint64_t *lev, uint32_t hub_min, const uint32_
         const uint32_t s1 = min(2 * eoff[gi + 1], s0 + kHubSlice);
         bool any = false;
         for (uint32_t w = s0 / kWave; w <= (s1 - 1) / kWave && !any; w++) {
-            uint64_t b = hub_word(lev, w, hub_first);
+            uint64_t b = hub_word(planes, w, hub_first);
             const uint32_t wlo = w * kWave;
             if (s0 > wlo) b &= ~0ull << (s0 - wlo);
             if (s1 - wlo < kWave) b &= (1ull << (s1 - wlo)) - 1;
@@ -907,7 +905,7 @@ struct HubArgs {
     const uint2 *epos2;
     const uint32_t *Wf;  // window sizes: window i of entry p at i * len + p
     uint64_t len;        // entries of S
-    const uint64_t *lev;
+    const uint64_t *planes;  // window bit planes (k_wlevels)
     const uint32_t *eoff, *htfirst, *count, *list;
     uint32_t G, hub_min;
     uint64_t lvl_stride;  // level l's rows go to hpart + l * lvl_stride
@@ -952,7 +950,7 @@ k_tri_hub(HubArgs a, uint64_t *hpart) {
             const uint32_t p = s0 + kHubPer * threadIdx.x + k;
             rp[k] = p;
             rw[k] = rq[k] = rwo[k] = 0;
-            if (p < s1 && ((hub_word(a.lev, p / kWave, hub_first) >> (p % kWave)) & 1ull)) {
+            if (p < s1 && ((hub_word(a.planes, p / kWave, hub_first) >> (p % kWave)) & 1ull)) {
                 const uint32_t W = Wtop[p];
                 const uint2 e = a.epos2[S.rk[p]];
                 const bool is_s = e.x == p;
@@ -1228,7 +1226,7 @@ struct Workspace {
     int64_t *deltas;
     uint32_t *Wf;       // window i of entry p at i * len + p
     uint2 *recR, *recL; // window records for the star/pair sweeps, same layout
-    uint64_t *wbits, *lev;
+    uint64_t *planes;   // window bit planes, 3 words per 64 entries
     uint32_t *tflag, *tidx;
     uint4 *cand;
     uint32_t *n_itiles, *tfirst, *n_ctiles, *ctfirst, *tmp;
@@ -1246,8 +1244,7 @@ static size_t workspace_bytes(const tm_graph *g, Workspace *w, uint32_t K = 1) {
     w->max_htiles = len / kHubSlice + G + 1;
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    return up((size_t)G * K * 8) + up(len * 4 * K) + up(len * 8 * K) * 2 + up((len / kWave + 1) * 8) +
-           up((len / kWave + 1) * 16) +
+    return up((size_t)G * K * 8) + up(len * 4 * K) + up(len * 8 * K) * 2 + up((len / kWave + 1) * 24) +
            up((G + 1) * 4) * 2 + up(4) + up(w->max_htiles * 4) + up(w->max_htiles * 8 * 8 * K) +
            up((size_t)G * sum_split(G) * 40 * 8) +
            up(m * 4) + up((m + 1) * 4) + up(m * sizeof(uint4)) + up((G + 1) * 4) * 4 +
@@ -1263,8 +1260,7 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     w->Wf = sc.take<uint32_t>(len * K);
     w->recR = sc.take<uint2>(len * K);
     w->recL = sc.take<uint2>(len * K);
-    w->wbits = sc.take<uint64_t>(len / kWave + 1);
-    w->lev = sc.take<uint64_t>(2 * (len / kWave + 1));
+    w->planes = sc.take<uint64_t>(3 * (len / kWave + 1));
     w->n_htiles = sc.take<uint32_t>(G + 1);
     w->htfirst = sc.take<uint32_t>(G + 1);
     w->hcount = sc.take<uint32_t>(1);
@@ -1326,16 +1322,16 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     ProfRow row_a4("a4");
     TM_LAUNCH_K("windows", k_windows, K, dim3(std::min<uint32_t>(g->n_t_entries, 16384)), dim3(kBlock),
                 0, s, S, g->t_entries, g->n_t_entries, len, w.deltas, w.Wf, pr.hub_min,
-                fused_levels ? w.wbits : nullptr, fused_levels ? w.lev : nullptr,
+                fused_levels ? w.planes : nullptr,
                 nm ? w.recR : nullptr, nm ? w.recL : nullptr);
     // ---- triangles: candidate first edges (of the largest window)
     if (do_tri) {
         ProfRow row_a5("a5");
         if (!fused_levels)  // batches: K == 1
             TM_LAUNCH("wlevels", k_wlevels, grid_for(2 * m, 16384), dim3(kBlock), 0, s, w.Wf, 2 * m,
-                      pr.hub_min, w.wbits, w.lev);
+                      pr.hub_min, w.planes);
         TM_LAUNCH("tri_flags", k_tri_flags, grid_for(m, 16384), dim3(kBlock), 0, s,
-                  reinterpret_cast<const uint2 *>(g->epos), w.wbits, w.lev, pr.hub_min, m, w.tflag);
+                  reinterpret_cast<const uint2 *>(g->epos), w.planes, pr.hub_min, m, w.tflag);
         rc = scan_u32_array(w.tflag, w.tidx, m, w.tmp, s);
         if (rc) return rc;
         TM_LAUNCH("tri_compact", k_tri_compact, grid_for(m, 16384), dim3(kBlock), 0, s,
@@ -1354,7 +1350,7 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     rc = scan_u32_array(w.n_htiles, w.htfirst, G, w.tmp, s);
     if (rc) return rc;
     if (do_hub)
-        TM_LAUNCH("hub_tiles", k_hub_tiles, grid_for(w.max_htiles, 4096), dim3(kBlock), 0, s, w.lev,
+        TM_LAUNCH("hub_tiles", k_hub_tiles, grid_for(w.max_htiles, 4096), dim3(kBlock), 0, s, w.planes,
                   pr.hub_min, g->d_eoff, w.htfirst, G, w.hcount, w.hlist, K, h_stride, w.hpart);
     }
     if (nm) {
@@ -1371,7 +1367,7 @@ static int enqueue_count(tm_graph *g, const Workspace &w, const Params &pr, uint
     }
     if (do_hub) {
         ProfRow row_a5("a5");
-        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, len, w.lev, g->d_eoff,
+        HubArgs ha{S, reinterpret_cast<const uint2 *>(g->epos), w.Wf, len, w.planes, g->d_eoff,
                    w.htfirst, w.hcount, w.hlist, G, pr.hub_min, h_stride};
         TM_LAUNCH_K("tri_hub", k_tri_hub, K, dim3((unsigned)std::min<uint64_t>(w.max_htiles, 4096)),
                     dim3(kHubBlock), 0, s, ha, w.hpart);
