@@ -127,9 +127,11 @@ __device__ inline void wave_lds_sync() {
 //
 // Several windows at once (K nested deltas, ascending; one graph): every step
 // searches the same ring once per window, each search starting where the
-// previous (smaller) window ended, and writes Wf, recR and recL of window i
-// at i * len + p (level-major: each store instruction of a window covers
-// whole lines).  The bit planes describe the largest window.
+// previous (smaller) window ended, and writes Wf of window i at i * len + p
+// and its records at recR / recL[2 (i * len + p)] (level-major, the two
+// records of an entry side by side: a window's stores cover whole lines
+// together, and the sweeps find both records of an entry in one line).
+// The bit planes describe the largest window.
 constexpr uint32_t kRing = 2 * kWave;
 constexpr uint32_t kHubCap = 2048;  // window entries per LDS segment of the hub pass
 constexpr int kMaxLevels = 4;       // windows counted in one pass
@@ -209,7 +211,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                     Wf[i * len + qa] = W;
                     Rq = (uint32_t)R;
                     // only read for a non-empty window
-                    if (recR) recR[i * len + qa] = W ? make_uint2(W, S.X[R + 1] - xq) : make_uint2(0u, 0u);
+                    if (recR) recR[2 * (i * len + qa)] = W ? make_uint2(W, S.X[R + 1] - xq) : make_uint2(0u, 0u);
                 }
                 if (i == K - 1) Wtop = W;
                 if (recL) {
@@ -231,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                             }
                             const uint32_t L = base + a;
                             // only read for a non-empty window
-                            recL[i * len + p] = L < p ? make_uint2(p - L, S.X[p] - S.X[L]) : make_uint2(0u, 0u);
+                            recL[2 * (i * len + p)] = L < p ? make_uint2(p - L, S.X[p] - S.X[L]) : make_uint2(0u, 0u);
                         }
                     }
                     p_next[i] = r_last + 1;
@@ -331,7 +333,7 @@ struct StarArgs {
     const uint8_t *me_o;     // bit 0: leaves the smaller node; bit 1: first of its pair
     const uint4 *me_a;
     const uint2 *me_p;       // element positions in S_lo, S_hi
-    const uint2 *recR, *recL;  // window records of entry p: [level * n_ent + p]
+    const uint2 *recR, *recL;  // window records of entry p: [2 (level * n_ent + p)]
     uint64_t n_ent;          // entries of S (2m)
     uint32_t K;              // windows of the pass; each tile runs all of them
     uint64_t part_stride;    // partial rows of window i start at partial + i * part_stride
@@ -459,7 +461,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
             // P_0, P_1 of S_c at q's window end R from q's record: with
             // (a0, a1) the counts before q, P_1(R) = a1 + dir-in entries in
             // [q, R], P_0(R) = entries up to R - P_1(R)
-            const uint2 r = a.recR[level * a.n_ent + (side ? pq.y : pq.x)];
+            const uint2 r = a.recR[2 * (level * a.n_ent + (side ? pq.y : pq.x))];
             const uint32_t p1 = eq.a1 + r.y;
             const uint64_t rp[2] = {(uint64_t)(eq.a0 + eq.a1 + r.x + 1 - p1), (uint64_t)p1};
             const uint64_t pin[2] = {(uint64_t)eq.a0 + (eq.dir == 0), (uint64_t)eq.a1 + (eq.dir == 1)};
@@ -510,7 +512,7 @@ k_star_pair(StarArgs a, uint64_t *partial) {
             }
             // P_0, P_1 of S_c just before q's window start L:
             // P_1(L - 1) = a1 - dir-in entries in [L, q), P_0 = L - start - P_1
-            const uint2 r = a.recL[level * a.n_ent + (side ? pq.y : pq.x)];
+            const uint2 r = a.recL[2 * (level * a.n_ent + (side ? pq.y : pq.x))];
             const uint32_t p1 = eq.a1 - r.y;
             const uint64_t lp[2] = {(uint64_t)(eq.a0 + eq.a1 - r.x - p1), (uint64_t)p1};
 #pragma unroll
@@ -1225,7 +1227,8 @@ struct Workspace {
     uint32_t K = 1;  // windows counted in one pass (one graph when K > 1)
     int64_t *deltas;
     uint32_t *Wf;       // window i of entry p at i * len + p
-    uint2 *recR, *recL; // window records for the star/pair sweeps, same layout
+    uint2 *recR, *recL; // window records: entry p's of window i at recR / recL[2 (i len + p)],
+                        // the two side by side (one array, recL = recR + 1)
     uint64_t *planes;   // window bit planes, 3 words per 64 entries
     uint32_t *tflag, *tidx;
     uint4 *cand;
@@ -1258,8 +1261,8 @@ static void workspace_carve(const tm_graph *g, Scratch &sc, Workspace *w) {
     const size_t n_tmp = scan_tmp_count(std::max<uint64_t>({m, nm, (uint64_t)G})) + 4;
     w->deltas = sc.take<int64_t>((size_t)G * K);
     w->Wf = sc.take<uint32_t>(len * K);
-    w->recR = sc.take<uint2>(len * K);
-    w->recL = sc.take<uint2>(len * K);
+    w->recR = sc.take<uint2>(2 * len * K);
+    w->recL = w->recR + 1;
     w->planes = sc.take<uint64_t>(3 * (len / kWave + 1));
     w->n_htiles = sc.take<uint32_t>(G + 1);
     w->htfirst = sc.take<uint32_t>(G + 1);
