@@ -391,7 +391,7 @@ __device__ inline void star_flush(const uint64_t (&acc)[N], int c0, uint64_t (*r
 // one after another on the staged tile, so an entry's records (side by side
 // for all windows) are read again while their line is still cached.
 constexpr uint32_t kStageHalo = 64;
-constexpr uint32_t kStageCap = 4 * kBlock + 2 * kStageHalo;
+constexpr uint32_t kStageCap = 2048;  // 51 KiB of LDS: three blocks per CU
 
 struct ElemView {
     uint32_t lo, hi;  // staged element range
@@ -570,6 +570,11 @@ __global__ void k_wlevels(const uint32_t *Wf, uint64_t len, uint32_t hub_min, ui
     }
 }
 
+// W >= 1 at entry p
+__device__ inline bool wbit(const uint64_t *planes, uint32_t p) {
+    return (planes[3 * (uint64_t)(p / kWave)] >> (p % kWave)) & 1ull;
+}
+
 // (W >= 1, W >= t2, W >= t3) of entry p as bits 0, 1 and 2
 __device__ inline uint32_t wplanes(const uint64_t *planes, uint32_t p) {
     const uint64_t *pw = planes + 3 * (uint64_t)(p / kWave);
@@ -593,9 +598,11 @@ __global__ void k_tri_flags(const uint2 *epos2, const uint64_t *planes, uint32_t
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (uint64_t)gridDim.x * blockDim.x) {
         const uint2 e = epos2[r];
-        const uint32_t ls = wplanes(planes, e.x), ld = wplanes(planes, e.y);
         uint32_t f = 0;
-        if (ls & ld & 1u) {
+        // the hub planes only for edges with both windows non-empty (their
+        // words share the line of the first plane's)
+        if (wbit(planes, e.x) && wbit(planes, e.y)) {
+            const uint32_t ls = wplanes(planes, e.x), ld = wplanes(planes, e.y);
             const bool hub = ((ls | ld) & bh) && !(ls & ld & bc);
             f = hub ? 0u : 1u;
         }
@@ -1704,7 +1711,7 @@ int count_graph_multi(tm_graph *g, const int64_t *h_deltas, uint32_t k, Params p
 // keyed by the graph's shape (log2 of edges, of multi-pair edges, and of the
 // graph count), which later graphs of that shape use by default.
 int autotune(tm_graph *g, const int64_t *h_deltas, Params *best, float *best_ms) {
-    static const uint32_t chunks[] = {1, 2, 4};  // tiles up to the staging capacity
+    static const uint32_t chunks[] = {2, 4, 8};
     static const uint32_t lanes[] = {8, 32, 64, 256, 1024};
     static const uint32_t hubs[] = {16, 32, 64, 128, 256, 1024, TM_HUB_OFF};
     Params bp;
