@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                     Wf[i * len + qa] = W;
                     Rq = (uint32_t)R;
                     // only read for a non-empty window
-                    if (recR) recR[2 * (i * len + qa)] = W ? make_uint2(W, S.X[R + 1] - xq) : make_uint2(0u, 0u);
+                    if (recR && W) recR[2 * (i * len + qa)] = make_uint2(W, S.X[R + 1] - xq);
                 }
                 if (i == K - 1) Wtop = W;
                 if (recL) {
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_windows(SeqView S, const Tile *tiles
                             }
                             const uint32_t L = base + a;
                             // only read for a non-empty window
-                            recL[2 * (i * len + p)] = L < p ? make_uint2(p - L, S.X[p] - S.X[L]) : make_uint2(0u, 0u);
+                            if (L < p) recL[2 * (i * len + p)] = make_uint2(p - L, S.X[p] - S.X[L]);
                         }
                     }
                     p_next[i] = r_last + 1;
