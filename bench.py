@@ -221,16 +221,19 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
         "sort_node_scatter_last": e2 * (20 + 24),
         # edge positions: (slot, position) pairs partitioned by the slot's
         # high bits (the first pass reads the slots alone), then each bucket
-        # filled through LDS
+        # filled through LDS, with each edge's record (t, both positions)
         "sort_slot_hist": e2 * 4,
         "sort_slot_scatter": e2 * 14,
-        "epos_fill": e2 * (8 + 4),
+        "epos_fill": e2 * (8 + 4) + m * (8 + 16),
         "offsets_fill": (n + 1) * 4,
         "offsets": e2 * 4 + (n + 1) * 4,
         "sort_pair_hist": m * 4,
         "sort_pair_scatter": m * (8 + 4) * 2,
-        "multi_flags": m * (8 + 8),
-        "multi_fill": m * 28 + me * (32 + 33) + nm * 12,
+        "pair_flags": m * (12 + 1),
+        # per edge its pair-flag prefix; per element of a pair with >= 2
+        # edges its pair-sort record, its edge record, X at its two entries
+        # and at the two nodes' first entries, and its 33 B of output
+        "multi_fill": m * 8 + me * (12 + 16 + 16 + 33) + nm * 12,
         # keys read; per window the sizes (4 B) and, for non-empty windows,
         # the two star/pair records (8 B each, with X read next to the entry;
         # counted here as one); one graph: the three window bit planes too
@@ -394,15 +397,16 @@ def run_single(args, workload: str, full: bool = True) -> dict:
         return outs
 
     # the library's autotuner, once, before warm-up and outside the timed
-    # region, at the workload's largest delta (the most work): its choice is
-    # kept in the process-wide table keyed by graph shape, so the timed
-    # steps' freshly built graphs of this shape count with it
+    # region, on the step's own count (all of the workload's windows in one
+    # pass): its choice is kept in the process-wide table keyed by graph
+    # shape, so the timed steps' freshly built graphs of this shape count
+    # with it
     tuned = None
     if not args.no_autotune:
         G0 = tm.build_graph(src, dst, tt, n=g.n, stream=stream)
-        tuned = G0.autotune([max(deltas)])
+        tuned = G0.autotune_multi(deltas) if multi else G0.autotune([max(deltas)])
         G0.free()
-        print(f"[bench] autotuned at delta {max(deltas)}: {tuned}", file=sys.stderr, flush=True)
+        print(f"[bench] autotuned at deltas {deltas}: {tuned}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         counts = step()

@@ -147,6 +147,16 @@ int tm_count_batch_raw_ex(tm_graph *g, const int64_t *deltas, uint32_t run_chunk
 int tm_autotune(tm_graph *g, const int64_t *deltas, uint32_t *run_chunk, uint32_t *tri_lane_max,
                 uint32_t *hub_min, float *best_ms);
 
+/*
+ * tm_autotune for the several-window count of one graph (tm_count_multi):
+ * times one pass over the largest min(k, 4) of the k windows deltas (host
+ * array, 0 <= delta < 2^62, 1 <= k <= TM_MAX_DELTAS), on the same grid, and
+ * keeps the fastest as tm_autotune does.  TM_EINVAL for a batch of several
+ * graphs, k out of range or a bad delta.
+ */
+int tm_autotune_multi(tm_graph *g, const int64_t *deltas, uint32_t k, uint32_t *run_chunk,
+                      uint32_t *tri_lane_max, uint32_t *hub_min, float *best_ms);
+
 /* Release a graph and its device memory.  NULL is ignored. */
 void tm_graph_free(tm_graph *g);
 

@@ -331,7 +331,44 @@ int tm_autotune(tm_graph *g, const int64_t *deltas, uint32_t *run_chunk, uint32_
     {
         std::lock_guard<std::mutex> lk(g->mu);
         tmc::Params best;
-        rc = tmc::autotune(g, deltas, &best, best_ms);
+        rc = tmc::autotune(g, deltas, 1, &best, best_ms);
+        if (rc == TM_OK) {
+            if (run_chunk) *run_chunk = best.run_chunk;
+            if (tri_lane_max) *tri_lane_max = best.tri_lane_max;
+            if (hub_min) *hub_min = best.hub_min;
+        }
+    }
+    if (cur != g->device) (void)hipSetDevice(cur);
+    return rc;
+}
+
+int tm_autotune_multi(tm_graph *g, const int64_t *deltas, uint32_t k, uint32_t *run_chunk,
+                      uint32_t *tri_lane_max, uint32_t *hub_min, float *best_ms) {
+    if (!g || !deltas) {
+        tmc::set_error("NULL graph or deltas");
+        return TM_EINVAL;
+    }
+    if (g->G != 1) {
+        tmc::set_error("a batch of several graphs is tuned with tm_autotune");
+        return TM_EINVAL;
+    }
+    if (k == 0 || k > TM_MAX_DELTAS) {
+        tmc::set_error("k must be in [1, TM_MAX_DELTAS]");
+        return TM_EINVAL;
+    }
+    for (uint32_t i = 0; i < k; i++)
+        if (deltas[i] < 0 || deltas[i] >= ((int64_t)1 << 62)) {
+            tmc::set_error("delta must satisfy 0 <= delta < 2^62");
+            return TM_EINVAL;
+        }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        tmc::Params best;
+        rc = tmc::autotune(g, deltas, k, &best, best_ms);
         if (rc == TM_OK) {
             if (run_chunk) *run_chunk = best.run_chunk;
             if (tri_lane_max) *tri_lane_max = best.tri_lane_max;

@@ -157,16 +157,15 @@ __global__ void k_offsets_gaps(const uint32_t *skey, uint64_t len, uint32_t n, u
     }
 }
 
-// Element g of the pair-sorted edges lies in a pair with >= 2 edges; head = first of its pair.
-__global__ void k_multi_flags(const uint32_t *pkey, const uint2 *pval, uint64_t m,
-                              uint32_t *in_multi, uint32_t *multi_head) {
+// Element g of the pair-sorted edges: bit 0 if its node pair has >= 2
+// edges, bit 1 if it is also the first of its pair.
+__global__ void k_pair_flags(const uint32_t *pkey, const uint2 *pval, uint64_t m, uint8_t *f) {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m;
          g += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t k = pkey[g], lo = pval[g].x;
         const bool same_prev = g > 0 && pkey[g - 1] == k && pval[g - 1].x == lo;
         const bool same_next = g + 1 < m && pkey[g + 1] == k && pval[g + 1].x == lo;
-        in_multi[g] = (same_prev || same_next) ? 1u : 0u;
-        multi_head[g] = (!same_prev && same_next) ? 1u : 0u;
+        f[g] = (uint8_t)((same_prev || same_next ? 1u : 0u) | (!same_prev && same_next ? 2u : 0u));
     }
 }
 
@@ -178,20 +177,27 @@ struct MultiOut {
     uint8_t *me_o;  // bit 0: leaves the smaller node, bit 1: first of its pair
 };
 
+// pre: scan_flag_pairs of k_pair_flags (m + 1 entries): element g
+// is in a pair with >= 2 edges iff the low words of pre[g] and pre[g + 1]
+// differ, the first of its pair iff the high words do, and the low and high
+// words of pre[g] are its element index and pair index.  An edge's time and
+// positions come from erec when it is given (one line per edge), else from
+// t_r and epos.
 __global__ void k_multi_fill(const uint32_t *pkey, const uint2 *pval, uint64_t m,
-                             const uint32_t *in_multi, const uint32_t *eidx,
-                             const uint32_t *multi_head, const uint32_t *pidx,
-                             const int64_t *t_r, const uint32_t *epos, const uint32_t *X,
-                             const uint32_t *off, uint64_t n_multi, uint64_t n_me, MultiOut o) {
+                             const uint64_t *pre, const EdgeRec *erec, const int64_t *t_r,
+                             const uint32_t *epos, const uint32_t *X, const uint32_t *off,
+                             uint64_t n_multi, uint64_t n_me, MultiOut o) {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < m;
          g += (uint64_t)gridDim.x * blockDim.x) {
         if (g == 0) o.mp_start[n_multi] = (uint32_t)n_me;
-        if (!in_multi[g]) continue;
-        const uint32_t k = eidx[g];
+        const uint64_t a = pre[g], b = pre[g + 1];
+        if ((uint32_t)a == (uint32_t)b) continue;
+        const bool head = (a >> 32) != (b >> 32);
+        const uint32_t k = (uint32_t)a;
         const uint2 pv = pval[g];
         const uint32_t lo = pv.x, hi = pkey[g];
-        if (multi_head[g]) {
-            const uint32_t q = pidx[g];
+        if (head) {
+            const uint32_t q = (uint32_t)(a >> 32);
             o.mp_start[q] = k;
             o.mp_lo[q] = lo;
             o.mp_hi[q] = hi;
@@ -200,15 +206,27 @@ __global__ void k_multi_fill(const uint32_t *pkey, const uint2 *pval, uint64_t m
         const uint32_t r = el & ~kOrientBit;
         const uint32_t src_is_lo = el >> 31;
         // entry of this edge at lo / at hi: the src entry sits at 2r, the dst entry at 2r+1
-        const uint32_t p_lo = epos[2 * (uint64_t)r + (src_is_lo ? 0 : 1)];
-        const uint32_t p_hi = epos[2 * (uint64_t)r + (src_is_lo ? 1 : 0)];
+        int64_t te;
+        uint32_t p_src, p_dst;
+        if (erec) {
+            const EdgeRec e = erec[r];
+            te = e.t;
+            p_src = e.p_src;
+            p_dst = e.p_dst;
+        } else {
+            te = t_r[r];
+            p_src = epos[2 * (uint64_t)r];
+            p_dst = epos[2 * (uint64_t)r + 1];
+        }
+        const uint32_t p_lo = src_is_lo ? p_src : p_dst;
+        const uint32_t p_hi = src_is_lo ? p_dst : p_src;
         const uint32_t s_lo = off[lo], s_hi = off[hi];
         const uint32_t a1_lo = X[p_lo] - X[s_lo], a1_hi = X[p_hi] - X[s_hi];
-        o.me_t[k] = t_r[r];
+        o.me_t[k] = te;
         o.me_p[k] = make_uint2(p_lo, p_hi);
         o.me_a[k] = make_uint4(p_lo - s_lo - a1_lo, a1_lo, p_hi - s_hi - a1_hi, a1_hi);
         // bit 0: the edge leaves the smaller node; bit 1: first element of its pair
-        o.me_o[k] = (uint8_t)(src_is_lo | (multi_head[g] ? 2u : 0u));
+        o.me_o[k] = (uint8_t)(src_is_lo | (head ? 2u : 0u));
     }
 }
 
@@ -339,6 +357,8 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     std::vector<uint32_t> node_base(G + 1, 0);
     std::vector<int64_t> tmin_g(G, 0);
     int tbits = 0;
+    bool any_t = false;
+    int64_t t_lo = 0, t_hi = 0;  // over all graphs
     for (uint32_t i = 0; i < G; i++) {
         if (h_st[i].bad) {
             const uint32_t bad = h_st[i].bad;
@@ -359,6 +379,9 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
             const int64_t hi = (int64_t)(h_st[i].tmax_key ^ 0x8000000000000000ull);
             tmin_g[i] = lo;
             tbits = std::max(tbits, bits_for((uint64_t)(hi - lo)));
+            t_lo = any_t ? std::min(t_lo, lo) : lo;
+            t_hi = any_t ? std::max(t_hi, hi) : hi;
+            any_t = true;
         }
     }
     const int gbits = bits_for(G - 1);
@@ -415,7 +438,8 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     // TR: i64 x m                 (timestamps by rank)
     // TMP: scan / histogram scratch
     const size_t ntmp =
-        std::max({radix_tmp_bytes(len) / 4 + 1, scan_tmp_count(len), (size_t)3 * (G + 1)}) + 16;
+        std::max({radix_tmp_bytes(len) / 4 + 1, scan_tmp_count(len), 2 * scan_tmp_count(m),
+                  (size_t)3 * (G + 1)}) + 16;
     Scratch sc;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t bytes = 2 * up(8 * len) + 2 * up(16 * len) + 2 * up(8 * m) + 2 * up(4 * m) +
@@ -439,14 +463,19 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     // keys and values go to the set it does not read.  One graph: the first
     // pass reads the input arrays themselves; a batch adds the graph index
     // and the node base in k_time_keys first.
+    // timestamps within 2^32 of the smallest go through the node sort as
+    // 32-bit offsets (|t| < 2^62, so the difference fits an int64)
+    const bool t32 = (uint64_t)(t_hi - t_lo) <= 0xffffffffull;
     uint32_t *nkey = nullptr;
     NodeVal *nval = nullptr;
+    EdgeRec *erec = nullptr;  // per-edge (t, positions), built with the bucketed index
     {
         const int tpasses = (std::max(kbits, 1) + 7) / 8;
         const bool to_b = (tpasses % 2) == 1;
         nkey = reinterpret_cast<uint32_t *>(to_b ? KB : KA);
         nval = reinterpret_cast<NodeVal *>(to_b ? VB : VA);
-        const RankOut ro{g->d_tmin, G > 1 ? tbits : 64, TR, g->perm, nkey, nval};
+        const RankOut ro{g->d_tmin, G > 1 ? tbits : 64, TR, g->perm, nkey, t32 ? nullptr : nval,
+                         t32 ? reinterpret_cast<NodeVal32 *>(nval) : nullptr, t_lo};
         EdgeVal *ev = reinterpret_cast<EdgeVal *>(VA), *ev_alt = reinterpret_cast<EdgeVal *>(VB);
         const dim3 tgrid((unsigned)std::min<uint32_t>(n_etiles, 4096));
         if (kbits <= 32) {
@@ -487,12 +516,19 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         // an index that fits the last-level cache is scattered directly
         const bool direct = len * sizeof(uint32_t) <= kDirectEposBytes && !g_force_edge_sort.load();
         const SeqOut so{g->ent_c, g->ent_t, g->ent_nd, g->ent_r, direct ? g->epos : nullptr, slots,
-                        (uint64_t)len};
-        TRY(radix_sort_nodes(nkey, k_alt, nval, v_alt, len, bits_for(n - 1), tmp, sort_err, s, so));
+                        (uint64_t)len, t_lo};
+        if (t32)
+            TRY(radix_sort_nodes(nkey, k_alt, reinterpret_cast<NodeVal32 *>(nval),
+                                 reinterpret_cast<NodeVal32 *>(v_alt), len, bits_for(n - 1), tmp,
+                                 sort_err, s, so));
+        else
+            TRY(radix_sort_nodes(nkey, k_alt, nval, v_alt, len, bits_for(n - 1), tmp, sort_err, s, so));
         if (!direct) {
             uint32_t *k0 = reinterpret_cast<uint32_t *>(k_read), *v0 = k0 + len;
             uint32_t *k1 = reinterpret_cast<uint32_t *>(k_free), *v1 = k1 + len;
-            TRY(edge_positions(slots, len, k0, v0, k1, v1, tmp, sort_err, s, g->epos));
+            // the edge records go to the value buffer the last pass read
+            erec = reinterpret_cast<EdgeRec *>(node_passes % 2 ? (void *)nval : (void *)v_alt);
+            TRY(edge_positions(slots, len, k0, v0, k1, v1, tmp, sort_err, s, g->epos, TR, erec));
         }
         TM_LAUNCH("offsets_fill", k_fill_u32, grid_for(n + 1), dim3(kBlock), 0, s, g->off, n + 1,
                   kUnset);
@@ -511,26 +547,24 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         uint2 *v = reinterpret_cast<uint2 *>(PKA), *v_alt = reinterpret_cast<uint2 *>(PKB);
         TRY(lower_side_pairs(g->ent_c, g->ent_nd, g->ent_r, len, k, v, tmp, s));
         TRY(radix_sort_pairs(&k, &k_alt, &v, &v_alt, m, bits_for(n - 1), tmp, sort_err, s));
-        // flags and their scans reuse the (now free) node-sort buffers
-        uint32_t *in_multi = reinterpret_cast<uint32_t *>(KA);
-        uint32_t *head = reinterpret_cast<uint32_t *>(KB);
-        uint32_t *eidx = reinterpret_cast<uint32_t *>(VA);
-        uint32_t *pidx = reinterpret_cast<uint32_t *>(VB);
-        TM_LAUNCH("multi_flags", k_multi_flags, grid_for(m), dim3(kBlock), 0, s, k, v, m, in_multi,
-                  head);
-        TRY(scan_u32_array(in_multi, eidx, m, tmp, s));
-        TRY(scan_u32_array(head, pidx, m, tmp, s));
-        uint32_t counts[3] = {0, 0, 0};
-        TM_HIP_TRY(hipMemcpyAsync(&counts[0], eidx + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        TM_HIP_TRY(hipMemcpyAsync(&counts[1], pidx + m, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        TM_HIP_TRY(hipMemcpyAsync(&counts[2], sort_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        // flag bytes, then the element and pair indices of the pairs with >=
+        // 2 edges, in the (now free) node-sort key buffers; tmp holds the
+        // scan's u64 partials
+        uint8_t *flags = reinterpret_cast<uint8_t *>(KB);
+        uint64_t *pre = reinterpret_cast<uint64_t *>(KA);
+        TM_LAUNCH("pair_flags", k_pair_flags, grid_for(m), dim3(kBlock), 0, s, k, v, m, flags);
+        TRY(scan_flag_pairs(flags, m, pre, reinterpret_cast<uint64_t *>(tmp), s));
+        uint64_t totals = 0;
+        uint32_t err = 0;
+        TM_HIP_TRY(hipMemcpyAsync(&totals, pre + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        TM_HIP_TRY(hipMemcpyAsync(&err, sort_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         TM_HIP_TRY(hipStreamSynchronize(s));
-        if (counts[2]) {
+        if (err) {
             set_error("radix sort: a look-back wait gave up (device graph not built)");
             return TM_EINTERNAL;
         }
-        g->n_me = counts[0];
-        g->n_multi = counts[1];
+        g->n_me = (uint32_t)totals;
+        g->n_multi = (uint32_t)(totals >> 32);
         TRY(galloc(g, &g->mp_start, g->n_multi + 1));
         TRY(galloc(g, &g->mp_lo, g->n_multi));
         TRY(galloc(g, &g->mp_hi, g->n_multi));
@@ -539,8 +573,8 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
         TRY(galloc(g, &g->me_a, g->n_me));
         TRY(galloc(g, &g->me_o, g->n_me));
         MultiOut o{g->mp_start, g->mp_lo, g->mp_hi, g->me_t, g->me_p, g->me_a, g->me_o};
-        TM_LAUNCH("multi_fill", k_multi_fill, grid_for(m), dim3(kBlock), 0, s, k, v, m, in_multi,
-                  eidx, head, pidx, TR, g->epos, g->X, g->off, g->n_multi, g->n_me, o);
+        TM_LAUNCH("multi_fill", k_multi_fill, grid_for(m), dim3(kBlock), 0, s, k, v, m, pre, erec,
+                  TR, g->epos, g->X, g->off, g->n_multi, g->n_me, o);
     }
 
     // ---- 5. per-graph ranges and the static work tiles

@@ -1703,14 +1703,16 @@ int count_graph_multi(tm_graph *g, const int64_t *h_deltas, uint32_t k, Params p
 }
 
 // ------------------------------------------------------------- autotuner
-// Times the eager count of this graph (its own deltas) over partition
-// parameters and keeps the fastest: first the work-item chunk of the
-// star/pair sweeps with the lane/wave split of the triangle matching, then,
-// with those fixed, the window size from which triangle candidates go to the
-// hub kernel.  The result is stored on the graph and in a process-wide table
-// keyed by the graph's shape (log2 of edges, of multi-pair edges, and of the
-// graph count), which later graphs of that shape use by default.
-int autotune(tm_graph *g, const int64_t *h_deltas, Params *best, float *best_ms) {
+// Times the eager count of this graph over partition parameters and keeps
+// the fastest: first the work-item chunk of the star/pair sweeps with the
+// lane/wave split of the triangle matching, then, with those fixed, the
+// window size from which triangle candidates go to the hub kernel.  k == 1:
+// the count of graph i at h_deltas[i]; k > 1 (one graph): one pass of the
+// several-window count over the largest min(k, kMaxLevels) of the k windows.
+// The result is stored on the graph and in a process-wide table keyed by the
+// graph's shape (log2 of edges, of multi-pair edges, and of the graph
+// count), which later graphs of that shape use by default.
+int autotune(tm_graph *g, const int64_t *h_deltas, uint32_t k, Params *best, float *best_ms) {
     static const uint32_t chunks[] = {2, 4, 8};
     static const uint32_t lanes[] = {8, 32, 64, 256, 1024};
     static const uint32_t hubs[] = {16, 32, 64, 128, 256, 1024, TM_HUB_OFF};
@@ -1721,12 +1723,20 @@ int autotune(tm_graph *g, const int64_t *h_deltas, Params *best, float *best_ms)
     float bt = 0;
     if (g->m >= 3) {
         hipStream_t s = g->stream;
+        const uint32_t K = k > 1 ? std::min<uint32_t>(k, (uint32_t)kMaxLevels) : 1u;
+        std::vector<int64_t> dl(h_deltas, h_deltas + (k > 1 ? k : g->G));
+        if (k > 1) {
+            std::sort(dl.begin(), dl.end());
+            dl.erase(dl.begin(), dl.end() - K);
+        }
         Workspace w;
         Scratch sc;
-        int rc = sc.reserve(workspace_bytes(g, &w), s);
+        int rc = sc.reserve(workspace_bytes(g, &w, K), s);
         if (rc) return rc;
         workspace_carve(g, sc, &w);
-        TM_HIP_TRY(hipMemcpyAsync(w.deltas, h_deltas, g->G * 8, hipMemcpyHostToDevice, s));
+        TM_HIP_TRY(hipMemcpyAsync(w.deltas, dl.data(), dl.size() * 8, hipMemcpyHostToDevice, s));
+        // the copy reads the host vector before it goes out of scope
+        TM_HIP_TRY(hipStreamSynchronize(s));
         hipEvent_t e0, e1;
         TM_HIP_TRY(hipEventCreate(&e0));
         TM_HIP_TRY(hipEventCreate(&e1));

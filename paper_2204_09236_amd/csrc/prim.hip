@@ -3,6 +3,7 @@
 // the ranking loop).
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 #include <utility>
 
 #include "tm_internal.h"
@@ -32,8 +33,9 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
-// Inclusive scan over the kBlock threads; *total receives the block sum.
-template <typename T>
+// Inclusive scan over the NT threads of the block; *total receives the
+// block sum; lds4 holds NT / 64 values.
+template <typename T, int NT = kBlock>
 __device__ inline T block_incl_scan(T v, T *total, T *lds4) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     T s = wave_incl_scan(v, lane);
@@ -41,7 +43,7 @@ __device__ inline T block_incl_scan(T v, T *total, T *lds4) {
     __syncthreads();
     T pre = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; i++) {
+    for (int i = 0; i < NT / kWave; i++) {
         T x = lds4[i];
         if (i < w) pre += x;
         tot += x;
@@ -64,44 +66,74 @@ __device__ inline T block_sum(T v, T *lds4) {
     return tot;
 }
 
+// A scan's input: ld(i) is element i's value, of type L::value_type.
 struct LoadArray {
+    using value_type = uint32_t;
     const uint32_t *p;
     __device__ uint32_t operator()(uint64_t i) const { return p[i]; }
 };
 struct LoadDirBit {
+    using value_type = uint32_t;
     const uint32_t *nd;
     __device__ uint32_t operator()(uint64_t i) const { return nd[i] & 1u; }
 };
 // 1 for an entry of S seen from the smaller node of its edge
 struct LoadLowerSide {
+    using value_type = uint32_t;
     const uint32_t *c, *nd;
     __device__ uint32_t operator()(uint64_t i) const { return (nd[i] >> 1) > c[i] ? 1u : 0u; }
 };
+// A flag byte (bit 0 to the low word, bit 1 to the high word)
+struct LoadFlagPair {
+    using value_type = uint64_t;
+    const uint8_t *f;
+    __device__ uint64_t operator()(uint64_t i) const {
+        const uint32_t b = f[i];
+        return (uint64_t)(b & 1u) | ((uint64_t)(b >> 1) << 32);
+    }
+};
 
 template <typename L>
-__global__ void __launch_bounds__(kBlock) k_tile_sum(L ld, uint64_t n, uint32_t *part) {
-    __shared__ uint32_t lds[kBlock / kWave];
+__global__ void __launch_bounds__(kBlock) k_tile_sum(L ld, uint64_t n, typename L::value_type *part) {
+    using T = typename L::value_type;
+    __shared__ T lds[kBlock / kWave];
     const uint64_t base = (uint64_t)blockIdx.x * kTile;
-    uint32_t acc = 0;
+    T acc = 0;
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
-        uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+        const uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
         if (idx < n) acc += ld(idx);
     }
     acc = block_sum(acc, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// One block: exclusive scan of np partial sums in place; part[np] = total.
-__global__ void __launch_bounds__(kBlock) k_scan_parts(uint32_t *part, uint32_t np) {
-    __shared__ uint32_t lds[kBlock / kWave];
-    uint32_t carry = 0;
-    for (uint32_t b = 0; b < np; b += kBlock) {
-        uint32_t i = b + threadIdx.x;
-        uint32_t v = i < np ? part[i] : 0;
-        uint32_t tot;
-        uint32_t inc = block_incl_scan(v, &tot, lds);
-        if (i < np) part[i] = carry + inc - v;
+// One block of kPartsThreads: exclusive scan of np partial sums in place;
+// part[np] = total.  Each thread takes kPartsPer consecutive sums a round.
+constexpr int kPartsThreads = 1024;
+constexpr int kPartsPer = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kPartsThreads) k_scan_parts(T *part, uint32_t np) {
+    __shared__ T lds[kPartsThreads / kWave];
+    T carry = 0;
+    for (uint64_t b = 0; b < np; b += (uint64_t)kPartsThreads * kPartsPer) {
+        const uint64_t i0 = b + (uint64_t)threadIdx.x * kPartsPer;
+        T x[kPartsPer];
+        T sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPartsPer; k++) {
+            x[k] = i0 + k < np ? part[i0 + k] : T(0);
+            sum += x[k];
+        }
+        T tot;
+        const T inc = block_incl_scan<T, kPartsThreads>(sum, &tot, lds);
+        T run = carry + inc - sum;
+#pragma unroll
+        for (int k = 0; k < kPartsPer; k++) {
+            if (i0 + k < np) part[i0 + k] = run;
+            run += x[k];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) part[np] = carry;
@@ -109,11 +141,18 @@ __global__ void __launch_bounds__(kBlock) k_scan_parts(uint32_t *part, uint32_t 
 
 // Where a scan's results go: wr(i, exclusive prefix, value) per element and
 // wr.total(n, total) once.  ArrayWrite stores the prefixes (out[n] = total).
-struct ArrayWrite {
-    uint32_t *out;
-    __device__ void operator()(uint64_t i, uint32_t ex, uint32_t) const { out[i] = ex; }
-    __device__ void total(uint64_t n, uint32_t t) const { out[n] = t; }
+// kLoads: the writer reads memory of its own per element; such a scan keeps
+// every element's load, scan and write in one round of the block (barriers
+// between rounds), so that the writer's loads of different rounds overlap
+// with other blocks' work rather than waiting one after another.
+template <typename T>
+struct ArrayWriteT {
+    static constexpr bool kLoads = false;
+    T *out;
+    __device__ void operator()(uint64_t i, T ex, T) const { out[i] = ex; }
+    __device__ void total(uint64_t n, T t) const { out[n] = t; }
 };
+using ArrayWrite = ArrayWriteT<uint32_t>;
 
 // The pair sort's input: each edge once, from its entry at the smaller node
 // (S order: smaller node, then (t, id)), as key = the larger node, value =
@@ -121,6 +160,7 @@ struct ArrayWrite {
 // A stable sort by the key then groups every node pair, its edges in (t, id)
 // order, pairs by (larger, smaller).
 struct LowerSideWrite {
+    static constexpr bool kLoads = true;
     const uint32_t *c, *nd, *r;
     uint32_t *key;
     uint2 *val;
@@ -134,44 +174,92 @@ struct LowerSideWrite {
     __device__ void total(uint64_t, uint32_t) const {}
 };
 
+// One tile of a scan, kTile elements from base.  Returns the tile's total.
+// Without writer loads: wave w owns the contiguous run [base + w * kItems *
+// 64, ...) and walks it in kItems rounds of 64 lanes, so (wave, round, lane)
+// is input order; all loads are issued first, each round is scanned within
+// the wave with a running carry, and one barrier exchanges the wave totals.
+// With writer loads: kItems rounds of kBlock elements, each scanned over the
+// block.
 template <typename L, typename W>
-__global__ void __launch_bounds__(kBlock) k_tile_scan(L ld, uint64_t n, const uint32_t *part,
-                                                      uint32_t np, W wr) {
-    __shared__ uint32_t lds[kBlock / kWave];
-    const uint64_t base = (uint64_t)blockIdx.x * kTile;
-    uint32_t carry = part[blockIdx.x];
-    for (int i = 0; i < kItems; i++) {
-        uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
-        uint32_t v = idx < n ? ld(idx) : 0;
-        uint32_t tot;
-        uint32_t inc = block_incl_scan(v, &tot, lds);
-        if (idx < n) wr(idx, carry + inc - v, v);
-        carry += tot;
+__device__ __forceinline__ typename L::value_type scan_tile_body(L ld, uint64_t n, uint64_t base,
+                                                        typename L::value_type start, W wr,
+                                                        typename L::value_type *wsum) {
+    using T = typename L::value_type;
+    if constexpr (W::kLoads) {
+        T carry = start;
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+            const T v = idx < n ? ld(idx) : T(0);
+            T tot;
+            const T inc = block_incl_scan(v, &tot, wsum);
+            if (idx < n) wr(idx, carry + inc - v, v);
+            carry += tot;
+        }
+        return carry - start;
+    } else {
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        const uint64_t wbase = base + (uint64_t)w * kItems * kWave;
+        T v[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t idx = wbase + (uint64_t)i * kWave + lane;
+            v[i] = idx < n ? ld(idx) : T(0);
+        }
+        T ex[kItems];
+        T carry = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const T inc = wave_incl_scan(v[i], lane);
+            ex[i] = carry + inc - v[i];
+            carry += __shfl(inc, kWave - 1, kWave);
+        }
+        if (lane == 0) wsum[w] = carry;
+        __syncthreads();
+        T off = start, tot = start;
+#pragma unroll
+        for (int j = 0; j < kBlock / kWave; j++) {
+            const T x = wsum[j];
+            off += j < w ? x : T(0);
+            tot += x;
+        }
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t idx = wbase + (uint64_t)i * kWave + lane;
+            if (idx < n) wr(idx, off + ex[i], v[i]);
+        }
+        return tot - start;
     }
+}
+
+template <typename L, typename W>
+__global__ void __launch_bounds__(kBlock) k_tile_scan(L ld, uint64_t n,
+                                                      const typename L::value_type *part,
+                                                      uint32_t np, W wr) {
+    using T = typename L::value_type;
+    __shared__ T wsum[kBlock / kWave];
+    scan_tile_body(ld, n, (uint64_t)blockIdx.x * kTile, part[blockIdx.x], wr, wsum);
     if (blockIdx.x == 0 && threadIdx.x == 0) wr.total(n, part[np]);
 }
 
 // The whole scan when the input fits one tile: one launch instead of three.
 template <typename L, typename W>
 __global__ void __launch_bounds__(kBlock) k_scan_one(L ld, uint64_t n, W wr) {
-    __shared__ uint32_t lds[kBlock / kWave];
-    uint32_t carry = 0;
-    for (int i = 0; i < kItems; i++) {
-        const uint64_t idx = (uint64_t)i * kBlock + threadIdx.x;
-        const uint32_t v = idx < n ? ld(idx) : 0;
-        uint32_t tot;
-        const uint32_t inc = block_incl_scan(v, &tot, lds);
-        if (idx < n) wr(idx, carry + inc - v, v);
-        carry += tot;
-    }
-    if (threadIdx.x == 0) wr.total(n, carry);
+    using T = typename L::value_type;
+    __shared__ T wsum[kBlock / kWave];
+    const T tot = scan_tile_body(ld, n, 0, T(0), wr, wsum);
+    if (threadIdx.x == 0) wr.total(n, tot);
 }
 
 template <typename W>
 __global__ void k_scan_empty(W wr) { wr.total(0, 0); }
 
+// tmp: scan_tmp_count(n) elements of L::value_type.
+// Trace names of the tile-sum and tile-scan launches: sum_name, tile_name.
 template <typename L, typename W = ArrayWrite>
-int scan_impl(L ld, W wr, uint64_t n, uint32_t *tmp, hipStream_t s) {
+int scan_impl(L ld, W wr, uint64_t n, typename L::value_type *tmp, hipStream_t s,
+              const char *sum_name = "scan_tile_sum", const char *tile_name = "scan_tile") {
+    using T = typename L::value_type;
     const uint64_t nb = (n + kTile - 1) / kTile;
     if (nb == 0) {
         // a kernel, not a memset: this may run inside a captured graph
@@ -182,9 +270,9 @@ int scan_impl(L ld, W wr, uint64_t n, uint32_t *tmp, hipStream_t s) {
         TM_LAUNCH("scan_one", (k_scan_one<L, W>), dim3(1), dim3(kBlock), 0, s, ld, n, wr);
         return TM_OK;
     }
-    TM_LAUNCH("scan_tile_sum", (k_tile_sum<L>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp);
-    TM_LAUNCH("scan_parts", k_scan_parts, dim3(1), dim3(kBlock), 0, s, tmp, (uint32_t)nb);
-    TM_LAUNCH("scan_tile", (k_tile_scan<L, W>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp,
+    TM_LAUNCH(sum_name, (k_tile_sum<L>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp);
+    TM_LAUNCH("scan_parts", k_scan_parts<T>, dim3(1), dim3(kPartsThreads), 0, s, tmp, (uint32_t)nb);
+    TM_LAUNCH(tile_name, (k_tile_scan<L, W>), dim3(nb), dim3(kBlock), 0, s, ld, n, tmp,
               (uint32_t)nb, wr);
     return TM_OK;
 }
@@ -220,12 +308,15 @@ constexpr uint64_t kMinTile = (uint64_t)kOsThreads * 6;
 
 // Block size and items per thread of a pass, by element type: the node
 // sort's 20-byte elements run in 1024-thread blocks with 6144-element tiles
-// (one block per CU, 141 KiB of LDS); the others in 512-thread blocks with
+// (one block per CU, 141 KiB of LDS), its 16-byte ones (NodeVal32) with
+// 8192-element tiles (145 KiB); the others in 512-thread blocks with
 // 3072-5120-element tiles (two blocks per CU).  Measured on gfx950: longer
 // digit runs per tile pay more than occupancy for the node sort.
 template <typename K, typename V>
 constexpr int os_threads() {
-    return sizeof(V) == sizeof(NodeVal) && sizeof(K) == 4 ? 1024 : kOsThreads;
+    return (std::is_same<V, NodeVal>::value || std::is_same<V, NodeVal32>::value) && sizeof(K) == 4
+               ? 1024
+               : kOsThreads;
 }
 
 template <typename K, typename V>
@@ -355,11 +446,17 @@ struct PairOut {
     }
 };
 
+__device__ inline int64_t node_time(const NodeVal &v, int64_t) { return v.t; }
+__device__ inline int64_t node_time(const NodeVal32 &v, int64_t base) {
+    return base + (int64_t)v.dt;
+}
+
+template <typename V>
 struct SeqWrite {
     SeqOut o;
-    __device__ inline void operator()(uint32_t pos, uint32_t k, const NodeVal &v) const {
+    __device__ inline void operator()(uint32_t pos, uint32_t k, const V &v) const {
         o.ent_c[pos] = k;
-        o.ent_t[pos] = v.t;
+        o.ent_t[pos] = node_time(v, o.tbase);
         o.ent_nd[pos] = v.nd;
         o.ent_r[pos] = v.r;
         // the entry's slot: 2r at the source, 2r + 1 at the destination
@@ -395,8 +492,14 @@ struct RankWrite {
         o.perm[r] = ev.id;
         o.nkey[2 * (uint64_t)r] = ev.src;
         o.nkey[2 * (uint64_t)r + 1] = ev.dst;
-        o.nval[2 * (uint64_t)r] = NodeVal{te, r, ev.dst << 1};
-        o.nval[2 * (uint64_t)r + 1] = NodeVal{te, r, (ev.src << 1) | 1u};
+        if (o.nval32) {
+            const uint32_t dt = (uint32_t)(te - o.tbase);
+            o.nval32[2 * (uint64_t)r] = NodeVal32{dt, r, ev.dst << 1};
+            o.nval32[2 * (uint64_t)r + 1] = NodeVal32{dt, r, (ev.src << 1) | 1u};
+        } else {
+            o.nval[2 * (uint64_t)r] = NodeVal{te, r, ev.dst << 1};
+            o.nval[2 * (uint64_t)r + 1] = NodeVal{te, r, (ev.src << 1) | 1u};
+        }
     }
 };
 
@@ -636,10 +739,15 @@ int scan_dirbits(const uint32_t *ent_nd, uint32_t *out, uint64_t n, uint32_t *tm
     return scan_impl(LoadDirBit{ent_nd}, ArrayWrite{out}, n, tmp, s);
 }
 
+int scan_flag_pairs(const uint8_t *f, uint64_t n, uint64_t *out, uint64_t *tmp, hipStream_t s) {
+    return scan_impl(LoadFlagPair{f}, ArrayWriteT<uint64_t>{out}, n, tmp, s, "scan_flags_sum",
+                     "scan_flags_tile");
+}
+
 int lower_side_pairs(const uint32_t *ent_c, const uint32_t *ent_nd, const uint32_t *ent_r,
                      uint64_t n, uint32_t *key, uint2 *val, uint32_t *tmp, hipStream_t s) {
     return scan_impl(LoadLowerSide{ent_c, ent_nd}, LowerSideWrite{ent_c, ent_nd, ent_r, key, val},
-                     n, tmp, s);
+                     n, tmp, s, "scan_lower_sum", "scan_lower_tile");
 }
 
 int radix_sort_pairs(uint32_t **keys, uint32_t **keys_alt, uint2 **vals, uint2 **vals_alt,
@@ -721,8 +829,12 @@ constexpr int kSlotBucketBits = 15;  // 128 KiB of LDS per bucket
 constexpr uint32_t kSlotBucket = 1u << kSlotBucketBits;
 
 // key: slots; val: their positions (null: position = index, the unsorted case).
+// With erec, also each edge's record (t, both positions) for the edges of
+// the bucket: a bucket starts at an even slot and n is even, so it holds
+// both slots of each of its edges.
 __global__ void __launch_bounds__(1024) k_epos_fill(const uint32_t *key, const uint32_t *val,
-                                                    uint64_t n, uint32_t *epos) {
+                                                    uint64_t n, uint32_t *epos,
+                                                    const int64_t *t_r, EdgeRec *erec) {
     __shared__ uint32_t buf[kSlotBucket];
     for (uint64_t b = blockIdx.x; b * kSlotBucket < n; b += gridDim.x) {
         const uint64_t lo = b * kSlotBucket;
@@ -731,13 +843,20 @@ __global__ void __launch_bounds__(1024) k_epos_fill(const uint32_t *key, const u
             buf[key[lo + i] & (kSlotBucket - 1)] = val ? val[lo + i] : (uint32_t)(lo + i);
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) epos[lo + i] = buf[i];
+        if (erec) {
+            const uint64_t r0 = lo / 2;
+            for (uint32_t i = threadIdx.x; i < cnt / 2; i += blockDim.x)
+                erec[r0 + i] = EdgeRec{t_r[r0 + i], buf[2 * i], buf[2 * i + 1]};
+        }
         __syncthreads();
     }
 }
 
 int edge_positions(const uint32_t *slot, uint64_t n, uint32_t *k0, uint32_t *v0, uint32_t *k1,
-                   uint32_t *v1, void *tmp, uint32_t *err, hipStream_t s, uint32_t *epos) {
+                   uint32_t *v1, void *tmp, uint32_t *err, hipStream_t s, uint32_t *epos,
+                   const int64_t *t_r, EdgeRec *erec) {
     if (n == 0) return TM_OK;
+    if (erec && n % 2) return TM_EINTERNAL;
     int bits = 0;
     while (bits < 32 && ((n - 1) >> bits) != 0) bits++;
     const uint32_t *key = slot, *val = nullptr;
@@ -752,18 +871,30 @@ int edge_positions(const uint32_t *slot, uint64_t n, uint32_t *k0, uint32_t *v0,
         val = vals;
     }
     const uint64_t nb = std::min<uint64_t>((n + kSlotBucket - 1) / kSlotBucket, 8192);
-    TM_LAUNCH("epos_fill", k_epos_fill, dim3((unsigned)nb), dim3(1024), 0, s, key, val, n, epos);
+    TM_LAUNCH("epos_fill", k_epos_fill, dim3((unsigned)nb), dim3(1024), 0, s, key, val, n, epos,
+              t_r, erec);
     return TM_OK;
+}
+
+template <typename V>
+static int node_sort(uint32_t *keys, uint32_t *keys_alt, V *vals, V *vals_alt, uint64_t n,
+                     int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut so) {
+    if (n == 0) return TM_OK;
+    const SeqWrite<V> fin{so};
+    const ArrayIn<uint32_t, V> in0{keys, vals};
+    return radix_impl<uint32_t, V, SeqWrite<V>>(&keys, &keys_alt, &vals, &vals_alt, n,
+                                                bits < 1 ? 1 : bits, tmp, err, s, "sort_node_hist",
+                                                "sort_node_scatter", &fin, in0);
 }
 
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
                      uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut so) {
-    if (n == 0) return TM_OK;
-    const SeqWrite fin{so};
-    const ArrayIn<uint32_t, NodeVal> in0{keys, vals};
-    return radix_impl<uint32_t, NodeVal, SeqWrite>(&keys, &keys_alt, &vals, &vals_alt, n,
-                                                   bits < 1 ? 1 : bits, tmp, err, s,
-                                                   "sort_node_hist", "sort_node_scatter", &fin, in0);
+    return node_sort(keys, keys_alt, vals, vals_alt, n, bits, tmp, err, s, so);
+}
+
+int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal32 *vals, NodeVal32 *vals_alt,
+                     uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut so) {
+    return node_sort(keys, keys_alt, vals, vals_alt, n, bits, tmp, err, s, so);
 }
 
 }  // namespace tmc

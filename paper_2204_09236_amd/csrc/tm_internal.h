@@ -101,6 +101,9 @@ int lower_side_pairs(const uint32_t *ent_c, const uint32_t *ent_nd, const uint32
 // key bits [0, bits); *keys / *vals point at the sorted data on return.
 int radix_sort_pairs(uint32_t **keys, uint32_t **keys_alt, uint2 **vals, uint2 **vals_alt,
                      uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s);
+// Exclusive prefix sums of the two bits of n flag bytes at once: bit 0's in
+// the low word of out[i], bit 1's in the high word; out[n] = the totals.
+int scan_flag_pairs(const uint8_t *f, uint64_t n, uint64_t *out, uint64_t *tmp, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, bits), 8 bits per
 // pass, ping-ponging between the two buffers; *keys / *vals point at the
@@ -128,6 +131,12 @@ struct NodeVal {
     int64_t t;
     uint32_t r, nd;
 };
+// The same with the timestamp as an offset from a base, used when every
+// timestamp of the build lies within 2^32 of the smallest: 12 bytes an
+// entry instead of 16 through the node sort's passes.
+struct NodeVal32 {
+    uint32_t dt, r, nd;
+};
 
 // Where the node sort's last pass writes: the sequence arrays S_u directly,
 // plus either each edge's two positions (epos[2r + dir], a random write per
@@ -141,7 +150,8 @@ struct SeqOut {
     uint32_t *ent_r;
     uint32_t *epos;
     uint32_t *slot;
-    uint64_t n;  // entries (epos slots)
+    uint64_t n;     // entries (epos slots)
+    int64_t tbase;  // NodeVal32: t = tbase + dt
 };
 
 // Where the time sort's last pass writes: the arrays by edge rank r (rank =
@@ -154,7 +164,9 @@ struct RankOut {
     int64_t *t_r;
     uint32_t *perm;
     uint32_t *nkey;
-    NodeVal *nval;
+    NodeVal *nval;      // with nval32 null
+    NodeVal32 *nval32;  // else, t - tbase
+    int64_t tbase;
 };
 
 // hist_name / scatter_name label the sort's kernels for the tracer.
@@ -180,14 +192,25 @@ int radix_sort_time_direct_u64(const int32_t *src, const int32_t *dst, const int
                                uint64_t *keys, uint64_t *keys_alt, EdgeVal *vals, EdgeVal *vals_alt,
                                uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s,
                                RankOut out);
+// An edge's time and its two entry positions in S (source, destination).
+struct alignas(16) EdgeRec {
+    int64_t t;
+    uint32_t p_src, p_dst;
+};
+static_assert(sizeof(EdgeRec) == 16, "EdgeRec");
+
 // epos[slot] = position of slot, from the slots in entry order (a
 // permutation of [0, n)); k0, v0, k1, v1: n words each of scratch, none of
-// them aliasing slot; tmp as for the radix sorts.
+// them aliasing slot; tmp as for the radix sorts.  With erec (n even):
+// erec[r] = (t_r[r], epos[2r], epos[2r + 1]) for the n / 2 edges as well.
 int edge_positions(const uint32_t *slot, uint64_t n, uint32_t *k0, uint32_t *v0, uint32_t *k1,
-                   uint32_t *v1, void *tmp, uint32_t *err, hipStream_t s, uint32_t *epos);
+                   uint32_t *v1, void *tmp, uint32_t *err, hipStream_t s, uint32_t *epos,
+                   const int64_t *t_r = nullptr, EdgeRec *erec = nullptr);
 // Node sort: (node, NodeVal) pairs on bits [0, bits); the last pass writes
 // SeqOut instead of the ping-pong buffers (at least one pass always runs).
 int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal *vals, NodeVal *vals_alt,
+                     uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut out);
+int radix_sort_nodes(uint32_t *keys, uint32_t *keys_alt, NodeVal32 *vals, NodeVal32 *vals_alt,
                      uint64_t n, int bits, void *tmp, uint32_t *err, hipStream_t s, SeqOut out);
 
 
@@ -296,7 +319,7 @@ size_t count_workspace_bytes(const tm_graph *g);
 // Upper bound of device bytes a build of m edges uses at its peak.
 size_t build_peak_bytes(uint64_t m, uint64_t n, uint32_t G);
 // Autotuner (count.hip) and its process-wide table (api.hip).
-int autotune(tm_graph *g, const int64_t *deltas, Params *best, float *best_ms);
+int autotune(tm_graph *g, const int64_t *deltas, uint32_t k, Params *best, float *best_ms);
 void tune_table_lookup(const tm_graph *g, Params *p);
 void tune_table_store(const tm_graph *g, const Params &p);
 }  // namespace tmc

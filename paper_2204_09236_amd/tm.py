@@ -75,6 +75,10 @@ def _load():
                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_float)]
     lib.tm_autotune.restype = ctypes.c_int
+    lib.tm_autotune_multi.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32,
+                                      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)]
+    lib.tm_autotune_multi.restype = ctypes.c_int
     lib.tm_count4.argtypes = [vp, ctypes.c_int64, u64p, u64p]
     lib.tm_count4.restype = ctypes.c_int
     lib.tm_count_multi.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_uint32, u64p]
@@ -243,6 +247,15 @@ class Graph:
         c, l, h, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
         _check(_lib.tm_autotune(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                 ctypes.byref(c), ctypes.byref(l), ctypes.byref(h), ctypes.byref(ms)))
+        return {"run_chunk": c.value, "tri_lane_max": l.value, "hub_min": h.value, "ms": ms.value}
+
+    def autotune_multi(self, deltas) -> dict:
+        """The autotuner for count_multi of one graph over these windows."""
+        d = np.ascontiguousarray(deltas, dtype=np.int64).reshape(-1)
+        c, l, h, ms = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
+        _check(_lib.tm_autotune_multi(self.handle, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      d.size, ctypes.byref(c), ctypes.byref(l), ctypes.byref(h),
+                                      ctypes.byref(ms)))
         return {"run_chunk": c.value, "tri_lane_max": l.value, "hub_min": h.value, "ms": ms.value}
 
     def info(self) -> dict:

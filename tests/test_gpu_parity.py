@@ -484,6 +484,32 @@ def test_autotune_then_count(tm):
         np.testing.assert_array_equal(G.count_raw(86400), oracle.alg(g.src, g.dst, g.t, 86400, n=g.n))
 
 
+def test_autotune_multi_then_count(tm):
+    """The several-window autotuner (k = 3, and k = 6 > four levels: the
+    largest four are timed) keeps a valid choice; counts after it still equal
+    the oracle's; a batch and bad arguments are rejected."""
+    g = graphgen.chung_lu_pareto(89, 5000, 150_000)
+    deltas = [600, 3600, 86400]
+    with tm.build_graph(g.src, g.dst, g.t, n=g.n) as G:
+        for ds in (deltas, [0, 10, 60, 600, 3600, 86400]):
+            case(f"autotune_multi {ds}")
+            best = G.autotune_multi(ds)
+            assert best["run_chunk"] in (2, 4, 8)
+            assert best["tri_lane_max"] in (8, 32, 64, 256, 1024)
+            assert best["hub_min"] in (16, 32, 64, 128, 256, 1024, 0xFFFFFFFF)
+            assert best["ms"] > 0
+        raw = G.count_multi_raw(deltas)
+        for i, d in enumerate(deltas):
+            np.testing.assert_array_equal(raw[i], oracle.alg(g.src, g.dst, g.t, d, n=g.n))
+        for bad in ([], [-1, 5]):
+            with pytest.raises(tm.TMError):
+                G.autotune_multi(bad)
+    src, dst, t = np.array([0, 1, 2], np.int32), np.array([1, 2, 0], np.int32), np.array([1, 2, 3])
+    with tm.build_batch([(src, dst, t, 3), (src, dst, t, 3)]) as B:
+        with pytest.raises(tm.TMError):
+            B.autotune_multi([5, 10])
+
+
 # motif-family masks (tm_count_masked): the selected cells equal the full
 # count, the others are zero
 STAR_CELLS = [(r, c) for r in range(6) for c in range(4)]
