@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <mutex>
@@ -197,7 +198,7 @@ struct alignas(16) EdgeRec {
     int64_t t;
     uint32_t p_src, p_dst;
 };
-static_assert(sizeof(EdgeRec) == 16, "EdgeRec");
+static_assert(sizeof(EdgeRec) == 16 && offsetof(EdgeRec, p_src) == 8, "EdgeRec layout");
 
 // epos[slot] = position of slot, from the slots in entry order (a
 // permutation of [0, n)); k0, v0, k1, v1: n words each of scratch, none of
