@@ -195,7 +195,9 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
     value) pair once; histogram passes read every key once.  The time sort
     of one graph reads the input arrays (src, dst, t: 16 B per edge) in its
     histogram and first pass, and its last pass writes the rank-ordered
-    arrays (t, input index, the two node-sort entries: 52 B per edge).  The
+    arrays (t, input index, the two node-sort entries: 44 B per edge when
+    the time span fits 32 bits and the entries carry 12-byte values, else
+    52 B).  The
     pair sort reads each edge once from its entry at the smaller node and
     sorts (larger node, (smaller node, rank)) pairs on the node bits.  The node sort's last pass writes the sequence arrays
     (node, t, other end | dir, rank) and each entry's slot instead of the
@@ -203,9 +205,11 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
     partition of (slot, position) pairs and a bucket fill."""
     e2 = 2 * m
     tk = 4 if info["tbits"] <= 32 else 8
+    nv = 12 if info["tbits"] <= 32 else 16   # node-sort value bytes
+    rank_out = 12 + 2 * (4 + nv)
     me, nm = info["multi_pair_edges"], info["multi_pairs"]
     pt = max(passes["time"], 1)
-    time_first = 16 + ((tk + 12) if pt > 1 else 52)
+    time_first = 16 + ((tk + 12) if pt > 1 else rank_out)
     # "sort_time_scatter": every pass but the last (the first reads the inputs)
     time_scatter = ((m * time_first + m * (tk + 12) * 2 * max(pt - 2, 0)) / (pt - 1)
                     if pt > 1 else 0)
@@ -214,11 +218,11 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
         "time_keys": m * (16 + tk + 12),   # batches only
         "sort_time_hist": m * 8,
         "sort_time_scatter": time_scatter,
-        "sort_time_scatter_last": m * (tk + 12 + 52) if pt > 1 else m * (16 + 52),
+        "sort_time_scatter_last": m * (tk + 12 + rank_out) if pt > 1 else m * (16 + rank_out),
         "sort_node_hist": e2 * 4,
-        "sort_node_scatter": e2 * 40,
+        "sort_node_scatter": e2 * 2 * (4 + nv),
         # the last pass also writes each entry's slot (2r + dir) in entry order
-        "sort_node_scatter_last": e2 * (20 + 24),
+        "sort_node_scatter_last": e2 * (4 + nv + 24),
         # edge positions: (slot, position) pairs partitioned by the slot's
         # high bits (the first pass reads the slots alone), then each bucket
         # filled through LDS, with each edge's record (t, both positions)
