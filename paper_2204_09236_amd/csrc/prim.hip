@@ -436,6 +436,19 @@ __global__ void __launch_bounds__(256) k_os_hist_sum(const uint32_t *part, uint3
     if (s) atomicAdd(&ghist[i], s);
 }
 
+// Digit counts of every pass when the keys are exactly 0 .. n-1 in some
+// order (the edge slots): in pass p (bits [shift0 + 8p, +8)), digit d holds
+// n / 2^(sh+8) full runs of 2^sh keys plus what the last, partial cycle
+// gives it.  Grid: one block of 256 per pass.
+__global__ void __launch_bounds__(256) k_os_hist_iota(uint64_t n, int shift0, uint32_t *ghist) {
+    const int p = blockIdx.x, d = threadIdx.x;
+    const int sh = shift0 + 8 * p;
+    const uint64_t w = 1ull << sh, cyc = w << 8;
+    const uint64_t rem = n % cyc, lo = (uint64_t)d * w;
+    const uint64_t extra = rem > lo ? min(rem - lo, w) : 0ull;
+    ghist[256 * p + d] = (uint32_t)((n / cyc) * w + extra);
+}
+
 template <typename K, typename V>
 struct PairOut {
     K *kout;
@@ -666,7 +679,7 @@ inline OsTmp os_tmp(void *tmp, uint64_t ntiles) {
 template <typename K, typename V, typename Final, typename In0>
 int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int bits, void *tmp,
                uint32_t *err, hipStream_t s, const char *hist_name, const char *scatter_name,
-               const Final *fin, const In0 &in0, int shift0 = 0) {
+               const Final *fin, const In0 &in0, int shift0 = 0, bool iota_keys = false) {
     constexpr int kItems_ = os_items<K, V>();
     constexpr int kThr = os_threads<K, V>();
     constexpr uint64_t kT = (uint64_t)kThr * kItems_;
@@ -680,12 +693,18 @@ int radix_impl(K **keys, K **keys_alt, V **vals, V **vals_alt, uint64_t n, int b
     const uint64_t n_status = ntiles * 256;
     TM_LAUNCH("sort_init", k_os_init, dim3((unsigned)std::min<uint64_t>((n_status + kBlock - 1) / kBlock + 1, 4096)),
               dim3(kBlock), 0, s, t.ghist, (uint32_t)(kMaxPasses * 257), t.status[0], n_status);
-    const uint64_t hchunk = (uint64_t)kOsThreads * kHistItems;
-    const uint32_t hblocks = (uint32_t)std::min<uint64_t>((n + hchunk - 1) / hchunk, kHistBlocks);
-    TM_LAUNCH(hist_name, (k_os_hist<K, In0>), dim3(hblocks), dim3(kOsThreads), 0, s, in0, n, passes,
-              shift0, t.part);
-    TM_LAUNCH("sort_hist_sum", k_os_hist_sum, dim3((unsigned)passes, kHistSumSplit), dim3(256), 0, s,
-              t.part, hblocks, passes, t.ghist);
+    if (iota_keys) {
+        // keys 0 .. n-1: the digit counts follow from n alone
+        TM_LAUNCH(hist_name, k_os_hist_iota, dim3((unsigned)passes), dim3(256), 0, s, n, shift0,
+                  t.ghist);
+    } else {
+        const uint64_t hchunk = (uint64_t)kOsThreads * kHistItems;
+        const uint32_t hblocks = (uint32_t)std::min<uint64_t>((n + hchunk - 1) / hchunk, kHistBlocks);
+        TM_LAUNCH(hist_name, (k_os_hist<K, In0>), dim3(hblocks), dim3(kOsThreads), 0, s, in0, n,
+                  passes, shift0, t.part);
+        TM_LAUNCH("sort_hist_sum", k_os_hist_sum, dim3((unsigned)passes, kHistSumSplit), dim3(256), 0,
+                  s, t.part, hblocks, passes, t.ghist);
+    }
     const uint32_t spin = lookback_spin_limit();
     // the pass that writes the final arrays is traced under its own name
     const std::string last_name = std::string(scatter_name) + "_last";
@@ -865,7 +884,7 @@ int edge_positions(const uint32_t *slot, uint64_t n, uint32_t *k0, uint32_t *v0,
         const SlotIn in0{slot};
         const int rc = radix_impl<uint32_t, uint32_t, PairOut<uint32_t, uint32_t>>(
             &keys, &keys_alt, &vals, &vals_alt, n, bits, tmp, err, s, "sort_slot_hist",
-            "sort_slot_scatter", nullptr, in0, kSlotBucketBits);
+            "sort_slot_scatter", nullptr, in0, kSlotBucketBits, /*iota_keys=*/true);
         if (rc) return rc;
         key = keys;
         val = vals;
