@@ -226,7 +226,7 @@ def byte_model(m: int, n: int, info: dict, ws: dict | None, passes: dict, levels
         # edge positions: (slot, position) pairs partitioned by the slot's
         # high bits (the first pass reads the slots alone), then each bucket
         # filled through LDS, with each edge's record (t, both positions)
-        "sort_slot_hist": e2 * 4,
+        "sort_slot_hist": 0,   # the slots are 0 .. 2m-1: digit counts from 2m alone
         "sort_slot_scatter": e2 * 14,
         "epos_fill": e2 * (8 + 4) + m * (8 + 16),
         "offsets_fill": (n + 1) * 4,
