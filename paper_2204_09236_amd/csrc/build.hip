@@ -432,11 +432,13 @@ int build_graph_device(tm_graph *g, const int32_t *src, const int32_t *dst, cons
     TRY(upload_tiles(g, etiles, &d_etiles, &n_etiles, s));
 
     // ---- scratch (stream-ordered, released when this function returns)
-    // KA, KB: 8 bytes x 2m each   (time keys, node keys)
-    // VA, VB: 16 bytes x 2m each  (EdgeVal of m, NodeVal of 2m)
+    // KA, KB: 8 bytes x 2m each   (time keys, node keys; later the pair
+    //                              flags' prefix (KA) and bytes (KB))
+    // VA, VB: 16 bytes x 2m each  (EdgeVal of m, NodeVal(32) of 2m; later the
+    //                              slots and the EdgeRec of m)
     // PKA, PKB: 8 bytes x m; PVA, PVB: u32 x m   (pair sort values, keys)
     // TR: i64 x m                 (timestamps by rank)
-    // TMP: scan / histogram scratch
+    // TMP: scan / histogram scratch (the flag scan's u64 partials too)
     const size_t ntmp =
         std::max({radix_tmp_bytes(len) / 4 + 1, scan_tmp_count(len), 2 * scan_tmp_count(m),
                   (size_t)3 * (G + 1)}) + 16;
