@@ -81,3 +81,33 @@ def test_merge_rejects_broken_symmetry():
     raw[32] = 3
     with pytest.raises(TMError):
         merge(raw)
+
+
+def test_null_arguments_rejected_without_a_device():
+    """Entry points check their pointers before any HIP call: a NULL graph
+    or output gives TM_EINVAL (-1) and an error message, on a host with no
+    GPU as well."""
+    import ctypes
+    import paper_2204_09236_amd as pkg
+    lib = pkg.tm.library()
+    d = (ctypes.c_int64 * 3)(600, 3600, 86400)
+    out36 = (ctypes.c_uint64 * (36 * 3))()
+    raw56 = (ctypes.c_uint64 * (56 * 3))()
+    out32 = (ctypes.c_uint64 * 32)()
+    calls = [
+        ("tm_autotune", (None, d, None, None, None, None)),
+        ("tm_autotune_multi", (None, d, 3, None, None, None, None)),
+        ("tm_count", (None, 600, None)),
+        ("tm_count_raw", (None, 600, raw56)),
+        ("tm_count_masked", (None, 600, 7, None)),
+        ("tm_count_multi", (None, d, 3, None)),
+        ("tm_count_multi_raw", (None, d, 3, raw56)),
+        ("tm_count4", (None, 600, raw56, out32)),
+        ("tm_graph_info", (None, None, None, None, None, None)),
+        ("tm_merge", (None, out36)),
+    ]
+    for name, args in calls:
+        rc = getattr(lib, name)(*args)
+        assert rc == -1, (name, rc)
+    msg = lib.tm_last_error()
+    assert msg, "no error message after a rejected call"
